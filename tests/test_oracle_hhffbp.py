@@ -1,0 +1,104 @@
+"""Pins of the oracle HHFFBPA (CPU only).
+
+HHFFBPA approximates eq. (4); the oracle is pinned to eq. (4) by:
+* the special case S = 0 (one subarray whose grid is the voxel grid), which is
+  eq. (4) exactly;
+* the error bound: <= -30 dB NRMSE against eq. (4) at the default settings;
+* convergence: the error falls as the grid oversampling and the taps grow;
+* linearity in the echoes and the global-phase identity;
+* the Lagrange kernel reproducing polynomials of degree < T;
+* the grid construction: every position in exactly one leaf, preimages that
+  map back to their (u, v, n), no stencil leaving its grid.
+"""
+import numpy as np
+import pytest
+
+from oracle import geometry as G
+from oracle import hhffbp as OH
+from oracle import plan as OP
+from workloads import voxel_centres
+
+
+def _plan(w, S, gamma=3.0, T=4, Q=4):
+    return OP.build_plan(w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims,
+                         S, Q, gamma, T)
+
+
+@pytest.fixture(scope="module")
+def direct_small(small):
+    vox = voxel_centres(small.grid_origin, small.grid_pitch, small.grid_dims)
+    return OH.direct_bp(small.positions, small.freqs_hz, small.echoes, vox).reshape(small.grid_dims)
+
+
+def test_lagrange_reproduces_polynomials():
+    x = np.linspace(0, 0.999, 37)
+    for T in (4, 6):
+        w = OH.lagrange_weights(x, T)
+        nodes = OP.lagrange_offsets(T)
+        for deg in range(T):
+            poly = w @ (nodes.astype(float) ** deg)
+            assert np.max(np.abs(poly - x ** deg)) < 1e-12
+        # exact at the node x = 0
+        w0 = OH.lagrange_weights(np.array([0.0]), T)[0]
+        assert abs(w0[T // 2 - 1] - 1) < 1e-15 and np.sum(np.abs(w0)) - 1 < 1e-15
+
+
+def test_stage_zero_is_eq4(small, direct_small):
+    img = OH.image(_plan(small, 0), small.echoes, small.positions)
+    assert np.max(np.abs(img - direct_small)) <= 1e-12 * np.max(np.abs(direct_small))
+
+
+@pytest.mark.parametrize("S", [1, 2])
+def test_error_bound_against_eq4(small, direct_small, S):
+    img = OH.image(_plan(small, S), small.echoes, small.positions)
+    e = OH.nrmse(img, direct_small)
+    assert 20 * np.log10(e) <= -30.0
+
+
+def test_binary_merges(small, direct_small):
+    """Q = 2: the paper's binary, alternating-axis merges (two stages = one Q=4 stage)."""
+    img = OH.image(_plan(small, 2, Q=2), small.echoes, small.positions)
+    assert 20 * np.log10(OH.nrmse(img, direct_small)) <= -30.0
+
+
+def test_convergence_with_oversampling_and_taps(small, direct_small):
+    errs = {}
+    for gamma, T in ((2.0, 4), (3.0, 4), (3.0, 6)):
+        img = OH.image(_plan(small, 1, gamma, T), small.echoes, small.positions)
+        errs[(gamma, T)] = OH.nrmse(img, direct_small)
+    assert errs[(3.0, 4)] < 0.5 * errs[(2.0, 4)]
+    assert errs[(3.0, 6)] < 0.5 * errs[(3.0, 4)]
+
+
+def test_linearity_and_global_phase(small):
+    pl = _plan(small, 1)
+    rng = np.random.default_rng(0)
+    s2 = rng.standard_normal(small.echoes.shape) + 1j * rng.standard_normal(small.echoes.shape)
+    a, b = 0.3 + 1j, -2.0
+    f1 = OH.image(pl, small.echoes, small.positions)
+    f2 = OH.image(pl, s2, small.positions)
+    f12 = OH.image(pl, a * small.echoes + b * s2, small.positions)
+    assert np.max(np.abs(f12 - a * f1 - b * f2)) <= 1e-11 * np.max(np.abs(f12))
+    fp = OH.image(pl, small.echoes * np.exp(0.7j), small.positions)
+    assert np.max(np.abs(fp - f1 * np.exp(0.7j))) <= 1e-11 * np.max(np.abs(f1))
+
+
+def test_partition_and_grids(small):
+    pl = _plan(small, 2)
+    S = len(pl.levels) - 1
+    members = np.concatenate([n.members for n in pl.levels[S]])
+    assert np.array_equal(np.sort(members), np.arange(small.n_pos))
+    for d in range(1, S + 1):
+        for node in pl.levels[d]:
+            x0, x1, y0, y1 = node.rect
+            xy = small.positions[node.members, :2]
+            assert np.all((xy[:, 0] >= x0) & (xy[:, 0] <= x1) & (xy[:, 1] >= y0) & (xy[:, 1] <= y1))
+            if node.empty:
+                assert node.lattice is None
+                continue
+            L = node.lattice
+            ok = L.valid
+            back = G.uvn(L.xyz[ok], node.rect, pl.kmin, pl.kmax) * pl.gamma
+            assert np.max(np.abs(back - L.ijl[ok])) < 1e-8
+    # config 0 has an empty leaf: it must be skipped, not fail
+    assert any(n.empty for n in pl.levels[S])
