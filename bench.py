@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Throughput of HHFFBPA against direct backprojection on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+
+Workload: 16384 handheld positions (64 serpentine strokes over 0.3 x 0.3 m,
+2 mm lateral and 1 mm depth jitter), 64 frequencies 24-40 GHz, a 128x128x64
+voxel grid at 1.5 mm centred 0.3 m in front of the aperture, 50 point targets
+and a 10x10x10 scatterer cube; HHFFBPA with 3 merge stages of factor 4.
+
+A step is one hhffbp_image call: range compression, level-1 backprojection,
+the two intermediate merges and the final merge, with the echoes already
+resident in device memory.  The metric counts voxel x position
+backprojections: N_vox * N_pos per step (the direct-BP work that HHFFBPA
+replaces).  Plan construction (host) is timed separately and reported as
+``plan_ms``.  One JSON line is printed.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel·position backprojections/s, HHFFBPA vs direct BP on 1 GPU at ≤−30 dB NRMSE"
+GAMMA = (3.0, 3.0, 3.5)
+TAPS = 4
+# VALU issue peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane-ops/s
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# Algorithmic VALU lane-ops of one (leaf grid point, position) backprojection
+# with the 7-tap ES range kernel: distance 7, distance difference 7, bin
+# coordinate 5, kernel weights 6 per tap, tap sums 2 per tap, carrier 5,
+# complex accumulate 4.
+LEAF_OPS_PER_PAIR = 7 + 7 + 5 + 6 * 7 + 2 * 7 + 5 + 4
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def oracle_cpu_baseline(w, target_s=15.0):
+    """The float64 oracle's eq. (4) on seeded voxels of the same workload."""
+    import numpy as np
+
+    from oracle import hhffbp as OH
+    from oracle import native
+    from workloads import voxel_centres
+
+    vox = voxel_centres(w.grid_origin, w.grid_pitch, w.grid_dims)
+    rng = np.random.default_rng(3)
+    n = 32
+    t = time.time()
+    OH.direct_bp(w.positions, w.freqs_hz, w.echoes, vox[rng.choice(vox.shape[0], n, replace=False)])
+    dt = time.time() - t
+    n2 = int(max(n, min(vox.shape[0], n * target_s / max(dt, 1e-3))))
+    sel = rng.choice(vox.shape[0], n2, replace=False)
+    t = time.time()
+    OH.direct_bp(w.positions, w.freqs_hz, w.echoes, vox[sel])
+    dt = time.time() - t
+    return {"value": n2 * w.n_pos / dt, "unit": "vp/s", "cores": native._nthreads(),
+            "kind": "oracle",
+            "sample": f"float64 eq. (4) on {n2} seeded voxels x {w.n_pos} positions x "
+                      f"{w.n_f} frequencies of the same workload ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md for how the work would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2506_23568_amd as H
+    from workloads import make_config
+
+    log("synthesising the workload")
+    w = make_config(1)
+    args3 = (w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims)
+    dev = torch.device("cuda:0")
+    ech = torch.from_numpy(w.echoes.astype(np.complex64)).to(dev)
+    t = time.time()
+    plan = H.Plan(*args3, stages=3, merge_factor=4, oversample=GAMMA, interp_taps=TAPS,
+                  range_kernel="es", range_oversample=2.0, range_taps=7)
+    plan_ms = (time.time() - t) * 1e3
+    info = plan.info()
+    ws = plan._workspace(torch)
+    img = torch.empty(w.grid_dims, dtype=torch.complex64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    log("warm-up")
+    for _ in range(args.warmup):
+        plan.image(ech, out=img, workspace=ws)
+    torch.cuda.synchronize()
+    plan.profile_begin(args.steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.image(ech, out=img, workspace=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    stages = plan.profile_end()
+    kernels_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items()}
+    value = w.n_vox * w.n_pos / (ms * 1e-3)
+
+    log("direct-BP references")
+    ref_plan = H.Plan(*args3, mode="direct_rc", range_kernel="es", range_oversample=2.0,
+                      range_taps=7)
+    ref = ref_plan.image(ech)
+    torch.cuda.synchronize()
+    nref = torch.linalg.norm(ref)
+    nrmse = (torch.linalg.norm(img - ref) / nref).item()
+    fast = H.Plan(*args3, mode="direct_rc", range_kernel="linear", range_oversample=8.0)
+    dimg = fast.image(ech)
+    torch.cuda.synchronize()
+    nd = 3
+    d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    d0.record(stream)
+    for _ in range(nd):
+        fast.image(ech, out=dimg)
+    d1.record(stream)
+    torch.cuda.synchronize()
+    dms = d0.elapsed_time(d1) / nd
+    d_nrmse = (torch.linalg.norm(dimg - ref) / nref).item()
+    direct_vp = w.n_vox * w.n_pos / (dms * 1e-3)
+
+    leaf_ms = kernels_ms.get("leaf_bp", float("nan"))
+    achieved = info["leaf_pairs"] * LEAF_OPS_PER_PAIR / (leaf_ms * 1e-3) / 1e12
+    peak = VALU_PEAK_OPS / 1e12
+    roofline = {"kernel": "leaf_bp", "bound": "alu", "achieved": achieved, "peak": peak,
+                "unit": "Tops/s", "frac": achieved / peak, "traffic": None,
+                "ops_per_pair": LEAF_OPS_PER_PAIR, "pairs_per_launch": info["leaf_pairs"],
+                "avg_launch_ms": leaf_ms}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline")
+        cpu = oracle_cpu_baseline(w)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "vp/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "HHFFBPA mid: 16384 handheld positions (64 serpentine strokes, "
+                               "0.3x0.3 m), 64 f 24-40 GHz, 128x128x64 voxels at 1.5 mm, "
+                               "50 points + 10x10x10 cube at 0.3 m",
+                   "n_pos": w.n_pos, "n_freq": w.n_f, "grid": list(w.grid_dims),
+                   "stages": 3, "merge_factor": 4, "oversample": list(GAMMA), "interp_taps": TAPS,
+                   "range_kernel": "es", "range_taps": 7, "range_oversample": 2.0,
+                   "parallelism": "single GPU"},
+        "nrmse_vs_direct_db": 20 * np.log10(nrmse),
+        "direct_bp": {"value": direct_vp, "unit": "vp/s", "ms": dms, "mode": "linear U=8",
+                      "nrmse_vs_es_direct_db": 20 * np.log10(d_nrmse)},
+        "speedup_vs_direct": value / direct_vp,
+        "plan_ms": plan_ms, "kernels_ms": kernels_ms,
+        "work": {"leaf_pairs": info["leaf_pairs"], "merge_pairs": info["merge_pairs"],
+                 "final_pairs": info["final_pairs"], "level_points": info["level_points"][1:]},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * hhffbp.h - C ABI of the MI355X (gfx950) HHFFBPA library.
+ *
+ * Near-range handheld-SAR imaging by fast factorised backprojection with
+ * analytic spectrum compression (Wang, Yao, Song, Sun, "A Fast and Accurate
+ * 3-D Reconstruction Algorithm for Near-Range Microwave Imaging with Handheld
+ * Synthetic Aperture Radar").
+ *
+ * Problem (Sec. II-A): antenna positions p'_i = (x', y', z') in metres, an
+ * arbitrary and non-uniform set; stepped frequencies f_j with k_j = 2 pi f_j / c;
+ * echoes s(p'_i, k_j); the output is the complex reflectivity f(p) on a regular
+ * voxel grid in front of the aperture.  Direct BPA is eq. (4):
+ *     f(p) = sum_i sum_j s(p'_i, k_j) exp(+j 2 k_j |p - p'_i|)
+ * (unit weights for the integral measures).  HHFFBPA (Sec. III, IV-A)
+ * approximates it: range compression (eq. 2), backprojection of each level-1
+ * subarray onto a coarse grid that is uniform in the LLT coordinates (u, v, n)
+ * of eq. uvw_xyz, spatial downconversion by exp(-j Phi) (eq. sdc_mul,
+ * eq. sdc_phi), and recursive merges that interpolate the compressed children
+ * onto the parent's grid, undo the downconversion and sum them.
+ *
+ * Conventions
+ *  - Every function returns an hhffbp_status; out-parameters are untouched on
+ *    error and no exception crosses the ABI.  hhffbp_last_error() gives a
+ *    human-readable detail for the calling thread's last failure.
+ *  - Complex values are interleaved (re, im) pairs: float32 pairs
+ *    (HHFFBP_C64), IEEE half pairs (HHFFBP_F16) or bfloat16 pairs (HHFFBP_BF16).
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory on the plan's device.  The caller owns every device buffer,
+ *    including the workspace; the library owns only the plan (its host tables
+ *    and a plan-time device upload of the geometry).
+ *  - Compute calls enqueue work on `stream` (a hipStream_t, passed as void*),
+ *    do not allocate and do not synchronise.
+ */
+#ifndef HHFFBP_H
+#define HHFFBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hhffbp_plan_s *hhffbp_plan_t; /* opaque, owned by the library */
+
+typedef enum {
+    HHFFBP_OK = 0,
+    HHFFBP_E_INVALID = -1,     /* bad argument or configuration            */
+    HHFFBP_E_UNSUPPORTED = -2, /* valid but not implemented                */
+    HHFFBP_E_NOMEM = -3,       /* host or plan-time device allocation      */
+    HHFFBP_E_DEVICE = -4,      /* HIP runtime or launch failure            */
+    HHFFBP_E_WORKSPACE = -5,   /* workspace missing or too small           */
+    HHFFBP_E_NUMERIC = -6      /* plan geometry failed (e.g. no inverse)   */
+} hhffbp_status;
+
+/* Imaging mode. */
+enum {
+    HHFFBP_FACTORIZED = 0,   /* HHFFBPA (Sec. IV-A); stages = 0 is one subarray */
+    HHFFBP_DIRECT_RC = 1     /* direct BPA of eq. (3) on range-compressed data   */
+};
+
+/* Storage type of echoes (and, later, of profiles and subimages). */
+enum { HHFFBP_C64 = 0, HHFFBP_F16 = 1, HHFFBP_BF16 = 2 };
+
+/* Kernel used to evaluate a range profile between its samples. */
+enum {
+    HHFFBP_RANGE_ES = 0,     /* exponential-of-semicircle, pre-corrected DFT    */
+    HHFFBP_RANGE_LINEAR = 1  /* two-tap linear, uncorrected (fast, ~-40 dB)      */
+};
+
+typedef struct {
+    int64_t n_pos;              /* number of antenna positions, >= 1              */
+    int64_t n_freq;             /* number of frequency samples, >= 2              */
+    const double *positions;    /* host, [n_pos][3] metres; scene at z > max z'  */
+    const double *freqs_hz;     /* host, [n_freq], any order and spacing, > 0     */
+    double grid_origin[3];      /* centre of voxel (0,0,0), metres                */
+    double grid_pitch[3];       /* voxel pitch per axis, > 0                      */
+    int64_t grid_dims[3];       /* (nx, ny, nz); image index (ix*ny + iy)*nz + iz */
+    int32_t mode;               /* HHFFBP_FACTORIZED or HHFFBP_DIRECT_RC          */
+    int32_t stages;             /* S >= 0: number of merge stages                 */
+    int32_t merge_factor;       /* Q = 2 (binary, alternating axes) or 4          */
+    double oversample[3];       /* gamma per LLT axis (u, v, n), each in [1, 8]   */
+    int32_t interp_taps;        /* T, Lagrange taps per axis: 4 or 6              */
+    int32_t range_kernel;       /* HHFFBP_RANGE_ES or HHFFBP_RANGE_LINEAR         */
+    double range_oversample;    /* U: range-bin spacing pi / (U (kmax - kmin))    */
+    int32_t range_taps;         /* W: ES taps (4..8); ignored for linear          */
+    int32_t storage;            /* HHFFBP_C64 (F16/BF16: HHFFBP_E_UNSUPPORTED)    */
+    double position_slack;      /* metres the positions may move after planning  */
+    int32_t device;             /* HIP device ordinal; -1 plans on the host only  */
+} hhffbp_config;
+
+/* Fill `cfg` with defaults: FACTORIZED, S = 3, Q = 4, gamma = (3, 3, 3.5), T = 4, ES with
+ * U = 2 and W = 7, C64 storage, 5 mm slack, device 0.  Pointers and sizes are
+ * zeroed and must be set by the caller. */
+void hhffbp_config_default(hhffbp_config *cfg);
+
+/*
+ * Build a plan (Sec. IV-A): the subarray tree, the sampling grid G of every
+ * subarray below the root, the (x, y, z) preimage of every grid point, the
+ * range window and the range-compression matrix, uploaded to `cfg->device`.
+ * Runs on the host in float64.  Reads `cfg` and the host arrays it points to
+ * only during the call.  On success *out receives a plan that must be released
+ * with hhffbp_plan_destroy.  With cfg->device = -1 nothing touches a GPU: the
+ * plan holds its host tables only (for inspection) and hhffbp_image refuses it.  Errors: HHFFBP_E_INVALID (non-finite input, empty
+ * grid, grid not in front of the aperture, unsupported Q/T/W/U/gamma),
+ * HHFFBP_E_NUMERIC (a grid point without a preimage), HHFFBP_E_NOMEM,
+ * HHFFBP_E_DEVICE.
+ */
+hhffbp_status hhffbp_plan(const hhffbp_config *cfg, hhffbp_plan_t *out);
+
+/* Release a plan and its device tables.  NULL is ignored.  No call that uses
+ * the plan may still be running on any stream. */
+void hhffbp_plan_destroy(hhffbp_plan_t plan);
+
+/* Bytes of device workspace that hhffbp_image (with_backward = 0) needs. */
+hhffbp_status hhffbp_workspace_bytes(hhffbp_plan_t plan, int32_t with_backward,
+                                     size_t *bytes);
+
+/*
+ * Form the image.
+ *   echoes      device, [n_pos][n_freq] complex in the plan's storage type,
+ *               rows in the order of cfg->positions.
+ *   positions   device float64 [n_pos][3] to backproject with, or NULL for
+ *               the plan's own positions.  The tree and grids stay as planned;
+ *               positions must stay within cfg->position_slack of the planned
+ *               ones for the range window to hold them.
+ *   image       device complex64 [nx][ny][nz] (z fastest), overwritten.
+ *   workspace   device, at least hhffbp_workspace_bytes(plan, 0) bytes,
+ *               256-byte aligned; its contents on entry do not matter.
+ * Enqueued on `stream`; returns after the launches.  Errors: HHFFBP_E_INVALID
+ * (NULL echoes or image), HHFFBP_E_WORKSPACE, HHFFBP_E_DEVICE.
+ */
+hhffbp_status hhffbp_image(hhffbp_plan_t plan, const void *echoes, const double *positions,
+                           void *image, void *workspace, size_t ws_bytes, void *stream);
+
+/* Read-only description of a plan, for sizing and work accounting. */
+typedef struct {
+    int32_t stages, merge_factor, n_leaves, n_nodes;
+    int64_t n_pos, n_freq, n_vox;
+    int64_t n_range_bins;           /* N_r                                      */
+    double range_lo, range_step;    /* R_0 and delta R of the profile grid (m)  */
+    int64_t level_points[16];       /* grid points summed over depth d = 1..S   */
+    int64_t leaf_pairs;             /* sum over leaves of points x positions    */
+    int64_t merge_pairs;            /* (parent point, child) pairs, depths 1..S-1 */
+    int64_t final_pairs;            /* (voxel, child) pairs at the root         */
+    double plan_seconds;            /* host time spent in hhffbp_plan           */
+} hhffbp_plan_info;
+
+hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info);
+
+/*
+ * Where the compressed subimage f' of node (depth, index) lives in the
+ * workspace after hhffbp_image, and its grid: lattice column (i, j) covers
+ * i in [i0, i0 + ni), j in [j0, j0 + nj); column c = (i - i0) * nj + (j - j0)
+ * holds l in [l_lo[c], l_hi[c]] contiguously from point offset col_off[c].
+ * Values are complex64 at byte offset *ws_offset + 8 * point.  Arrays may be
+ * NULL to query sizes only; otherwise they must hold ni * nj entries.
+ * Depth 0 is the user grid and has no lattice (HHFFBP_E_INVALID); an empty
+ * node reports npoints = 0.
+ */
+hhffbp_status hhffbp_node_layout(hhffbp_plan_t plan, int32_t depth, int32_t index,
+                                 int32_t dims[4] /* i0, j0, ni, nj */, int64_t *npoints,
+                                 int64_t *ws_offset, int32_t *l_lo, int32_t *l_hi,
+                                 int64_t *col_off);
+
+/* Float64 (x, y, z) preimages of a node's grid points, [npoints][3], host. */
+hhffbp_status hhffbp_node_points(hhffbp_plan_t plan, int32_t depth, int32_t index,
+                                 double *xyz);
+
+/*
+ * Optional per-stage timing with HIP events on the caller's stream.  After
+ * hhffbp_profile_begin(plan, max_calls) the next max_calls hhffbp_image calls
+ * record an event before their first kernel and after each stage.
+ * hhffbp_profile_end waits for the last recorded event, writes into
+ * stage_ms[k] (k < min(max_stages, *n_stages)) the milliseconds stage k took
+ * summed over the recorded calls, reports the stage count and the number of
+ * recorded calls, and releases the events.  hhffbp_stage_name(plan, k) names
+ * stage k ("rc_gemm", "leaf_bp", "merge_d<d>", "final", "direct_bp", ...).
+ * Creating the events allocates (host side); use it outside capture regions.
+ */
+hhffbp_status hhffbp_profile_begin(hhffbp_plan_t plan, int32_t max_calls);
+hhffbp_status hhffbp_profile_end(hhffbp_plan_t plan, double *stage_ms, int32_t max_stages,
+                                 int32_t *n_stages, int32_t *n_calls);
+const char *hhffbp_stage_name(hhffbp_plan_t plan, int32_t index);
+
+/* Static strings; never NULL. */
+const char *hhffbp_status_string(hhffbp_status status);
+const char *hhffbp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HHFFBP_H */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) HHFFBPA: handheld fast factorised backprojection.
+
+Thin Python binding of ``libhhffbp.so`` (C ABI in ``include/hhffbp.h``).  This
+module only marshals arguments: every step of the imaging path runs in the HIP
+kernels of the library.  PyTorch supplies device memory and streams.  If the
+library has not been built the import still succeeds, but every call raises.
+"""
+from .binding import (  # noqa: F401
+    Plan, HHFFBPError, lib, library_path, STATUS, MODES, RANGE_KERNELS, STORAGE,
+)
+
+__all__ = ["Plan", "HHFFBPError", "lib", "library_path"]

@@ -1,0 +1,277 @@
+// extern "C" entry points of libhhffbp (declared in include/hhffbp.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "hhffbp_internal.hpp"
+
+struct hhffbp_plan_s {
+    hh::Plan plan;
+};
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+hhffbp_status fail(hhffbp_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+}  // namespace
+
+static void destroy_events(hh::Plan &P);
+
+extern "C" {
+
+void hhffbp_config_default(hhffbp_config *cfg)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->mode = HHFFBP_FACTORIZED;
+    cfg->stages = 3;
+    cfg->merge_factor = 4;
+    cfg->oversample[0] = cfg->oversample[1] = 3.0;
+    cfg->oversample[2] = 3.5;  // the n axis carries the widest compressed spectrum
+    cfg->interp_taps = 4;
+    cfg->range_kernel = HHFFBP_RANGE_ES;
+    cfg->range_oversample = 2.0;
+    cfg->range_taps = 7;
+    cfg->storage = HHFFBP_C64;
+    cfg->position_slack = 5e-3;
+    cfg->device = 0;
+}
+
+hhffbp_status hhffbp_plan(const hhffbp_config *cfg, hhffbp_plan_t *out)
+{
+    if (!cfg || !out) return fail(HHFFBP_E_INVALID, "hhffbp_plan: NULL argument");
+    hhffbp_plan_s *h = nullptr;
+    try {
+        h = new hhffbp_plan_s();
+        h->plan.cfg = *cfg;
+        hh::build_plan_host(h->plan);
+        h->plan.cfg.positions = nullptr;
+        h->plan.cfg.freqs_hz = nullptr;
+        hh::upload_plan(h->plan);
+    } catch (const hh::Error &e) {
+        if (h) {
+            hh::release_plan(h->plan);
+            delete h;
+        }
+        return fail(e.status, e.msg);
+    } catch (const std::bad_alloc &) {
+        if (h) {
+            hh::release_plan(h->plan);
+            delete h;
+        }
+        return fail(HHFFBP_E_NOMEM, "host allocation failed while planning");
+    } catch (...) {
+        if (h) {
+            hh::release_plan(h->plan);
+            delete h;
+        }
+        return fail(HHFFBP_E_INVALID, "unexpected error while planning");
+    }
+    *out = h;
+    return HHFFBP_OK;
+}
+
+void hhffbp_plan_destroy(hhffbp_plan_t plan)
+{
+    if (!plan) return;
+    destroy_events(plan->plan);
+    hh::release_plan(plan->plan);
+    delete plan;
+}
+
+hhffbp_status hhffbp_workspace_bytes(hhffbp_plan_t plan, int32_t with_backward, size_t *bytes)
+{
+    if (!plan || !bytes) return fail(HHFFBP_E_INVALID, "hhffbp_workspace_bytes: NULL argument");
+    if (with_backward) return fail(HHFFBP_E_UNSUPPORTED, "backward workspace not built");
+    *bytes = plan->plan.ws_total;
+    return HHFFBP_OK;
+}
+
+hhffbp_status hhffbp_image(hhffbp_plan_t plan, const void *echoes, const double *positions,
+                           void *image, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (!plan || !echoes || !image) return fail(HHFFBP_E_INVALID, "hhffbp_image: NULL argument");
+    const hh::Plan &P = plan->plan;
+    if (P.cfg.device < 0) return fail(HHFFBP_E_DEVICE, "hhffbp_image: host-only plan (device < 0)");
+    if (!workspace || ws_bytes < P.ws_total)
+        return fail(HHFFBP_E_WORKSPACE, "hhffbp_image: workspace missing or smaller than " +
+                                            std::to_string(P.ws_total) + " bytes");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(HHFFBP_E_WORKSPACE, "hhffbp_image: workspace must be 256-byte aligned");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(HHFFBP_E_DEVICE, "hipGetDevice failed");
+    if (cur != P.cfg.device && hipSetDevice(P.cfg.device) != hipSuccess)
+        return fail(HHFFBP_E_DEVICE, "hipSetDevice failed");
+    hipEvent_t *ev = nullptr;
+    hh::Plan &Pm = plan->plan;
+    if (Pm.prof_calls < Pm.prof_max_calls) {
+        ev = &Pm.prof_events[(size_t)Pm.prof_calls * (Pm.stage_names().size() + 1)];
+        ++Pm.prof_calls;
+    }
+    hhffbp_status st = hh::launch_image(P, echoes, positions, image, (char *)workspace,
+                                        (hipStream_t)stream, ev);
+    if (cur != P.cfg.device) (void)hipSetDevice(cur);
+    if (st != HHFFBP_OK) return fail(st, std::string("hhffbp_image: launch failed: ") +
+                                             hipGetErrorString(hipGetLastError()));
+    return HHFFBP_OK;
+}
+
+hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info)
+{
+    if (!plan || !info) return fail(HHFFBP_E_INVALID, "hhffbp_get_plan_info: NULL argument");
+    const hh::Plan &P = plan->plan;
+    std::memset(info, 0, sizeof(*info));
+    info->stages = P.S;
+    info->merge_factor = P.Q;
+    info->n_leaves = (int32_t)P.compact_to_tree[P.S].size();
+    int32_t nn = 0;
+    for (auto &v : P.compact_to_tree) nn += (int32_t)v.size();
+    info->n_nodes = nn;
+    info->n_pos = P.cfg.n_pos;
+    info->n_freq = P.cfg.n_freq;
+    info->n_vox = P.n_vox();
+    info->n_range_bins = P.Nr;
+    info->range_lo = P.R0;
+    info->range_step = P.dR;
+    for (int d = 1; d <= P.S && d < 16; ++d) info->level_points[d] = P.depth_points[d];
+    info->leaf_pairs = P.leaf_pairs;
+    info->merge_pairs = P.merge_pairs;
+    info->final_pairs = P.final_pairs;
+    info->plan_seconds = P.plan_seconds;
+    return HHFFBP_OK;
+}
+
+static const hh::HostNode *find_node(const hh::Plan &P, int32_t depth, int32_t index)
+{
+    if (depth < 1 || depth > P.S) return nullptr;
+    if (index < 0 || index >= (int32_t)P.levels[depth].size()) return nullptr;
+    return &P.levels[depth][index];
+}
+
+hhffbp_status hhffbp_node_layout(hhffbp_plan_t plan, int32_t depth, int32_t index,
+                                 int32_t dims[4], int64_t *npoints, int64_t *ws_offset,
+                                 int32_t *l_lo, int32_t *l_hi, int64_t *col_off)
+{
+    if (!plan || !dims || !npoints || !ws_offset)
+        return fail(HHFFBP_E_INVALID, "hhffbp_node_layout: NULL argument");
+    const hh::Plan &P = plan->plan;
+    const hh::HostNode *n = find_node(P, depth, index);
+    if (!n) return fail(HHFFBP_E_INVALID, "hhffbp_node_layout: no such node");
+    const hh::HostLattice &L = n->lat;
+    dims[0] = L.i0;
+    dims[1] = L.j0;
+    dims[2] = L.ni;
+    dims[3] = L.nj;
+    *npoints = n->empty() ? 0 : L.npts;
+    int64_t base = 0;
+    for (int32_t ti : P.compact_to_tree[depth]) {
+        if (ti == index) break;
+        base += P.levels[depth][ti].lat.npts;
+    }
+    *ws_offset = (int64_t)P.ws_vals[depth] + 8 * base;
+    const int64_t nc = (int64_t)L.ni * L.nj;
+    for (int64_t c = 0; c < nc; ++c) {
+        if (l_lo) l_lo[c] = L.lo[c];
+        if (l_hi) l_hi[c] = L.hi[c];
+        if (col_off) col_off[c] = L.off[c];
+    }
+    return HHFFBP_OK;
+}
+
+hhffbp_status hhffbp_node_points(hhffbp_plan_t plan, int32_t depth, int32_t index, double *xyz)
+{
+    if (!plan || !xyz) return fail(HHFFBP_E_INVALID, "hhffbp_node_points: NULL argument");
+    const hh::HostNode *n = find_node(plan->plan, depth, index);
+    if (!n) return fail(HHFFBP_E_INVALID, "hhffbp_node_points: no such node");
+    if (!n->lat.xyz.empty()) std::memcpy(xyz, n->lat.xyz.data(), n->lat.xyz.size() * sizeof(double));
+    return HHFFBP_OK;
+}
+
+static void destroy_events(hh::Plan &P)
+{
+    for (hipEvent_t e : P.prof_events) (void)hipEventDestroy(e);
+    P.prof_events.clear();
+    P.prof_max_calls = P.prof_calls = 0;
+}
+
+hhffbp_status hhffbp_profile_begin(hhffbp_plan_t plan, int32_t max_calls)
+{
+    if (!plan || max_calls < 1) return fail(HHFFBP_E_INVALID, "hhffbp_profile_begin: bad argument");
+    hh::Plan &P = plan->plan;
+    if (P.cfg.device < 0) return fail(HHFFBP_E_DEVICE, "hhffbp_profile_begin: host-only plan");
+    destroy_events(P);
+    const size_t per = P.stage_names().size() + 1;
+    P.prof_events.assign((size_t)max_calls * per, nullptr);
+    for (auto &e : P.prof_events) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            destroy_events(P);
+            return fail(HHFFBP_E_DEVICE, "hipEventCreate failed");
+        }
+    }
+    P.prof_max_calls = max_calls;
+    P.prof_calls = 0;
+    return HHFFBP_OK;
+}
+
+hhffbp_status hhffbp_profile_end(hhffbp_plan_t plan, double *stage_ms, int32_t max_stages,
+                                 int32_t *n_stages, int32_t *n_calls)
+{
+    if (!plan || !n_stages || !n_calls) return fail(HHFFBP_E_INVALID, "hhffbp_profile_end: NULL");
+    hh::Plan &P = plan->plan;
+    const int ns = (int)P.stage_names().size();
+    *n_stages = ns;
+    *n_calls = P.prof_calls;
+    if (stage_ms) {
+        for (int k = 0; k < std::min(ns, (int)max_stages); ++k) stage_ms[k] = 0.0;
+        for (int c = 0; c < P.prof_calls; ++c) {
+            hipEvent_t *ev = &P.prof_events[(size_t)c * (ns + 1)];
+            if (hipEventSynchronize(ev[ns]) != hipSuccess) {
+                destroy_events(P);
+                return fail(HHFFBP_E_DEVICE, "hipEventSynchronize failed");
+            }
+            for (int k = 0; k < std::min(ns, (int)max_stages); ++k) {
+                float ms = 0.0f;
+                if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) stage_ms[k] += ms;
+            }
+        }
+    }
+    destroy_events(P);
+    return HHFFBP_OK;
+}
+
+const char *hhffbp_stage_name(hhffbp_plan_t plan, int32_t i)
+{
+    static thread_local std::string name;
+    if (!plan) return "";
+    auto n = plan->plan.stage_names();
+    name = (i >= 0 && i < (int32_t)n.size()) ? n[i] : std::string();
+    return name.c_str();
+}
+
+const char *hhffbp_status_string(hhffbp_status s)
+{
+    switch (s) {
+    case HHFFBP_OK: return "ok";
+    case HHFFBP_E_INVALID: return "invalid argument";
+    case HHFFBP_E_UNSUPPORTED: return "unsupported";
+    case HHFFBP_E_NOMEM: return "out of memory";
+    case HHFFBP_E_DEVICE: return "device error";
+    case HHFFBP_E_WORKSPACE: return "workspace too small";
+    case HHFFBP_E_NUMERIC: return "numerical failure";
+    }
+    return "unknown status";
+}
+
+const char *hhffbp_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

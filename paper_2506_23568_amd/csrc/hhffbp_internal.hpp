@@ -1,0 +1,149 @@
+// Internal structures shared by the host plan and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hhffbp.h"
+
+namespace hh {
+
+constexpr double kLight = 299792458.0;  // m/s
+constexpr double kPi = 3.14159265358979323846;
+// Base index of an interpolation stencil: floor(t + kStencilEps).  A parent grid
+// point seen by a child that shares an edge with it (Q = 2) sits on a child node
+// up to rounding; the offset makes every code path choose the same stencil.
+constexpr double kStencilEps = 1e-9;
+
+// One non-empty subarray as the kernels see it.  Rectangles are the cell
+// rectangles of the bisection (aperture plane z' = 0).
+struct NodeDev {
+    double x0, x1, y0, y1, d2;  // rectangle and D^2 = 4 Lx^2 + 4 Ly^2
+    int32_t i0, j0, ni, nj;     // lattice columns (i, j) in [i0, i0+ni) x [j0, j0+nj)
+    int32_t col_base;           // first entry in this depth's column table
+    int32_t val_base;           // first value in this depth's value array
+    int32_t npts;               // grid points
+    int32_t nchild;             // non-empty children (compact indices at depth + 1)
+    int32_t child[4];
+    int32_t pos_begin, pos_end; // leaves: range in leaf-sorted position order
+    int32_t pad0, pad1;
+};
+
+// One pencil (column) of a lattice: l in [lo, hi] stored from value offset `off`
+// (relative to the node's val_base).  An empty column has hi < lo.
+struct ColEntry {
+    int32_t off, lo, hi, pad;
+};
+
+// Per leaf grid point, precomputed in float64 on the host:
+//   d      = q - c (float32), c = leaf centre on the aperture plane
+//   bin    = floor((|q - c| - R0) / dR), frac the remainder in [0, 1)
+//   pre    = exp(j (2 kc |q - c| - Phi(q)))
+struct LeafPoint {
+    float dx, dy, dz;
+    int32_t bin;
+    float frac;
+    float pre_re, pre_im;
+    int32_t pad;
+};
+
+// Work item of a per-node point loop: node (compact index) and first point.
+struct BlockItem {
+    int32_t node, start;
+};
+
+struct Rect {
+    double x0, x1, y0, y1;
+};
+
+// Host view of one grid G of a subarray.
+struct HostLattice {
+    int32_t i0 = 0, j0 = 0, ni = 0, nj = 0;
+    std::vector<int32_t> lo, hi;  // per column
+    std::vector<int64_t> off;     // per column, first point
+    int64_t npts = 0;
+    int64_t n_absent = 0;         // points without a preimage (xyz = NaN, value 0)
+    std::vector<double> xyz;      // [npts][3]
+};
+
+struct HostNode {
+    int depth = 0;
+    Rect rect{};
+    std::vector<int32_t> members;  // position indices (caller order)
+    std::vector<int32_t> children; // tree indices at depth + 1
+    int32_t parent = -1;
+    int32_t compact = -1;          // index among the non-empty nodes of its depth
+    HostLattice lat;
+    bool empty() const { return members.empty(); }
+};
+
+struct DeviceBuffers {
+    void *B = nullptr;              // range-compression matrix, float [2 Nf][2 Nr]
+    void *perm = nullptr;           // int32 [n_pos], sorted -> caller index
+    void *leaf_of_sorted = nullptr; // int32 [n_pos]
+    void *leaf_centre = nullptr;    // double2 [n_leaves]
+    void *pos64 = nullptr;          // double [n_pos][3], caller order
+    std::vector<void *> nodes;      // per depth: NodeDev[]
+    std::vector<void *> cols;       // per depth: ColEntry[]
+    std::vector<void *> px, py, pz; // per depth < S: float64 SoA grid points
+    void *leafpts = nullptr;        // LeafPoint[] of depth S
+    void *leaf_blocks = nullptr;    // BlockItem[]
+    std::vector<void *> merge_blocks;  // per depth 1..S-1: BlockItem[]
+};
+
+struct Plan {
+    hhffbp_config cfg{};
+    int S = 0, Q = 4, T = 4;
+    double gamma[3] = {3, 3, 3};
+    // band
+    std::vector<double> k;
+    double kmin = 0, kmax = 0, kc = 0;
+    // range profiles
+    int W = 7, kernel = HHFFBP_RANGE_ES;
+    double U = 2, dR = 0, R0 = 0, beta = 0;
+    int64_t Nr = 0;
+    std::vector<float> Bmat;  // [2 Nf][2 Nr]
+    // tree
+    std::vector<std::vector<HostNode>> levels;
+    std::vector<int32_t> perm;           // sorted -> caller index
+    std::vector<int32_t> leaf_of_sorted; // compact leaf index per sorted position
+    std::vector<double> leaf_centre;     // [n_leaves][2]
+    std::vector<double> positions;       // caller order, [n_pos][3]
+    std::vector<std::vector<int32_t>> compact_to_tree;  // per depth
+    std::vector<int64_t> depth_points;   // per depth
+    std::vector<int64_t> n_blocks_merge; // per depth
+    int64_t n_blocks_leaf = 0;
+    int64_t leaf_pairs = 0, merge_pairs = 0, final_pairs = 0;
+    // workspace layout (bytes)
+    size_t ws_prof = 0, ws_posoff = 0, ws_total = 0;
+    std::vector<size_t> ws_vals;         // per depth
+    DeviceBuffers dev;
+    double plan_seconds = 0;
+    double z_valid = 0;
+    // optional per-stage HIP events (hhffbp_profile_begin/_end)
+    std::vector<hipEvent_t> prof_events;  // [max_calls][n_stages + 1]
+    int prof_max_calls = 0, prof_calls = 0;
+    std::vector<std::string> stage_names() const;
+    int64_t n_vox() const { return cfg.grid_dims[0] * cfg.grid_dims[1] * cfg.grid_dims[2]; }
+};
+
+// Plan construction (host, float64).  Throws hh::Error on failure.
+struct Error {
+    hhffbp_status status;
+    std::string msg;
+};
+
+void build_plan_host(Plan &plan);
+void upload_plan(Plan &plan);
+void release_plan(Plan &plan);
+
+// Launchers (kernels.hip).
+// `events`, when non-null, holds stage_names().size() + 1 events recorded on
+// `stream` before the first stage and after each stage.
+hhffbp_status launch_image(const Plan &plan, const void *echoes, const double *positions,
+                           void *image, char *ws, hipStream_t stream, hipEvent_t *events);
+
+}  // namespace hh

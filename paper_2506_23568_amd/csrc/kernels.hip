@@ -1,0 +1,630 @@
+// gfx950 kernels of the HHFFBPA hot path and their launcher.
+//
+//   k_prep_positions  antenna offsets from their leaf centre (float64 -> float32)
+//   k_rc_gemm         range compression, eq. (2): profiles = echoes x W on MFMA
+//   k_leaf_bp         level-1 BP onto each leaf grid + SDC (Sec. IV-A, eq. sdc_mul)
+//   k_merge           interpolate compressed children onto a parent grid, undo
+//                     their SDC, sum, compress with the parent's Phi (Sec. IV-A)
+//   k_final           the same onto the user voxels, without a parent SDC
+//   k_direct_bp       direct BP of eq. (3) on range profiles (mode DIRECT_RC / S = 0)
+//
+// Precision plan.  Large distances (~0.3 m) never enter float32 phases directly:
+// leaf BP works with distance differences to the leaf centre, direct BP with
+// differences to a per-tile reference point whose own distance is float64, and
+// the merge geometry ((u, v, n) and Phi of each child) is evaluated in float64.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hhffbp_internal.hpp"
+
+namespace hh {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kPosChunkMax = 16;
+constexpr size_t kLdsBudget = 20 * 1024;  // dynamic LDS per block
+
+// Positions staged per LDS chunk with their profiles.  Small chunks keep the
+// LDS per block near 12 KB so that eight 256-lane blocks fit on a CU; the
+// inner loop's dependency chain (sqrt, rcp, gather, sincos) needs that many
+// waves to hide its latency.
+inline int pos_chunk(int64_t Nr, size_t per_pos_header)
+{
+    const size_t per = per_pos_header + (size_t)Nr * sizeof(float2);
+    int c = (int)(kLdsBudget / per);
+    return c > kPosChunkMax ? kPosChunkMax : (c < 1 ? 1 : c);
+}
+
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float exp2_f(float x) { return __builtin_amdgcn_exp2f(x); }
+// v_sin_f32 / v_cos_f32 take their argument in turns; callers reduce it to [-0.5, 0.5].
+__device__ __forceinline__ float sin_turns(float t) { return __builtin_amdgcn_sinf(t); }
+__device__ __forceinline__ float cos_turns(float t) { return __builtin_amdgcn_cosf(t); }
+
+// Weights of the W range taps r_first .. r_first+W-1 for fractional offset x in [0, 1)
+// of tau = t - W/2 (t the continuous bin coordinate, r_first = floor(tau) + 1).
+template <int KERNEL, int W>
+__device__ __forceinline__ void range_weights(float x, float beta_log2e, float *w)
+{
+    if constexpr (KERNEL == HHFFBP_RANGE_LINEAR) {
+        w[0] = 1.0f - x;
+        w[1] = x;
+    } else {
+        constexpr float s = 2.0f / W;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const float z = ((float)k + 1.0f - 0.5f * W - x) * s;
+            const float a = fmaxf(1.0f - z * z, 0.0f);
+            w[k] = exp2_f(beta_log2e * (fast_sqrt(a) - 1.0f));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_prep_positions(const double *__restrict__ pos64,
+                                                           const int32_t *__restrict__ perm,
+                                                           const int32_t *__restrict__ leaf_of,
+                                                           const double *__restrict__ centre,
+                                                           int n, float4 *__restrict__ out)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int m = perm[i], lf = leaf_of[i];
+    const double dx = pos64[3 * m] - centre[2 * lf];
+    const double dy = pos64[3 * m + 1] - centre[2 * lf + 1];
+    const double dz = pos64[3 * m + 2];
+    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+    out[i] = make_float4(fx, fy, fz, fx * fx + fy * fy + fz * fz);
+}
+
+// ---------------------------------------------------------------------------
+// Range compression as a real GEMM, C[M x N] = A[perm(M) x K] * B[K x N], with
+// A the echoes as interleaved floats (K = 2 Nf), B the block form of the
+// pre-corrected DFT matrix (N = 2 Nr) and C the profiles (interleaved).
+// Block tile 64 x 64, four waves of 32 x 32, each 2 x 2 v_mfma_f32_16x16x4f32.
+constexpr int kGemmKC = 32;
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kBlock) void k_rc_gemm(const float *__restrict__ A,
+                                                    const int32_t *__restrict__ perm, int M,
+                                                    int K, const float *__restrict__ B, int N,
+                                                    float *__restrict__ C)
+{
+    __shared__ float As[64][kGemmKC + 1];
+    __shared__ float Bs[kGemmKC][64 + 4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    v4f acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < K; k0 += kGemmKC) {
+        // A tile: 64 rows x 32 k; thread t loads 8 consecutive floats of one row
+        {
+            const int r = tid >> 2, kk = (tid & 3) * 8;
+            const int grow = row0 + r;
+            const bool ok = grow < M;
+            const float *src = ok ? A + (size_t)perm[grow] * K + k0 + kk : nullptr;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int kg = k0 + kk + e;
+                As[r][kk + e] = (ok && kg < K) ? src[e] : 0.0f;
+            }
+        }
+        // B tile: 32 k x 64 cols; thread t loads 8 consecutive floats of one k row
+        {
+            const int kr = tid >> 3, cc = (tid & 7) * 8;
+            const int kg = k0 + kr;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int cg = col0 + cc + e;
+                Bs[kr][cc + e] = (kg < K && cg < N) ? B[(size_t)kg * N + cg] : 0.0f;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kGemmKC; kk += 4) {
+            float av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = As[wr + a * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + (lane >> 4)][wc + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + wr + a * 16 + 4 * (lane >> 4) + r;
+                const int col = col0 + wc + b * 16 + (lane & 15);
+                if (row < M && col < N) C[(size_t)row * N + col] = acc[a][b][r];
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Level-1 BP.  One lane per leaf grid point q; the leaf's positions are staged
+// through LDS in chunks together with their range profiles (leaf-sorted, so a
+// chunk's profiles are one contiguous block).  Per (q, i):
+//   Delta R = |q - p'_i| - |q - c| = (|delta|^2 - 2 d.delta) / (|q - p'_i| + |q - c|)
+//   g = sum_w phi_w(t) prof_i[r_first + w],   t = (|q - c| - R0)/dR + Delta R / dR
+//   acc += g exp(j 2 kc Delta R)
+// and f'(q) = acc exp(j (2 kc |q - c| - Phi(q))), the last factor precomputed.
+template <int KERNEL, int W>
+__global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ leaves,
+                                                    const BlockItem *__restrict__ blocks,
+                                                    const LeafPoint *__restrict__ pts,
+                                                    const float4 *__restrict__ posoff,
+                                                    const float2 *__restrict__ prof, int Nr,
+                                                    int chunk, float inv_dR, float beta_log2e,
+                                                    float kc_turns, float2 *__restrict__ out)
+{
+    extern __shared__ unsigned char smem[];
+    float4 *s_pos = reinterpret_cast<float4 *>(smem);
+    float2 *s_prof = reinterpret_cast<float2 *>(smem + chunk * sizeof(float4));
+    const BlockItem blk = blocks[blockIdx.x];
+    const NodeDev nd = leaves[blk.node];
+    const int p = blk.start + threadIdx.x;
+    const bool active = p < nd.npts;
+    LeafPoint q = active ? pts[nd.val_base + p] : LeafPoint{0, 0, 1, 0, 0, 0, 0, 0};
+    const float Rc = fast_sqrt(q.dx * q.dx + q.dy * q.dy + q.dz * q.dz);
+    float acc_re = 0.0f, acc_im = 0.0f;
+    for (int c0 = nd.pos_begin; c0 < nd.pos_end; c0 += chunk) {
+        const int n = min(chunk, nd.pos_end - c0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < n; t += kBlock) s_pos[t] = posoff[c0 + t];
+        const float2 *src = prof + (size_t)c0 * Nr;
+        for (int t = threadIdx.x; t < n * Nr; t += kBlock) s_prof[t] = src[t];
+        __syncthreads();
+        if (active) {
+            for (int i = 0; i < n; ++i) {
+                const float4 d = s_pos[i];
+                const float ex = q.dx - d.x, ey = q.dy - d.y, ez = q.dz - d.z;
+                const float R = fast_sqrt(ex * ex + ey * ey + ez * ez);
+                const float num = d.w - 2.0f * (q.dx * d.x + q.dy * d.y + q.dz * d.z);
+                const float dR = num * fast_rcp(R + Rc);
+                const float tau = q.frac + dR * inv_dR - 0.5f * W;
+                const float fl = floorf(tau);
+                const float x = tau - fl;
+                const int r = q.bin + (int)fl + 1;
+                float w[W];
+                range_weights<KERNEL, W>(x, beta_log2e, w);
+                const float2 *pr = s_prof + i * Nr;
+                float gre = 0.0f, gim = 0.0f;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    const int rr = r + k;
+                    const float2 v = (rr >= 0 && rr < Nr) ? pr[rr] : make_float2(0.0f, 0.0f);
+                    gre = fmaf(w[k], v.x, gre);
+                    gim = fmaf(w[k], v.y, gim);
+                }
+                float ph = dR * kc_turns;
+                ph -= rintf(ph);
+                const float sn = sin_turns(ph), cs = cos_turns(ph);
+                acc_re = fmaf(gre, cs, fmaf(-gim, sn, acc_re));
+                acc_im = fmaf(gre, sn, fmaf(gim, cs, acc_im));
+            }
+        }
+    }
+    if (active) {
+        out[nd.val_base + p] =
+            make_float2(acc_re * q.pre_re - acc_im * q.pre_im, acc_re * q.pre_im + acc_im * q.pre_re);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Child coordinates and SDC phase at a point, float64 (Sec. III, eq. uvw_xyz,
+// eq. sdc_phi); the continuous lattice coordinate t = gamma (u, v, n) is split
+// into an integer base floor(t) and a float32 fraction.
+struct ChildCoord {
+    int bi, bj, bl;
+    float fu, fv, fn;
+    double phi;
+};
+
+__device__ __forceinline__ double phi_only(const NodeDev &c, double x, double y, double z,
+                                           double kmin, double kmax)
+{
+    const double zz = z * z;
+    const double dx0 = x - c.x0, dx1 = x - c.x1, dy0 = y - c.y0, dy1 = y - c.y1;
+    const double r = sqrt(dx0 * dx0 + dy0 * dy0 + zz) + sqrt(dx0 * dx0 + dy1 * dy1 + zz) +
+                     sqrt(dx1 * dx1 + dy0 * dy0 + zz) + sqrt(dx1 * dx1 + dy1 * dy1 + zz);
+    return 0.25 * (kmax * sqrt(r * r - c.d2) + kmin * r);
+}
+
+__device__ __forceinline__ ChildCoord child_coord(const NodeDev &c, double x, double y, double z,
+                                                  double gu, double gv, double gn, double kmin,
+                                                  double kmax)
+{
+    const double zz = z * z;
+    const double cx = fmin(fmax(x, c.x0), c.x1), cy = fmin(fmax(y, c.y0), c.y1);
+    const double dx0 = x - c.x0, dx1 = x - c.x1, dy0 = y - c.y0, dy1 = y - c.y1;
+    const double ex = x - cx, ey = y - cy;
+    const double ru0 = sqrt(dx0 * dx0 + ey * ey + zz), ru1 = sqrt(dx1 * dx1 + ey * ey + zz);
+    const double rv0 = sqrt(ex * ex + dy0 * dy0 + zz), rv1 = sqrt(ex * ex + dy1 * dy1 + zz);
+    const double r = sqrt(dx0 * dx0 + dy0 * dy0 + zz) + sqrt(dx0 * dx0 + dy1 * dy1 + zz) +
+                     sqrt(dx1 * dx1 + dy0 * dy0 + zz) + sqrt(dx1 * dx1 + dy1 * dy1 + zz);
+    const double s = sqrt(r * r - c.d2);
+    const double tu = gu * (kmax / kPi) * (ru0 - ru1);
+    const double tv = gv * (kmax / kPi) * (rv0 - rv1);
+    const double tn = gn * (kmax * s - kmin * r) * (0.25 / kPi);
+    ChildCoord o;
+    const double fu = floor(tu + kStencilEps), fv = floor(tv + kStencilEps),
+                 fn = floor(tn + kStencilEps);
+    o.bi = (int)fu;
+    o.bj = (int)fv;
+    o.bl = (int)fn;
+    o.fu = (float)(tu - fu);
+    o.fv = (float)(tv - fv);
+    o.fn = (float)(tn - fn);
+    o.phi = 0.25 * (kmax * s + kmin * r);
+    return o;
+}
+
+// Lagrange weights on nodes -T/2+1 .. T/2 at x in [0, 1).
+template <int T>
+__device__ __forceinline__ void lagrange(float x, float *w)
+{
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+        float num = 1.0f, den = 1.0f;
+        const float na = (float)(a - T / 2 + 1);
+#pragma unroll
+        for (int m = 0; m < T; ++m) {
+            if (m == a) continue;
+            const float nm = (float)(m - T / 2 + 1);
+            num *= (x - nm);
+            den *= (na - nm);
+        }
+        w[a] = num / den;
+    }
+}
+
+// Separable T^3 interpolation of a compressed child subimage (missing points are 0).
+template <int T>
+__device__ __forceinline__ float2 interp_child(const NodeDev &c, const ColEntry *__restrict__ cols,
+                                               const float2 *__restrict__ vals,
+                                               const ChildCoord &g)
+{
+    float wu[T], wv[T], wn[T];
+    lagrange<T>(g.fu, wu);
+    lagrange<T>(g.fv, wv);
+    lagrange<T>(g.fn, wn);
+    float are = 0.0f, aim = 0.0f;
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+        const int ci = g.bi + a - T / 2 + 1 - c.i0;
+        if ((unsigned)ci >= (unsigned)c.ni) continue;
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            const int cj = g.bj + b - T / 2 + 1 - c.j0;
+            if ((unsigned)cj >= (unsigned)c.nj) continue;
+            const ColEntry e = cols[c.col_base + ci * c.nj + cj];
+            const float2 *colv = vals + c.val_base + e.off - e.lo;
+            float sre = 0.0f, sim = 0.0f;
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                const int l = g.bl + k - T / 2 + 1;
+                if (l >= e.lo && l <= e.hi) {
+                    const float2 v = colv[l];
+                    sre = fmaf(wn[k], v.x, sre);
+                    sim = fmaf(wn[k], v.y, sim);
+                }
+            }
+            const float wab = wu[a] * wv[b];
+            are = fmaf(wab, sre, are);
+            aim = fmaf(wab, sim, aim);
+        }
+    }
+    return make_float2(are, aim);
+}
+
+__device__ __forceinline__ void phase_mac(float2 v, double phase, float &are, float &aim)
+{
+    double t = phase * (0.5 / kPi);
+    t -= rint(t);
+    const float tf = (float)t;
+    const float sn = sin_turns(tf), cs = cos_turns(tf);
+    are = fmaf(v.x, cs, fmaf(-v.y, sn, are));
+    aim = fmaf(v.x, sn, fmaf(v.y, cs, aim));
+}
+
+struct GeoParams {
+    double gu, gv, gn, kmin, kmax;
+};
+
+// Merge at depth d: parent grid points (float64 SoA) of the depth-d nodes,
+// children at depth d + 1.  Output: compressed parent values.
+template <int T>
+__global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ parents,
+                                                  const BlockItem *__restrict__ blocks,
+                                                  const double *__restrict__ px,
+                                                  const double *__restrict__ py,
+                                                  const double *__restrict__ pz,
+                                                  const NodeDev *__restrict__ children,
+                                                  const ColEntry *__restrict__ ccols,
+                                                  const float2 *__restrict__ cvals, GeoParams gp,
+                                                  float2 *__restrict__ out)
+{
+    const BlockItem blk = blocks[blockIdx.x];
+    const NodeDev nd = parents[blk.node];
+    const int p = blk.start + threadIdx.x;
+    if (p >= nd.npts) return;
+    const int gi = nd.val_base + p;
+    const double x = px[gi], y = py[gi], z = pz[gi];
+    if (!(z > 0.0)) {  // absent grid point (no preimage): holds 0
+        out[gi] = make_float2(0.0f, 0.0f);
+        return;
+    }
+    const double phip = phi_only(nd, x, y, z, gp.kmin, gp.kmax);
+    float are = 0.0f, aim = 0.0f;
+    const int32_t *child_idx = parents[blk.node].child;  // global: no dynamic index into a local copy
+    for (int c = 0; c < nd.nchild; ++c) {
+        const NodeDev ch = children[child_idx[c]];
+        const ChildCoord g = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
+        const float2 v = interp_child<T>(ch, ccols, cvals, g);
+        phase_mac(v, g.phi - phip, are, aim);
+    }
+    out[gi] = make_float2(are, aim);
+}
+
+// Final stage: user voxels, children are the depth-1 nodes.
+template <int T>
+__global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ children,
+                                                  int nchild, const ColEntry *__restrict__ ccols,
+                                                  const float2 *__restrict__ cvals, GeoParams gp,
+                                                  double ox, double oy, double oz, double sx,
+                                                  double sy, double sz, int nx, int ny, int nz,
+                                                  float2 *__restrict__ image)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t nv = (int64_t)nx * ny * nz;
+    if (v >= nv) return;
+    const int iz = (int)(v % nz);
+    const int iy = (int)((v / nz) % ny);
+    const int ix = (int)(v / ((int64_t)nz * ny));
+    const double x = ox + ix * sx, y = oy + iy * sy, z = oz + iz * sz;
+    float are = 0.0f, aim = 0.0f;
+    for (int c = 0; c < nchild; ++c) {
+        const NodeDev ch = children[c];
+        const ChildCoord g = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
+        const float2 val = interp_child<T>(ch, ccols, cvals, g);
+        phase_mac(val, g.phi, are, aim);
+    }
+    image[v] = make_float2(are, aim);
+}
+
+// ---------------------------------------------------------------------------
+// Direct BP on range profiles, eq. (3).  A block is a 4 x 8 x 8 voxel tile with
+// a float64 reference point at its centre.  Per staged position the reference
+// distance R_ref, its bin and fraction and the carrier exp(j 2 kc R_ref) are
+// formed once in float64; per voxel only Delta R = |p - p'| - R_ref enters
+// float32:  Delta R = (|e|^2 - 2 e.delta) / (|p - p'| + R_ref), e = p - ref.
+struct StagedPos {
+    float dx, dy, dz;  // p' - ref
+    float rref;        // |p' - ref| (float32, as a denominator only)
+    int32_t bin;
+    float frac;
+    float car_re, car_im;
+};
+
+template <int KERNEL, int W>
+__global__ __launch_bounds__(kBlock) void k_direct_bp(
+    const double *__restrict__ pos64, int n_pos, const float2 *__restrict__ prof, int Nr,
+    int chunk, double R0, double dR, float inv_dR, float beta_log2e, double kc, float kc_turns, double ox,
+    double oy, double oz, double sx, double sy, double sz, int nx, int ny, int nz,
+    float2 *__restrict__ image)
+{
+    extern __shared__ unsigned char smem[];
+    StagedPos *s_pos = reinterpret_cast<StagedPos *>(smem);
+    float2 *s_prof = reinterpret_cast<float2 *>(smem + chunk * sizeof(StagedPos));
+    const int tnx = (nx + 3) / 4, tny = (ny + 7) / 8;
+    const int b = blockIdx.x;
+    const int tx = b % tnx, ty = (b / tnx) % tny, tz = b / (tnx * tny);
+    const int lx = threadIdx.x >> 6, ly = (threadIdx.x >> 3) & 7, lz = threadIdx.x & 7;
+    const int ix = tx * 4 + lx, iy = ty * 8 + ly, iz = tz * 8 + lz;
+    const bool active = ix < nx && iy < ny && iz < nz;
+    const double rx = ox + (tx * 4 + 1.5) * sx, ry = oy + (ty * 8 + 3.5) * sy,
+                 rz = oz + (tz * 8 + 3.5) * sz;
+    const float ex = (float)((lx - 1.5) * sx), ey = (float)((ly - 3.5) * sy),
+                ez = (float)((lz - 3.5) * sz);
+    const float e2 = ex * ex + ey * ey + ez * ez;
+    float acc_re = 0.0f, acc_im = 0.0f;
+    for (int c0 = 0; c0 < n_pos; c0 += chunk) {
+        const int n = min(chunk, n_pos - c0);
+        __syncthreads();
+        if (threadIdx.x < n) {
+            const int i = c0 + threadIdx.x;
+            const double dx = pos64[3 * i] - rx, dy = pos64[3 * i + 1] - ry,
+                         dz = pos64[3 * i + 2] - rz;
+            const double rr = sqrt(dx * dx + dy * dy + dz * dz);
+            const double t = (rr - R0) / dR;
+            const double fb = floor(t);
+            double turns = rr * (kc / kPi);
+            turns -= rint(turns);
+            double sn, cs;
+            sincos(2.0 * kPi * turns, &sn, &cs);
+            StagedPos sp;
+            sp.dx = (float)dx;
+            sp.dy = (float)dy;
+            sp.dz = (float)dz;
+            sp.rref = (float)rr;
+            sp.bin = (int)fb;
+            sp.frac = (float)(t - fb);
+            sp.car_re = (float)cs;
+            sp.car_im = (float)sn;
+            s_pos[threadIdx.x] = sp;
+        }
+        const float2 *src = prof + (size_t)c0 * Nr;
+        for (int t = threadIdx.x; t < n * Nr; t += kBlock) s_prof[t] = src[t];
+        __syncthreads();
+        if (active) {
+            for (int i = 0; i < n; ++i) {
+                const StagedPos sp = s_pos[i];
+                const float qx = ex - sp.dx, qy = ey - sp.dy, qz = ez - sp.dz;
+                const float R = fast_sqrt(qx * qx + qy * qy + qz * qz);
+                const float num = e2 - 2.0f * (ex * sp.dx + ey * sp.dy + ez * sp.dz);
+                const float dr = num * fast_rcp(R + sp.rref);
+                const float tau = sp.frac + dr * inv_dR - 0.5f * W;
+                const float fl = floorf(tau);
+                const float x = tau - fl;
+                const int r = sp.bin + (int)fl + 1;
+                float w[W];
+                range_weights<KERNEL, W>(x, beta_log2e, w);
+                const float2 *pr = s_prof + i * Nr;
+                float gre = 0.0f, gim = 0.0f;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    const int rr = r + k;
+                    const float2 v = (rr >= 0 && rr < Nr) ? pr[rr] : make_float2(0.0f, 0.0f);
+                    gre = fmaf(w[k], v.x, gre);
+                    gim = fmaf(w[k], v.y, gim);
+                }
+                float ph = dr * kc_turns;
+                ph -= rintf(ph);
+                const float sn = sin_turns(ph), cs = cos_turns(ph);
+                // carrier = exp(j 2 kc R_ref) exp(j 2 kc Delta R)
+                const float cre = sp.car_re * cs - sp.car_im * sn;
+                const float cim = sp.car_re * sn + sp.car_im * cs;
+                acc_re = fmaf(gre, cre, fmaf(-gim, cim, acc_re));
+                acc_im = fmaf(gre, cim, fmaf(gim, cre, acc_im));
+            }
+        }
+    }
+    if (active) image[((int64_t)ix * ny + iy) * nz + iz] = make_float2(acc_re, acc_im);
+}
+
+// ---------------------------------------------------------------------------
+template <int KERNEL, int W>
+hipError_t launch_bp_kernels(const Plan &P, const double *pos64, const float2 *prof,
+                             const float4 *posoff, char *ws, void *image, hipStream_t st)
+{
+    const float inv_dR = (float)(1.0 / P.dR);
+    const float beta_log2e = (float)(P.beta * 1.4426950408889634);
+    const float kc_turns = (float)(P.kc / kPi);
+    const hhffbp_config &c = P.cfg;
+    if (P.S == 0) {
+        const int nx = (int)c.grid_dims[0], ny = (int)c.grid_dims[1], nz = (int)c.grid_dims[2];
+        const int nblk = ((nx + 3) / 4) * ((ny + 7) / 8) * ((nz + 7) / 8);
+        const int chunk = pos_chunk(P.Nr, sizeof(StagedPos));
+        const size_t sh = chunk * (sizeof(StagedPos) + P.Nr * sizeof(float2));
+        hipLaunchKernelGGL((k_direct_bp<KERNEL, W>), dim3(nblk), dim3(kBlock), sh, st,
+                           pos64, (int)c.n_pos, prof, (int)P.Nr, chunk, P.R0, P.dR,
+                           inv_dR, beta_log2e, P.kc, kc_turns, c.grid_origin[0], c.grid_origin[1],
+                           c.grid_origin[2], c.grid_pitch[0], c.grid_pitch[1], c.grid_pitch[2], nx,
+                           ny, nz, (float2 *)image);
+        return hipGetLastError();
+    }
+    const int chunk = pos_chunk(P.Nr, sizeof(float4));
+    const size_t sh = chunk * (sizeof(float4) + P.Nr * sizeof(float2));
+    hipLaunchKernelGGL((k_leaf_bp<KERNEL, W>), dim3(P.n_blocks_leaf), dim3(kBlock), sh, st,
+                       (const NodeDev *)P.dev.nodes[P.S], (const BlockItem *)P.dev.leaf_blocks,
+                       (const LeafPoint *)P.dev.leafpts, posoff, prof, (int)P.Nr, chunk, inv_dR,
+                       beta_log2e, kc_turns, (float2 *)(ws + P.ws_vals[P.S]));
+    return hipGetLastError();
+}
+
+template <int T>
+hipError_t launch_merges(const Plan &P, char *ws, void *image, hipStream_t st, hipEvent_t *ev)
+{
+    GeoParams gp{P.gamma[0], P.gamma[1], P.gamma[2], P.kmin, P.kmax};
+    for (int d = P.S - 1; d >= 1; --d) {
+        if (P.n_blocks_merge[d] == 0) continue;
+        hipLaunchKernelGGL((k_merge<T>), dim3(P.n_blocks_merge[d]), dim3(kBlock), 0, st,
+                           (const NodeDev *)P.dev.nodes[d], (const BlockItem *)P.dev.merge_blocks[d],
+                           (const double *)P.dev.px[d], (const double *)P.dev.py[d],
+                           (const double *)P.dev.pz[d], (const NodeDev *)P.dev.nodes[d + 1],
+                           (const ColEntry *)P.dev.cols[d + 1],
+                           (const float2 *)(ws + P.ws_vals[d + 1]), gp,
+                           (float2 *)(ws + P.ws_vals[d]));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (ev) (void)hipEventRecord(*ev++, st);
+    }
+    const hhffbp_config &c = P.cfg;
+    const int nx = (int)c.grid_dims[0], ny = (int)c.grid_dims[1], nz = (int)c.grid_dims[2];
+    const int64_t nv = (int64_t)nx * ny * nz;
+    const int nblk = (int)((nv + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_final<T>), dim3(nblk), dim3(kBlock), 0, st,
+                       (const NodeDev *)P.dev.nodes[1], (int)P.compact_to_tree[1].size(),
+                       (const ColEntry *)P.dev.cols[1], (const float2 *)(ws + P.ws_vals[1]), gp,
+                       c.grid_origin[0], c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0],
+                       c.grid_pitch[1], c.grid_pitch[2], nx, ny, nz, (float2 *)image);
+    hipError_t e = hipGetLastError();
+    if (ev && e == hipSuccess) (void)hipEventRecord(*ev, st);
+    return e;
+}
+
+}  // namespace
+
+std::vector<std::string> Plan::stage_names() const
+{
+    std::vector<std::string> n;
+    if (S == 0) {
+        n = {"rc_gemm", "direct_bp"};
+    } else {
+        n = {"prep_positions", "rc_gemm", "leaf_bp"};
+        for (int d = S - 1; d >= 1; --d) n.push_back("merge_d" + std::to_string(d));
+        n.push_back("final");
+    }
+    return n;
+}
+
+hhffbp_status launch_image(const Plan &P, const void *echoes, const double *positions,
+                           void *image, char *ws, hipStream_t st, hipEvent_t *ev)
+{
+    if (ev) (void)hipEventRecord(*ev++, st);
+    const hhffbp_config &c = P.cfg;
+    const int n = (int)c.n_pos;
+    const double *pos64 = positions ? positions : (const double *)P.dev.pos64;
+    float2 *prof = (float2 *)(ws + P.ws_prof);
+    float4 *posoff = (float4 *)(ws + P.ws_posoff);
+    hipError_t e = hipSuccess;
+    if (P.S > 0) {
+        hipLaunchKernelGGL(k_prep_positions, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                           pos64, (const int32_t *)P.dev.perm, (const int32_t *)P.dev.leaf_of_sorted,
+                           (const double *)P.dev.leaf_centre, n, posoff);
+        if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
+        if (ev) (void)hipEventRecord(*ev++, st);
+    }
+    {
+        const int M = n, K = (int)(2 * c.n_freq), N = (int)(2 * P.Nr);
+        dim3 grid((M + 63) / 64, (N + 63) / 64);
+        hipLaunchKernelGGL(k_rc_gemm, grid, dim3(kBlock), 0, st, (const float *)echoes,
+                           (const int32_t *)P.dev.perm, M, K, (const float *)P.dev.B, N,
+                           (float *)prof);
+        if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
+        if (ev) (void)hipEventRecord(*ev++, st);
+    }
+    if (P.kernel == HHFFBP_RANGE_LINEAR) {
+        e = launch_bp_kernels<HHFFBP_RANGE_LINEAR, 2>(P, pos64, prof, posoff, ws, image, st);
+    } else {
+        switch (P.W) {
+        case 4: e = launch_bp_kernels<HHFFBP_RANGE_ES, 4>(P, pos64, prof, posoff, ws, image, st); break;
+        case 5: e = launch_bp_kernels<HHFFBP_RANGE_ES, 5>(P, pos64, prof, posoff, ws, image, st); break;
+        case 6: e = launch_bp_kernels<HHFFBP_RANGE_ES, 6>(P, pos64, prof, posoff, ws, image, st); break;
+        case 7: e = launch_bp_kernels<HHFFBP_RANGE_ES, 7>(P, pos64, prof, posoff, ws, image, st); break;
+        case 8: e = launch_bp_kernels<HHFFBP_RANGE_ES, 8>(P, pos64, prof, posoff, ws, image, st); break;
+        default: return HHFFBP_E_UNSUPPORTED;
+        }
+    }
+    if (e != hipSuccess) return HHFFBP_E_DEVICE;
+    if (ev) (void)hipEventRecord(*ev++, st);
+    if (P.S == 0) return HHFFBP_OK;
+    e = (P.T == 4) ? launch_merges<4>(P, ws, image, st, ev) : launch_merges<6>(P, ws, image, st, ev);
+    return e == hipSuccess ? HHFFBP_OK : HHFFBP_E_DEVICE;
+}
+
+}  // namespace hh

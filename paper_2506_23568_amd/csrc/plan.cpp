@@ -1,0 +1,772 @@
+// Host-side plan of the HHFFBPA library (float64): subarray tree, sampling
+// grids, grid preimages, range window and range-compression matrix.
+//
+// Section references are to the paper (Sec. III: analytic SDC and LLT,
+// Sec. IV-A: implementation).
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <limits>
+#include <thread>
+
+#include "hhffbp_internal.hpp"
+
+namespace hh {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Small thread pool helper: run fn(begin, end) over [0, n) in chunks.
+void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)> &fn)
+{
+    if (n <= 0) return;
+    unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    int64_t nchunks = (n + grain - 1) / grain;
+    if (hw == 1 || nchunks == 1) {
+        fn(0, n);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    auto worker = [&]() {
+        for (;;) {
+            int64_t c = next.fetch_add(1);
+            if (c >= nchunks) break;
+            int64_t b = c * grain;
+            fn(b, std::min(n, b + grain));
+        }
+    };
+    std::vector<std::thread> th;
+    unsigned nt = (unsigned)std::min<int64_t>(hw, nchunks);
+    for (unsigned t = 1; t < nt; ++t) th.emplace_back(worker);
+    worker();
+    for (auto &t : th) t.join();
+}
+
+// ---------------------------------------------------------------------------
+// Spectrum-compression maps of one subarray (Sec. III).  For a point p the
+// focal points of u are (x'_min, y'_0, 0) and (x'_max, y'_0, 0), those of v are
+// (x'_0, y'_min, 0) and (x'_0, y'_max, 0), with (x'_0, y'_0) the clamp of
+// (x, y) onto the rectangle; r sums the distances to the four vertices.
+//   u = kmax/pi (|p-Fu-| - |p-Fu+|),  v = kmax/pi (|p-Fv-| - |p-Fv+|)
+//   n = (kmax sqrt(r^2 - D^2) - kmin r) / 4pi,   Phi = (kmax sqrt(r^2-D^2) + kmin r) / 4
+struct SubarrayMap {
+    double x0, x1, y0, y1, d2, kmin, kmax;
+
+    SubarrayMap(const Rect &r, double kmn, double kmx)
+        : x0(r.x0), x1(r.x1), y0(r.y0), y1(r.y1), kmin(kmn), kmax(kmx)
+    {
+        d2 = 4.0 * (x1 - x0) * (x1 - x0) + 4.0 * (y1 - y0) * (y1 - y0);
+    }
+
+    // w = (u, v, n); optional Jacobian rows (grad u, grad v, grad n).
+    void eval(const double *p, double *w, double *phi, double *jac) const
+    {
+        const double x = p[0], y = p[1], z = p[2], zz = z * z;
+        const double cx = std::min(std::max(x, x0), x1);
+        const double cy = std::min(std::max(y, y0), y1);
+        const double dx0 = x - x0, dx1 = x - x1, dy0 = y - y0, dy1 = y - y1;
+        const double ex = x - cx, ey = y - cy;
+        const double ru0 = std::sqrt(dx0 * dx0 + ey * ey + zz);
+        const double ru1 = std::sqrt(dx1 * dx1 + ey * ey + zz);
+        const double rv0 = std::sqrt(ex * ex + dy0 * dy0 + zz);
+        const double rv1 = std::sqrt(ex * ex + dy1 * dy1 + zz);
+        const double q00 = std::sqrt(dx0 * dx0 + dy0 * dy0 + zz);
+        const double q01 = std::sqrt(dx0 * dx0 + dy1 * dy1 + zz);
+        const double q10 = std::sqrt(dx1 * dx1 + dy0 * dy0 + zz);
+        const double q11 = std::sqrt(dx1 * dx1 + dy1 * dy1 + zz);
+        const double r = q00 + q01 + q10 + q11;
+        const double s = std::sqrt(r * r - d2);
+        const double cu = kmax / kPi;
+        w[0] = cu * (ru0 - ru1);
+        w[1] = cu * (rv0 - rv1);
+        w[2] = (kmax * s - kmin * r) / (4.0 * kPi);
+        if (phi) *phi = 0.25 * (kmax * s + kmin * r);
+        if (jac) {
+            // grad |p - a| = (p - a) / |p - a|; the clamped coordinates add nothing.
+            jac[0] = cu * (dx0 / ru0 - dx1 / ru1);
+            jac[1] = cu * (ey / ru0 - ey / ru1);
+            jac[2] = cu * (z / ru0 - z / ru1);
+            jac[3] = cu * (ex / rv0 - ex / rv1);
+            jac[4] = cu * (dy0 / rv0 - dy1 / rv1);
+            jac[5] = cu * (z / rv0 - z / rv1);
+            const double grx = dx0 / q00 + dx0 / q01 + dx1 / q10 + dx1 / q11;
+            const double gry = dy0 / q00 + dy1 / q01 + dy0 / q10 + dy1 / q11;
+            const double grz = z * (1.0 / q00 + 1.0 / q01 + 1.0 / q10 + 1.0 / q11);
+            const double a = (kmax * r / s - kmin) / (4.0 * kPi);
+            jac[6] = a * grx;
+            jac[7] = a * gry;
+            jac[8] = a * grz;
+        }
+    }
+};
+
+bool solve3(const double *J, const double *f, double *x)
+{
+    const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                       J[2] * (J[3] * J[7] - J[4] * J[6]);
+    if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return false;
+    const double id = 1.0 / det;
+    x[0] = id * (f[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (f[1] * J[8] - J[5] * f[2]) +
+                 J[2] * (f[1] * J[7] - J[4] * f[2]));
+    x[1] = id * (J[0] * (f[1] * J[8] - J[5] * f[2]) - f[0] * (J[3] * J[8] - J[5] * J[6]) +
+                 J[2] * (J[3] * f[2] - f[1] * J[6]));
+    x[2] = id * (J[0] * (J[4] * f[2] - f[1] * J[7]) - J[1] * (J[3] * f[2] - f[1] * J[6]) +
+                 f[0] * (J[3] * J[7] - J[4] * J[6]));
+    return true;
+}
+
+double norm3(const double *a) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
+
+// Newton with backtracking on |uvn(p) - target|; p holds the start on entry.
+bool newton_invert(const SubarrayMap &m, const double *target, double *p)
+{
+    double w[3], F[3], J[9], dp[3], pn[3], Fn[3];
+    m.eval(p, w, nullptr, J);
+    for (int a = 0; a < 3; ++a) F[a] = w[a] - target[a];
+    double nf = norm3(F);
+    for (int it = 0; it < 80; ++it) {
+        if (!solve3(J, F, dp)) return false;
+        const double ndp = norm3(dp);
+        double lam = 1.0;
+        double nfn = 0.0;
+        for (int bt = 0; bt < 50; ++bt) {
+            for (int a = 0; a < 3; ++a) pn[a] = p[a] - lam * dp[a];
+            if (pn[2] < 1e-4) pn[2] = 1e-4;
+            m.eval(pn, w, nullptr, nullptr);
+            for (int a = 0; a < 3; ++a) Fn[a] = w[a] - target[a];
+            nfn = norm3(Fn);
+            if (nfn < nf || lam * ndp < 1e-13) break;
+            lam *= 0.5;
+        }
+        std::memcpy(p, pn, sizeof(pn));
+        std::memcpy(F, Fn, sizeof(Fn));
+        nf = nfn;
+        if (lam * ndp < 1e-12) return nf < 1e-8;
+        m.eval(p, w, nullptr, J);
+    }
+    return false;
+}
+
+// Starting point for the first grid point of a pencil: n is close to
+// (kmax - kmin) / pi times the distance to the subarray centre, and u, v are
+// close to kmax L / pi times the direction cosines along x and y.
+void pencil_start(const SubarrayMap &m, const double *target, double *p)
+{
+    const double lx = m.x1 - m.x0, ly = m.y1 - m.y0;
+    double rho = kPi * target[2] / (m.kmax - m.kmin);
+    // refine rho on the boresight axis, where n(rho) = (kmax rho - kmin sqrt(h^2 + rho^2)) / pi
+    const double h2 = 0.25 * (lx * lx + ly * ly);
+    for (int it = 0; it < 20; ++it) {
+        const double s = std::sqrt(h2 + rho * rho);
+        const double f = (m.kmax * rho - m.kmin * s) / kPi - target[2];
+        const double df = (m.kmax - m.kmin * rho / s) / kPi;
+        rho -= f / df;
+        if (rho < 1e-3) rho = 1e-3;
+    }
+    double ax = kPi * target[0] / (m.kmax * lx);
+    double ay = kPi * target[1] / (m.kmax * ly);
+    ax = std::max(-0.7, std::min(0.7, ax));
+    ay = std::max(-0.7, std::min(0.7, ay));
+    const double c = std::sqrt(std::max(0.1, 1.0 - ax * ax - ay * ay));
+    const double R = rho / c;
+    p[0] = 0.5 * (m.x0 + m.x1) + R * ax;
+    p[1] = 0.5 * (m.y0 + m.y1) + R * ay;
+    p[2] = R * c;
+}
+
+// ---------------------------------------------------------------------------
+void partition(Plan &P)
+{
+    const int64_t n = P.cfg.n_pos;
+    const double *pos = P.positions.data();
+    double xa = pos[0], xb = pos[0], ya = pos[1], yb = pos[1];
+    for (int64_t i = 1; i < n; ++i) {
+        xa = std::min(xa, pos[3 * i]);
+        xb = std::max(xb, pos[3 * i]);
+        ya = std::min(ya, pos[3 * i + 1]);
+        yb = std::max(yb, pos[3 * i + 1]);
+    }
+    if (P.S > 0 && !(xb > xa && yb > ya))
+        throw Error{HHFFBP_E_INVALID, "aperture has zero extent along x' or y'"};
+    const int first_axis = (xb - xa) >= (yb - ya) ? 0 : 1;
+    P.levels.assign(P.S + 1, {});
+    HostNode root;
+    root.depth = 0;
+    root.rect = {xa, xb, ya, yb};
+    root.members.resize(n);
+    for (int64_t i = 0; i < n; ++i) root.members[i] = (int32_t)i;
+    P.levels[0].push_back(std::move(root));
+    for (int d = 0; d < P.S; ++d) {
+        auto &cur = P.levels[d];
+        auto &nxt = P.levels[d + 1];
+        for (size_t pi = 0; pi < cur.size(); ++pi) {
+            const Rect rc = cur[pi].rect;
+            // (rectangle, predicate on (x', y')) for each child, in a fixed order
+            std::vector<Rect> rects;
+            std::vector<std::function<bool(double, double)>> take;
+            if (P.Q == 4) {
+                const double xm = 0.5 * (rc.x0 + rc.x1), ym = 0.5 * (rc.y0 + rc.y1);
+                rects = {{rc.x0, xm, rc.y0, ym}, {rc.x0, xm, ym, rc.y1},
+                         {xm, rc.x1, rc.y0, ym}, {xm, rc.x1, ym, rc.y1}};
+                take = {[=](double x, double y) { return x < xm && y < ym; },
+                        [=](double x, double y) { return x < xm && y >= ym; },
+                        [=](double x, double y) { return x >= xm && y < ym; },
+                        [=](double x, double y) { return x >= xm && y >= ym; }};
+            } else if ((first_axis + d) % 2 == 0) {
+                const double xm = 0.5 * (rc.x0 + rc.x1);
+                rects = {{rc.x0, xm, rc.y0, rc.y1}, {xm, rc.x1, rc.y0, rc.y1}};
+                take = {[=](double x, double) { return x < xm; },
+                        [=](double x, double) { return x >= xm; }};
+            } else {
+                const double ym = 0.5 * (rc.y0 + rc.y1);
+                rects = {{rc.x0, rc.x1, rc.y0, ym}, {rc.x0, rc.x1, ym, rc.y1}};
+                take = {[=](double, double y) { return y < ym; },
+                        [=](double, double y) { return y >= ym; }};
+            }
+            for (size_t c = 0; c < rects.size(); ++c) {
+                HostNode ch;
+                ch.depth = d + 1;
+                ch.rect = rects[c];
+                ch.parent = (int32_t)pi;
+                for (int32_t m : cur[pi].members)
+                    if (take[c](pos[3 * m], pos[3 * m + 1])) ch.members.push_back(m);
+                cur[pi].children.push_back((int32_t)nxt.size());
+                nxt.push_back(std::move(ch));
+            }
+        }
+    }
+}
+
+// Grid of `node`: every Lagrange stencil its parent's points need, closed into
+// one pencil per (i, j) column (Sec. IV-A, grids G_{m,n}).
+void build_lattice(Plan &P, HostNode &node, const std::vector<double> &parent_all)
+{
+    const SubarrayMap map(node.rect, P.kmin, P.kmax);
+    // absent parent points (no preimage) need no children
+    std::vector<double> parent_xyz;
+    parent_xyz.reserve(parent_all.size());
+    for (size_t q = 0; q + 2 < parent_all.size(); q += 3)
+        if (std::isfinite(parent_all[q + 2]))
+            parent_xyz.insert(parent_xyz.end(), &parent_all[q], &parent_all[q] + 3);
+    const int64_t np = (int64_t)parent_xyz.size() / 3;
+    if (np == 0) throw Error{HHFFBP_E_NUMERIC, "a subarray's parent grid has no valid point"};
+    const int T = P.T;
+    const int margin = 0;
+    const int slo = -(T / 2) + 1 - margin, shi = T / 2 + margin;
+    std::vector<int32_t> base(3 * np);
+    parallel_for(np, 4096, [&](int64_t b, int64_t e) {
+        double w[3];
+        for (int64_t q = b; q < e; ++q) {
+            map.eval(&parent_xyz[3 * q], w, nullptr, nullptr);
+            for (int a = 0; a < 3; ++a)
+                base[3 * q + a] = (int32_t)std::floor(P.gamma[a] * w[a] + kStencilEps);
+        }
+    });
+    int32_t imin = INT32_MAX, imax = INT32_MIN, jmin = INT32_MAX, jmax = INT32_MIN;
+    for (int64_t q = 0; q < np; ++q) {
+        imin = std::min(imin, base[3 * q]);
+        imax = std::max(imax, base[3 * q]);
+        jmin = std::min(jmin, base[3 * q + 1]);
+        jmax = std::max(jmax, base[3 * q + 1]);
+    }
+    HostLattice &L = node.lat;
+    L.i0 = imin + slo;
+    L.j0 = jmin + slo;
+    L.ni = imax - imin + (shi - slo) + 1;
+    L.nj = jmax - jmin + (shi - slo) + 1;
+    const int64_t ncol = (int64_t)L.ni * L.nj;
+    L.lo.assign(ncol, INT32_MAX);
+    L.hi.assign(ncol, INT32_MIN);
+    for (int64_t q = 0; q < np; ++q) {
+        const int32_t bi = base[3 * q], bj = base[3 * q + 1], bl = base[3 * q + 2];
+        for (int a = slo; a <= shi; ++a) {
+            const int64_t ci = bi + a - L.i0;
+            for (int b = slo; b <= shi; ++b) {
+                const int64_t c = ci * L.nj + (bj + b - L.j0);
+                L.lo[c] = std::min(L.lo[c], bl + slo);
+                L.hi[c] = std::max(L.hi[c], bl + shi);
+            }
+        }
+    }
+    L.off.assign(ncol, 0);
+    int64_t tot = 0;
+    for (int64_t c = 0; c < ncol; ++c) {
+        if (L.hi[c] < L.lo[c]) {
+            L.lo[c] = 0;
+            L.hi[c] = -1;
+        }
+        L.off[c] = tot;
+        tot += (int64_t)L.hi[c] - L.lo[c] + 1;
+    }
+    L.npts = tot;
+    L.xyz.assign(3 * tot, std::numeric_limits<double>::quiet_NaN());
+    std::atomic<int64_t> absent{0};
+    const double zv = P.z_valid;
+    parallel_for(ncol, 64, [&](int64_t b, int64_t e) {
+        for (int64_t c = b; c < e; ++c) {
+            if (L.hi[c] < L.lo[c]) continue;
+            const int32_t i = L.i0 + (int32_t)(c / L.nj), j = L.j0 + (int32_t)(c % L.nj);
+            double p[3], prev[3];
+            bool have_prev = false;
+            for (int32_t l = L.lo[c]; l <= L.hi[c]; ++l) {
+                const double target[3] = {i / P.gamma[0], j / P.gamma[1], l / P.gamma[2]};
+                if (have_prev) {
+                    std::memcpy(p, prev, sizeof(p));
+                } else {
+                    pencil_start(map, target, p);
+                }
+                bool ok = newton_invert(map, target, p) && p[2] >= zv;
+                if (!ok && have_prev) {
+                    pencil_start(map, target, p);
+                    ok = newton_invert(map, target, p) && p[2] >= zv;
+                }
+                if (!ok) {
+                    // beyond the (u, v, n) image of the scene half-space: absent
+                    absent.fetch_add(1);
+                    have_prev = false;
+                    continue;
+                }
+                std::memcpy(&L.xyz[3 * (L.off[c] + (l - L.lo[c]))], p, sizeof(p));
+                std::memcpy(prev, p, sizeof(p));
+                have_prev = true;
+            }
+        }
+    });
+    L.n_absent = absent.load();
+}
+
+// Fourier transform of the truncated ES kernel phi(t) = exp(beta (sqrt(1 - (2t/W)^2) - 1))
+// on |t| <= W/2, at angular frequency theta (rad per bin); composite Simpson.
+double es_hat(double theta, int W, double beta)
+{
+    const int n = 8000;
+    const double a = 0.5 * W, h = a / n;
+    double s = 0.0;
+    for (int i = 0; i <= n; ++i) {
+        const double t = i * h;
+        const double z = t / a;
+        const double v = std::exp(beta * (std::sqrt(std::max(0.0, 1.0 - z * z)) - 1.0)) *
+                         std::cos(theta * t);
+        const double wgt = (i == 0 || i == n) ? 1.0 : ((i & 1) ? 4.0 : 2.0);
+        s += wgt * v;
+    }
+    return 2.0 * s * h / 3.0;
+}
+
+double linear_hat(double theta)
+{
+    if (std::fabs(theta) < 1e-12) return 1.0;
+    const double s = std::sin(0.5 * theta) / (0.5 * theta);
+    return s * s;
+}
+
+// Range window and the pre-corrected DFT matrix of eq. (2) onto it.
+void range_setup(Plan &P, double rmin, double rmax)
+{
+    const double dk = P.kmax - P.kmin;
+    P.dR = kPi / (P.U * dk);
+    const int W = P.W;
+    const double pad = (0.5 * W + 2.0) * P.dR;
+    P.R0 = rmin - pad;
+    int64_t nr = (int64_t)std::ceil((rmax + pad - P.R0) / P.dR) + 1;
+    nr = (nr + 31) / 32 * 32;
+    P.Nr = nr;
+    const int64_t nf = P.cfg.n_freq;
+    P.Bmat.assign((size_t)(2 * nf) * (size_t)(2 * nr), 0.0f);
+    for (int64_t f = 0; f < nf; ++f) {
+        const double om = 2.0 * (P.k[f] - P.kc);
+        const double corr = (P.kernel == HHFFBP_RANGE_ES) ? es_hat(om * P.dR, W, P.beta)
+                                                         : linear_hat(om * P.dR);
+        for (int64_t r = 0; r < nr; ++r) {
+            const double ph = om * (P.R0 + r * P.dR);
+            const double wr = std::cos(ph) / corr, wi = std::sin(ph) / corr;
+            float *row0 = &P.Bmat[(size_t)(2 * f) * (2 * nr)];
+            float *row1 = &P.Bmat[(size_t)(2 * f + 1) * (2 * nr)];
+            row0[2 * r] = (float)wr;
+            row0[2 * r + 1] = (float)wi;
+            row1[2 * r] = (float)(-wi);
+            row1[2 * r + 1] = (float)wr;
+        }
+    }
+}
+
+// Distance range from points to a box (for the range window).
+void box_dist(const double *q, const double *lo, const double *hi, double *dmin, double *dmax)
+{
+    double s0 = 0, s1 = 0;
+    for (int a = 0; a < 3; ++a) {
+        const double c = std::min(std::max(q[a], lo[a]), hi[a]);
+        s0 += (q[a] - c) * (q[a] - c);
+        const double f = std::max(std::fabs(q[a] - lo[a]), std::fabs(q[a] - hi[a]));
+        s1 += f * f;
+    }
+    *dmin = std::sqrt(s0);
+    *dmax = std::sqrt(s1);
+}
+
+void validate(const hhffbp_config &c)
+{
+    auto bad = [](const std::string &m) { throw Error{HHFFBP_E_INVALID, m}; };
+    if (c.n_pos < 1) bad("n_pos must be >= 1");
+    if (c.n_freq < 2) bad("n_freq must be >= 2");
+    if (!c.positions || !c.freqs_hz) bad("positions and freqs_hz must be non-NULL");
+    if (c.n_pos > (int64_t)INT32_MAX / 2) bad("n_pos too large");
+    for (int a = 0; a < 3; ++a) {
+        if (c.grid_dims[a] < 1) bad("grid_dims must be >= 1");
+        if (!(c.grid_pitch[a] > 0) || !std::isfinite(c.grid_pitch[a])) bad("grid_pitch must be > 0");
+        if (!std::isfinite(c.grid_origin[a])) bad("grid_origin must be finite");
+        if (!(c.oversample[a] >= 1.0 && c.oversample[a] <= 8.0)) bad("oversample must be in [1, 8]");
+    }
+    if (c.grid_dims[0] * c.grid_dims[1] * c.grid_dims[2] > ((int64_t)1 << 31))
+        bad("grid too large");
+    if (c.mode != HHFFBP_FACTORIZED && c.mode != HHFFBP_DIRECT_RC) bad("unknown mode");
+    if (c.stages < 0 || c.stages > 8) bad("stages must be in [0, 8]");
+    if (c.merge_factor != 2 && c.merge_factor != 4) bad("merge_factor must be 2 or 4");
+    if (c.interp_taps != 4 && c.interp_taps != 6) bad("interp_taps must be 4 or 6");
+    if (c.range_kernel == HHFFBP_RANGE_ES) {
+        if (c.range_taps < 4 || c.range_taps > 8) bad("range_taps must be in [4, 8]");
+    } else if (c.range_kernel != HHFFBP_RANGE_LINEAR) {
+        bad("unknown range_kernel");
+    }
+    if (!(c.range_oversample >= 1.5 && c.range_oversample <= 16.0))
+        bad("range_oversample must be in [1.5, 16]");
+    if (!(c.position_slack >= 0.0 && c.position_slack < 0.1)) bad("position_slack must be in [0, 0.1)");
+    if (c.storage != HHFFBP_C64) throw Error{HHFFBP_E_UNSUPPORTED, "only HHFFBP_C64 storage is built"};
+    double zmax = -1e300;
+    for (int64_t i = 0; i < 3 * c.n_pos; ++i)
+        if (!std::isfinite(c.positions[i])) bad("positions must be finite");
+    for (int64_t i = 0; i < c.n_pos; ++i) zmax = std::max(zmax, c.positions[3 * i + 2]);
+    for (int64_t f = 0; f < c.n_freq; ++f)
+        if (!(c.freqs_hz[f] > 0) || !std::isfinite(c.freqs_hz[f])) bad("freqs_hz must be finite and > 0");
+    if (!(c.grid_origin[2] > zmax + c.position_slack))
+        bad("the voxel grid must lie in front of the aperture (z > max z' + slack)");
+    if (c.mode == HHFFBP_FACTORIZED && c.stages > 0 && c.grid_origin[2] <= 0.0)
+        bad("factorised imaging needs the grid at z > 0");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+void build_plan_host(Plan &P)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    const hhffbp_config &c = P.cfg;
+    validate(c);
+    P.S = (c.mode == HHFFBP_FACTORIZED) ? c.stages : 0;
+    P.Q = c.merge_factor;
+    P.T = c.interp_taps;
+    for (int a = 0; a < 3; ++a) P.gamma[a] = c.oversample[a];
+    P.kernel = c.range_kernel;
+    P.W = (c.range_kernel == HHFFBP_RANGE_ES) ? c.range_taps : 2;
+    P.U = c.range_oversample;
+    P.beta = kPi * P.W * (1.0 - 1.0 / (2.0 * P.U)) * 0.98;
+    P.positions.assign(c.positions, c.positions + 3 * c.n_pos);
+    P.k.resize(c.n_freq);
+    for (int64_t f = 0; f < c.n_freq; ++f) P.k[f] = 2.0 * kPi * c.freqs_hz[f] / kLight;
+    P.kmin = *std::min_element(P.k.begin(), P.k.end());
+    P.kmax = *std::max_element(P.k.begin(), P.k.end());
+    if (!(P.kmax > P.kmin)) throw Error{HHFFBP_E_INVALID, "need at least two distinct frequencies"};
+    P.kc = 0.5 * (P.kmin + P.kmax);
+
+    partition(P);
+    const int S = P.S;
+
+    // voxel centres, float64
+    const int64_t nx = c.grid_dims[0], ny = c.grid_dims[1], nz = c.grid_dims[2];
+    std::vector<double> vox;
+    if (S > 0) {
+        vox.resize(3 * P.n_vox());
+        for (int64_t ix = 0; ix < nx; ++ix)
+            for (int64_t iy = 0; iy < ny; ++iy)
+                for (int64_t iz = 0; iz < nz; ++iz) {
+                    const int64_t v = (ix * ny + iy) * nz + iz;
+                    vox[3 * v] = c.grid_origin[0] + ix * c.grid_pitch[0];
+                    vox[3 * v + 1] = c.grid_origin[1] + iy * c.grid_pitch[1];
+                    vox[3 * v + 2] = c.grid_origin[2] + iz * c.grid_pitch[2];
+                }
+    }
+    // grid points whose preimage lies below half the lowest voxel plane are absent
+    P.z_valid = 0.5 * c.grid_origin[2];
+    // grids, top-down: depth d needs the points of depth d - 1
+    for (int d = 1; d <= S; ++d) {
+        for (auto &node : P.levels[d]) {
+            if (node.empty()) continue;
+            const std::vector<double> &ppts =
+                (d == 1) ? vox : P.levels[d - 1][node.parent].lat.xyz;
+            build_lattice(P, node, ppts);
+        }
+    }
+    // compact indices, leaf-sorted positions
+    P.compact_to_tree.assign(S + 1, {});
+    P.depth_points.assign(S + 1, 0);
+    for (int d = 0; d <= S; ++d) {
+        for (size_t i = 0; i < P.levels[d].size(); ++i) {
+            HostNode &nd = P.levels[d][i];
+            if (nd.empty()) continue;
+            nd.compact = (int32_t)P.compact_to_tree[d].size();
+            P.compact_to_tree[d].push_back((int32_t)i);
+            P.depth_points[d] += nd.lat.npts;
+        }
+    }
+    P.perm.clear();
+    P.leaf_of_sorted.clear();
+    P.leaf_centre.clear();
+    for (int32_t ti : P.compact_to_tree[S]) {
+        const HostNode &lf = P.levels[S][ti];
+        for (int32_t m : lf.members) {
+            P.perm.push_back(m);
+            P.leaf_of_sorted.push_back(lf.compact);
+        }
+        P.leaf_centre.push_back(0.5 * (lf.rect.x0 + lf.rect.x1));
+        P.leaf_centre.push_back(0.5 * (lf.rect.y0 + lf.rect.y1));
+    }
+
+    // range window: all (point, position) distances the backprojection uses
+    double rmin = std::numeric_limits<double>::max(), rmax = 0.0;
+    const double slack = c.position_slack;
+    auto member_box = [&](const HostNode &nd, double *lo, double *hi) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = 1e300;
+            hi[a] = -1e300;
+        }
+        for (int32_t m : nd.members)
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], P.positions[3 * m + a] - slack);
+                hi[a] = std::max(hi[a], P.positions[3 * m + a] + slack);
+            }
+    };
+    if (S == 0) {
+        double lo[3], hi[3];
+        member_box(P.levels[0][0], lo, hi);
+        // the voxel box's extreme distances to the position box
+        for (int cx = 0; cx < 2; ++cx)
+            for (int cy = 0; cy < 2; ++cy)
+                for (int cz = 0; cz < 2; ++cz) {
+                    const double q[3] = {c.grid_origin[0] + cx * (nx - 1) * c.grid_pitch[0],
+                                         c.grid_origin[1] + cy * (ny - 1) * c.grid_pitch[1],
+                                         c.grid_origin[2] + cz * (nz - 1) * c.grid_pitch[2]};
+                    double dmn, dmx;
+                    box_dist(q, lo, hi, &dmn, &dmx);
+                    rmax = std::max(rmax, dmx);
+                }
+        // nearest approach: the grid's lowest plane to the position box
+        const double zg = c.grid_origin[2];
+        double s0 = std::max(0.0, zg - hi[2]);
+        double gx0 = c.grid_origin[0], gx1 = gx0 + (nx - 1) * c.grid_pitch[0];
+        double gy0 = c.grid_origin[1], gy1 = gy0 + (ny - 1) * c.grid_pitch[1];
+        double ddx = std::max(0.0, std::max(lo[0] - gx1, gx0 - hi[0]));
+        double ddy = std::max(0.0, std::max(lo[1] - gy1, gy0 - hi[1]));
+        rmin = std::sqrt(s0 * s0 + ddx * ddx + ddy * ddy);
+    } else {
+        for (int32_t ti : P.compact_to_tree[S]) {
+            const HostNode &lf = P.levels[S][ti];
+            double lo[3], hi[3];
+            member_box(lf, lo, hi);
+            for (int64_t q = 0; q < lf.lat.npts; ++q) {
+                if (!std::isfinite(lf.lat.xyz[3 * q + 2])) continue;
+                double dmn, dmx;
+                box_dist(&lf.lat.xyz[3 * q], lo, hi, &dmn, &dmx);
+                rmin = std::min(rmin, dmn);
+                rmax = std::max(rmax, dmx);
+            }
+        }
+    }
+    range_setup(P, rmin, rmax);
+
+    // work accounting
+    P.leaf_pairs = 0;
+    P.merge_pairs = 0;
+    P.final_pairs = 0;
+    if (S == 0) {
+        P.leaf_pairs = P.n_vox() * c.n_pos;
+    } else {
+        for (int32_t ti : P.compact_to_tree[S]) {
+            const HostNode &lf = P.levels[S][ti];
+            P.leaf_pairs += lf.lat.npts * (int64_t)lf.members.size();
+        }
+        for (int d = 1; d < S; ++d)
+            for (int32_t ti : P.compact_to_tree[d]) {
+                const HostNode &nd = P.levels[d][ti];
+                int nch = 0;
+                for (int32_t ch : nd.children) nch += P.levels[d + 1][ch].empty() ? 0 : 1;
+                P.merge_pairs += nd.lat.npts * nch;
+            }
+        P.final_pairs = P.n_vox() * (int64_t)P.compact_to_tree[1].size();
+    }
+
+    // workspace layout
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    size_t off = 0;
+    P.ws_prof = off;
+    off += al((size_t)c.n_pos * P.Nr * 8);
+    P.ws_posoff = off;
+    off += al((size_t)c.n_pos * 16);
+    P.ws_vals.assign(S + 1, 0);
+    for (int d = 1; d <= S; ++d) {
+        P.ws_vals[d] = off;
+        off += al((size_t)P.depth_points[d] * 8);
+    }
+    P.ws_total = off;
+    P.plan_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace hh
+
+namespace hh {
+
+// ---------------------------------------------------------------------------
+namespace {
+
+template <class T>
+void upload_vec(void **dst, const std::vector<T> &v)
+{
+    *dst = nullptr;
+    if (v.empty()) return;
+    if (hipMalloc(dst, v.size() * sizeof(T)) != hipSuccess) {
+        *dst = nullptr;
+        throw Error{HHFFBP_E_NOMEM, "hipMalloc failed during plan upload"};
+    }
+    if (hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        throw Error{HHFFBP_E_DEVICE, "hipMemcpy failed during plan upload"};
+}
+
+}  // namespace
+
+void upload_plan(Plan &P)
+{
+    const int S = P.S;
+    P.dev.nodes.assign(S + 1, nullptr);
+    P.dev.cols.assign(S + 1, nullptr);
+    P.dev.px.assign(S + 1, nullptr);
+    P.dev.py.assign(S + 1, nullptr);
+    P.dev.pz.assign(S + 1, nullptr);
+    P.dev.merge_blocks.assign(S + 1, nullptr);
+    P.n_blocks_merge.assign(S + 1, 0);
+    if (P.cfg.device < 0) return;  // host-only plan: geometry and sizes, no device tables
+    if (hipSetDevice(P.cfg.device) != hipSuccess)
+        throw Error{HHFFBP_E_DEVICE, "hipSetDevice failed"};
+    DeviceBuffers &D = P.dev;
+    upload_vec(&D.B, P.Bmat);
+    upload_vec(&D.perm, P.perm);
+    upload_vec(&D.leaf_of_sorted, P.leaf_of_sorted);
+    upload_vec(&D.leaf_centre, P.leaf_centre);
+    upload_vec(&D.pos64, P.positions);
+    if (S == 0) return;
+    int32_t pos_cursor = 0;
+    for (int d = 1; d <= S; ++d) {
+        std::vector<NodeDev> nodes;
+        std::vector<ColEntry> cols;
+        std::vector<BlockItem> blocks;
+        std::vector<double> x, y, z;
+        std::vector<LeafPoint> lpts;
+        int32_t vbase = 0, cbase = 0;
+        for (int32_t ti : P.compact_to_tree[d]) {
+            const HostNode &hn = P.levels[d][ti];
+            const HostLattice &L = hn.lat;
+            NodeDev nd{};
+            nd.x0 = hn.rect.x0;
+            nd.x1 = hn.rect.x1;
+            nd.y0 = hn.rect.y0;
+            nd.y1 = hn.rect.y1;
+            nd.d2 = 4.0 * (nd.x1 - nd.x0) * (nd.x1 - nd.x0) + 4.0 * (nd.y1 - nd.y0) * (nd.y1 - nd.y0);
+            nd.i0 = L.i0;
+            nd.j0 = L.j0;
+            nd.ni = L.ni;
+            nd.nj = L.nj;
+            nd.col_base = cbase;
+            nd.val_base = vbase;
+            nd.npts = (int32_t)L.npts;
+            nd.nchild = 0;
+            for (int a = 0; a < 4; ++a) nd.child[a] = -1;
+            if (d < S) {
+                for (int32_t ch : hn.children) {
+                    const HostNode &cn = P.levels[d + 1][ch];
+                    if (!cn.empty()) nd.child[nd.nchild++] = cn.compact;
+                }
+            }
+            nd.pos_begin = nd.pos_end = 0;
+            if (d == S) {
+                nd.pos_begin = pos_cursor;
+                pos_cursor += (int32_t)hn.members.size();
+                nd.pos_end = pos_cursor;
+            }
+            for (int64_t c = 0; c < (int64_t)L.ni * L.nj; ++c)
+                cols.push_back(ColEntry{(int32_t)L.off[c], L.lo[c], L.hi[c], 0});
+            for (int32_t st = 0; st < nd.npts; st += 256) blocks.push_back(BlockItem{hn.compact, st});
+            if (d < S) {
+                for (int64_t q = 0; q < L.npts; ++q) {
+                    x.push_back(L.xyz[3 * q]);
+                    y.push_back(L.xyz[3 * q + 1]);
+                    z.push_back(L.xyz[3 * q + 2]);
+                }
+            } else {
+                const SubarrayMap map(hn.rect, P.kmin, P.kmax);
+                const double xc = 0.5 * (hn.rect.x0 + hn.rect.x1), yc = 0.5 * (hn.rect.y0 + hn.rect.y1);
+                for (int64_t q = 0; q < L.npts; ++q) {
+                    const double *pq = &L.xyz[3 * q];
+                    if (!std::isfinite(pq[2])) {
+                        // absent point: contributes nothing, evaluates to exactly 0
+                        lpts.push_back(LeafPoint{0.0f, 0.0f, 1.0f, 0, 0.0f, 0.0f, 0.0f, 0});
+                        continue;
+                    }
+                    const double dx = pq[0] - xc, dy = pq[1] - yc, dz = pq[2];
+                    const double rc = std::sqrt(dx * dx + dy * dy + dz * dz);
+                    const double t = (rc - P.R0) / P.dR;
+                    const double fb = std::floor(t);
+                    double w[3], phi;
+                    map.eval(pq, w, &phi, nullptr);
+                    const double ph = 2.0 * P.kc * rc - phi;
+                    LeafPoint lp;
+                    lp.dx = (float)dx;
+                    lp.dy = (float)dy;
+                    lp.dz = (float)dz;
+                    lp.bin = (int32_t)fb;
+                    lp.frac = (float)(t - fb);
+                    lp.pre_re = (float)std::cos(ph);
+                    lp.pre_im = (float)std::sin(ph);
+                    lp.pad = 0;
+                    lpts.push_back(lp);
+                }
+            }
+            vbase += nd.npts;
+            cbase += L.ni * L.nj;
+            nodes.push_back(nd);
+        }
+        upload_vec(&D.nodes[d], nodes);
+        upload_vec(&D.cols[d], cols);
+        if (d < S) {
+            upload_vec(&D.px[d], x);
+            upload_vec(&D.py[d], y);
+            upload_vec(&D.pz[d], z);
+            upload_vec(&D.merge_blocks[d], blocks);
+            P.n_blocks_merge[d] = (int64_t)blocks.size();
+        } else {
+            upload_vec(&D.leafpts, lpts);
+            upload_vec(&D.leaf_blocks, blocks);
+            P.n_blocks_leaf = (int64_t)blocks.size();
+        }
+    }
+}
+
+void release_plan(Plan &P)
+{
+    DeviceBuffers &D = P.dev;
+    auto fr = [](void *&p) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    };
+    fr(D.B);
+    fr(D.perm);
+    fr(D.leaf_of_sorted);
+    fr(D.leaf_centre);
+    fr(D.pos64);
+    fr(D.leafpts);
+    fr(D.leaf_blocks);
+    for (auto *v : {&D.nodes, &D.cols, &D.px, &D.py, &D.pz, &D.merge_blocks})
+        for (auto &p : *v) fr(p);
+}
+
+}  // namespace hh

@@ -1,0 +1,111 @@
+"""C-ABI contract on the CPU: the library loads, exports every declared symbol,
+validates its inputs without touching a GPU, and its host plan (device = -1)
+reproduces the oracle's tree, grids and preimages exactly (independent code)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hhffbp.h")
+
+H = pytest.importorskip("paper_2506_23568_amd")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hhffbp_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = H.lib()
+    names = _declared()
+    assert "hhffbp_plan" in names and "hhffbp_image" in names
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", H.library_path()], capture_output=True,
+                         text=True, check=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}\b", out), n
+
+
+def test_config_default_layout():
+    c = H.binding.default_config()
+    assert (c.mode, c.stages, c.merge_factor, c.interp_taps) == (0, 3, 4, 4)
+    assert list(c.oversample) == [3.0, 3.0, 3.5]
+    assert (c.range_kernel, c.range_taps, c.storage, c.device) == (0, 7, 0, 0)
+    assert c.range_oversample == 2.0 and abs(c.position_slack - 5e-3) < 1e-15
+
+
+def _args(w):
+    return (w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims)
+
+
+@pytest.mark.parametrize("change,status", [
+    (dict(merge_factor=3), -1), (dict(interp_taps=5), -1), (dict(range_taps=11), -1),
+    (dict(oversample=0.5), -1), (dict(storage="f16"), -2), (dict(stages=-1), -1),
+])
+def test_invalid_configurations_are_rejected(small, change, status):
+    kw = dict(device=-1)
+    kw.update(change)
+    with pytest.raises(H.HHFFBPError) as e:
+        H.Plan(*_args(small), **kw)
+    assert e.value.status == status
+
+
+def test_invalid_inputs_are_rejected(small):
+    pos = small.positions.copy()
+    pos[3, 1] = np.nan
+    with pytest.raises(H.HHFFBPError) as e:
+        H.Plan(pos, *_args(small)[1:], device=-1)
+    assert e.value.status == -1
+    behind = small.grid_origin.copy()
+    behind[2] = -0.1
+    with pytest.raises(H.HHFFBPError):
+        H.Plan(small.positions, small.freqs_hz, behind, small.grid_pitch, small.grid_dims, device=-1)
+    with pytest.raises(H.HHFFBPError):
+        H.Plan(small.positions, small.freqs_hz[:1], *_args(small)[2:], device=-1)
+    with pytest.raises(H.HHFFBPError):
+        H.Plan(small.positions, np.full(4, 30e9), *_args(small)[2:], device=-1)
+    L = H.lib()
+    h = ctypes.c_void_p()
+    assert L.hhffbp_plan(None, ctypes.byref(h)) == -1
+    assert b"NULL" in L.hhffbp_last_error()
+
+
+def test_host_only_plan_refuses_image(small):
+    pl = H.Plan(*_args(small), stages=1, device=-1)
+    assert pl.workspace_bytes() > 0
+    L = H.lib()
+    assert L.hhffbp_image(pl._h, 1, None, 1, 256, 1 << 30, None) == -4
+    with pytest.raises(H.HHFFBPError):
+        pl.node_layout(0, 0)
+    with pytest.raises(H.HHFFBPError):
+        pl.node_layout(2, 0)
+
+
+@pytest.mark.parametrize("S,Q,gamma,T", [(1, 4, 3.0, 4), (2, 4, 3.0, 4), (2, 2, (2.5, 2.5, 3.0), 6)])
+def test_host_plan_matches_oracle_plan(small, S, Q, gamma, T):
+    from oracle import plan as OP
+
+    pl = H.Plan(*_args(small), stages=S, merge_factor=Q, oversample=gamma, interp_taps=T, device=-1)
+    op = OP.build_plan(*_args(small), S, Q, gamma, T)
+    info = pl.info()
+    assert info["n_leaves"] == sum(1 for n in op.levels[S] if not n.empty)
+    for d in range(1, S + 1):
+        for i, node in enumerate(op.levels[d]):
+            lay = pl.node_layout(d, i)
+            if node.empty:
+                assert lay["npoints"] == 0
+                continue
+            L = node.lattice
+            assert (lay["i0"], lay["j0"], lay["ni"], lay["nj"]) == (L.i0, L.j0, L.ni, L.nj)
+            assert np.array_equal(lay["l_lo"], L.l_lo) and np.array_equal(lay["l_hi"], L.l_hi)
+            assert np.array_equal(lay["off"], L.off)
+            xyz = pl.node_points(d, i)
+            assert np.array_equal(np.isfinite(xyz[:, 2]), L.valid)
+            assert np.max(np.abs(xyz[L.valid] - L.xyz[L.valid])) < 1e-12

@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path (through the C ABI) against the float64 oracle.
+
+Tolerances
+* direct BP (range-compressed, ES kernel W = 7, U = 2) vs eq. (4): NRMSE <= 1e-5;
+* HHFFBPA vs the oracle HHFFBPA with the same plan choices: NRMSE <= 1e-5 over
+  the image and over every intermediate compressed subimage;
+* HHFFBPA vs eq. (4): <= -30 dB NRMSE, and the same peak voxel for isolated
+  point targets.
+The error budget behind 1e-5: range-profile interpolation ~1e-6 (ES kernel),
+float32 phase of a distance difference of <= 3 cm ~2e-6 rad, float32 storage
+and accumulation ~1e-6 per stage.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+H = pytest.importorskip("paper_2506_23568_amd")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+GAMMA = (3.0, 3.0, 3.5)   # the library default and the benchmark's setting
+TAPS = 4
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def oracle_small(small):
+    from oracle import hhffbp as OH
+    from workloads import voxel_centres
+    vox = voxel_centres(small.grid_origin, small.grid_pitch, small.grid_dims)
+    return OH.direct_bp(small.positions, small.freqs_hz, small.echoes, vox).reshape(small.grid_dims)
+
+
+def _args(w):
+    return (w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims)
+
+
+def _nrmse(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def _run(torch, plan, w, positions=None, workspace=None):
+    ech = torch.from_numpy(w.echoes.astype(np.complex64)).cuda()
+    pos = None if positions is None else torch.from_numpy(np.ascontiguousarray(positions)).cuda()
+    img = plan.image(ech, positions=pos, workspace=workspace)
+    torch.cuda.synchronize()
+    return img.cpu().numpy().astype(np.complex128)
+
+
+def _isolated_peaks(w, ref, margin=2, min_sep=0.01):
+    """Voxel indices of isolated, well-separated point targets inside the grid."""
+    from workloads import grid_box
+    lo, hi = grid_box(w.grid_origin, w.grid_pitch, w.grid_dims)
+    pts = w.target_pos
+    out = []
+    for i, p in enumerate(pts):
+        if np.any(p < lo + margin * w.grid_pitch) or np.any(p > hi - margin * w.grid_pitch):
+            continue
+        d = np.linalg.norm(pts - p, axis=1)
+        d[i] = np.inf
+        if d.min() < min_sep:
+            continue
+        c = np.rint((p - w.grid_origin) / w.grid_pitch).astype(int)
+        sl = tuple(slice(max(0, c[a] - 3), c[a] + 4) for a in range(3))
+        blk = np.abs(ref[sl])
+        flat = np.sort(blk.ravel())
+        if flat[-1] - flat[-2] <= 1e-3 * flat[-1]:
+            continue
+        out.append((sl, np.unravel_index(np.argmax(blk), blk.shape)))
+    return out
+
+
+def test_direct_rc_small_vs_eq4(torch, small, oracle_small):
+    _say("direct_rc, config small, ES W=7 U=2")
+    pl = H.Plan(*_args(small), mode="direct_rc")
+    img = _run(torch, pl, small)
+    e = _nrmse(img, oracle_small)
+    _say(f"  NRMSE {e:.3e}")
+    assert e <= 1e-5
+
+
+def test_direct_linear_fast_mode_small(torch, small, oracle_small):
+    _say("direct_rc linear U=8, config small")
+    pl = H.Plan(*_args(small), mode="direct_rc", range_kernel="linear", range_oversample=8.0)
+    e = _nrmse(_run(torch, pl, small), oracle_small)
+    _say(f"  NRMSE {e:.3e} ({20 * np.log10(e):.1f} dB)")
+    assert 20 * np.log10(e) <= -30.0
+
+
+def test_factorized_stage_zero_is_direct(torch, small):
+    a = _run(torch, H.Plan(*_args(small), stages=0), small)
+    b = _run(torch, H.Plan(*_args(small), mode="direct_rc"), small)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("S,Q", [(1, 4), (2, 4), (2, 2)])
+def test_hhffbp_small_vs_oracle(torch, small, oracle_small, S, Q):
+    from oracle import hhffbp as OH
+    from oracle import plan as OP
+    _say(f"hhffbp config small S={S} Q={Q}")
+    op = OP.build_plan(*_args(small), S, Q, GAMMA, TAPS)
+    ref, vals = OH.image(op, small.echoes, small.positions, keep=True)
+    pl = H.Plan(*_args(small), stages=S, merge_factor=Q, oversample=GAMMA, interp_taps=TAPS)
+    ws = pl._workspace(torch)
+    img = _run(torch, pl, small, workspace=ws)
+    e = _nrmse(img, ref)
+    e_bp = _nrmse(img, oracle_small)
+    _say(f"  vs oracle HHFFBPA {e:.3e}; vs eq.4 {20 * np.log10(e_bp):.1f} dB")
+    # every intermediate compressed subimage
+    worst = 0.0
+    for (d, i), v in vals.items():
+        g = pl.workspace_view(ws, d, i).cpu().numpy().astype(np.complex128)
+        worst = max(worst, _nrmse(g, v))
+    _say(f"  worst stage NRMSE {worst:.3e}")
+    assert e <= 1e-5
+    assert worst <= 1e-5
+    assert 20 * np.log10(e_bp) <= -30.0
+    for sl, pk in _isolated_peaks(small, oracle_small):
+        assert np.unravel_index(np.argmax(np.abs(img[sl])), img[sl].shape) == pk
+
+
+def test_repeatable_and_workspace_checks(torch, small):
+    pl = H.Plan(*_args(small), stages=2)
+    a = _run(torch, pl, small)
+    b = _run(torch, pl, small)
+    assert np.array_equal(a, b)
+    ech = torch.from_numpy(small.echoes.astype(np.complex64)).cuda()
+    small_ws = torch.empty(256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(H.HHFFBPError) as e:
+        pl.image(ech, workspace=small_ws)
+    assert e.value.status == -5
+
+
+def test_positions_override(torch, small):
+    """Backprojecting with device positions: the planned ones give the same
+    image; moved ones (frozen plan) match the oracle with the moved positions."""
+    from oracle import hhffbp as OH
+    from oracle import plan as OP
+    pl = H.Plan(*_args(small), stages=2, oversample=GAMMA, interp_taps=TAPS)
+    a = _run(torch, pl, small)
+    b = _run(torch, pl, small, positions=small.positions)
+    assert np.array_equal(a, b)
+    t = np.arange(small.n_pos)
+    moved = small.positions + 1e-3 * np.column_stack(
+        [np.sin(t / 97.0), np.cos(t / 61.0), 0.5 * np.sin(t / 41.0)])
+    c = _run(torch, pl, small, positions=moved)
+    op = OP.build_plan(*_args(small), 2, 4, GAMMA, TAPS)
+    ref = OH.image(op, small.echoes, moved)
+    e = _nrmse(c, ref)
+    _say(f"  moved positions vs oracle {e:.3e}")
+    assert e <= 1e-5
+
+
+def test_mid_config_full_size(torch):
+    """The benchmark's launch configuration: 16384 positions, 64 f, 128x128x64
+    voxels, S = 3, Q = 4.  GPU direct BP is pinned to eq. (4) on 1024 sampled
+    voxels (<= 1e-5) and then serves as the full-grid reference for the
+    HHFFBPA error (<= -30 dB) and peak positions; where the stored oracle
+    HHFFBPA exists the same voxels are compared with it (<= 1e-5)."""
+    from oracle import hhffbp as OH
+    from workloads import make_config, voxel_centres
+    _say("mid config: synthesising echoes")
+    w = make_config(1)
+    vox = voxel_centres(w.grid_origin, w.grid_pitch, w.grid_dims)
+    rng = np.random.default_rng(7)
+    samp = rng.choice(vox.shape[0], 1024, replace=False)
+    _say("mid config: oracle eq.4 on 1024 voxels")
+    ref_bp = OH.direct_bp(w.positions, w.freqs_hz, w.echoes, vox[samp])
+    _say("mid config: GPU")
+    pl = H.Plan(*_args(w), stages=3, merge_factor=4, oversample=GAMMA, interp_taps=TAPS)
+    img = _run(torch, pl, w)
+    pd = H.Plan(*_args(w), mode="direct_rc")
+    img_d = _run(torch, pd, w)
+    e_d = _nrmse(img_d.ravel()[samp], ref_bp)
+    e_h = _nrmse(img, img_d)
+    _say(f"  direct_rc vs eq.4 (sampled) {e_d:.3e}; hhffbp vs direct (full grid) "
+         f"{20 * np.log10(e_h):.1f} dB")
+    assert e_d <= 1e-5
+    assert 20 * np.log10(e_h) <= -30.0
+    peaks = _isolated_peaks(w, img_d)
+    _say(f"  {len(peaks)} isolated point targets checked")
+    assert len(peaks) >= 10
+    for sl, pk in peaks:
+        assert np.unravel_index(np.argmax(np.abs(img[sl])), img[sl].shape) == pk
+    gold = os.path.join(GOLDEN, "mid_oracle_hhffbp.npz")
+    if os.path.exists(gold):
+        g = np.load(gold)
+        assert tuple(g["gamma"]) == GAMMA and int(g["taps"]) == TAPS
+        e_o = _nrmse(img.ravel()[g["index"]], g["hhffbp"])
+        _say(f"  hhffbp vs stored oracle HHFFBPA {e_o:.3e}")
+        assert e_o <= 1e-5
