@@ -55,9 +55,10 @@ __device__ __forceinline__ void range_weights(float x, float beta_log2e, float *
         constexpr float s = 2.0f / W;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            const float z = ((float)k + 1.0f - 0.5f * W - x) * s;
-            const float a = fmaxf(1.0f - z * z, 0.0f);
-            w[k] = exp2_f(beta_log2e * (fast_sqrt(a) - 1.0f));
+            // z = (k + 1 - W/2 - x) (2/W) in [-1, 1];  w = exp(beta (sqrt(1 - z^2) - 1))
+            const float z = fmaf(-s, x, ((float)k + 1.0f - 0.5f * W) * s);
+            const float a = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+            w[k] = exp2_f(fmaf(beta_log2e, fast_sqrt(a), -beta_log2e));
         }
     }
 }
@@ -180,6 +181,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
     const bool active = p < nd.npts;
     LeafPoint q = active ? pts[nd.val_base + p] : LeafPoint{0, 0, 1, 0, 0, 0, 0, 0};
     const float Rc = fast_sqrt(q.dx * q.dx + q.dy * q.dy + q.dz * q.dz);
+    const float frac_w = q.frac - 0.5f * W;  // tau = t - W/2 relative to the point's bin
+    const int bin1 = q.bin + 1;
     float acc_re = 0.0f, acc_im = 0.0f;
     for (int c0 = nd.pos_begin; c0 < nd.pos_end; c0 += chunk) {
         const int n = min(chunk, nd.pos_end - c0);
@@ -195,18 +198,19 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
                 const float R = fast_sqrt(ex * ex + ey * ey + ez * ez);
                 const float num = d.w - 2.0f * (q.dx * d.x + q.dy * d.y + q.dz * d.z);
                 const float dR = num * fast_rcp(R + Rc);
-                const float tau = q.frac + dR * inv_dR - 0.5f * W;
+                const float tau = fmaf(dR, inv_dR, frac_w);
                 const float fl = floorf(tau);
                 const float x = tau - fl;
-                const int r = q.bin + (int)fl + 1;
+                // the plan's range window holds every tap; the clamp only keeps
+                // positions moved beyond the planned slack inside the profile
+                const int r = min(max(bin1 + (int)fl, 0), Nr - W);
                 float w[W];
                 range_weights<KERNEL, W>(x, beta_log2e, w);
-                const float2 *pr = s_prof + i * Nr;
+                const float2 *pr = s_prof + i * Nr + r;
                 float gre = 0.0f, gim = 0.0f;
 #pragma unroll
                 for (int k = 0; k < W; ++k) {
-                    const int rr = r + k;
-                    const float2 v = (rr >= 0 && rr < Nr) ? pr[rr] : make_float2(0.0f, 0.0f);
+                    const float2 v = pr[k];
                     gre = fmaf(w[k], v.x, gre);
                     gim = fmaf(w[k], v.y, gim);
                 }
@@ -415,8 +419,8 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
 struct StagedPos {
     float dx, dy, dz;  // p' - ref
     float rref;        // |p' - ref| (float32, as a denominator only)
-    int32_t bin;
-    float frac;
+    int32_t bin;       // floor((R_ref - R0)/dR) + 1
+    float frac;        // fractional part minus W/2
     float car_re, car_im;
 };
 
@@ -461,8 +465,8 @@ __global__ __launch_bounds__(kBlock) void k_direct_bp(
             sp.dy = (float)dy;
             sp.dz = (float)dz;
             sp.rref = (float)rr;
-            sp.bin = (int)fb;
-            sp.frac = (float)(t - fb);
+            sp.bin = (int)fb + 1;                   // first tap is floor(t - W/2) + 1
+            sp.frac = (float)(t - fb) - 0.5f * W;   // tau = t - W/2 relative to bin
             sp.car_re = (float)cs;
             sp.car_im = (float)sn;
             s_pos[threadIdx.x] = sp;
@@ -477,18 +481,17 @@ __global__ __launch_bounds__(kBlock) void k_direct_bp(
                 const float R = fast_sqrt(qx * qx + qy * qy + qz * qz);
                 const float num = e2 - 2.0f * (ex * sp.dx + ey * sp.dy + ez * sp.dz);
                 const float dr = num * fast_rcp(R + sp.rref);
-                const float tau = sp.frac + dr * inv_dR - 0.5f * W;
+                const float tau = fmaf(dr, inv_dR, sp.frac);
                 const float fl = floorf(tau);
                 const float x = tau - fl;
-                const int r = sp.bin + (int)fl + 1;
+                const int r = min(max(sp.bin + (int)fl, 0), Nr - W);
                 float w[W];
                 range_weights<KERNEL, W>(x, beta_log2e, w);
-                const float2 *pr = s_prof + i * Nr;
+                const float2 *pr = s_prof + i * Nr + r;
                 float gre = 0.0f, gim = 0.0f;
 #pragma unroll
                 for (int k = 0; k < W; ++k) {
-                    const int rr = r + k;
-                    const float2 v = (rr >= 0 && rr < Nr) ? pr[rr] : make_float2(0.0f, 0.0f);
+                    const float2 v = pr[k];
                     gre = fmaf(w[k], v.x, gre);
                     gim = fmaf(w[k], v.y, gim);
                 }
