@@ -112,7 +112,8 @@ hhffbp_status hhffbp_plan(const hhffbp_config *cfg, hhffbp_plan_t *out);
  * the plan may still be running on any stream. */
 void hhffbp_plan_destroy(hhffbp_plan_t plan);
 
-/* Bytes of device workspace that hhffbp_image (with_backward = 0) needs. */
+/* Bytes of device workspace that hhffbp_image (with_backward = 0) or
+ * hhffbp_backward (with_backward = 1) needs. */
 hhffbp_status hhffbp_workspace_bytes(hhffbp_plan_t plan, int32_t with_backward,
                                      size_t *bytes);
 
@@ -132,6 +133,28 @@ hhffbp_status hhffbp_workspace_bytes(hhffbp_plan_t plan, int32_t with_backward,
  */
 hhffbp_status hhffbp_image(hhffbp_plan_t plan, const void *echoes, const double *positions,
                            void *image, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Gradients of a real loss L(image) with respect to the echoes and the antenna
+ * positions (autofocus of handheld motion errors, Sec. I), with the plan frozen:
+ * the tree and grids stay as planned and only the level-1 backprojection
+ * depends on the positions.  The image is linear in the echoes, f = A s, so
+ *     grad_echoes    = A^H grad_image                 (the transposed HHFFBPA)
+ *     grad_positions = Re sum_q conj(G_q) d f'_q / d p'   (G: level-1 cotangents)
+ * with the complex convention grad = dL/dRe + j dL/dIm.
+ *   echoes          device, as for hhffbp_image (needed for grad_positions)
+ *   positions       device float64 [n_pos][3] used by the forward, or NULL
+ *   grad_image      device complex64 [nx][ny][nz]
+ *   grad_echoes     device complex64 [n_pos][n_freq] or NULL, overwritten
+ *   grad_positions  device float64 [n_pos][3] or NULL, overwritten
+ *   workspace       at least hhffbp_workspace_bytes(plan, 1) bytes, 256-B aligned
+ * The transposed merges scatter with float atomics, so results may differ in
+ * the last bits between calls.  Needs a factorised plan with stages >= 1
+ * (HHFFBP_E_UNSUPPORTED otherwise).  Errors as for hhffbp_image.
+ */
+hhffbp_status hhffbp_backward(hhffbp_plan_t plan, const void *echoes, const double *positions,
+                              const void *grad_image, void *grad_echoes, double *grad_positions,
+                              void *workspace, size_t ws_bytes, void *stream);
 
 /* Read-only description of a plan, for sizing and work accounting. */
 typedef struct {

@@ -9,4 +9,10 @@ from .binding import (  # noqa: F401
     Plan, HHFFBPError, lib, library_path, STATUS, MODES, RANGE_KERNELS, STORAGE,
 )
 
-__all__ = ["Plan", "HHFFBPError", "lib", "library_path"]
+__all__ = ["Plan", "HHFFBPError", "lib", "library_path", "hhffbp_image"]
+
+
+def hhffbp_image(echoes, positions, plan):
+    """Differentiable HHFFBPA image (see autograd.HHFFBPFunction)."""
+    from .autograd import hhffbp_image as _f
+    return _f(echoes, positions, plan)

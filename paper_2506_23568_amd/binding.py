@@ -73,6 +73,8 @@ def lib():
         L.hhffbp_workspace_bytes.restype = ctypes.c_int
         L.hhffbp_image.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.hhffbp_image.restype = ctypes.c_int
+        L.hhffbp_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.hhffbp_backward.restype = ctypes.c_int
         L.hhffbp_get_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.hhffbp_get_plan_info.restype = ctypes.c_int
         L.hhffbp_node_layout.argtypes = [vp, i32, i32, ctypes.POINTER(i32 * 4),
@@ -200,8 +202,13 @@ class Plan:
             _check(lib().hhffbp_node_points(self._h, depth, index, xyz.ctypes.data))
         return xyz
 
-    def _workspace(self, torch):
-        nb = self.workspace_bytes()
+    def workspace_bytes_backward(self):
+        n = ctypes.c_size_t()
+        _check(lib().hhffbp_workspace_bytes(self._h, 1, ctypes.byref(n)))
+        return n.value
+
+    def _workspace(self, torch, backward=False):
+        nb = self.workspace_bytes_backward() if backward else self.workspace_bytes()
         if self._ws is None or self._ws.numel() < nb:
             self._ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
         return self._ws
@@ -230,6 +237,39 @@ class Plan:
         _check(lib().hhffbp_image(self._h, echoes.data_ptr(), pptr, out.data_ptr(),
                                   workspace.data_ptr(), workspace.numel(), stream))
         return out
+
+    def backward(self, echoes, grad_image, positions=None, want_echoes=True, want_positions=True,
+                 workspace=None, stream=None):
+        """(grad_echoes complex64 [n_pos, n_freq] | None, grad_positions float64 [n_pos, 3] | None)."""
+        import torch
+
+        if grad_image.dtype != torch.complex64 or tuple(grad_image.shape) != self.dims:
+            raise TypeError("grad_image must be complex64 with the image's shape")
+        grad_image = grad_image.contiguous()
+        dev = grad_image.device
+        ge = torch.empty((self.config.n_pos, self.config.n_freq), dtype=torch.complex64,
+                         device=dev) if want_echoes else None
+        gp = torch.empty((self.config.n_pos, 3), dtype=torch.float64,
+                         device=dev) if want_positions else None
+        eptr = None
+        if echoes is not None:
+            if echoes.dtype != torch.complex64 or tuple(echoes.shape) != (self.config.n_pos, self.config.n_freq):
+                raise TypeError("echoes must be complex64 (n_pos, n_freq)")
+            echoes = echoes.contiguous()
+            eptr = echoes.data_ptr()
+        pptr = None
+        if positions is not None:
+            positions = positions.contiguous()
+            pptr = positions.data_ptr()
+        if workspace is None:
+            workspace = self._workspace(torch, backward=True)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev).cuda_stream
+        _check(lib().hhffbp_backward(self._h, eptr, pptr, grad_image.data_ptr(),
+                                     ge.data_ptr() if ge is not None else None,
+                                     gp.data_ptr() if gp is not None else None,
+                                     workspace.data_ptr(), workspace.numel(), stream))
+        return ge, gp
 
     def profile_begin(self, max_calls):
         _check(lib().hhffbp_profile_begin(self._h, int(max_calls)))

@@ -91,8 +91,36 @@ void hhffbp_plan_destroy(hhffbp_plan_t plan)
 hhffbp_status hhffbp_workspace_bytes(hhffbp_plan_t plan, int32_t with_backward, size_t *bytes)
 {
     if (!plan || !bytes) return fail(HHFFBP_E_INVALID, "hhffbp_workspace_bytes: NULL argument");
-    if (with_backward) return fail(HHFFBP_E_UNSUPPORTED, "backward workspace not built");
-    *bytes = plan->plan.ws_total;
+    *bytes = with_backward ? plan->plan.ws_total_bwd : plan->plan.ws_total;
+    return HHFFBP_OK;
+}
+
+hhffbp_status hhffbp_backward(hhffbp_plan_t plan, const void *echoes, const double *positions,
+                              const void *grad_image, void *grad_echoes, double *grad_positions,
+                              void *workspace, size_t ws_bytes, void *stream)
+{
+    if (!plan || !grad_image) return fail(HHFFBP_E_INVALID, "hhffbp_backward: NULL argument");
+    const hh::Plan &P = plan->plan;
+    if (P.cfg.device < 0) return fail(HHFFBP_E_DEVICE, "hhffbp_backward: host-only plan");
+    if (P.S < 1)
+        return fail(HHFFBP_E_UNSUPPORTED, "hhffbp_backward: needs a factorised plan with stages >= 1");
+    if (!grad_echoes && !grad_positions) return HHFFBP_OK;
+    if (grad_positions && !echoes)
+        return fail(HHFFBP_E_INVALID, "hhffbp_backward: the position gradient needs the echoes");
+    if (!workspace || ws_bytes < P.ws_total_bwd)
+        return fail(HHFFBP_E_WORKSPACE, "hhffbp_backward: workspace missing or smaller than " +
+                                            std::to_string(P.ws_total_bwd) + " bytes");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(HHFFBP_E_WORKSPACE, "hhffbp_backward: workspace must be 256-byte aligned");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(HHFFBP_E_DEVICE, "hipGetDevice failed");
+    if (cur != P.cfg.device && hipSetDevice(P.cfg.device) != hipSuccess)
+        return fail(HHFFBP_E_DEVICE, "hipSetDevice failed");
+    hhffbp_status st = hh::launch_backward(P, echoes, positions, grad_image, grad_echoes,
+                                           grad_positions, (char *)workspace, (hipStream_t)stream);
+    if (cur != P.cfg.device) (void)hipSetDevice(cur);
+    if (st != HHFFBP_OK) return fail(st, std::string("hhffbp_backward: launch failed: ") +
+                                             hipGetErrorString(hipGetLastError()));
     return HHFFBP_OK;
 }
 

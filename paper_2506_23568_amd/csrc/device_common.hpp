@@ -1,0 +1,178 @@
+// Device helpers shared by the forward and adjoint kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hhffbp_internal.hpp"
+
+namespace hh {
+namespace dev {
+
+constexpr int kBlock = 256;
+constexpr int kPosChunkMax = 16;
+constexpr size_t kLdsBudget = 20 * 1024;  // dynamic LDS per block
+
+// Positions staged per LDS chunk with their profiles.  Small chunks keep the
+// LDS per block near 12 KB so that eight 256-lane blocks fit on a CU; the
+// inner loop's dependency chain (sqrt, rcp, gather, sincos) needs that many
+// waves to hide its latency.
+inline int pos_chunk(int64_t Nr, size_t per_pos_header)
+{
+    const size_t per = per_pos_header + (size_t)Nr * sizeof(float2);
+    int c = (int)(kLdsBudget / per);
+    return c > kPosChunkMax ? kPosChunkMax : (c < 1 ? 1 : c);
+}
+
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float exp2_f(float x) { return __builtin_amdgcn_exp2f(x); }
+// v_sin_f32 / v_cos_f32 take their argument in turns; callers reduce it to [-0.5, 0.5].
+__device__ __forceinline__ float sin_turns(float t) { return __builtin_amdgcn_sinf(t); }
+__device__ __forceinline__ float cos_turns(float t) { return __builtin_amdgcn_cosf(t); }
+
+// Weights of the W range taps r_first .. r_first+W-1 for fractional offset x in [0, 1)
+// of tau = t - W/2 (t the continuous bin coordinate, r_first = floor(tau) + 1).
+template <int KERNEL, int W>
+__device__ __forceinline__ void range_weights(float x, float beta_log2e, float *w)
+{
+    if constexpr (KERNEL == HHFFBP_RANGE_LINEAR) {
+        w[0] = 1.0f - x;
+        w[1] = x;
+    } else {
+        constexpr float s = 2.0f / W;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            // z = (k + 1 - W/2 - x) (2/W) in [-1, 1];  w = exp(beta (sqrt(1 - z^2) - 1))
+            const float z = fmaf(-s, x, ((float)k + 1.0f - 0.5f * W) * s);
+            const float a = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+            w[k] = exp2_f(fmaf(beta_log2e, fast_sqrt(a), -beta_log2e));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Child coordinates and SDC phase at a point, float64 (Sec. III, eq. uvw_xyz,
+// eq. sdc_phi); the continuous lattice coordinate t = gamma (u, v, n) is split
+// into an integer base floor(t) and a float32 fraction.
+struct ChildCoord {
+    int bi, bj, bl;
+    float fu, fv, fn;
+    double phi;
+};
+
+__device__ __forceinline__ double phi_only(const NodeDev &c, double x, double y, double z,
+                                           double kmin, double kmax)
+{
+    const double zz = z * z;
+    const double dx0 = x - c.x0, dx1 = x - c.x1, dy0 = y - c.y0, dy1 = y - c.y1;
+    const double r = sqrt(dx0 * dx0 + dy0 * dy0 + zz) + sqrt(dx0 * dx0 + dy1 * dy1 + zz) +
+                     sqrt(dx1 * dx1 + dy0 * dy0 + zz) + sqrt(dx1 * dx1 + dy1 * dy1 + zz);
+    return 0.25 * (kmax * sqrt(r * r - c.d2) + kmin * r);
+}
+
+__device__ __forceinline__ ChildCoord child_coord(const NodeDev &c, double x, double y, double z,
+                                                  double gu, double gv, double gn, double kmin,
+                                                  double kmax)
+{
+    const double zz = z * z;
+    const double cx = fmin(fmax(x, c.x0), c.x1), cy = fmin(fmax(y, c.y0), c.y1);
+    const double dx0 = x - c.x0, dx1 = x - c.x1, dy0 = y - c.y0, dy1 = y - c.y1;
+    const double ex = x - cx, ey = y - cy;
+    const double ru0 = sqrt(dx0 * dx0 + ey * ey + zz), ru1 = sqrt(dx1 * dx1 + ey * ey + zz);
+    const double rv0 = sqrt(ex * ex + dy0 * dy0 + zz), rv1 = sqrt(ex * ex + dy1 * dy1 + zz);
+    const double r = sqrt(dx0 * dx0 + dy0 * dy0 + zz) + sqrt(dx0 * dx0 + dy1 * dy1 + zz) +
+                     sqrt(dx1 * dx1 + dy0 * dy0 + zz) + sqrt(dx1 * dx1 + dy1 * dy1 + zz);
+    const double s = sqrt(r * r - c.d2);
+    const double tu = gu * (kmax / kPi) * (ru0 - ru1);
+    const double tv = gv * (kmax / kPi) * (rv0 - rv1);
+    const double tn = gn * (kmax * s - kmin * r) * (0.25 / kPi);
+    ChildCoord o;
+    const double fu = floor(tu + kStencilEps), fv = floor(tv + kStencilEps),
+                 fn = floor(tn + kStencilEps);
+    o.bi = (int)fu;
+    o.bj = (int)fv;
+    o.bl = (int)fn;
+    o.fu = (float)(tu - fu);
+    o.fv = (float)(tv - fv);
+    o.fn = (float)(tn - fn);
+    o.phi = 0.25 * (kmax * s + kmin * r);
+    return o;
+}
+
+// Lagrange weights on nodes -T/2+1 .. T/2 at x in [0, 1).
+template <int T>
+__device__ __forceinline__ void lagrange(float x, float *w)
+{
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+        float num = 1.0f, den = 1.0f;
+        const float na = (float)(a - T / 2 + 1);
+#pragma unroll
+        for (int m = 0; m < T; ++m) {
+            if (m == a) continue;
+            const float nm = (float)(m - T / 2 + 1);
+            num *= (x - nm);
+            den *= (na - nm);
+        }
+        w[a] = num / den;
+    }
+}
+
+// Separable T^3 interpolation of a compressed child subimage (missing points are 0).
+template <int T>
+__device__ __forceinline__ float2 interp_child(const NodeDev &c, const ColEntry *__restrict__ cols,
+                                               const float2 *__restrict__ vals,
+                                               const ChildCoord &g)
+{
+    float wu[T], wv[T], wn[T];
+    lagrange<T>(g.fu, wu);
+    lagrange<T>(g.fv, wv);
+    lagrange<T>(g.fn, wn);
+    float are = 0.0f, aim = 0.0f;
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+        const int ci = g.bi + a - T / 2 + 1 - c.i0;
+        if ((unsigned)ci >= (unsigned)c.ni) continue;
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            const int cj = g.bj + b - T / 2 + 1 - c.j0;
+            if ((unsigned)cj >= (unsigned)c.nj) continue;
+            const ColEntry e = cols[c.col_base + ci * c.nj + cj];
+            const float2 *colv = vals + c.val_base + e.off - e.lo;
+            float sre = 0.0f, sim = 0.0f;
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                const int l = g.bl + k - T / 2 + 1;
+                if (l >= e.lo && l <= e.hi) {
+                    const float2 v = colv[l];
+                    sre = fmaf(wn[k], v.x, sre);
+                    sim = fmaf(wn[k], v.y, sim);
+                }
+            }
+            const float wab = wu[a] * wv[b];
+            are = fmaf(wab, sre, are);
+            aim = fmaf(wab, sim, aim);
+        }
+    }
+    return make_float2(are, aim);
+}
+
+__device__ __forceinline__ void phase_mac(float2 v, double phase, float &are, float &aim)
+{
+    double t = phase * (0.5 / kPi);
+    t -= rint(t);
+    const float tf = (float)t;
+    const float sn = sin_turns(tf), cs = cos_turns(tf);
+    are = fmaf(v.x, cs, fmaf(-v.y, sn, are));
+    aim = fmaf(v.x, sn, fmaf(v.y, cs, aim));
+}
+
+struct GeoParams {
+    double gu, gv, gn, kmin, kmax;
+};
+
+
+}  // namespace dev
+}  // namespace hh

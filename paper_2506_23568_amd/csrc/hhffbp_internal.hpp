@@ -91,6 +91,9 @@ struct DeviceBuffers {
     std::vector<void *> px, py, pz; // per depth < S: float64 SoA grid points
     void *leafpts = nullptr;        // LeafPoint[] of depth S
     void *leaf_blocks = nullptr;    // BlockItem[]
+    void *adj_blocks = nullptr;     // BlockItem[]: (leaf, first sorted position of 16)
+    void *Bd = nullptr;             // range-derivative matrix (rows x j 2 k_f), [2 Nf][2 Nr]
+    void *Badj = nullptr;           // conj-transposed DFT matrix, [2 Nr][2 Nf]
     std::vector<void *> merge_blocks;  // per depth 1..S-1: BlockItem[]
 };
 
@@ -106,6 +109,8 @@ struct Plan {
     double U = 2, dR = 0, R0 = 0, beta = 0;
     int64_t Nr = 0;
     std::vector<float> Bmat;  // [2 Nf][2 Nr]
+    std::vector<float> Bdmat; // [2 Nf][2 Nr]
+    std::vector<float> Badjmat; // [2 Nr][2 Nf]
     // tree
     std::vector<std::vector<HostNode>> levels;
     std::vector<int32_t> perm;           // sorted -> caller index
@@ -115,10 +120,11 @@ struct Plan {
     std::vector<std::vector<int32_t>> compact_to_tree;  // per depth
     std::vector<int64_t> depth_points;   // per depth
     std::vector<int64_t> n_blocks_merge; // per depth
-    int64_t n_blocks_leaf = 0;
+    int64_t n_blocks_leaf = 0, n_blocks_adj = 0;
     int64_t leaf_pairs = 0, merge_pairs = 0, final_pairs = 0;
     // workspace layout (bytes)
     size_t ws_prof = 0, ws_posoff = 0, ws_total = 0;
+    size_t ws_gprof = 0, ws_gpos = 0, ws_gmax = 0, ws_total_bwd = 0;  // backward additions
     std::vector<size_t> ws_vals;         // per depth
     DeviceBuffers dev;
     double plan_seconds = 0;
@@ -140,7 +146,13 @@ void build_plan_host(Plan &plan);
 void upload_plan(Plan &plan);
 void release_plan(Plan &plan);
 
-// Launchers (kernels.hip).
+// Launchers (kernels.hip, kernels_adjoint.hip).
+hipError_t launch_prep(const Plan &P, const double *pos64, float4 *posoff, hipStream_t st);
+hipError_t launch_rc_gemm(const float *A, const int32_t *a_perm, int M, int K, const float *B,
+                          int N, float *C, const int32_t *c_perm, hipStream_t st);
+hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *positions,
+                              const void *grad_image, void *grad_echoes, double *grad_positions,
+                              char *ws, hipStream_t st);
 // `events`, when non-null, holds stage_names().size() + 1 events recorded on
 // `stream` before the first stage and after each stage.
 hhffbp_status launch_image(const Plan &plan, const void *echoes, const double *positions,

@@ -1,0 +1,612 @@
+// gfx950 adjoint kernels of HHFFBPA: echo and antenna-position gradients.
+//
+// The image is linear in the echoes, f = F M_{S-1} .. M_1 L R s (final stage,
+// merges, level-1 BP, range compression).  For an image cotangent g
+// (dL/dRe f + j dL/dIm f) the backward pass forms
+//   grad_s  = R^H L^H M_1^H .. F^H g
+//   grad_p' = Re sum_q conj(G_q) d f'_q / d p'     (G = leaf-level cotangent)
+// with the plan frozen: only the level-1 BP depends on the positions.
+//
+//   k_zero        clear the cotangent arrays (a kernel, never a memset)
+//   k_final_adj   F^H: scatter voxel cotangents into depth-1 grids (float atomics)
+//   k_merge_adj   M_d^H: scatter parent-grid cotangents into the children
+//   k_leaf_adj    L^H and the position gradient: one block per 16 positions of a
+//                 leaf, looping over all its grid points; the range-profile
+//                 cotangents accumulate in LDS and the position gradients in
+//                 registers, so each output is written exactly once
+//   k_pos_out     float32 partials -> float64 gradients in caller order
+// R^H is k_rc_gemm with the conjugate-transposed DFT matrix.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "device_common.hpp"
+#include "hhffbp_internal.hpp"
+
+namespace hh {
+namespace {
+using namespace dev;
+
+constexpr int kAdjPos = 16;
+constexpr size_t kLdsLimit = 64 * 1024;  // dynamic LDS available without opting in
+
+__global__ __launch_bounds__(kBlock) void k_zero(float4 *__restrict__ p, int64_t n4)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4;
+         i += (int64_t)gridDim.x * kBlock)
+        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Transpose of interp_child: grad[tap] += w(tap) * (gre + j gim).
+template <int T>
+__device__ __forceinline__ void scatter_child(const NodeDev &c, const ColEntry *__restrict__ cols,
+                                              float2 *__restrict__ grad, const ChildCoord &g,
+                                              float gre, float gim)
+{
+    float wu[T], wv[T], wn[T];
+    lagrange<T>(g.fu, wu);
+    lagrange<T>(g.fv, wv);
+    lagrange<T>(g.fn, wn);
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+        const int ci = g.bi + a - T / 2 + 1 - c.i0;
+        if ((unsigned)ci >= (unsigned)c.ni) continue;
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            const int cj = g.bj + b - T / 2 + 1 - c.j0;
+            if ((unsigned)cj >= (unsigned)c.nj) continue;
+            const ColEntry e = cols[c.col_base + ci * c.nj + cj];
+            float2 *colg = grad + c.val_base + e.off - e.lo;
+            const float wab = wu[a] * wv[b];
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                const int l = g.bl + k - T / 2 + 1;
+                if (l >= e.lo && l <= e.hi) {
+                    const float w = wab * wn[k];
+                    unsafeAtomicAdd(&colg[l].x, w * gre);
+                    unsafeAtomicAdd(&colg[l].y, w * gim);
+                }
+            }
+        }
+    }
+}
+
+// (gre + j gim) = v exp(-j phase)
+__device__ __forceinline__ void rotate_back(float2 v, double phase, float &gre, float &gim)
+{
+    double t = phase * (0.5 / kPi);
+    t -= rint(t);
+    const float tf = (float)t;
+    const float sn = sin_turns(tf), cs = cos_turns(tf);
+    gre = v.x * cs + v.y * sn;
+    gim = v.y * cs - v.x * sn;
+}
+
+// --- block-aggregated scatter --------------------------------------------
+// The stencils of one block's points cover a small box of the child's (i, j, l)
+// index space.  The block accumulates its contributions there in LDS (int32
+// fixed point: float LDS atomics are serialised on gfx950, integer ones are not)
+// and then adds each non-zero box entry to the child's grid with one float
+// atomic.  The fixed-point scale 2^31 / (1.3 sum |g|) over the block cannot
+// overflow (a Lagrange weight product is below 1.3 and each point adds to a box
+// entry at most once) and resolves every contribution to ~1.5e-7 of itself.
+constexpr int kBoxCap = 4096;
+
+struct BoxShared {
+    int mn[3], mx[3];
+    float gsum;
+    float gpart[kBlock / 64];
+    int ipart[kBlock / 64][6];
+    int box_re[kBoxCap];
+    int box_im[kBoxCap];
+};
+
+__device__ __forceinline__ int wave_min_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_sum_f(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Every lane of the block calls this (inactive lanes with active = false).
+template <int T>
+__device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c,
+                                    const ColEntry *__restrict__ cols, float2 *__restrict__ grad,
+                                    const ChildCoord &g, float gre, float gim)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int lo = -T / 2 + 1;
+    int v6[6] = {active ? g.bi : INT_MAX, active ? g.bj : INT_MAX, active ? g.bl : INT_MAX,
+                 active ? g.bi : INT_MIN, active ? g.bj : INT_MIN, active ? g.bl : INT_MIN};
+    float ga = active ? fabsf(gre) + fabsf(gim) : 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v6[a] = wave_min_i(v6[a]);
+#pragma unroll
+    for (int a = 3; a < 6; ++a) v6[a] = wave_max_i(v6[a]);
+    ga = wave_sum_f(ga);
+    if (lane == 0) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) sh.ipart[wave][a] = v6[a];
+        sh.gpart[wave] = ga;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float gs = 0.0f;
+        for (int a = 0; a < 3; ++a) {
+            int m = INT_MAX, M = INT_MIN;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                m = min(m, sh.ipart[w][a]);
+                M = max(M, sh.ipart[w][a + 3]);
+            }
+            sh.mn[a] = m;
+            sh.mx[a] = M;
+        }
+        for (int w = 0; w < kBlock / 64; ++w) gs += sh.gpart[w];
+        sh.gsum = gs;
+    }
+    __syncthreads();
+    if (sh.mn[0] > sh.mx[0] || !(sh.gsum > 0.0f)) {  // nothing to scatter
+        __syncthreads();
+        return;
+    }
+    const int o0 = sh.mn[0] + lo, o1 = sh.mn[1] + lo, o2 = sh.mn[2] + lo;
+    const int B0 = sh.mx[0] - sh.mn[0] + T, B1 = sh.mx[1] - sh.mn[1] + T, B2 = sh.mx[2] - sh.mn[2] + T;
+    const long long nbox = (long long)B0 * B1 * B2;
+    if (nbox > kBoxCap) {
+        // box too large for LDS: direct global atomics
+        if (active) scatter_child<T>(c, cols, grad, g, gre, gim);
+        __syncthreads();
+        return;
+    }
+    const int nb = (int)nbox;
+    for (int t = tid; t < nb; t += kBlock) {
+        sh.box_re[t] = 0;
+        sh.box_im[t] = 0;
+    }
+    const float q = 1651910204.0f / sh.gsum;  // 2^31 / 1.3
+    __syncthreads();
+    if (active) {
+        float wu[T], wv[T], wn[T];
+        lagrange<T>(g.fu, wu);
+        lagrange<T>(g.fv, wv);
+        lagrange<T>(g.fn, wn);
+        const float qre = gre * q, qim = gim * q;
+        const int bi = g.bi + lo - o0, bj = g.bj + lo - o1, bl = g.bl + lo - o2;
+#pragma unroll
+        for (int a = 0; a < T; ++a)
+#pragma unroll
+            for (int b = 0; b < T; ++b) {
+                const float wab = wu[a] * wv[b];
+                const int row = ((bi + a) * B1 + (bj + b)) * B2 + bl;
+#pragma unroll
+                for (int k = 0; k < T; ++k) {
+                    const float w = wab * wn[k];
+                    atomicAdd(&sh.box_re[row + k], (int)rintf(w * qre));
+                    atomicAdd(&sh.box_im[row + k], (int)rintf(w * qim));
+                }
+            }
+    }
+    __syncthreads();
+    const float inv = 1.0f / q;
+    for (int t = tid; t < nb; t += kBlock) {
+        const int vr = sh.box_re[t], vi = sh.box_im[t];
+        if (vr == 0 && vi == 0) continue;
+        const int l = o2 + t % B2;
+        const int j = o1 + (t / B2) % B1;
+        const int i = o0 + t / (B2 * B1);
+        const int ci = i - c.i0, cj = j - c.j0;
+        if ((unsigned)ci >= (unsigned)c.ni || (unsigned)cj >= (unsigned)c.nj) continue;
+        const ColEntry e = cols[c.col_base + ci * c.nj + cj];
+        if (l < e.lo || l > e.hi) continue;  // not a point of the child's grid
+        float2 *dst = grad + c.val_base + e.off + (l - e.lo);
+        unsafeAtomicAdd(&dst->x, (float)vr * inv);
+        unsafeAtomicAdd(&dst->y, (float)vi * inv);
+    }
+    __syncthreads();
+}
+
+template <int T>
+__global__ __launch_bounds__(kBlock) void k_final_adj(const NodeDev *__restrict__ children,
+                                                      int nchild, const ColEntry *__restrict__ ccols,
+                                                      float2 *__restrict__ cgrad, GeoParams gp,
+                                                      double ox, double oy, double oz, double sx,
+                                                      double sy, double sz, int nx, int ny, int nz,
+                                                      const float2 *__restrict__ gimg)
+{
+    __shared__ BoxShared sh;
+    // a block is a 4 x 8 x 8 voxel tile
+    const int tnx = (nx + 3) / 4, tny = (ny + 7) / 8;
+    const int b = blockIdx.x;
+    const int tx = b % tnx, ty = (b / tnx) % tny, tz = b / (tnx * tny);
+    const int ix = tx * 4 + (threadIdx.x >> 6), iy = ty * 8 + ((threadIdx.x >> 3) & 7),
+              iz = tz * 8 + (threadIdx.x & 7);
+    bool active = ix < nx && iy < ny && iz < nz;
+    float2 g = make_float2(0.f, 0.f);
+    if (active) g = gimg[((int64_t)ix * ny + iy) * nz + iz];
+    active = active && (g.x != 0.0f || g.y != 0.0f);
+    const double x = ox + ix * sx, y = oy + iy * sy, z = oz + iz * sz;
+    for (int c = 0; c < nchild; ++c) {
+        const NodeDev ch = children[c];
+        ChildCoord cc{};
+        float gre = 0.0f, gim = 0.0f;
+        if (active) {
+            cc = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
+            rotate_back(g, cc.phi, gre, gim);
+        }
+        block_scatter_child<T>(sh, active, ch, ccols, cgrad, cc, gre, gim);
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(kBlock) void k_merge_adj(const NodeDev *__restrict__ parents,
+                                                      const BlockItem *__restrict__ blocks,
+                                                      const double *__restrict__ px,
+                                                      const double *__restrict__ py,
+                                                      const double *__restrict__ pz,
+                                                      const float2 *__restrict__ pgrad,
+                                                      const NodeDev *__restrict__ children,
+                                                      const ColEntry *__restrict__ ccols,
+                                                      float2 *__restrict__ cgrad, GeoParams gp)
+{
+    __shared__ BoxShared sh;
+    const BlockItem blk = blocks[blockIdx.x];
+    const NodeDev nd = parents[blk.node];
+    const int p = blk.start + threadIdx.x;
+    bool active = p < nd.npts;
+    const int gi = nd.val_base + (active ? p : 0);
+    double x = 0.0, y = 0.0, z = 1.0;
+    float2 g = make_float2(0.f, 0.f);
+    if (active) {
+        x = px[gi];
+        y = py[gi];
+        z = pz[gi];
+        g = pgrad[gi];
+    }
+    active = active && (z > 0.0) && (g.x != 0.0f || g.y != 0.0f);  // absent points hold nothing
+    const double phip = active ? phi_only(nd, x, y, z, gp.kmin, gp.kmax) : 0.0;
+    const int32_t *child_idx = parents[blk.node].child;
+    for (int c = 0; c < nd.nchild; ++c) {
+        const NodeDev ch = children[child_idx[c]];
+        ChildCoord cc{};
+        float gre = 0.0f, gim = 0.0f;
+        if (active) {
+            cc = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
+            rotate_back(g, cc.phi - phip, gre, gim);
+        }
+        block_scatter_child<T>(sh, active, ch, ccols, cgrad, cc, gre, gim);
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Largest |Re|, |Im| of each leaf's grid cotangents: the fixed-point scale of the
+// leaf's range-profile cotangents.  One block per leaf.
+__global__ __launch_bounds__(kBlock) void k_leaf_gmax(const NodeDev *__restrict__ leaves,
+                                                      const float2 *__restrict__ gleaf,
+                                                      float *__restrict__ gmax)
+{
+    __shared__ float s_m[kBlock / 64];
+    const NodeDev nd = leaves[blockIdx.x];
+    float m = 0.0f;
+    for (int p = threadIdx.x; p < nd.npts; p += kBlock) {
+        const float2 g = gleaf[nd.val_base + p];
+        m = fmaxf(m, fmaxf(fabsf(g.x), fabsf(g.y)));
+    }
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float r = 0.0f;
+        for (int w = 0; w < kBlock / 64; ++w) r = fmaxf(r, s_m[w]);
+        gmax[blockIdx.x] = r;
+    }
+}
+
+// L^H and the position gradient for the 16 positions [p0, p0 + n) of one leaf.
+// For each (grid point q, position i), with gi = conj(pre_q e^{j 2 kc dR}) G_q:
+//   profile cotangent  gprof_i[r_w] += phi_w gi
+//   position gradient  grad p'_i  += Re{conj(gi) sum_w phi_w dprof_i[r_w]} * (-(q - p'_i)/|q - p'_i|)
+// where dprof holds the range profiles of the echoes weighted by j 2 k_f (the
+// range derivative of the compressed data).
+template <int KERNEL, int W, bool WANT_S, bool WANT_P>
+__global__ __launch_bounds__(kBlock) void k_leaf_adj(
+    const NodeDev *__restrict__ leaves, const BlockItem *__restrict__ blocks,
+    const LeafPoint *__restrict__ pts, const float4 *__restrict__ posoff,
+    const float2 *__restrict__ dprof, int Nr, float inv_dR, float beta_log2e, float kc_turns,
+    const float2 *__restrict__ gleaf, const float *__restrict__ gmax, float2 *__restrict__ gprof,
+    float4 *__restrict__ gpos)
+{
+    extern __shared__ unsigned char smem[];
+    __shared__ float4 s_pos[kAdjPos];
+    __shared__ float s_red[kBlock / 64][kAdjPos][3];
+    // Range-profile cotangents accumulate in fixed point: float LDS atomics are
+    // serialised on gfx950 while 64-bit integer ones run at full rate.  Every
+    // contribution (|.| <= max |G| of the leaf) is rounded to an int32 at scale
+    // 2^30 / max |G| and summed exactly in int64; real and imaginary parts are
+    // separate arrays so that neighbouring bins fall in different banks.
+    float2 *s_dprof = reinterpret_cast<float2 *>(smem);
+    const int gs = Nr + 1;
+    unsigned long long *s_gre = reinterpret_cast<unsigned long long *>(
+        smem + (WANT_P ? (size_t)kAdjPos * Nr * sizeof(float2) : 0));
+    unsigned long long *s_gim = s_gre + (size_t)kAdjPos * gs;
+    const BlockItem blk = blocks[blockIdx.x];
+    const NodeDev nd = leaves[blk.node];
+    const int p0 = blk.start;
+    const int n = min(kAdjPos, nd.pos_end - p0);
+    const int tid = threadIdx.x;
+    if (tid < kAdjPos) s_pos[tid] = (tid < n) ? posoff[p0 + tid] : make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (WANT_P) {
+        const float2 *src = dprof + (size_t)p0 * Nr;
+        for (int t = tid; t < kAdjPos * Nr; t += kBlock)
+            s_dprof[t] = (t < n * Nr) ? src[t] : make_float2(0.f, 0.f);
+    }
+    float qscale = 0.0f;
+    if constexpr (WANT_S) {
+        for (int t = tid; t < kAdjPos * gs; t += kBlock) {
+            s_gre[t] = 0ull;
+            s_gim[t] = 0ull;
+        }
+        const float gm = gmax[blk.node];
+        qscale = gm > 0.0f ? 1073741824.0f / gm : 0.0f;
+    }
+    __syncthreads();
+    float ap[kAdjPos][3];
+#pragma unroll
+    for (int i = 0; i < kAdjPos; ++i) ap[i][0] = ap[i][1] = ap[i][2] = 0.0f;
+    for (int pt0 = 0; pt0 < nd.npts; pt0 += kBlock) {
+        const int p = pt0 + tid;
+        if (p >= nd.npts) continue;
+        const LeafPoint q = pts[nd.val_base + p];
+        const float2 G = gleaf[nd.val_base + p];
+        // f' = pre * sum  ->  cotangent of the sum is conj(pre) G
+        const float gcre = q.pre_re * G.x + q.pre_im * G.y;
+        const float gcim = q.pre_re * G.y - q.pre_im * G.x;
+        if (gcre == 0.0f && gcim == 0.0f) continue;
+        const float Rc = fast_sqrt(q.dx * q.dx + q.dy * q.dy + q.dz * q.dz);
+        const float frac_w = q.frac - 0.5f * W;
+        const int bin1 = q.bin + 1;
+#pragma unroll
+        for (int i = 0; i < kAdjPos; ++i) {
+            if (i < n) {  // predicated, so every ap[i] index stays a constant
+                const float4 d = s_pos[i];
+                const float ex = q.dx - d.x, ey = q.dy - d.y, ez = q.dz - d.z;
+                const float R = fast_sqrt(ex * ex + ey * ey + ez * ez);
+                const float num = d.w - 2.0f * (q.dx * d.x + q.dy * d.y + q.dz * d.z);
+                const float dR = num * fast_rcp(R + Rc);
+                const float tau = fmaf(dR, inv_dR, frac_w);
+                const float fl = floorf(tau);
+                const float x = tau - fl;
+                const int r = min(max(bin1 + (int)fl, 0), Nr - W);
+                float w[W];
+                range_weights<KERNEL, W>(x, beta_log2e, w);
+                float ph = dR * kc_turns;
+                ph -= rintf(ph);
+                const float sn = sin_turns(ph), cs = cos_turns(ph);
+                const float gire = gcre * cs + gcim * sn;
+                const float giim = gcim * cs - gcre * sn;
+                if constexpr (WANT_S) {
+                    unsigned long long *rre = s_gre + i * gs + r;
+                    unsigned long long *rim = s_gim + i * gs + r;
+                    const float qre = gire * qscale, qim = giim * qscale;
+#pragma unroll
+                    for (int k = 0; k < W; ++k) {
+                        const long long a = (long long)(int)rintf(w[k] * qre);
+                        const long long b = (long long)(int)rintf(w[k] * qim);
+                        atomicAdd(&rre[k], (unsigned long long)a);
+                        atomicAdd(&rim[k], (unsigned long long)b);
+                    }
+                }
+                if constexpr (WANT_P) {
+                    const float2 *pr = s_dprof + i * Nr + r;
+                    float dre = 0.0f, dim = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < W; ++k) {
+                        const float2 v = pr[k];
+                        dre = fmaf(w[k], v.x, dre);
+                        dim = fmaf(w[k], v.y, dim);
+                    }
+                    const float val = gire * dre + giim * dim;
+                    const float sc = -val * fast_rcp(R);
+                    ap[i][0] = fmaf(sc, ex, ap[i][0]);
+                    ap[i][1] = fmaf(sc, ey, ap[i][1]);
+                    ap[i][2] = fmaf(sc, ez, ap[i][2]);
+                }
+            }
+        }
+    }
+    if constexpr (WANT_P) {
+        const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+        for (int i = 0; i < kAdjPos; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float v = wave_sum(ap[i][c]);
+                if (lane == 0) s_red[wave][i][c] = v;
+            }
+    }
+    __syncthreads();
+    if constexpr (WANT_P) {
+        if (tid < n * 3) {
+            const int i = tid / 3, c = tid % 3;
+            float v = 0.0f;
+#pragma unroll
+            for (int wv = 0; wv < kBlock / 64; ++wv) v += s_red[wv][i][c];
+            reinterpret_cast<float *>(gpos + p0 + i)[c] = v;
+        }
+    }
+    if constexpr (WANT_S) {
+        float2 *dst = gprof + (size_t)p0 * Nr;
+        const double inv = qscale > 0.0f ? 1.0 / (double)qscale : 0.0;
+        for (int t = tid; t < n * Nr; t += kBlock) {
+            const int o = (t / Nr) * gs + (t % Nr);
+            dst[t] = make_float2((float)((double)(long long)s_gre[o] * inv),
+                                 (float)((double)(long long)s_gim[o] * inv));
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pos_out(const float4 *__restrict__ gpos,
+                                                    const int32_t *__restrict__ perm, int n,
+                                                    double *__restrict__ out)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const float4 g = gpos[i];
+    const int m = perm[i];
+    out[3 * m] = (double)g.x;
+    out[3 * m + 1] = (double)g.y;
+    out[3 * m + 2] = (double)g.z;
+}
+
+template <int KERNEL, int W, bool S_, bool P_>
+hipError_t launch_leaf_adj(const Plan &P, const float4 *posoff, const float2 *dprof,
+                           const float2 *gleaf, const float *gmax, float2 *gprof, float4 *gpos,
+                           hipStream_t st)
+{
+    const size_t sh = (P_ ? (size_t)kAdjPos * P.Nr * sizeof(float2) : 0) +
+                      (S_ ? (size_t)kAdjPos * (P.Nr + 1) * 2 * sizeof(unsigned long long) : 0);
+    if (sh > kLdsLimit) return hipErrorInvalidConfiguration;  // caller maps to UNSUPPORTED
+    hipLaunchKernelGGL((k_leaf_adj<KERNEL, W, S_, P_>), dim3(P.n_blocks_adj), dim3(kBlock), sh, st,
+                       (const NodeDev *)P.dev.nodes[P.S], (const BlockItem *)P.dev.adj_blocks,
+                       (const LeafPoint *)P.dev.leafpts, posoff, dprof, (int)P.Nr,
+                       (float)(1.0 / P.dR), (float)(P.beta * 1.4426950408889634),
+                       (float)(P.kc / kPi), gleaf, gmax, gprof, gpos);
+    return hipGetLastError();
+}
+
+template <int KERNEL, int W>
+hipError_t leaf_adj_dispatch(const Plan &P, bool want_s, bool want_p, const float4 *posoff,
+                             const float2 *dprof, const float2 *gleaf, const float *gmax,
+                             float2 *gprof, float4 *gpos, hipStream_t st)
+{
+    if (want_s && want_p)
+        return launch_leaf_adj<KERNEL, W, true, true>(P, posoff, dprof, gleaf, gmax, gprof, gpos, st);
+    if (want_s)
+        return launch_leaf_adj<KERNEL, W, true, false>(P, posoff, dprof, gleaf, gmax, gprof, gpos, st);
+    return launch_leaf_adj<KERNEL, W, false, true>(P, posoff, dprof, gleaf, gmax, gprof, gpos, st);
+}
+
+template <int T>
+hipError_t launch_scatters(const Plan &P, const void *grad_image, char *ws, hipStream_t st)
+{
+    const hhffbp_config &c = P.cfg;
+    GeoParams gp{P.gamma[0], P.gamma[1], P.gamma[2], P.kmin, P.kmax};
+    const int nx = (int)c.grid_dims[0], ny = (int)c.grid_dims[1], nz = (int)c.grid_dims[2];
+    const int64_t nv = (int64_t)nx * ny * nz;
+    const unsigned ntile = (unsigned)(((nx + 3) / 4) * ((ny + 7) / 8) * ((nz + 7) / 8));
+    (void)nv;
+    hipLaunchKernelGGL((k_final_adj<T>), dim3(ntile), dim3(kBlock), 0, st, (const NodeDev *)P.dev.nodes[1], (int)P.compact_to_tree[1].size(),
+                       (const ColEntry *)P.dev.cols[1], (float2 *)(ws + P.ws_vals[1]), gp,
+                       c.grid_origin[0], c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0],
+                       c.grid_pitch[1], c.grid_pitch[2], nx, ny, nz, (const float2 *)grad_image);
+    hipError_t e = hipGetLastError();
+    for (int d = 1; d < P.S && e == hipSuccess; ++d) {
+        if (P.n_blocks_merge[d] == 0) continue;
+        hipLaunchKernelGGL((k_merge_adj<T>), dim3(P.n_blocks_merge[d]), dim3(kBlock), 0, st,
+                           (const NodeDev *)P.dev.nodes[d], (const BlockItem *)P.dev.merge_blocks[d],
+                           (const double *)P.dev.px[d], (const double *)P.dev.py[d],
+                           (const double *)P.dev.pz[d], (const float2 *)(ws + P.ws_vals[d]),
+                           (const NodeDev *)P.dev.nodes[d + 1], (const ColEntry *)P.dev.cols[d + 1],
+                           (float2 *)(ws + P.ws_vals[d + 1]), gp);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace
+
+hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *positions,
+                              const void *grad_image, void *grad_echoes, double *grad_positions,
+                              char *ws, hipStream_t st)
+{
+    const hhffbp_config &c = P.cfg;
+    const int n = (int)c.n_pos;
+    const bool want_s = grad_echoes != nullptr, want_p = grad_positions != nullptr;
+    const double *pos64 = positions ? positions : (const double *)P.dev.pos64;
+    float2 *dprof = (float2 *)(ws + P.ws_prof);
+    float4 *posoff = (float4 *)(ws + P.ws_posoff);
+    float2 *gprof = (float2 *)(ws + P.ws_gprof);
+    float4 *gpos = (float4 *)(ws + P.ws_gpos);
+    hipError_t e;
+    // positions relative to their leaf centres
+    if ((e = launch_prep(P, pos64, posoff, st)) != hipSuccess) return HHFFBP_E_DEVICE;
+    // range-derivative profiles (only the position gradient needs them)
+    if (want_p) {
+        e = launch_rc_gemm((const float *)echoes, (const int32_t *)P.dev.perm, n,
+                           (int)(2 * c.n_freq), (const float *)P.dev.Bd, (int)(2 * P.Nr),
+                           (float *)dprof, nullptr, st);
+        if (e != hipSuccess) return HHFFBP_E_DEVICE;
+    }
+    // clear every grid cotangent (depths 1..S are contiguous)
+    {
+        const size_t b0 = P.ws_vals[1];
+        const size_t b1 = P.ws_vals[P.S] + (size_t)P.depth_points[P.S] * sizeof(float2);
+        const int64_t n4 = (int64_t)((b1 - b0) / sizeof(float4));
+        hipLaunchKernelGGL(k_zero, dim3(1024), dim3(kBlock), 0, st, (float4 *)(ws + b0), n4);
+        if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
+    }
+    e = (P.T == 4) ? launch_scatters<4>(P, grad_image, ws, st) : launch_scatters<6>(P, grad_image, ws, st);
+    if (e != hipSuccess) return HHFFBP_E_DEVICE;
+    const float2 *gleaf = (const float2 *)(ws + P.ws_vals[P.S]);
+    float *gmax = (float *)(ws + P.ws_gmax);
+    if (want_s) {
+        hipLaunchKernelGGL(k_leaf_gmax, dim3((unsigned)P.compact_to_tree[P.S].size()), dim3(kBlock), 0,
+                           st, (const NodeDev *)P.dev.nodes[P.S], gleaf, gmax);
+        if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
+    }
+    if (P.kernel == HHFFBP_RANGE_LINEAR) {
+        e = leaf_adj_dispatch<HHFFBP_RANGE_LINEAR, 2>(P, want_s, want_p, posoff, dprof, gleaf, gmax,
+                                                      gprof, gpos, st);
+    } else {
+        switch (P.W) {
+        case 4: e = leaf_adj_dispatch<HHFFBP_RANGE_ES, 4>(P, want_s, want_p, posoff, dprof, gleaf, gmax, gprof, gpos, st); break;
+        case 5: e = leaf_adj_dispatch<HHFFBP_RANGE_ES, 5>(P, want_s, want_p, posoff, dprof, gleaf, gmax, gprof, gpos, st); break;
+        case 6: e = leaf_adj_dispatch<HHFFBP_RANGE_ES, 6>(P, want_s, want_p, posoff, dprof, gleaf, gmax, gprof, gpos, st); break;
+        case 7: e = leaf_adj_dispatch<HHFFBP_RANGE_ES, 7>(P, want_s, want_p, posoff, dprof, gleaf, gmax, gprof, gpos, st); break;
+        case 8: e = leaf_adj_dispatch<HHFFBP_RANGE_ES, 8>(P, want_s, want_p, posoff, dprof, gleaf, gmax, gprof, gpos, st); break;
+        default: return HHFFBP_E_UNSUPPORTED;
+        }
+    }
+    if (e == hipErrorInvalidConfiguration) return HHFFBP_E_UNSUPPORTED;  // profile window too long
+    if (e != hipSuccess) return HHFFBP_E_DEVICE;
+    if (want_s) {
+        // grad_s = gprof conj(W)^T, rows back to the caller's position order
+        e = launch_rc_gemm((const float *)gprof, nullptr, n, (int)(2 * P.Nr),
+                           (const float *)P.dev.Badj, (int)(2 * c.n_freq), (float *)grad_echoes,
+                           (const int32_t *)P.dev.perm, st);
+        if (e != hipSuccess) return HHFFBP_E_DEVICE;
+    }
+    if (want_p) {
+        hipLaunchKernelGGL(k_pos_out, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, gpos,
+                           (const int32_t *)P.dev.perm, n, grad_positions);
+        if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
+    }
+    return HHFFBP_OK;
+}
+
+}  // namespace hh

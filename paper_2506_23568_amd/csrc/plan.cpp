@@ -375,6 +375,8 @@ void range_setup(Plan &P, double rmin, double rmax)
     P.Nr = nr;
     const int64_t nf = P.cfg.n_freq;
     P.Bmat.assign((size_t)(2 * nf) * (size_t)(2 * nr), 0.0f);
+    P.Bdmat.assign((size_t)(2 * nf) * (size_t)(2 * nr), 0.0f);
+    P.Badjmat.assign((size_t)(2 * nr) * (size_t)(2 * nf), 0.0f);
     for (int64_t f = 0; f < nf; ++f) {
         const double om = 2.0 * (P.k[f] - P.kc);
         const double corr = (P.kernel == HHFFBP_RANGE_ES) ? es_hat(om * P.dR, W, P.beta)
@@ -382,12 +384,21 @@ void range_setup(Plan &P, double rmin, double rmax)
         for (int64_t r = 0; r < nr; ++r) {
             const double ph = om * (P.R0 + r * P.dR);
             const double wr = std::cos(ph) / corr, wi = std::sin(ph) / corr;
-            float *row0 = &P.Bmat[(size_t)(2 * f) * (2 * nr)];
-            float *row1 = &P.Bmat[(size_t)(2 * f + 1) * (2 * nr)];
-            row0[2 * r] = (float)wr;
-            row0[2 * r + 1] = (float)wi;
-            row1[2 * r] = (float)(-wi);
-            row1[2 * r + 1] = (float)wr;
+            // block-real form of a complex matrix M acting on interleaved rows:
+            // out.re += in.re M.re - in.im M.im, out.im += in.re M.im + in.im M.re
+            auto put = [](std::vector<float> &B, int64_t ncol, int64_t a, int64_t b, double mr,
+                          double mi) {
+                B[(size_t)(2 * a) * ncol + 2 * b] = (float)mr;
+                B[(size_t)(2 * a) * ncol + 2 * b + 1] = (float)mi;
+                B[(size_t)(2 * a + 1) * ncol + 2 * b] = (float)(-mi);
+                B[(size_t)(2 * a + 1) * ncol + 2 * b + 1] = (float)mr;
+            };
+            put(P.Bmat, 2 * nr, f, r, wr, wi);
+            // range derivative of the compressed data: rows scaled by j 2 k_f
+            const double s2k = 2.0 * P.k[f];
+            put(P.Bdmat, 2 * nr, f, r, -s2k * wi, s2k * wr);
+            // adjoint: grad_s[f] = sum_r conj(W[f][r]) gprof[r]
+            put(P.Badjmat, 2 * nf, r, f, wr, -wi);
         }
     }
 }
@@ -609,6 +620,13 @@ void build_plan_host(Plan &P)
         off += al((size_t)P.depth_points[d] * 8);
     }
     P.ws_total = off;
+    P.ws_gprof = off;
+    off += al((size_t)c.n_pos * P.Nr * 8);
+    P.ws_gpos = off;
+    off += al((size_t)c.n_pos * 16);
+    P.ws_gmax = off;
+    off += al((size_t)std::max<size_t>(1, P.compact_to_tree[S].size()) * sizeof(float));
+    P.ws_total_bwd = off;
     P.plan_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -650,6 +668,8 @@ void upload_plan(Plan &P)
         throw Error{HHFFBP_E_DEVICE, "hipSetDevice failed"};
     DeviceBuffers &D = P.dev;
     upload_vec(&D.B, P.Bmat);
+    upload_vec(&D.Bd, P.Bdmat);
+    upload_vec(&D.Badj, P.Badjmat);
     upload_vec(&D.perm, P.perm);
     upload_vec(&D.leaf_of_sorted, P.leaf_of_sorted);
     upload_vec(&D.leaf_centre, P.leaf_centre);
@@ -747,6 +767,13 @@ void upload_plan(Plan &P)
             upload_vec(&D.leafpts, lpts);
             upload_vec(&D.leaf_blocks, blocks);
             P.n_blocks_leaf = (int64_t)blocks.size();
+            // adjoint work items: each leaf's positions in groups of 16
+            std::vector<BlockItem> ab;
+            for (size_t li = 0; li < nodes.size(); ++li)
+                for (int32_t p0 = nodes[li].pos_begin; p0 < nodes[li].pos_end; p0 += 16)
+                    ab.push_back(BlockItem{(int32_t)li, p0});
+            upload_vec(&D.adj_blocks, ab);
+            P.n_blocks_adj = (int64_t)ab.size();
         }
     }
 }
@@ -765,6 +792,9 @@ void release_plan(Plan &P)
     fr(D.pos64);
     fr(D.leafpts);
     fr(D.leaf_blocks);
+    fr(D.adj_blocks);
+    fr(D.Bd);
+    fr(D.Badj);
     for (auto *v : {&D.nodes, &D.cols, &D.px, &D.py, &D.pz, &D.merge_blocks})
         for (auto &p : *v) fr(p);
 }

@@ -1,0 +1,71 @@
+"""Pins of the oracle's adjoint and trajectory gradient (CPU only).
+
+* the adjoint identity <A s, g> = <s, A^H g> for the factorised operator;
+* the position gradient against central finite differences of the oracle
+  image (frozen plan), h = 1e-6 m;
+* the loss cotangent against finite differences of the loss.
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint as OA
+from oracle import hhffbp as OH
+from oracle import loss as OL
+from oracle import plan as OP
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    """A reduced handheld scan: 192 positions of the small walk, 6x6x4 voxels."""
+    from workloads import make_config
+    w = make_config(0)
+    sel = np.arange(0, w.n_pos, 5)[:192]
+    pos, ech = w.positions[sel], w.echoes[sel]
+    origin = np.array([-0.005, -0.005, 0.245])
+    pitch = np.full(3, 2e-3)
+    dims = (6, 6, 4)
+    pl = OP.build_plan(pos, w.freqs_hz, origin, pitch, dims, 1, 4, (3.0, 3.0, 3.5), 4)
+    return pl, pos, ech
+
+
+def test_factorised_adjoint_identity(tiny):
+    pl, pos, ech = tiny
+    rng = np.random.default_rng(0)
+    s = rng.standard_normal(ech.shape) + 1j * rng.standard_normal(ech.shape)
+    g = rng.standard_normal(pl.dims) + 1j * rng.standard_normal(pl.dims)
+    lhs = np.vdot(g.ravel(), OH.image(pl, s, pos).ravel())
+    rhs = np.vdot(OA.echo_gradient(pl, g, pos).ravel(), s.ravel())
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+
+
+def test_position_gradient_against_central_differences(tiny):
+    pl, pos, ech = tiny
+    rng = np.random.default_rng(1)
+    g = rng.standard_normal(pl.dims) + 1j * rng.standard_normal(pl.dims)
+
+    def L(p):
+        return float(np.real(np.vdot(g.ravel(), OH.image(pl, ech, p).ravel())))
+
+    grad = OA.position_gradient(pl, ech, pos, g)
+    scale = np.max(np.abs(grad))
+    h = 1e-6
+    for i, a in [(0, 0), (7, 1), (31, 2), (100, 0), (150, 2), (191, 1)]:
+        pp, pm = pos.copy(), pos.copy()
+        pp[i, a] += h
+        pm[i, a] -= h
+        fd = (L(pp) - L(pm)) / (2 * h)
+        assert abs(fd - grad[i, a]) <= 1e-5 * scale, (i, a, fd, grad[i, a])
+
+
+def test_loss_cotangent_against_central_differences():
+    rng = np.random.default_rng(2)
+    f = rng.standard_normal(40) + 1j * rng.standard_normal(40)
+    fc = f + 0.3 * (rng.standard_normal(40) + 1j * rng.standard_normal(40))
+    g = OL.loss_cotangent(f, fc)
+    h = 1e-7
+    for v in range(0, 40, 7):
+        e = np.zeros(40)
+        e[v] = h
+        d_re = (OL.loss(f + e, fc) - OL.loss(f - e, fc)) / (2 * h)
+        d_im = (OL.loss(f + 1j * e, fc) - OL.loss(f - 1j * e, fc)) / (2 * h)
+        assert abs(d_re - g[v].real) < 1e-7 and abs(d_im - g[v].imag) < 1e-7
