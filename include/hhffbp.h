@@ -59,7 +59,10 @@ enum {
     HHFFBP_DIRECT_RC = 1     /* direct BPA of eq. (3) on range-compressed data   */
 };
 
-/* Storage type of echoes (and, later, of profiles and subimages). */
+/* Storage type of the echoes, range profiles and subimages.  Sums, phases and
+ * interpolation are float32 in every case; the image is always complex64.
+ * HHFFBP_F16 arrays carry per-stage power-of-two scales chosen per call from the
+ * largest echo component, so that no stored value exceeds 2^15. */
 enum { HHFFBP_C64 = 0, HHFFBP_F16 = 1, HHFFBP_BF16 = 2 };
 
 /* Kernel used to evaluate a range profile between its samples. */
@@ -84,7 +87,7 @@ typedef struct {
     int32_t range_kernel;       /* HHFFBP_RANGE_ES or HHFFBP_RANGE_LINEAR         */
     double range_oversample;    /* U: range-bin spacing pi / (U (kmax - kmin))    */
     int32_t range_taps;         /* W: ES taps (4..8); ignored for linear          */
-    int32_t storage;            /* HHFFBP_C64 (F16/BF16: HHFFBP_E_UNSUPPORTED)    */
+    int32_t storage;            /* HHFFBP_C64, HHFFBP_F16 or HHFFBP_BF16          */
     double position_slack;      /* metres the positions may move after planning  */
     int32_t device;             /* HIP device ordinal; -1 plans on the host only  */
 } hhffbp_config;
@@ -119,8 +122,9 @@ hhffbp_status hhffbp_workspace_bytes(hhffbp_plan_t plan, int32_t with_backward,
 
 /*
  * Form the image.
- *   echoes      device, [n_pos][n_freq] complex in the plan's storage type,
- *               rows in the order of cfg->positions.
+ *   echoes      device, [n_pos][n_freq] complex pairs in the plan's storage
+ *               type (float32, IEEE half or bfloat16 re/im), rows in the order
+ *               of cfg->positions.
  *   positions   device float64 [n_pos][3] to backproject with, or NULL for
  *               the plan's own positions.  The tree and grids stay as planned;
  *               positions must stay within cfg->position_slack of the planned
@@ -167,6 +171,10 @@ typedef struct {
     int64_t merge_pairs;            /* (parent point, child) pairs, depths 1..S-1 */
     int64_t final_pairs;            /* (voxel, child) pairs at the root         */
     double plan_seconds;            /* host time spent in hhffbp_plan           */
+    int32_t storage;                /* storage type of profiles and subimages   */
+    int64_t ws_scales_offset;       /* workspace byte offset of float scale[S+1]:
+                                       stored profiles carry scale[0], depth-d
+                                       subimages scale[d] (1 unless HHFFBP_F16) */
 } hhffbp_plan_info;
 
 hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info);
@@ -176,7 +184,10 @@ hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info);
  * workspace after hhffbp_image, and its grid: lattice column (i, j) covers
  * i in [i0, i0 + ni), j in [j0, j0 + nj); column c = (i - i0) * nj + (j - j0)
  * holds l in [l_lo[c], l_hi[c]] contiguously from point offset col_off[c].
- * Values are complex64 at byte offset *ws_offset + 8 * point.  Arrays may be
+ * Values are complex pairs of the plan's storage type (8 bytes per point for
+ * HHFFBP_C64, 4 for HHFFBP_F16 and HHFFBP_BF16) at byte offset
+ * *ws_offset + size * point, multiplied by the depth's scale (see
+ * hhffbp_plan_info.ws_scales_offset).  Arrays may be
  * NULL to query sizes only; otherwise they must hold ni * nj entries.
  * Depth 0 is the user grid and has no lattice (HHFFBP_E_INVALID); an empty
  * node reports npoints = 0.

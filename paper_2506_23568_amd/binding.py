@@ -47,6 +47,7 @@ class PlanInfo(ctypes.Structure):
         ("range_step", ctypes.c_double), ("level_points", ctypes.c_int64 * 16),
         ("leaf_pairs", ctypes.c_int64), ("merge_pairs", ctypes.c_int64),
         ("final_pairs", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
+        ("storage", ctypes.c_int32), ("ws_scales_offset", ctypes.c_int64),
     ]
 
 
@@ -213,15 +214,39 @@ class Plan:
             self._ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
         return self._ws
 
-    def image(self, echoes, positions=None, out=None, workspace=None, stream=None):
-        """Image from device echoes (complex64 [n_pos, n_freq]); returns complex64 (nx, ny, nz)."""
+    def _check_echoes(self, echoes):
         import torch
 
-        if echoes.dtype != torch.complex64 or not echoes.is_cuda:
-            raise TypeError("echoes must be a complex64 CUDA tensor")
-        if tuple(echoes.shape) != (self.config.n_pos, self.config.n_freq):
-            raise ValueError("echoes must be (n_pos, n_freq)")
-        echoes = echoes.contiguous()
+        st = self.config.storage
+        shp = (self.config.n_pos, self.config.n_freq)
+        if not echoes.is_cuda:
+            raise TypeError("echoes must be a CUDA tensor")
+        if st == STORAGE["c64"]:
+            ok = echoes.dtype == torch.complex64 and tuple(echoes.shape) == shp
+            want = "complex64 (n_pos, n_freq)"
+        else:
+            dt = torch.float16 if st == STORAGE["f16"] else torch.bfloat16
+            ok = echoes.dtype == dt and tuple(echoes.shape) == shp + (2,)
+            want = f"{dt} (n_pos, n_freq, 2) re/im pairs"
+        if not ok:
+            raise TypeError(f"echoes must be {want}")
+        return echoes.contiguous()
+
+    @staticmethod
+    def pack_echoes(echoes_c, storage):
+        """Complex echoes (any device) -> the tensor layout of ``storage``."""
+        import torch
+
+        if storage == "c64":
+            return echoes_c.to(torch.complex64)
+        dt = torch.float16 if storage == "f16" else torch.bfloat16
+        return torch.view_as_real(echoes_c.to(torch.complex64)).to(dt).contiguous()
+
+    def image(self, echoes, positions=None, out=None, workspace=None, stream=None):
+        """Image from device echoes (storage layout, see pack_echoes); complex64 (nx, ny, nz)."""
+        import torch
+
+        echoes = self._check_echoes(echoes)
         if out is None:
             out = torch.empty(self.dims, dtype=torch.complex64, device=echoes.device)
         if workspace is None:
@@ -253,9 +278,7 @@ class Plan:
                          device=dev) if want_positions else None
         eptr = None
         if echoes is not None:
-            if echoes.dtype != torch.complex64 or tuple(echoes.shape) != (self.config.n_pos, self.config.n_freq):
-                raise TypeError("echoes must be complex64 (n_pos, n_freq)")
-            echoes = echoes.contiguous()
+            echoes = self._check_echoes(echoes)
             eptr = echoes.data_ptr()
         pptr = None
         if positions is not None:
@@ -284,9 +307,16 @@ class Plan:
                 for k in range(ns.value)}
 
     def workspace_view(self, workspace, depth, index):
-        """Compressed subimage of node (depth, index) from a workspace after ``image``."""
+        """Compressed subimage of node (depth, index) after ``image``, as complex64 (unscaled)."""
         import torch
 
         lay = self.node_layout(depth, index)
         o, n = lay["ws_offset"], lay["npoints"]
-        return workspace[o:o + 8 * n].view(torch.complex64)
+        st = self.config.storage
+        if st == STORAGE["c64"]:
+            return workspace[o:o + 8 * n].view(torch.complex64)
+        dt = torch.float16 if st == STORAGE["f16"] else torch.bfloat16
+        so = self.info()["ws_scales_offset"]
+        scale = workspace[so + 4 * depth:so + 4 * depth + 4].view(torch.float32)
+        v = workspace[o:o + 4 * n].view(dt).reshape(n, 2).to(torch.float32)
+        return torch.view_as_complex(v.contiguous()) / scale

@@ -175,6 +175,8 @@ hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info)
     info->merge_pairs = P.merge_pairs;
     info->final_pairs = P.final_pairs;
     info->plan_seconds = P.plan_seconds;
+    info->storage = P.cfg.storage;
+    info->ws_scales_offset = (int64_t)P.ws_scales;
     return HHFFBP_OK;
 }
 
@@ -205,7 +207,8 @@ hhffbp_status hhffbp_node_layout(hhffbp_plan_t plan, int32_t depth, int32_t inde
         if (ti == index) break;
         base += P.levels[depth][ti].lat.npts;
     }
-    *ws_offset = (int64_t)P.ws_vals[depth] + 8 * base;
+    const int64_t csz = (P.cfg.storage == HHFFBP_C64) ? 8 : 4;
+    *ws_offset = (int64_t)P.ws_vals[depth] + csz * base;
     const int64_t nc = (int64_t)L.ni * L.nj;
     for (int64_t c = 0; c < nc; ++c) {
         if (l_lo) l_lo[c] = L.lo[c];

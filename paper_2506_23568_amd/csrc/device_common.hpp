@@ -10,6 +10,67 @@
 namespace hh {
 namespace dev {
 
+// ---------------------------------------------------------------------------
+// Storage of complex profiles and subimages: float32 pairs (C64), IEEE half
+// pairs (F16) or bfloat16 pairs (BF16).  Arithmetic is always float32: values
+// are widened on load and rounded to nearest even on store.  `C` is one
+// complex value, `R` one real component (the range-compression GEMM sees the
+// interleaved arrays as real matrices).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t f32_to_f16(float f)
+{
+    return __builtin_bit_cast(uint16_t, (_Float16)f);
+}
+__device__ __forceinline__ float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+
+template <int ST>
+struct Store;
+template <>
+struct Store<HHFFBP_C64> {
+    using C = float2;
+    using R = float;
+    static __device__ __forceinline__ float2 ld(C v) { return v; }
+    static __device__ __forceinline__ C st(float2 v) { return v; }
+    static __device__ __forceinline__ float ldr(R v) { return v; }
+    static __device__ __forceinline__ R str(float v) { return v; }
+};
+template <>
+struct Store<HHFFBP_F16> {
+    using C = uint32_t;
+    using R = uint16_t;
+    static __device__ __forceinline__ float2 ld(C v)
+    {
+        return make_float2(f16_to_f32((uint16_t)(v & 0xffffu)), f16_to_f32((uint16_t)(v >> 16)));
+    }
+    static __device__ __forceinline__ C st(float2 v)
+    {
+        return (uint32_t)f32_to_f16(v.x) | ((uint32_t)f32_to_f16(v.y) << 16);
+    }
+    static __device__ __forceinline__ float ldr(R v) { return f16_to_f32(v); }
+    static __device__ __forceinline__ R str(float v) { return f32_to_f16(v); }
+};
+template <>
+struct Store<HHFFBP_BF16> {
+    using C = uint32_t;
+    using R = uint16_t;
+    static __device__ __forceinline__ float2 ld(C v)
+    {
+        return make_float2(__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u));
+    }
+    static __device__ __forceinline__ C st(float2 v)
+    {
+        return (uint32_t)f32_to_bf16(v.x) | ((uint32_t)f32_to_bf16(v.y) << 16);
+    }
+    static __device__ __forceinline__ float ldr(R v) { return bf16_to_f32(v); }
+    static __device__ __forceinline__ R str(float v) { return f32_to_bf16(v); }
+};
+
 constexpr int kBlock = 256;
 constexpr int kPosChunkMax = 16;
 constexpr size_t kLdsBudget = 20 * 1024;  // dynamic LDS per block
@@ -121,9 +182,9 @@ __device__ __forceinline__ void lagrange(float x, float *w)
 }
 
 // Separable T^3 interpolation of a compressed child subimage (missing points are 0).
-template <int T>
+template <int T, int ST = HHFFBP_C64>
 __device__ __forceinline__ float2 interp_child(const NodeDev &c, const ColEntry *__restrict__ cols,
-                                               const float2 *__restrict__ vals,
+                                               const typename Store<ST>::C *__restrict__ vals,
                                                const ChildCoord &g)
 {
     float wu[T], wv[T], wn[T];
@@ -140,13 +201,13 @@ __device__ __forceinline__ float2 interp_child(const NodeDev &c, const ColEntry 
             const int cj = g.bj + b - T / 2 + 1 - c.j0;
             if ((unsigned)cj >= (unsigned)c.nj) continue;
             const ColEntry e = cols[c.col_base + ci * c.nj + cj];
-            const float2 *colv = vals + c.val_base + e.off - e.lo;
+            const typename Store<ST>::C *colv = vals + c.val_base + e.off - e.lo;
             float sre = 0.0f, sim = 0.0f;
 #pragma unroll
             for (int k = 0; k < T; ++k) {
                 const int l = g.bl + k - T / 2 + 1;
                 if (l >= e.lo && l <= e.hi) {
-                    const float2 v = colv[l];
+                    const float2 v = Store<ST>::ld(colv[l]);
                     sre = fmaf(wn[k], v.x, sre);
                     sim = fmaf(wn[k], v.y, sim);
                 }

@@ -94,6 +94,7 @@ struct DeviceBuffers {
     void *adj_blocks = nullptr;     // BlockItem[]: (leaf, first sorted position of 16)
     void *Bd = nullptr;             // range-derivative matrix (rows x j 2 k_f), [2 Nf][2 Nr]
     void *Badj = nullptr;           // conj-transposed DFT matrix, [2 Nr][2 Nf]
+    void *scale_mult = nullptr;     // float [S + 1]: worst-case gain from echoes to each stage
     std::vector<void *> merge_blocks;  // per depth 1..S-1: BlockItem[]
 };
 
@@ -124,7 +125,10 @@ struct Plan {
     int64_t leaf_pairs = 0, merge_pairs = 0, final_pairs = 0;
     // workspace layout (bytes)
     size_t ws_prof = 0, ws_posoff = 0, ws_total = 0;
+    size_t ws_scales = 0, ws_amax = 0;  // per-call storage scales (float [S + 1]) and max |echo|
     size_t ws_gprof = 0, ws_gpos = 0, ws_gmax = 0, ws_total_bwd = 0;  // backward additions
+    std::vector<size_t> ws_gvals;        // backward: float32 cotangents per depth
+    std::vector<float> scale_mult;       // host copy of dev.scale_mult
     std::vector<size_t> ws_vals;         // per depth
     DeviceBuffers dev;
     double plan_seconds = 0;
@@ -148,8 +152,9 @@ void release_plan(Plan &plan);
 
 // Launchers (kernels.hip, kernels_adjoint.hip).
 hipError_t launch_prep(const Plan &P, const double *pos64, float4 *posoff, hipStream_t st);
-hipError_t launch_rc_gemm(const float *A, const int32_t *a_perm, int M, int K, const float *B,
-                          int N, float *C, const int32_t *c_perm, hipStream_t st);
+// Range-compression GEMM with float32 output; A stored as `storage_a` reals.
+hipError_t launch_rc_gemm(int storage_a, const void *A, const int32_t *a_perm, int M, int K,
+                          const float *B, int N, float *C, const int32_t *c_perm, hipStream_t st);
 hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *positions,
                               const void *grad_image, void *grad_echoes, double *grad_positions,
                               char *ws, hipStream_t st);

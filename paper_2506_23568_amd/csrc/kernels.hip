@@ -1,6 +1,7 @@
 // gfx950 kernels of the HHFFBPA hot path and their launcher.
 //
 //   k_prep_positions  antenna offsets from their leaf centre (float64 -> float32)
+//   k_absmax, k_scales  per-call power-of-two scales for half-precision storage
 //   k_rc_gemm         range compression, eq. (2): profiles = echoes x W on MFMA
 //   k_leaf_bp         level-1 BP onto each leaf grid + SDC (Sec. IV-A, eq. sdc_mul)
 //   k_merge           interpolate compressed children onto a parent grid, undo
@@ -12,6 +13,11 @@
 // leaf BP works with distance differences to the leaf centre, direct BP with
 // differences to a per-tile reference point whose own distance is float64, and
 // the merge geometry ((u, v, n) and Phi of each child) is evaluated in float64.
+// Echoes, profiles and subimages may be stored as half or bfloat16 pairs
+// (template parameter ST); every sum is float32.  With IEEE half each stage's
+// array carries a power-of-two scale, scales[0] for the profiles and scales[d]
+// for depth d, chosen per call from the largest echo component and the plan's
+// worst-case gain of each stage, so that no stored value can exceed 2^15.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -41,18 +47,59 @@ __global__ __launch_bounds__(kBlock) void k_prep_positions(const double *__restr
 }
 
 // ---------------------------------------------------------------------------
-// Range compression as a real GEMM, C[M x N] = A[perm(M) x K] * B[K x N], with
-// A the echoes as interleaved floats (K = 2 Nf), B the block form of the
-// pre-corrected DFT matrix (N = 2 Nr) and C the profiles (interleaved).
-// Block tile 64 x 64, four waves of 32 x 32, each 2 x 2 v_mfma_f32_16x16x4f32.
+// Scales for half storage.  k_absmax: the largest |component| of the echoes
+// (non-negative float bits order like unsigned integers).  k_scales:
+// scale_k = 2^-ceil(log2(m mult_k / 2^15)), mult_k the worst-case gain from the
+// echoes to stage k; without a mult (other storage types) every scale is 1.
+__global__ __launch_bounds__(kBlock) void k_zero_u32(uint32_t *p) { if (threadIdx.x == 0) *p = 0u; }
+
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_absmax(const typename Store<ST>::R *__restrict__ a,
+                                                   int64_t n, uint32_t *__restrict__ out)
+{
+    float m = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        m = fmaxf(m, fabsf(Store<ST>::ldr(a[i])));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+__global__ __launch_bounds__(64) void k_scales(const uint32_t *__restrict__ amax,
+                                               const float *__restrict__ mult, int n,
+                                               float *__restrict__ scales)
+{
+    const int k = threadIdx.x;
+    if (k >= n) return;
+    float s = 1.0f;
+    if (mult) {
+        const float b = __uint_as_float(*amax) * mult[k];
+        if (b > 0.0f && isfinite(b)) {
+            int e = (int)ceilf(log2f(b)) - 15;
+            e = max(-100, min(100, e));
+            s = ldexpf(1.0f, -e);
+        }
+    }
+    scales[k] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Range compression as a real GEMM, C[M x N] = scale A[perm(M) x K] B[K x N], with
+// A the echoes as interleaved reals (K = 2 Nf), B the block form of the
+// pre-corrected DFT matrix (float32, N = 2 Nr) and C the profiles (interleaved).
+// Inputs are widened to float32 in LDS; block tile 64 x 64, four waves of
+// 32 x 32, each 2 x 2 v_mfma_f32_16x16x4f32.
 constexpr int kGemmKC = 32;
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(kBlock) void k_rc_gemm(const float *__restrict__ A,
+template <int SA, int SC>
+__global__ __launch_bounds__(kBlock) void k_rc_gemm(const typename Store<SA>::R *__restrict__ A,
                                                     const int32_t *__restrict__ perm, int M,
                                                     int K, const float *__restrict__ B, int N,
-                                                    float *__restrict__ C,
-                                                    const int32_t *__restrict__ c_perm)
+                                                    typename Store<SC>::R *__restrict__ C,
+                                                    const int32_t *__restrict__ c_perm,
+                                                    const float *__restrict__ scale)
 {
     __shared__ float As[64][kGemmKC + 1];
     __shared__ float Bs[kGemmKC][64 + 4];
@@ -66,17 +113,17 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const float *__restrict__ A,
         for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
     for (int k0 = 0; k0 < K; k0 += kGemmKC) {
-        // A tile: 64 rows x 32 k; thread t loads 8 consecutive floats of one row
+        // A tile: 64 rows x 32 k; thread t loads 8 consecutive reals of one row
         {
             const int r = tid >> 2, kk = (tid & 3) * 8;
             const int grow = row0 + r;
             const bool ok = grow < M;
             const int arow = ok ? (perm ? perm[grow] : grow) : 0;
-            const float *src = A + (size_t)arow * K + k0 + kk;
+            const typename Store<SA>::R *src = A + (size_t)arow * K + k0 + kk;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int kg = k0 + kk + e;
-                As[r][kk + e] = (ok && kg < K) ? src[e] : 0.0f;
+                As[r][kk + e] = (ok && kg < K) ? Store<SA>::ldr(src[e]) : 0.0f;
             }
         }
         // B tile: 32 k x 64 cols; thread t loads 8 consecutive floats of one k row
@@ -105,6 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const float *__restrict__ A,
         }
         __syncthreads();
     }
+    const float sc = scale ? scale[0] : 1.0f;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -115,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const float *__restrict__ A,
                 const int col = col0 + wc + b * 16 + (lane & 15);
                 if (row < M && col < N) {
                     const int crow = c_perm ? c_perm[row] : row;
-                    C[(size_t)crow * N + col] = acc[a][b][r];
+                    C[(size_t)crow * N + col] = Store<SC>::str(acc[a][b][r] * sc);
                 }
             }
 }
@@ -123,19 +171,22 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const float *__restrict__ A,
 // ---------------------------------------------------------------------------
 // Level-1 BP.  One lane per leaf grid point q; the leaf's positions are staged
 // through LDS in chunks together with their range profiles (leaf-sorted, so a
-// chunk's profiles are one contiguous block).  Per (q, i):
+// chunk's profiles are one contiguous block, widened to float32 on staging).
+// Per (q, i):
 //   Delta R = |q - p'_i| - |q - c| = (|delta|^2 - 2 d.delta) / (|q - p'_i| + |q - c|)
 //   g = sum_w phi_w(t) prof_i[r_first + w],   t = (|q - c| - R0)/dR + Delta R / dR
 //   acc += g exp(j 2 kc Delta R)
 // and f'(q) = acc exp(j (2 kc |q - c| - Phi(q))), the last factor precomputed.
-template <int KERNEL, int W>
+template <int KERNEL, int W, int ST>
 __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ leaves,
                                                     const BlockItem *__restrict__ blocks,
                                                     const LeafPoint *__restrict__ pts,
                                                     const float4 *__restrict__ posoff,
-                                                    const float2 *__restrict__ prof, int Nr,
-                                                    int chunk, float inv_dR, float beta_log2e,
-                                                    float kc_turns, float2 *__restrict__ out)
+                                                    const typename Store<ST>::C *__restrict__ prof,
+                                                    int Nr, int chunk, float inv_dR,
+                                                    float beta_log2e, float kc_turns,
+                                                    const float *__restrict__ scales, int S,
+                                                    typename Store<ST>::C *__restrict__ out)
 {
     extern __shared__ unsigned char smem[];
     float4 *s_pos = reinterpret_cast<float4 *>(smem);
@@ -153,8 +204,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
         const int n = min(chunk, nd.pos_end - c0);
         __syncthreads();
         for (int t = threadIdx.x; t < n; t += kBlock) s_pos[t] = posoff[c0 + t];
-        const float2 *src = prof + (size_t)c0 * Nr;
-        for (int t = threadIdx.x; t < n * Nr; t += kBlock) s_prof[t] = src[t];
+        const typename Store<ST>::C *src = prof + (size_t)c0 * Nr;
+        for (int t = threadIdx.x; t < n * Nr; t += kBlock) s_prof[t] = Store<ST>::ld(src[t]);
         __syncthreads();
         if (active) {
             for (int i = 0; i < n; ++i) {
@@ -188,14 +239,15 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
         }
     }
     if (active) {
-        out[nd.val_base + p] =
-            make_float2(acc_re * q.pre_re - acc_im * q.pre_im, acc_re * q.pre_im + acc_im * q.pre_re);
+        const float rs = scales[S] / scales[0];
+        out[nd.val_base + p] = Store<ST>::st(make_float2(rs * (acc_re * q.pre_re - acc_im * q.pre_im),
+                                                         rs * (acc_re * q.pre_im + acc_im * q.pre_re)));
     }
 }
 
 // Merge at depth d: parent grid points (float64 SoA) of the depth-d nodes,
 // children at depth d + 1.  Output: compressed parent values.
-template <int T>
+template <int T, int ST>
 __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ parents,
                                                   const BlockItem *__restrict__ blocks,
                                                   const double *__restrict__ px,
@@ -203,8 +255,9 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
                                                   const double *__restrict__ pz,
                                                   const NodeDev *__restrict__ children,
                                                   const ColEntry *__restrict__ ccols,
-                                                  const float2 *__restrict__ cvals, GeoParams gp,
-                                                  float2 *__restrict__ out)
+                                                  const typename Store<ST>::C *__restrict__ cvals,
+                                                  GeoParams gp, const float *__restrict__ scales,
+                                                  int d, typename Store<ST>::C *__restrict__ out)
 {
     const BlockItem blk = blocks[blockIdx.x];
     const NodeDev nd = parents[blk.node];
@@ -213,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
     const int gi = nd.val_base + p;
     const double x = px[gi], y = py[gi], z = pz[gi];
     if (!(z > 0.0)) {  // absent grid point (no preimage): holds 0
-        out[gi] = make_float2(0.0f, 0.0f);
+        out[gi] = Store<ST>::st(make_float2(0.0f, 0.0f));
         return;
     }
     const double phip = phi_only(nd, x, y, z, gp.kmin, gp.kmax);
@@ -222,17 +275,19 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
     for (int c = 0; c < nd.nchild; ++c) {
         const NodeDev ch = children[child_idx[c]];
         const ChildCoord g = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
-        const float2 v = interp_child<T>(ch, ccols, cvals, g);
+        const float2 v = interp_child<T, ST>(ch, ccols, cvals, g);
         phase_mac(v, g.phi - phip, are, aim);
     }
-    out[gi] = make_float2(are, aim);
+    const float rs = scales[d] / scales[d + 1];
+    out[gi] = Store<ST>::st(make_float2(rs * are, rs * aim));
 }
 
 // Final stage: user voxels, children are the depth-1 nodes.
-template <int T>
+template <int T, int ST>
 __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ children,
                                                   int nchild, const ColEntry *__restrict__ ccols,
-                                                  const float2 *__restrict__ cvals, GeoParams gp,
+                                                  const typename Store<ST>::C *__restrict__ cvals,
+                                                  GeoParams gp, const float *__restrict__ scales,
                                                   double ox, double oy, double oz, double sx,
                                                   double sy, double sz, int nx, int ny, int nz,
                                                   float2 *__restrict__ image)
@@ -248,10 +303,11 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
     for (int c = 0; c < nchild; ++c) {
         const NodeDev ch = children[c];
         const ChildCoord g = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
-        const float2 val = interp_child<T>(ch, ccols, cvals, g);
+        const float2 val = interp_child<T, ST>(ch, ccols, cvals, g);
         phase_mac(val, g.phi, are, aim);
     }
-    image[v] = make_float2(are, aim);
+    const float rs = 1.0f / scales[1];
+    image[v] = make_float2(rs * are, rs * aim);
 }
 
 // ---------------------------------------------------------------------------
@@ -268,12 +324,12 @@ struct StagedPos {
     float car_re, car_im;
 };
 
-template <int KERNEL, int W>
+template <int KERNEL, int W, int ST>
 __global__ __launch_bounds__(kBlock) void k_direct_bp(
-    const double *__restrict__ pos64, int n_pos, const float2 *__restrict__ prof, int Nr,
-    int chunk, double R0, double dR, float inv_dR, float beta_log2e, double kc, float kc_turns, double ox,
-    double oy, double oz, double sx, double sy, double sz, int nx, int ny, int nz,
-    float2 *__restrict__ image)
+    const double *__restrict__ pos64, int n_pos, const typename Store<ST>::C *__restrict__ prof,
+    int Nr, int chunk, double R0, double dR, float inv_dR, float beta_log2e, double kc,
+    float kc_turns, double ox, double oy, double oz, double sx, double sy, double sz, int nx,
+    int ny, int nz, const float *__restrict__ scales, float2 *__restrict__ image)
 {
     extern __shared__ unsigned char smem[];
     StagedPos *s_pos = reinterpret_cast<StagedPos *>(smem);
@@ -315,8 +371,8 @@ __global__ __launch_bounds__(kBlock) void k_direct_bp(
             sp.car_im = (float)sn;
             s_pos[threadIdx.x] = sp;
         }
-        const float2 *src = prof + (size_t)c0 * Nr;
-        for (int t = threadIdx.x; t < n * Nr; t += kBlock) s_prof[t] = src[t];
+        const typename Store<ST>::C *src = prof + (size_t)c0 * Nr;
+        for (int t = threadIdx.x; t < n * Nr; t += kBlock) s_prof[t] = Store<ST>::ld(src[t]);
         __syncthreads();
         if (active) {
             for (int i = 0; i < n; ++i) {
@@ -350,14 +406,19 @@ __global__ __launch_bounds__(kBlock) void k_direct_bp(
             }
         }
     }
-    if (active) image[((int64_t)ix * ny + iy) * nz + iz] = make_float2(acc_re, acc_im);
+    if (active) {
+        const float rs = 1.0f / scales[0];
+        image[((int64_t)ix * ny + iy) * nz + iz] = make_float2(rs * acc_re, rs * acc_im);
+    }
 }
 
 // ---------------------------------------------------------------------------
-template <int KERNEL, int W>
-hipError_t launch_bp_kernels(const Plan &P, const double *pos64, const float2 *prof,
-                             const float4 *posoff, char *ws, void *image, hipStream_t st)
+template <int KERNEL, int W, int ST>
+hipError_t launch_bp_kernels(const Plan &P, const double *pos64, const void *prof,
+                             const float4 *posoff, char *ws, void *image, const float *scales,
+                             hipStream_t st)
 {
+    using C = typename Store<ST>::C;
     const float inv_dR = (float)(1.0 / P.dR);
     const float beta_log2e = (float)(P.beta * 1.4426950408889634);
     const float kc_turns = (float)(P.kc / kPi);
@@ -367,51 +428,124 @@ hipError_t launch_bp_kernels(const Plan &P, const double *pos64, const float2 *p
         const int nblk = ((nx + 3) / 4) * ((ny + 7) / 8) * ((nz + 7) / 8);
         const int chunk = pos_chunk(P.Nr, sizeof(StagedPos));
         const size_t sh = chunk * (sizeof(StagedPos) + P.Nr * sizeof(float2));
-        hipLaunchKernelGGL((k_direct_bp<KERNEL, W>), dim3(nblk), dim3(kBlock), sh, st,
-                           pos64, (int)c.n_pos, prof, (int)P.Nr, chunk, P.R0, P.dR,
-                           inv_dR, beta_log2e, P.kc, kc_turns, c.grid_origin[0], c.grid_origin[1],
+        hipLaunchKernelGGL((k_direct_bp<KERNEL, W, ST>), dim3(nblk), dim3(kBlock), sh, st, pos64,
+                           (int)c.n_pos, (const C *)prof, (int)P.Nr, chunk, P.R0, P.dR, inv_dR,
+                           beta_log2e, P.kc, kc_turns, c.grid_origin[0], c.grid_origin[1],
                            c.grid_origin[2], c.grid_pitch[0], c.grid_pitch[1], c.grid_pitch[2], nx,
-                           ny, nz, (float2 *)image);
+                           ny, nz, scales, (float2 *)image);
         return hipGetLastError();
     }
     const int chunk = pos_chunk(P.Nr, sizeof(float4));
     const size_t sh = chunk * (sizeof(float4) + P.Nr * sizeof(float2));
-    hipLaunchKernelGGL((k_leaf_bp<KERNEL, W>), dim3(P.n_blocks_leaf), dim3(kBlock), sh, st,
+    hipLaunchKernelGGL((k_leaf_bp<KERNEL, W, ST>), dim3(P.n_blocks_leaf), dim3(kBlock), sh, st,
                        (const NodeDev *)P.dev.nodes[P.S], (const BlockItem *)P.dev.leaf_blocks,
-                       (const LeafPoint *)P.dev.leafpts, posoff, prof, (int)P.Nr, chunk, inv_dR,
-                       beta_log2e, kc_turns, (float2 *)(ws + P.ws_vals[P.S]));
+                       (const LeafPoint *)P.dev.leafpts, posoff, (const C *)prof, (int)P.Nr, chunk,
+                       inv_dR, beta_log2e, kc_turns, scales, P.S, (C *)(ws + P.ws_vals[P.S]));
     return hipGetLastError();
 }
 
-template <int T>
-hipError_t launch_merges(const Plan &P, char *ws, void *image, hipStream_t st, hipEvent_t *ev)
+template <int T, int ST>
+hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scales, hipStream_t st,
+                         hipEvent_t *ev)
 {
+    using C = typename Store<ST>::C;
     GeoParams gp{P.gamma[0], P.gamma[1], P.gamma[2], P.kmin, P.kmax};
     for (int d = P.S - 1; d >= 1; --d) {
-        if (P.n_blocks_merge[d] == 0) continue;
-        hipLaunchKernelGGL((k_merge<T>), dim3(P.n_blocks_merge[d]), dim3(kBlock), 0, st,
-                           (const NodeDev *)P.dev.nodes[d], (const BlockItem *)P.dev.merge_blocks[d],
-                           (const double *)P.dev.px[d], (const double *)P.dev.py[d],
-                           (const double *)P.dev.pz[d], (const NodeDev *)P.dev.nodes[d + 1],
-                           (const ColEntry *)P.dev.cols[d + 1],
-                           (const float2 *)(ws + P.ws_vals[d + 1]), gp,
-                           (float2 *)(ws + P.ws_vals[d]));
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if (P.n_blocks_merge[d] > 0) {
+            hipLaunchKernelGGL((k_merge<T, ST>), dim3(P.n_blocks_merge[d]), dim3(kBlock), 0, st,
+                               (const NodeDev *)P.dev.nodes[d],
+                               (const BlockItem *)P.dev.merge_blocks[d], (const double *)P.dev.px[d],
+                               (const double *)P.dev.py[d], (const double *)P.dev.pz[d],
+                               (const NodeDev *)P.dev.nodes[d + 1],
+                               (const ColEntry *)P.dev.cols[d + 1],
+                               (const C *)(ws + P.ws_vals[d + 1]), gp, scales, d,
+                               (C *)(ws + P.ws_vals[d]));
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
         if (ev) (void)hipEventRecord(*ev++, st);
     }
     const hhffbp_config &c = P.cfg;
     const int nx = (int)c.grid_dims[0], ny = (int)c.grid_dims[1], nz = (int)c.grid_dims[2];
     const int64_t nv = (int64_t)nx * ny * nz;
     const int nblk = (int)((nv + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_final<T>), dim3(nblk), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((k_final<T, ST>), dim3(nblk), dim3(kBlock), 0, st,
                        (const NodeDev *)P.dev.nodes[1], (int)P.compact_to_tree[1].size(),
-                       (const ColEntry *)P.dev.cols[1], (const float2 *)(ws + P.ws_vals[1]), gp,
+                       (const ColEntry *)P.dev.cols[1], (const C *)(ws + P.ws_vals[1]), gp, scales,
                        c.grid_origin[0], c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0],
                        c.grid_pitch[1], c.grid_pitch[2], nx, ny, nz, (float2 *)image);
     hipError_t e = hipGetLastError();
     if (ev && e == hipSuccess) (void)hipEventRecord(*ev, st);
     return e;
+}
+
+template <int ST>
+hipError_t launch_scales(const Plan &P, const void *echoes, char *ws, hipStream_t st)
+{
+    float *scales = (float *)(ws + P.ws_scales);
+    uint32_t *amax = (uint32_t *)(ws + P.ws_amax);
+    const int ns = P.S + 1;
+    if (ST == HHFFBP_F16) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, st, amax);
+        const int64_t n = 2 * P.cfg.n_pos * P.cfg.n_freq;
+        const int nb = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL((k_absmax<ST>), dim3(nb), dim3(kBlock), 0, st,
+                           (const typename Store<ST>::R *)echoes, n, amax);
+        hipLaunchKernelGGL(k_scales, dim3(1), dim3(64), 0, st, (const uint32_t *)amax,
+                           (const float *)P.dev.scale_mult, ns, scales);
+    } else {
+        hipLaunchKernelGGL(k_scales, dim3(1), dim3(64), 0, st, (const uint32_t *)amax,
+                           (const float *)nullptr, ns, scales);
+    }
+    return hipGetLastError();
+}
+
+template <int ST>
+hhffbp_status image_for_storage(const Plan &P, const void *echoes, const double *pos64,
+                                void *image, char *ws, hipStream_t st, hipEvent_t *ev)
+{
+    const hhffbp_config &c = P.cfg;
+    const int n = (int)c.n_pos;
+    void *prof = ws + P.ws_prof;
+    float4 *posoff = (float4 *)(ws + P.ws_posoff);
+    const float *scales = (const float *)(ws + P.ws_scales);
+    hipError_t e = launch_scales<ST>(P, echoes, ws, st);
+    if (e != hipSuccess) return HHFFBP_E_DEVICE;
+    if (P.S > 0) {
+        hipLaunchKernelGGL(k_prep_positions, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                           pos64, (const int32_t *)P.dev.perm, (const int32_t *)P.dev.leaf_of_sorted,
+                           (const double *)P.dev.leaf_centre, n, posoff);
+        if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
+        if (ev) (void)hipEventRecord(*ev++, st);
+    }
+    {
+        const int M = n, K = (int)(2 * c.n_freq), N = (int)(2 * P.Nr);
+        dim3 grid((M + 63) / 64, (N + 63) / 64);
+        hipLaunchKernelGGL((k_rc_gemm<ST, ST>), grid, dim3(kBlock), 0, st,
+                           (const typename Store<ST>::R *)echoes, (const int32_t *)P.dev.perm, M, K,
+                           (const float *)P.dev.B, N, (typename Store<ST>::R *)prof,
+                           (const int32_t *)nullptr, scales);
+        if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
+        if (ev) (void)hipEventRecord(*ev++, st);
+    }
+    if (P.kernel == HHFFBP_RANGE_LINEAR) {
+        e = launch_bp_kernels<HHFFBP_RANGE_LINEAR, 2, ST>(P, pos64, prof, posoff, ws, image, scales, st);
+    } else {
+        switch (P.W) {
+        case 4: e = launch_bp_kernels<HHFFBP_RANGE_ES, 4, ST>(P, pos64, prof, posoff, ws, image, scales, st); break;
+        case 5: e = launch_bp_kernels<HHFFBP_RANGE_ES, 5, ST>(P, pos64, prof, posoff, ws, image, scales, st); break;
+        case 6: e = launch_bp_kernels<HHFFBP_RANGE_ES, 6, ST>(P, pos64, prof, posoff, ws, image, scales, st); break;
+        case 7: e = launch_bp_kernels<HHFFBP_RANGE_ES, 7, ST>(P, pos64, prof, posoff, ws, image, scales, st); break;
+        case 8: e = launch_bp_kernels<HHFFBP_RANGE_ES, 8, ST>(P, pos64, prof, posoff, ws, image, scales, st); break;
+        default: return HHFFBP_E_UNSUPPORTED;
+        }
+    }
+    if (e != hipSuccess) return HHFFBP_E_DEVICE;
+    if (ev) (void)hipEventRecord(*ev++, st);
+    if (P.S == 0) return HHFFBP_OK;
+    e = (P.T == 4) ? launch_merges<4, ST>(P, ws, image, scales, st, ev)
+                   : launch_merges<6, ST>(P, ws, image, scales, st, ev);
+    return e == hipSuccess ? HHFFBP_OK : HHFFBP_E_DEVICE;
 }
 
 }  // namespace
@@ -425,11 +559,23 @@ hipError_t launch_prep(const Plan &P, const double *pos64, float4 *posoff, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_rc_gemm(const float *A, const int32_t *a_perm, int M, int K, const float *B,
-                          int N, float *C, const int32_t *c_perm, hipStream_t st)
+hipError_t launch_rc_gemm(int storage_a, const void *A, const int32_t *a_perm, int M, int K,
+                          const float *B, int N, float *C, const int32_t *c_perm, hipStream_t st)
 {
     dim3 grid((M + 63) / 64, (N + 63) / 64);
-    hipLaunchKernelGGL(k_rc_gemm, grid, dim3(kBlock), 0, st, A, a_perm, M, K, B, N, C, c_perm);
+    switch (storage_a) {
+    case HHFFBP_F16:
+        hipLaunchKernelGGL((k_rc_gemm<HHFFBP_F16, HHFFBP_C64>), grid, dim3(kBlock), 0, st,
+                           (const uint16_t *)A, a_perm, M, K, B, N, C, c_perm, (const float *)nullptr);
+        break;
+    case HHFFBP_BF16:
+        hipLaunchKernelGGL((k_rc_gemm<HHFFBP_BF16, HHFFBP_C64>), grid, dim3(kBlock), 0, st,
+                           (const uint16_t *)A, a_perm, M, K, B, N, C, c_perm, (const float *)nullptr);
+        break;
+    default:
+        hipLaunchKernelGGL((k_rc_gemm<HHFFBP_C64, HHFFBP_C64>), grid, dim3(kBlock), 0, st,
+                           (const float *)A, a_perm, M, K, B, N, C, c_perm, (const float *)nullptr);
+    }
     return hipGetLastError();
 }
 
@@ -450,45 +596,12 @@ hhffbp_status launch_image(const Plan &P, const void *echoes, const double *posi
                            void *image, char *ws, hipStream_t st, hipEvent_t *ev)
 {
     if (ev) (void)hipEventRecord(*ev++, st);
-    const hhffbp_config &c = P.cfg;
-    const int n = (int)c.n_pos;
     const double *pos64 = positions ? positions : (const double *)P.dev.pos64;
-    float2 *prof = (float2 *)(ws + P.ws_prof);
-    float4 *posoff = (float4 *)(ws + P.ws_posoff);
-    hipError_t e = hipSuccess;
-    if (P.S > 0) {
-        hipLaunchKernelGGL(k_prep_positions, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
-                           pos64, (const int32_t *)P.dev.perm, (const int32_t *)P.dev.leaf_of_sorted,
-                           (const double *)P.dev.leaf_centre, n, posoff);
-        if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
-        if (ev) (void)hipEventRecord(*ev++, st);
+    switch (P.cfg.storage) {
+    case HHFFBP_F16: return image_for_storage<HHFFBP_F16>(P, echoes, pos64, image, ws, st, ev);
+    case HHFFBP_BF16: return image_for_storage<HHFFBP_BF16>(P, echoes, pos64, image, ws, st, ev);
+    default: return image_for_storage<HHFFBP_C64>(P, echoes, pos64, image, ws, st, ev);
     }
-    {
-        const int M = n, K = (int)(2 * c.n_freq), N = (int)(2 * P.Nr);
-        dim3 grid((M + 63) / 64, (N + 63) / 64);
-        hipLaunchKernelGGL(k_rc_gemm, grid, dim3(kBlock), 0, st, (const float *)echoes,
-                           (const int32_t *)P.dev.perm, M, K, (const float *)P.dev.B, N,
-                           (float *)prof, (const int32_t *)nullptr);
-        if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
-        if (ev) (void)hipEventRecord(*ev++, st);
-    }
-    if (P.kernel == HHFFBP_RANGE_LINEAR) {
-        e = launch_bp_kernels<HHFFBP_RANGE_LINEAR, 2>(P, pos64, prof, posoff, ws, image, st);
-    } else {
-        switch (P.W) {
-        case 4: e = launch_bp_kernels<HHFFBP_RANGE_ES, 4>(P, pos64, prof, posoff, ws, image, st); break;
-        case 5: e = launch_bp_kernels<HHFFBP_RANGE_ES, 5>(P, pos64, prof, posoff, ws, image, st); break;
-        case 6: e = launch_bp_kernels<HHFFBP_RANGE_ES, 6>(P, pos64, prof, posoff, ws, image, st); break;
-        case 7: e = launch_bp_kernels<HHFFBP_RANGE_ES, 7>(P, pos64, prof, posoff, ws, image, st); break;
-        case 8: e = launch_bp_kernels<HHFFBP_RANGE_ES, 8>(P, pos64, prof, posoff, ws, image, st); break;
-        default: return HHFFBP_E_UNSUPPORTED;
-        }
-    }
-    if (e != hipSuccess) return HHFFBP_E_DEVICE;
-    if (ev) (void)hipEventRecord(*ev++, st);
-    if (P.S == 0) return HHFFBP_OK;
-    e = (P.T == 4) ? launch_merges<4>(P, ws, image, st, ev) : launch_merges<6>(P, ws, image, st, ev);
-    return e == hipSuccess ? HHFFBP_OK : HHFFBP_E_DEVICE;
 }
 
 }  // namespace hh

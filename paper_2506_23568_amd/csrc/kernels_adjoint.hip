@@ -521,7 +521,7 @@ hipError_t launch_scatters(const Plan &P, const void *grad_image, char *ws, hipS
     const unsigned ntile = (unsigned)(((nx + 3) / 4) * ((ny + 7) / 8) * ((nz + 7) / 8));
     (void)nv;
     hipLaunchKernelGGL((k_final_adj<T>), dim3(ntile), dim3(kBlock), 0, st, (const NodeDev *)P.dev.nodes[1], (int)P.compact_to_tree[1].size(),
-                       (const ColEntry *)P.dev.cols[1], (float2 *)(ws + P.ws_vals[1]), gp,
+                       (const ColEntry *)P.dev.cols[1], (float2 *)(ws + P.ws_gvals[1]), gp,
                        c.grid_origin[0], c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0],
                        c.grid_pitch[1], c.grid_pitch[2], nx, ny, nz, (const float2 *)grad_image);
     hipError_t e = hipGetLastError();
@@ -530,9 +530,9 @@ hipError_t launch_scatters(const Plan &P, const void *grad_image, char *ws, hipS
         hipLaunchKernelGGL((k_merge_adj<T>), dim3(P.n_blocks_merge[d]), dim3(kBlock), 0, st,
                            (const NodeDev *)P.dev.nodes[d], (const BlockItem *)P.dev.merge_blocks[d],
                            (const double *)P.dev.px[d], (const double *)P.dev.py[d],
-                           (const double *)P.dev.pz[d], (const float2 *)(ws + P.ws_vals[d]),
+                           (const double *)P.dev.pz[d], (const float2 *)(ws + P.ws_gvals[d]),
                            (const NodeDev *)P.dev.nodes[d + 1], (const ColEntry *)P.dev.cols[d + 1],
-                           (float2 *)(ws + P.ws_vals[d + 1]), gp);
+                           (float2 *)(ws + P.ws_gvals[d + 1]), gp);
         e = hipGetLastError();
     }
     return e;
@@ -557,22 +557,24 @@ hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *p
     if ((e = launch_prep(P, pos64, posoff, st)) != hipSuccess) return HHFFBP_E_DEVICE;
     // range-derivative profiles (only the position gradient needs them)
     if (want_p) {
-        e = launch_rc_gemm((const float *)echoes, (const int32_t *)P.dev.perm, n,
+        e = launch_rc_gemm(c.storage, echoes, (const int32_t *)P.dev.perm, n,
                            (int)(2 * c.n_freq), (const float *)P.dev.Bd, (int)(2 * P.Nr),
                            (float *)dprof, nullptr, st);
         if (e != hipSuccess) return HHFFBP_E_DEVICE;
     }
-    // clear every grid cotangent (depths 1..S are contiguous)
+    // clear every grid cotangent: depths 1..S are contiguous and end at the
+    // 256-byte aligned start of gprof (a point count may be odd, so the float4
+    // clear runs to that aligned end rather than to the last point)
     {
-        const size_t b0 = P.ws_vals[1];
-        const size_t b1 = P.ws_vals[P.S] + (size_t)P.depth_points[P.S] * sizeof(float2);
+        const size_t b0 = P.ws_gvals[1];
+        const size_t b1 = P.ws_gprof;
         const int64_t n4 = (int64_t)((b1 - b0) / sizeof(float4));
         hipLaunchKernelGGL(k_zero, dim3(1024), dim3(kBlock), 0, st, (float4 *)(ws + b0), n4);
         if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
     }
     e = (P.T == 4) ? launch_scatters<4>(P, grad_image, ws, st) : launch_scatters<6>(P, grad_image, ws, st);
     if (e != hipSuccess) return HHFFBP_E_DEVICE;
-    const float2 *gleaf = (const float2 *)(ws + P.ws_vals[P.S]);
+    const float2 *gleaf = (const float2 *)(ws + P.ws_gvals[P.S]);
     float *gmax = (float *)(ws + P.ws_gmax);
     if (want_s) {
         hipLaunchKernelGGL(k_leaf_gmax, dim3((unsigned)P.compact_to_tree[P.S].size()), dim3(kBlock), 0,
@@ -596,7 +598,7 @@ hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *p
     if (e != hipSuccess) return HHFFBP_E_DEVICE;
     if (want_s) {
         // grad_s = gprof conj(W)^T, rows back to the caller's position order
-        e = launch_rc_gemm((const float *)gprof, nullptr, n, (int)(2 * P.Nr),
+        e = launch_rc_gemm(HHFFBP_C64, gprof, nullptr, n, (int)(2 * P.Nr),
                            (const float *)P.dev.Badj, (int)(2 * c.n_freq), (float *)grad_echoes,
                            (const int32_t *)P.dev.perm, st);
         if (e != hipSuccess) return HHFFBP_E_DEVICE;

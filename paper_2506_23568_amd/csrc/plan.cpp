@@ -444,7 +444,8 @@ void validate(const hhffbp_config &c)
     if (!(c.range_oversample >= 1.5 && c.range_oversample <= 16.0))
         bad("range_oversample must be in [1.5, 16]");
     if (!(c.position_slack >= 0.0 && c.position_slack < 0.1)) bad("position_slack must be in [0, 0.1)");
-    if (c.storage != HHFFBP_C64) throw Error{HHFFBP_E_UNSUPPORTED, "only HHFFBP_C64 storage is built"};
+    if (c.storage != HHFFBP_C64 && c.storage != HHFFBP_F16 && c.storage != HHFFBP_BF16)
+        bad("unknown storage type");
     double zmax = -1e300;
     for (int64_t i = 0; i < 3 * c.n_pos; ++i)
         if (!std::isfinite(c.positions[i])) bad("positions must be finite");
@@ -607,19 +608,29 @@ void build_plan_host(Plan &P)
         P.final_pairs = P.n_vox() * (int64_t)P.compact_to_tree[1].size();
     }
 
-    // workspace layout
+    // workspace layout; profiles and subimages in the storage type
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t csz = (c.storage == HHFFBP_C64) ? 8 : 4;
     size_t off = 0;
     P.ws_prof = off;
-    off += al((size_t)c.n_pos * P.Nr * 8);
+    off += al((size_t)c.n_pos * P.Nr * 8);  // also the backward's float32 range-derivative profiles
     P.ws_posoff = off;
     off += al((size_t)c.n_pos * 16);
+    P.ws_scales = off;
+    off += al(64 * sizeof(float));
+    P.ws_amax = off;
+    off += al(sizeof(uint32_t));
     P.ws_vals.assign(S + 1, 0);
     for (int d = 1; d <= S; ++d) {
         P.ws_vals[d] = off;
-        off += al((size_t)P.depth_points[d] * 8);
+        off += al((size_t)P.depth_points[d] * csz);
     }
     P.ws_total = off;
+    P.ws_gvals.assign(S + 1, 0);
+    for (int d = 1; d <= S; ++d) {
+        P.ws_gvals[d] = off;
+        off += al((size_t)P.depth_points[d] * 8);
+    }
     P.ws_gprof = off;
     off += al((size_t)c.n_pos * P.Nr * 8);
     P.ws_gpos = off;
@@ -627,6 +638,31 @@ void build_plan_host(Plan &P)
     P.ws_gmax = off;
     off += al((size_t)std::max<size_t>(1, P.compact_to_tree[S].size()) * sizeof(float));
     P.ws_total_bwd = off;
+
+    // worst-case gain from the echoes to each stage (half-precision scales):
+    // profiles <= sqrt(2) Nf max|W| max|s|; a leaf sums <= members x W taps of
+    // them; a merge sums <= children x L_T^3 (L_T the Lagrange kernel's
+    // largest absolute weight sum on [0, 1)).
+    {
+        double wmax = 0.0;
+        for (size_t i = 0; i < P.Bmat.size(); ++i) wmax = std::max(wmax, (double)std::fabs(P.Bmat[i]));
+        const double lt = (P.T == 4) ? 1.25 : 1.40;
+        P.scale_mult.assign(S + 1, 0.0f);
+        const double m0 = std::sqrt(2.0) * (double)c.n_freq * wmax;
+        P.scale_mult[0] = (float)m0;
+        if (S > 0) {
+            size_t mem_max = 0;
+            for (int32_t ti : P.compact_to_tree[S]) mem_max = std::max(mem_max, P.levels[S][ti].members.size());
+            double m = m0 * (double)mem_max * (double)P.W;
+            P.scale_mult[S] = (float)m;
+            for (int d = S - 1; d >= 1; --d) {
+                size_t nch = 0;
+                for (int32_t ti : P.compact_to_tree[d]) nch = std::max(nch, P.levels[d][ti].children.size());
+                m *= (double)nch * lt * lt * lt;
+                P.scale_mult[d] = (float)m;
+            }
+        }
+    }
     P.plan_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -670,6 +706,7 @@ void upload_plan(Plan &P)
     upload_vec(&D.B, P.Bmat);
     upload_vec(&D.Bd, P.Bdmat);
     upload_vec(&D.Badj, P.Badjmat);
+    upload_vec(&D.scale_mult, P.scale_mult);
     upload_vec(&D.perm, P.perm);
     upload_vec(&D.leaf_of_sorted, P.leaf_of_sorted);
     upload_vec(&D.leaf_centre, P.leaf_centre);
@@ -795,6 +832,7 @@ void release_plan(Plan &P)
     fr(D.adj_blocks);
     fr(D.Bd);
     fr(D.Badj);
+    fr(D.scale_mult);
     for (auto *v : {&D.nodes, &D.cols, &D.px, &D.py, &D.pz, &D.merge_blocks})
         for (auto &p : *v) fr(p);
 }

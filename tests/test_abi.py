@@ -47,7 +47,7 @@ def _args(w):
 
 @pytest.mark.parametrize("change,status", [
     (dict(merge_factor=3), -1), (dict(interp_taps=5), -1), (dict(range_taps=11), -1),
-    (dict(oversample=0.5), -1), (dict(storage="f16"), -2), (dict(stages=-1), -1),
+    (dict(oversample=0.5), -1), (dict(stages=-1), -1),
 ])
 def test_invalid_configurations_are_rejected(small, change, status):
     kw = dict(device=-1)
@@ -55,6 +55,25 @@ def test_invalid_configurations_are_rejected(small, change, status):
     with pytest.raises(H.HHFFBPError) as e:
         H.Plan(*_args(small), **kw)
     assert e.value.status == status
+
+
+def test_unknown_storage_is_rejected(small):
+    c = H.binding.default_config()
+    pos = np.ascontiguousarray(small.positions)
+    fr = np.ascontiguousarray(small.freqs_hz)
+    c.n_pos, c.n_freq = pos.shape[0], fr.shape[0]
+    c.positions = pos.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    c.freqs_hz = fr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for a in range(3):
+        c.grid_origin[a], c.grid_pitch[a], c.grid_dims[a] = (small.grid_origin[a], small.grid_pitch[a],
+                                                             small.grid_dims[a])
+    c.device = -1
+    h = ctypes.c_void_p()
+    for st, want in ((7, -1), (1, 0), (2, 0)):
+        c.storage = st
+        assert H.lib().hhffbp_plan(ctypes.byref(c), ctypes.byref(h)) == want
+        if want == 0:
+            H.lib().hhffbp_plan_destroy(h)
 
 
 def test_invalid_inputs_are_rejected(small):
