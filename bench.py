@@ -34,6 +34,8 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # coordinate 5, kernel weights 6 per tap, tap sums 2 per tap, carrier 5,
 # complex accumulate 4.
 LEAF_OPS_PER_PAIR = 7 + 7 + 5 + 6 * 7 + 2 * 7 + 5 + 4
+KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "hhffbp_internal.hpp")
+TRAFFIC_SUMMARY = "hhffbp_mid_hbm_traffic.md"
 
 
 def log(msg):
@@ -41,7 +43,10 @@ def log(msg):
 
 
 def oracle_cpu_baseline(w, target_s=15.0):
-    """The float64 oracle's eq. (4) on seeded voxels of the same workload."""
+    """The float64 oracle's eq. (4) on seeded voxels of the same workload.
+
+    The sample grows by 4x until one pass takes >= 2 s, then is sized for about
+    ``target_s`` seconds of oracle work; only the last pass is reported."""
     import numpy as np
 
     from oracle import hhffbp as OH
@@ -49,13 +54,19 @@ def oracle_cpu_baseline(w, target_s=15.0):
     from workloads import voxel_centres
 
     vox = voxel_centres(w.grid_origin, w.grid_pitch, w.grid_dims)
+    nv = vox.shape[0]
     rng = np.random.default_rng(3)
-    n = 32
-    t = time.time()
-    OH.direct_bp(w.positions, w.freqs_hz, w.echoes, vox[rng.choice(vox.shape[0], n, replace=False)])
-    dt = time.time() - t
-    n2 = int(max(n, min(vox.shape[0], n * target_s / max(dt, 1e-3))))
-    sel = rng.choice(vox.shape[0], n2, replace=False)
+    n = 8
+    while True:
+        sel = rng.choice(nv, n, replace=False)
+        t = time.time()
+        OH.direct_bp(w.positions, w.freqs_hz, w.echoes, vox[sel])
+        dt = time.time() - t
+        if dt >= 2.0 or n >= nv:
+            break
+        n = min(nv, 4 * n)
+    n2 = int(min(nv, max(n, round(n * target_s / max(dt, 1e-3)))))
+    sel = rng.choice(nv, n2, replace=False)
     t = time.time()
     OH.direct_bp(w.positions, w.freqs_hz, w.echoes, vox[sel])
     dt = time.time() - t
@@ -65,12 +76,53 @@ def oracle_cpu_baseline(w, target_s=15.0):
                       f"{w.n_f} frequencies of the same workload ({dt:.1f} s)"}
 
 
+def kernel_source_hash():
+    """sha256 over the sources that make up the imaging kernels."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2506_23568_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary, or None when it is missing or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic_json:"):
+                rec = json.loads(line[len("traffic_json:"):])
+                if rec.get("source_sha256") != kernel_source_hash():
+                    return None
+                k = rec.get("kernels", {}).get(kernel)
+                return None if k is None else k["bytes_per_launch"]
+    return None
+
+
+def copy_probe(torch, mib):
+    """One plain device copy of ``mib`` MiB (scale reference for HBM counters)."""
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one plain copy of this size first (HBM counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -83,6 +135,8 @@ def main():
     import paper_2506_23568_amd as H
     from workloads import make_config
 
+    if args.copy_mib > 0:
+        copy_probe(torch, args.copy_mib)
     log("synthesising the workload")
     w = make_config(1)
     args3 = (w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims)
@@ -136,12 +190,16 @@ def main():
     direct_vp = w.n_vox * w.n_pos / (dms * 1e-3)
 
     leaf_ms = kernels_ms.get("leaf_bp", float("nan"))
+    leaf_pts = info["level_points"][-1]
     achieved = info["leaf_pairs"] * LEAF_OPS_PER_PAIR / (leaf_ms * 1e-3) / 1e12
     peak = VALU_PEAK_OPS / 1e12
     roofline = {"kernel": "leaf_bp", "bound": "alu", "achieved": achieved, "peak": peak,
-                "unit": "Tops/s", "frac": achieved / peak, "traffic": None,
+                "unit": "Tops/s", "frac": achieved / peak, "traffic": measured_traffic("leaf_bp"),
                 "ops_per_pair": LEAF_OPS_PER_PAIR, "pairs_per_launch": info["leaf_pairs"],
-                "avg_launch_ms": leaf_ms}
+                "avg_launch_ms": leaf_ms,
+                # profiles + leaf points (32 B) + antenna offsets (16 B) in, subimages out
+                "algorithmic_bytes": w.n_pos * info["n_range_bins"] * 8 + leaf_pts * 32
+                + w.n_pos * 16 + leaf_pts * 8}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -13,13 +13,18 @@ _lib = None
 
 
 def _nthreads():
+    """ORACLE_THREADS if set, else the usable cores capped by OMP_NUM_THREADS."""
     n = os.environ.get("ORACLE_THREADS")
     if n:
         return int(n)
     try:
-        return max(1, len(os.sched_getaffinity(0)))
+        c = max(1, len(os.sched_getaffinity(0)))
     except AttributeError:
-        return os.cpu_count() or 1
+        c = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit() and int(omp) > 0:
+        c = min(c, int(omp))
+    return c
 
 
 def lib():
