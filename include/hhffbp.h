@@ -217,6 +217,46 @@ hhffbp_status hhffbp_profile_end(hhffbp_plan_t plan, double *stage_ms, int32_t m
                                  int32_t *n_stages, int32_t *n_calls);
 const char *hhffbp_stage_name(hhffbp_plan_t plan, int32_t index);
 
+/*
+ * Image reductions: quality metrics and the autofocus loss (no plan; they run
+ * on the current HIP device).  image, reference and clean are device
+ * complex64 arrays of n elements in linear order (n = 0 is allowed).  |f|^2 is
+ * formed in float64 from the float32 parts and every sum accumulates in
+ * float64 in a fixed order, so results repeat bit for bit.
+ *
+ * hhffbp_image_stats writes 8 doubles to the device array stats:
+ *   [0] S = sum |f|^2       [1] sum |r|^2         [2] sum |f - r|^2
+ *   [3] sum |f|^2 ln |f|^2, voxels with f = 0 counting 0
+ *   [4] max |f|^2 (0 if n = 0)   [5] its lowest linear index (-1 if n = 0)
+ *   [6] entropy H = -sum q ln q, q = |f|^2 / S, computed as ln S - [3] / S
+ *       (0 if S = 0); the autofocus sharpness measure mentioned in Sec. I
+ *   [7] NRMSE ||f - r|| / ||r|| (NaN without a reference or if ||r|| = 0)
+ * reference may be NULL ([1] = [2] = 0).  workspace: device memory of at least
+ * hhffbp_stats_workspace_bytes() bytes, 8-byte aligned, clobbered.
+ *
+ * hhffbp_loss_grad: from stats of hhffbp_image_stats(image, clean, ...),
+ * enqueued earlier on the same stream, the loss
+ *     L = H(f) + sum |f - c|^2 / sum |c|^2     (second term dropped if clean = NULL)
+ * into the device double *loss (if not NULL) and its cotangent in the
+ * convention dL/dRe f + j dL/dIm f into the device complex64 array grad
+ * (if not NULL):
+ *     grad = -2 f (ln q + H) / S + 2 (f - c) / sum |c|^2
+ * (voxels with f = 0 take no entropy term).  grad may alias neither input.
+ *
+ * hhffbp_box_peaks: for each of n_boxes voxel boxes of a [d0][d1][d2] image
+ * (z fastest), boxes = device int32 [n_boxes][6] (x_lo, x_hi, y_lo, y_hi, z_lo,
+ * z_hi) inclusive and clipped to the grid, writes to the device int64 array
+ * peaks the lowest linear index (ix d1 + iy) d2 + iz of the largest |f|^2 in
+ * the box, or -1 for a box with no voxel inside.
+ */
+hhffbp_status hhffbp_stats_workspace_bytes(size_t *bytes);
+hhffbp_status hhffbp_image_stats(const void *image, const void *reference, int64_t n,
+                                 double *stats, void *workspace, size_t ws_bytes, void *stream);
+hhffbp_status hhffbp_loss_grad(const void *image, const void *clean, int64_t n,
+                               const double *stats, double *loss, void *grad, void *stream);
+hhffbp_status hhffbp_box_peaks(const void *image, const int64_t dims[3], int32_t n_boxes,
+                               const int32_t *boxes, int64_t *peaks, void *stream);
+
 /* Static strings; never NULL. */
 const char *hhffbp_status_string(hhffbp_status status);
 const char *hhffbp_last_error(void);

@@ -93,6 +93,14 @@ def lib():
         L.hhffbp_status_string.restype = ctypes.c_char_p
         L.hhffbp_last_error.argtypes = []
         L.hhffbp_last_error.restype = ctypes.c_char_p
+        L.hhffbp_stats_workspace_bytes.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
+        L.hhffbp_stats_workspace_bytes.restype = ctypes.c_int
+        L.hhffbp_image_stats.argtypes = [vp, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
+        L.hhffbp_image_stats.restype = ctypes.c_int
+        L.hhffbp_loss_grad.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp]
+        L.hhffbp_loss_grad.restype = ctypes.c_int
+        L.hhffbp_box_peaks.argtypes = [vp, ctypes.POINTER(ctypes.c_int64 * 3), i32, vp, vp, vp]
+        L.hhffbp_box_peaks.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -320,3 +328,94 @@ class Plan:
         scale = workspace[so + 4 * depth:so + 4 * depth + 4].view(torch.float32)
         v = workspace[o:o + 4 * n].view(dt).reshape(n, 2).to(torch.float32)
         return torch.view_as_complex(v.contiguous()) / scale
+
+
+# ---------------------------------------------------------------------------
+# Image reductions (hhffbp_image_stats / hhffbp_loss_grad / hhffbp_box_peaks)
+
+STATS_FIELDS = ("energy", "ref_energy", "diff_energy", "sum_a_ln_a", "max_abs2", "argmax",
+                "entropy", "nrmse")
+
+
+def _c64(t, name):
+    import torch
+
+    if not t.is_cuda or t.dtype != torch.complex64:
+        raise TypeError(f"{name} must be a complex64 CUDA tensor")
+    return t.contiguous()
+
+
+def image_stats(image, reference=None, workspace=None, stream=None):
+    """Device float64 tensor [8] (see STATS_FIELDS) of one image, optionally
+    against a reference of the same size."""
+    import torch
+
+    image = _c64(image, "image")
+    n = image.numel()
+    rptr = None
+    if reference is not None:
+        reference = _c64(reference, "reference")
+        if reference.numel() != n:
+            raise ValueError("reference must have as many elements as image")
+        rptr = reference.data_ptr()
+    out = torch.empty(8, dtype=torch.float64, device=image.device)
+    nb = ctypes.c_size_t()
+    _check(lib().hhffbp_stats_workspace_bytes(ctypes.byref(nb)))
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = torch.empty(nb.value, dtype=torch.uint8, device=image.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(image.device).cuda_stream
+    _check(lib().hhffbp_image_stats(image.data_ptr() if n else None, rptr, n, out.data_ptr(),
+                                    workspace.data_ptr(), workspace.numel(), stream))
+    return out
+
+
+def stats_dict(stats):
+    v = stats.cpu().tolist()
+    d = dict(zip(STATS_FIELDS, v))
+    d["argmax"] = int(d["argmax"])
+    return d
+
+
+def loss_grad(image, clean=None, stats=None, want_grad=True, stream=None):
+    """(loss as a device float64 [1], cotangent complex64 like image or None) of
+    L = entropy + ||f - clean||^2 / ||clean||^2."""
+    import torch
+
+    image = _c64(image, "image")
+    n = image.numel()
+    cptr = None
+    if clean is not None:
+        clean = _c64(clean, "clean")
+        if clean.numel() != n:
+            raise ValueError("clean must have as many elements as image")
+        cptr = clean.data_ptr()
+    if stats is None:
+        stats = image_stats(image, clean)
+    loss = torch.empty(1, dtype=torch.float64, device=image.device)
+    grad = torch.empty_like(image) if want_grad else None
+    if stream is None:
+        stream = torch.cuda.current_stream(image.device).cuda_stream
+    _check(lib().hhffbp_loss_grad(image.data_ptr() if n else None, cptr, n, stats.data_ptr(),
+                                  loss.data_ptr(), grad.data_ptr() if grad is not None else None,
+                                  stream))
+    return loss, grad
+
+
+def box_peaks(image, boxes, stream=None):
+    """Lowest linear index of the largest |f|^2 in each inclusive voxel box
+    (int32 [n, 6]: x_lo, x_hi, y_lo, y_hi, z_lo, z_hi; clipped to the grid),
+    -1 for an empty box; device int64 [n]."""
+    import torch
+
+    image = _c64(image, "image")
+    if image.dim() != 3:
+        raise ValueError("image must be 3-D")
+    b = torch.as_tensor(boxes, dtype=torch.int32).reshape(-1, 6).to(image.device).contiguous()
+    out = torch.empty(b.shape[0], dtype=torch.int64, device=image.device)
+    dims = (ctypes.c_int64 * 3)(*image.shape)
+    if stream is None:
+        stream = torch.cuda.current_stream(image.device).cuda_stream
+    _check(lib().hhffbp_box_peaks(image.data_ptr(), ctypes.byref(dims), b.shape[0], b.data_ptr(),
+                                  out.data_ptr(), stream))
+    return out

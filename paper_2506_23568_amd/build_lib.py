@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhhffbp.so")
-SOURCES = ["api.cpp", "plan.cpp", "kernels.hip", "kernels_adjoint.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "kernels.hip", "kernels_adjoint.hip", "kernels_metrics.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -289,6 +289,58 @@ const char *hhffbp_stage_name(hhffbp_plan_t plan, int32_t i)
     return name.c_str();
 }
 
+hhffbp_status hhffbp_stats_workspace_bytes(size_t *bytes)
+{
+    if (!bytes) return fail(HHFFBP_E_INVALID, "hhffbp_stats_workspace_bytes: NULL argument");
+    *bytes = hh::stats_workspace_bytes();
+    return HHFFBP_OK;
+}
+
+hhffbp_status hhffbp_image_stats(const void *image, const void *reference, int64_t n,
+                                 double *stats, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (n < 0) return fail(HHFFBP_E_INVALID, "hhffbp_image_stats: n < 0");
+    if (!stats || (n > 0 && !image))
+        return fail(HHFFBP_E_INVALID, "hhffbp_image_stats: NULL argument");
+    if (!workspace || ws_bytes < hh::stats_workspace_bytes())
+        return fail(HHFFBP_E_WORKSPACE, "hhffbp_image_stats: workspace missing or smaller than " +
+                                            std::to_string(hh::stats_workspace_bytes()) + " bytes");
+    if (reinterpret_cast<uintptr_t>(workspace) % 8 != 0)
+        return fail(HHFFBP_E_WORKSPACE, "hhffbp_image_stats: workspace must be 8-byte aligned");
+    const hipError_t e = hh::launch_image_stats(image, reference, n, stats, workspace,
+                                                (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(HHFFBP_E_DEVICE, std::string("hhffbp_image_stats: ") + hipGetErrorString(e));
+    return HHFFBP_OK;
+}
+
+hhffbp_status hhffbp_loss_grad(const void *image, const void *clean, int64_t n,
+                               const double *stats, double *loss, void *grad, void *stream)
+{
+    if (n < 0) return fail(HHFFBP_E_INVALID, "hhffbp_loss_grad: n < 0");
+    if (!stats || (grad && n > 0 && !image))
+        return fail(HHFFBP_E_INVALID, "hhffbp_loss_grad: NULL argument");
+    const hipError_t e = hh::launch_loss_grad(image, clean, n, stats, loss, grad,
+                                              (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(HHFFBP_E_DEVICE, std::string("hhffbp_loss_grad: ") + hipGetErrorString(e));
+    return HHFFBP_OK;
+}
+
+hhffbp_status hhffbp_box_peaks(const void *image, const int64_t dims[3], int32_t n_boxes,
+                               const int32_t *boxes, int64_t *peaks, void *stream)
+{
+    if (!dims || n_boxes < 0 || (n_boxes > 0 && (!image || !boxes || !peaks)))
+        return fail(HHFFBP_E_INVALID, "hhffbp_box_peaks: bad argument");
+    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1)
+        return fail(HHFFBP_E_INVALID, "hhffbp_box_peaks: dims must be positive");
+    const hipError_t e = hh::launch_box_peaks(image, dims, n_boxes, boxes, peaks,
+                                              (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(HHFFBP_E_DEVICE, std::string("hhffbp_box_peaks: ") + hipGetErrorString(e));
+    return HHFFBP_OK;
+}
+
 const char *hhffbp_status_string(hhffbp_status s)
 {
     switch (s) {

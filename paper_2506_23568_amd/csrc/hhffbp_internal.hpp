@@ -163,4 +163,13 @@ hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *p
 hhffbp_status launch_image(const Plan &plan, const void *echoes, const double *positions,
                            void *image, char *ws, hipStream_t stream, hipEvent_t *events);
 
+// Image reductions (kernels_metrics.hip); no plan, current device.
+size_t stats_workspace_bytes();
+hipError_t launch_image_stats(const void *image, const void *ref, int64_t n, double *stats,
+                              void *ws, hipStream_t st);
+hipError_t launch_loss_grad(const void *image, const void *clean, int64_t n, const double *stats,
+                            double *loss, void *grad, hipStream_t st);
+hipError_t launch_box_peaks(const void *image, const int64_t dims[3], int32_t n_boxes,
+                            const int32_t *boxes, int64_t *peaks, hipStream_t st);
+
 }  // namespace hh

@@ -128,3 +128,23 @@ def test_host_plan_matches_oracle_plan(small, S, Q, gamma, T):
             xyz = pl.node_points(d, i)
             assert np.array_equal(np.isfinite(xyz[:, 2]), L.valid)
             assert np.max(np.abs(xyz[L.valid] - L.xyz[L.valid])) < 1e-12
+
+
+def test_reductions_validate_without_a_gpu():
+    L = H.lib()
+    nb = ctypes.c_size_t()
+    assert L.hhffbp_stats_workspace_bytes(ctypes.byref(nb)) == 0 and nb.value == 1024 * 8 * 8
+    assert L.hhffbp_stats_workspace_bytes(None) == -1
+    dummy = ctypes.c_void_p(256)  # never dereferenced: every call below fails validation first
+    assert L.hhffbp_image_stats(None, None, 10, dummy, dummy, nb.value, None) == -1
+    assert L.hhffbp_image_stats(dummy, None, -1, dummy, dummy, nb.value, None) == -1
+    assert L.hhffbp_image_stats(dummy, None, 10, dummy, None, nb.value, None) == -5
+    assert L.hhffbp_image_stats(dummy, None, 10, dummy, dummy, nb.value - 8, None) == -5
+    assert L.hhffbp_loss_grad(dummy, None, 10, None, dummy, dummy, None) == -1
+    assert L.hhffbp_loss_grad(dummy, None, -3, dummy, dummy, dummy, None) == -1
+    dims = (ctypes.c_int64 * 3)(4, 0, 4)
+    assert L.hhffbp_box_peaks(dummy, ctypes.byref(dims), 1, dummy, dummy, None) == -1
+    dims = (ctypes.c_int64 * 3)(4, 4, 4)
+    assert L.hhffbp_box_peaks(dummy, ctypes.byref(dims), -1, dummy, dummy, None) == -1
+    assert L.hhffbp_box_peaks(None, ctypes.byref(dims), 2, dummy, dummy, None) == -1
+    assert b"box_peaks" in L.hhffbp_last_error()
