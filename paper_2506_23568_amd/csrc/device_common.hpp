@@ -123,14 +123,25 @@ struct ChildCoord {
     double phi;
 };
 
+// Square root of a positive float64 to ~2e-14 relative: the float32 reciprocal
+// square root as a seed, one Newton step in float64, times x.  The merge
+// geometry needs ~1e-12 relative (lattice coordinates to ~1e-11 of a step,
+// phases to ~1e-12 rad); correctly rounded sqrt costs several times more.
+__device__ __forceinline__ double sqrt_pos(double x)
+{
+    double r = (double)__builtin_amdgcn_rsqf((float)x);
+    r = r * fma(-0.5 * x, r * r, 1.5);
+    return x * r;
+}
+
 __device__ __forceinline__ double phi_only(const NodeDev &c, double x, double y, double z,
                                            double kmin, double kmax)
 {
     const double zz = z * z;
     const double dx0 = x - c.x0, dx1 = x - c.x1, dy0 = y - c.y0, dy1 = y - c.y1;
-    const double r = sqrt(dx0 * dx0 + dy0 * dy0 + zz) + sqrt(dx0 * dx0 + dy1 * dy1 + zz) +
-                     sqrt(dx1 * dx1 + dy0 * dy0 + zz) + sqrt(dx1 * dx1 + dy1 * dy1 + zz);
-    return 0.25 * (kmax * sqrt(r * r - c.d2) + kmin * r);
+    const double r = sqrt_pos(dx0 * dx0 + dy0 * dy0 + zz) + sqrt_pos(dx0 * dx0 + dy1 * dy1 + zz) +
+                     sqrt_pos(dx1 * dx1 + dy0 * dy0 + zz) + sqrt_pos(dx1 * dx1 + dy1 * dy1 + zz);
+    return 0.25 * (kmax * sqrt_pos(r * r - c.d2) + kmin * r);
 }
 
 __device__ __forceinline__ ChildCoord child_coord(const NodeDev &c, double x, double y, double z,
@@ -141,11 +152,11 @@ __device__ __forceinline__ ChildCoord child_coord(const NodeDev &c, double x, do
     const double cx = fmin(fmax(x, c.x0), c.x1), cy = fmin(fmax(y, c.y0), c.y1);
     const double dx0 = x - c.x0, dx1 = x - c.x1, dy0 = y - c.y0, dy1 = y - c.y1;
     const double ex = x - cx, ey = y - cy;
-    const double ru0 = sqrt(dx0 * dx0 + ey * ey + zz), ru1 = sqrt(dx1 * dx1 + ey * ey + zz);
-    const double rv0 = sqrt(ex * ex + dy0 * dy0 + zz), rv1 = sqrt(ex * ex + dy1 * dy1 + zz);
-    const double r = sqrt(dx0 * dx0 + dy0 * dy0 + zz) + sqrt(dx0 * dx0 + dy1 * dy1 + zz) +
-                     sqrt(dx1 * dx1 + dy0 * dy0 + zz) + sqrt(dx1 * dx1 + dy1 * dy1 + zz);
-    const double s = sqrt(r * r - c.d2);
+    const double ru0 = sqrt_pos(dx0 * dx0 + ey * ey + zz), ru1 = sqrt_pos(dx1 * dx1 + ey * ey + zz);
+    const double rv0 = sqrt_pos(ex * ex + dy0 * dy0 + zz), rv1 = sqrt_pos(ex * ex + dy1 * dy1 + zz);
+    const double r = sqrt_pos(dx0 * dx0 + dy0 * dy0 + zz) + sqrt_pos(dx0 * dx0 + dy1 * dy1 + zz) +
+                     sqrt_pos(dx1 * dx1 + dy0 * dy0 + zz) + sqrt_pos(dx1 * dx1 + dy1 * dy1 + zz);
+    const double s = sqrt_pos(r * r - c.d2);
     const double tu = gu * (kmax / kPi) * (ru0 - ru1);
     const double tv = gv * (kmax / kPi) * (rv0 - rv1);
     const double tn = gn * (kmax * s - kmin * r) * (0.25 / kPi);
@@ -177,11 +188,15 @@ __device__ __forceinline__ void lagrange(float x, float *w)
             num *= (x - nm);
             den *= (na - nm);
         }
-        w[a] = num / den;
+        w[a] = num * (1.0f / den);  // den is a compile-time integer: a multiply
     }
 }
 
 // Separable T^3 interpolation of a compressed child subimage (missing points are 0).
+// The grids are built so that every stencil of a planned point lies inside the
+// child's pencils; a pencil whose T taps along n are all present takes the
+// branch-free path (one index sum, T contiguous loads).  The guarded per-tap
+// path remains for stencils that rounding could push past a pencil end.
 template <int T, int ST = HHFFBP_C64>
 __device__ __forceinline__ float2 interp_child(const NodeDev &c, const ColEntry *__restrict__ cols,
                                                const typename Store<ST>::C *__restrict__ vals,
@@ -191,6 +206,7 @@ __device__ __forceinline__ float2 interp_child(const NodeDev &c, const ColEntry 
     lagrange<T>(g.fu, wu);
     lagrange<T>(g.fv, wv);
     lagrange<T>(g.fn, wn);
+    const int l0 = g.bl - T / 2 + 1;
     float are = 0.0f, aim = 0.0f;
 #pragma unroll
     for (int a = 0; a < T; ++a) {
@@ -201,15 +217,26 @@ __device__ __forceinline__ float2 interp_child(const NodeDev &c, const ColEntry 
             const int cj = g.bj + b - T / 2 + 1 - c.j0;
             if ((unsigned)cj >= (unsigned)c.nj) continue;
             const ColEntry e = cols[c.col_base + ci * c.nj + cj];
-            const typename Store<ST>::C *colv = vals + c.val_base + e.off - e.lo;
+            const int rel = l0 - e.lo;
+            const typename Store<ST>::C *colv = vals + (c.val_base + e.off);
             float sre = 0.0f, sim = 0.0f;
+            if (rel >= 0 && rel + T - 1 <= e.hi - e.lo) {
+                const typename Store<ST>::C *p = colv + rel;
 #pragma unroll
-            for (int k = 0; k < T; ++k) {
-                const int l = g.bl + k - T / 2 + 1;
-                if (l >= e.lo && l <= e.hi) {
-                    const float2 v = Store<ST>::ld(colv[l]);
+                for (int k = 0; k < T; ++k) {
+                    const float2 v = Store<ST>::ld(p[k]);
                     sre = fmaf(wn[k], v.x, sre);
                     sim = fmaf(wn[k], v.y, sim);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < T; ++k) {
+                    const int r = rel + k;
+                    if (r >= 0 && r <= e.hi - e.lo) {
+                        const float2 v = Store<ST>::ld(colv[r]);
+                        sre = fmaf(wn[k], v.x, sre);
+                        sim = fmaf(wn[k], v.y, sim);
+                    }
                 }
             }
             const float wab = wu[a] * wv[b];
