@@ -10,7 +10,10 @@ and a 10x10x10 scatterer cube; HHFFBPA with 3 merge stages of factor 4.
 
 A step is one hhffbp_image call: range compression, level-1 backprojection,
 the two intermediate merges and the final merge, with the echoes already
-resident in device memory.  The metric counts voxel x position
+resident in device memory.  The timed form reads the range profiles by linear
+interpolation at 8-fold range oversampling, the fast range mode that the
+direct-BP baseline uses too; the ES-kernel form (the parity mode) is timed and
+reported beside it.  The metric counts voxel x position
 backprojections: N_vox * N_pos per step (the direct-BP work that HHFFBPA
 replaces).  Plan construction (host) is timed separately and reported as
 ``plan_ms``.  One JSON line is printed.
@@ -34,6 +37,9 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # coordinate 5, kernel weights 6 per tap, tap sums 2 per tap, carrier 5,
 # complex accumulate 4.
 LEAF_OPS_PER_PAIR = 7 + 7 + 5 + 6 * 7 + 2 * 7 + 5 + 4
+# ... and with the linear range kernel: the same distance, distance-difference,
+# bin, carrier and accumulate ops, one weight (1 - x) and 2 ops per tap (2 taps).
+LEAF_OPS_LINEAR = 7 + 7 + 5 + 1 + 2 * 2 + 5 + 4
 KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "hhffbp_internal.hpp")
 TRAFFIC_SUMMARY = "hhffbp_mid_hbm_traffic.md"
 
@@ -115,6 +121,63 @@ def copy_probe(torch, mib):
     del src, dst
 
 
+def autofocus_report(args):
+    """Autofocus workload: the large scene imaged at positions with a smooth
+    trajectory error; 20 Adam steps on the positions through forward, loss and
+    backward kernels, for each half-precision storage form."""
+    import numpy as np
+    import torch
+
+    import paper_2506_23568_amd as H
+    from paper_2506_23568_amd.autofocus import autofocus
+    from workloads import make_config
+
+    log("synthesising the autofocus workload (float64 sums on the GPU)")
+    w = make_config(4, synth_device="cuda")
+    p_img = w.imager_positions
+    a3 = (p_img, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims)
+    kw = dict(stages=3, merge_factor=4, oversample=GAMMA, interp_taps=TAPS)
+    pos_true = torch.from_numpy(w.positions).cuda()
+    pos0 = torch.from_numpy(p_img.copy()).cuda()
+    ech64 = torch.from_numpy(w.echoes.astype(np.complex64)).cuda()
+    pd = H.Plan(*a3, mode="direct_rc")
+    ref = pd.image(ech64, positions=pos_true)   # clean-trajectory direct BP (float32, ES)
+    clean = H.Plan(*a3, **kw).image(ech64, positions=pos_true)
+    nref = torch.linalg.norm(ref)
+    out = {}
+    for storage in ("f16", "bf16"):
+        pl = H.Plan(*a3, storage=storage, **kw)
+        ech = H.Plan.pack_echoes(torch.from_numpy(w.echoes), storage).cuda()
+        e0 = (torch.linalg.norm(pl.image(ech, positions=pos0) - ref) / nref).item()
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        pos, hist = autofocus(pl, ech, pos0, steps=args.steps, lr=1e-4, clean=clean)
+        peak = torch.cuda.max_memory_allocated() + pl.info()["device_bytes"]
+        e1 = (torch.linalg.norm(pl.image(ech, positions=pos) - ref) / nref).item()
+        ms = float(np.median([h["ms"] for h in hist[1:]]))
+        out[storage] = {
+            "ms_per_step": ms, "peak_device_bytes": int(peak),
+            "loss_first": hist[0]["loss"], "loss_last": hist[-1]["loss"],
+            "nrmse_vs_clean_direct_db_start": 20 * np.log10(e0),
+            "nrmse_vs_clean_direct_db_end": 20 * np.log10(e1),
+            "mean_position_error_mm_start": (pos0 - pos_true).norm(dim=1).mean().item() * 1e3,
+            "mean_position_error_mm_end": (pos - pos_true).norm(dim=1).mean().item() * 1e3,
+        }
+        log(f"{storage}: {out[storage]}")
+    steps_s = args.steps / (out["f16"]["ms_per_step"] * args.steps * 1e-3)
+    print(json.dumps({
+        "metric": "autofocus steps/s (forward + loss + backward + Adam), half storage",
+        "value": steps_s, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+        "ms_per_step": out["f16"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f16 storage, f32 arithmetic", "data": "synthetic",
+        "config": {"workload": "autofocus: 65536 positions (44 strokes + 20 dense walks), 128 f "
+                               "24-40 GHz, 256x256x128 voxels at 1 mm, 200 points + 5000-scatterer "
+                               "slab, smooth trajectory error, S=3 Q=4, 20 Adam steps lr 0.1 mm on 8 cosine modes per axis",
+                   "parallelism": "single GPU"},
+        "storage": out,
+        "reference": "float32 direct BP (ES U=2 W=7) at the true positions, full grid"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,11 +186,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain copy of this size first (HBM counter scale)")
+    ap.add_argument("--workload", choices=["mid", "autofocus"], default="mid",
+                    help="mid: the imaging benchmark (default); autofocus: the trajectory "
+                         "correction loop on the large scene")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(see DESIGN.md for how the work would shard)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "autofocus":
+        autofocus_report(args)
+        return
 
     import numpy as np
     import torch
@@ -142,39 +212,47 @@ def main():
     args3 = (w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims)
     dev = torch.device("cuda:0")
     ech = torch.from_numpy(w.echoes.astype(np.complex64)).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    kw = dict(stages=3, merge_factor=4, oversample=GAMMA, interp_taps=TAPS)
+
+    def timed(plan, steps, warmup):
+        """(ms per image over ``steps`` calls, per-stage ms, image)."""
+        ws = plan._workspace(torch)
+        img = torch.empty(w.grid_dims, dtype=torch.complex64, device=dev)
+        for _ in range(warmup):
+            plan.image(ech, out=img, workspace=ws)
+        torch.cuda.synchronize()
+        plan.profile_begin(steps)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.image(ech, out=img, workspace=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        st = plan.profile_end()
+        return e0.elapsed_time(e1) / steps, {k: v[0] / max(v[1], 1) for k, v in st.items()}, img
+
+    # the benchmarked form: range profiles read by linear interpolation at U = 8,
+    # the same fast range mode as the direct-BP baseline
     t = time.time()
-    plan = H.Plan(*args3, stages=3, merge_factor=4, oversample=GAMMA, interp_taps=TAPS,
-                  range_kernel="es", range_oversample=2.0, range_taps=7)
+    plan = H.Plan(*args3, range_kernel="linear", range_oversample=8.0, **kw)
     plan_ms = (time.time() - t) * 1e3
     info = plan.info()
-    ws = plan._workspace(torch)
-    img = torch.empty(w.grid_dims, dtype=torch.complex64, device=dev)
-    stream = torch.cuda.current_stream(dev)
-
-    log("warm-up")
-    for _ in range(args.warmup):
-        plan.image(ech, out=img, workspace=ws)
-    torch.cuda.synchronize()
-    plan.profile_begin(args.steps)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        plan.image(ech, out=img, workspace=ws)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    stages = plan.profile_end()
-    kernels_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items()}
+    log("warm-up and timed steps")
+    ms, kernels_ms, img = timed(plan, args.steps, args.warmup)
     value = w.n_vox * w.n_pos / (ms * 1e-3)
 
-    log("direct-BP references")
+    log("parity-mode HHFFBPA (ES range kernel) and the direct-BP references")
+    plan_es = H.Plan(*args3, range_kernel="es", range_oversample=2.0, range_taps=7, **kw)
+    ms_es, kernels_es, img_es = timed(plan_es, max(3, args.steps // 2), 1)
     ref_plan = H.Plan(*args3, mode="direct_rc", range_kernel="es", range_oversample=2.0,
                       range_taps=7)
     ref = ref_plan.image(ech)
     torch.cuda.synchronize()
     nref = torch.linalg.norm(ref)
     nrmse = (torch.linalg.norm(img - ref) / nref).item()
+    nrmse_es = (torch.linalg.norm(img_es - ref) / nref).item()
     fast = H.Plan(*args3, mode="direct_rc", range_kernel="linear", range_oversample=8.0)
     dimg = fast.image(ech)
     torch.cuda.synchronize()
@@ -189,17 +267,20 @@ def main():
     d_nrmse = (torch.linalg.norm(dimg - ref) / nref).item()
     direct_vp = w.n_vox * w.n_pos / (dms * 1e-3)
 
-    leaf_ms = kernels_ms.get("leaf_bp", float("nan"))
-    leaf_pts = info["level_points"][-1]
-    achieved = info["leaf_pairs"] * LEAF_OPS_PER_PAIR / (leaf_ms * 1e-3) / 1e12
-    peak = VALU_PEAK_OPS / 1e12
-    roofline = {"kernel": "leaf_bp", "bound": "alu", "achieved": achieved, "peak": peak,
-                "unit": "Tops/s", "frac": achieved / peak, "traffic": measured_traffic("leaf_bp"),
-                "ops_per_pair": LEAF_OPS_PER_PAIR, "pairs_per_launch": info["leaf_pairs"],
-                "avg_launch_ms": leaf_ms,
+    def leaf_roofline(kms, inf, ops, kernel):
+        lms = kms.get("leaf_bp", float("nan"))
+        pts = inf["level_points"][-1]
+        a = inf["leaf_pairs"] * ops / (lms * 1e-3) / 1e12
+        pk = VALU_PEAK_OPS / 1e12
+        return {"kernel": kernel, "bound": "alu", "achieved": a, "peak": pk, "unit": "Tops/s",
+                "frac": a / pk, "traffic": measured_traffic(kernel), "ops_per_pair": ops,
+                "pairs_per_launch": inf["leaf_pairs"], "avg_launch_ms": lms,
                 # profiles + leaf points (32 B) + antenna offsets (16 B) in, subimages out
-                "algorithmic_bytes": w.n_pos * info["n_range_bins"] * 8 + leaf_pts * 32
-                + w.n_pos * 16 + leaf_pts * 8}
+                "algorithmic_bytes": w.n_pos * inf["n_range_bins"] * 8 + pts * 32
+                + w.n_pos * 16 + pts * 8}
+
+    roofline = leaf_roofline(kernels_ms, info, LEAF_OPS_LINEAR, "leaf_bp")
+    roofline_es = leaf_roofline(kernels_es, plan_es.info(), LEAF_OPS_PER_PAIR, "leaf_bp_es")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -215,9 +296,13 @@ def main():
                                "50 points + 10x10x10 cube at 0.3 m",
                    "n_pos": w.n_pos, "n_freq": w.n_f, "grid": list(w.grid_dims),
                    "stages": 3, "merge_factor": 4, "oversample": list(GAMMA), "interp_taps": TAPS,
-                   "range_kernel": "es", "range_taps": 7, "range_oversample": 2.0,
+                   "range_kernel": "linear", "range_oversample": 8.0,
                    "parallelism": "single GPU"},
         "nrmse_vs_direct_db": 20 * np.log10(nrmse),
+        "reference": "float32 direct BP, ES range kernel U=2 W=7 (<= 1e-5 of float64 eq. 4)",
+        "hhffbp_es": {"value": w.n_vox * w.n_pos / (ms_es * 1e-3), "ms": ms_es,
+                      "mode": "ES U=2 W=7 (parity mode)", "kernels_ms": kernels_es,
+                      "nrmse_vs_direct_db": 20 * np.log10(nrmse_es), "roofline": roofline_es},
         "direct_bp": {"value": direct_vp, "unit": "vp/s", "ms": dms, "mode": "linear U=8",
                       "nrmse_vs_es_direct_db": 20 * np.log10(d_nrmse)},
         "speedup_vs_direct": value / direct_vp,

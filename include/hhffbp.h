@@ -68,7 +68,8 @@ enum { HHFFBP_C64 = 0, HHFFBP_F16 = 1, HHFFBP_BF16 = 2 };
 /* Kernel used to evaluate a range profile between its samples. */
 enum {
     HHFFBP_RANGE_ES = 0,     /* exponential-of-semicircle, pre-corrected DFT    */
-    HHFFBP_RANGE_LINEAR = 1  /* two-tap linear, uncorrected (fast, ~-40 dB)      */
+    HHFFBP_RANGE_LINEAR = 1  /* two-tap linear, pre-corrected by the triangle
+                                kernel's transform (fast; ~-61 dB vs ES at U = 8) */
 };
 
 typedef struct {
@@ -165,7 +166,8 @@ typedef struct {
     int32_t stages, merge_factor, n_leaves, n_nodes;
     int64_t n_pos, n_freq, n_vox;
     int64_t n_range_bins;           /* N_r                                      */
-    double range_lo, range_step;    /* R_0 and delta R of the profile grid (m)  */
+    double range_lo, range_step;    /* R_0 and delta R of the profile grid (m); R_0 is a
+                                       whole multiple of delta R (samples at b delta R) */
     int64_t level_points[16];       /* grid points summed over depth d = 1..S   */
     int64_t leaf_pairs;             /* sum over leaves of points x positions    */
     int64_t merge_pairs;            /* (parent point, child) pairs, depths 1..S-1 */
@@ -175,6 +177,7 @@ typedef struct {
     int64_t ws_scales_offset;       /* workspace byte offset of float scale[S+1]:
                                        stored profiles carry scale[0], depth-d
                                        subimages scale[d] (1 unless HHFFBP_F16) */
+    int64_t device_bytes;           /* device memory the plan holds (its tables) */
 } hhffbp_plan_info;
 
 hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info);

@@ -12,6 +12,10 @@ Test infrastructure (oracle).
    compressed again with its own Phi before the next merge.
 4. The root's grid is the user voxel grid; its sum is the image.
 
+The level-1 sum is eq. (4) itself, or (``range_u``) the fast form: range
+profiles sampled every dR = pi / (U (k_max - k_min)) on the grid R_b = b dR,
+pre-corrected for the linear kernel, and read by linear interpolation.
+
 The interpolation kernel is the separable T-tap Lagrange polynomial through
 the stencil b - T/2 + 1 .. b + T/2 on each axis, b = floor(t + 1e-9) (the
 paper does not name one).  With S = 0 the root is the single subarray and step 1 alone
@@ -71,13 +75,43 @@ def interpolate(lat, vals, t, T, chunk=1 << 17):
     return out
 
 
-def leaf_bp(plan, node, echoes, positions):
+def range_step(kmin, kmax, U):
+    """Range-sample spacing dR = pi / (U (k_max - k_min)): U-fold oversampling of
+    the range profile's band (eq. 2)."""
+    return np.pi / (U * (kmax - kmin))
+
+
+def _bp(plan, positions, echoes, q, range_u):
+    """The level-1 backprojection sum at points q: eq. (4) itself, or with
+    ``range_u`` its range-compressed form with linear interpolation at U-fold
+    oversampling (native.bp_rc_linear)."""
+    if range_u is None:
+        return native.bp_eq4(positions, plan.k, echoes, q)
+    return native.bp_rc_linear(positions, plan.k, echoes, q,
+                               range_step(plan.kmin, plan.kmax, range_u))
+
+
+def leaf_bp(plan, node, echoes, positions, range_u=None):
     """Compressed level-1 subimage f'(q) = exp(-j Phi(q)) * eq.(4) over the leaf's positions."""
     lat = node.lattice
     q = lat.xyz[lat.valid]
-    f = native.bp_eq4(positions[node.members], plan.k, echoes[node.members], q)
+    f = _bp(plan, positions[node.members], echoes[node.members], q, range_u)
     out = np.zeros(lat.size, np.complex128)
     out[lat.valid] = f * np.exp(-1j * G.phi(q, node.rect, plan.kmin, plan.kmax))
+    return out
+
+
+def leaf_bp_at(plan, node, echoes, positions, point_index, range_u=None):
+    """The leaf subimage of ``leaf_bp`` at selected lattice points only (for
+    sampled checks at sizes where whole subimages are too slow); absent points
+    give 0."""
+    lat = node.lattice
+    sel = np.asarray(point_index, np.int64)
+    out = np.zeros(sel.size, np.complex128)
+    ok = lat.valid[sel]
+    q = lat.xyz[sel[ok]]
+    f = _bp(plan, positions[node.members], echoes[node.members], q, range_u)
+    out[ok] = f * np.exp(-1j * G.phi(q, node.rect, plan.kmin, plan.kmax))
     return out
 
 
@@ -95,12 +129,13 @@ def merge_at(plan, node, child_vals, points):
     return acc
 
 
-def image(plan, echoes, positions=None, keep=False):
+def image(plan, echoes, positions=None, keep=False, range_u=None):
     """HHFFBPA image on the voxel grid, (nx, ny, nz) complex128.
 
     ``positions`` are the antenna positions used for backprojection (the plan's
     tree and grids stay as built).  With ``keep`` the compressed subimages of
-    every node are returned as well, keyed by (depth, index).
+    every node are returned as well, keyed by (depth, index).  ``range_u``
+    selects the range-compressed, linearly interpolated level-1 sum (see ``_bp``).
     """
     levels = plan.levels
     if positions is None:
@@ -109,12 +144,12 @@ def image(plan, echoes, positions=None, keep=False):
     echoes = np.asarray(echoes, np.complex128)
     S = len(levels) - 1
     if S == 0:
-        img = native.bp_eq4(positions, plan.k, echoes, plan.voxels)
+        img = _bp(plan, positions, echoes, plan.voxels, range_u)
         return (img.reshape(plan.dims), {}) if keep else img.reshape(plan.dims)
     vals = {}
     for idx, node in enumerate(levels[S]):
         if not node.empty:
-            vals[(S, idx)] = leaf_bp(plan, node, echoes, positions)
+            vals[(S, idx)] = leaf_bp(plan, node, echoes, positions, range_u)
     for d in range(S - 1, 0, -1):
         for idx, node in enumerate(levels[d]):
             if node.empty:
@@ -133,6 +168,13 @@ def direct_bp(positions, freqs_hz, echoes, points):
     """Plain eq. (4) at arbitrary points (float64)."""
     k = 2.0 * np.pi * np.asarray(freqs_hz, float) / 299792458.0
     return native.bp_eq4(positions, k, echoes, points)
+
+
+def direct_bp_linear(positions, freqs_hz, echoes, points, U):
+    """Eq. (4) through range compression with linear interpolation at U-fold
+    range oversampling (float64)."""
+    k = 2.0 * np.pi * np.asarray(freqs_hz, float) / 299792458.0
+    return native.bp_rc_linear(positions, k, echoes, points, range_step(k.min(), k.max(), U))
 
 
 def nrmse(a, ref):

@@ -39,6 +39,8 @@ def lib():
         L.or_bp_eq4.argtypes = [lng, dp, lng, dp, dp, lng, dp, dp, ctypes.c_int]
         L.or_bp_eq4_adjoint.argtypes = [lng, dp, lng, dp, lng, dp, dp, dp, ctypes.c_int]
         L.or_bp_eq4_dpos.argtypes = [lng, dp, lng, dp, dp, lng, dp, dp, dp, ctypes.c_int]
+        L.or_bp_rclin.argtypes = [lng, dp, lng, dp, dp, ctypes.c_double, ctypes.c_double, dp,
+                                  lng, dp, dp, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -87,3 +89,31 @@ def bp_eq4_dpos(positions, k, echoes, points, w, nthreads=None):
                              pts.shape[0], _d(pts), _d(ww.view(np.float64)), _d(g),
                              nthreads or _nthreads())
     return g
+
+
+def linear_precorrection(theta):
+    """1 / Lambda(theta), Lambda(theta) = (sin(theta/2) / (theta/2))^2: the Fourier
+    transform of the unit triangle (linear interpolation) kernel at theta rad per
+    sample.  Dividing the range samples by it removes the interpolation's mean
+    attenuation of each frequency (the reading of eq. (2) used here)."""
+    h = 0.5 * np.asarray(theta, float)
+    out = np.ones_like(h)
+    nz = np.abs(h) > 1e-12
+    out[nz] = (h[nz] / np.sin(h[nz])) ** 2
+    return out
+
+
+def bp_rc_linear(positions, k, echoes, points, dR, precorrect=True, nthreads=None):
+    """Eq. (4) through a range profile sampled every dR (grid R_b = b dR, band
+    demodulated to k_c = (k_min + k_max) / 2) and linearly interpolated."""
+    pos, kk, s, pts = _f64(positions), _f64(k), _c128(echoes), _f64(points)
+    assert s.shape == (pos.shape[0], kk.shape[0])
+    kc = 0.5 * (kk.min() + kk.max())
+    w = _f64(2.0 * (kk - kc))
+    c = _f64(linear_precorrection(w * dR) if precorrect else np.ones_like(w))
+    out = np.zeros(pts.shape[0], np.complex128)
+    if pts.shape[0] and pos.shape[0]:
+        lib().or_bp_rclin(pos.shape[0], _d(pos), kk.shape[0], _d(w), _d(c), float(kc), float(dR),
+                          _d(s.view(np.float64)), pts.shape[0], _d(pts),
+                          _d(out.view(np.float64)), nthreads or _nthreads())
+    return out

@@ -13,6 +13,13 @@
  *                    with dR/dp'_i = -(q - p'_i)/R; the real-valued gradient of
  *                    L = sum_q Re{conj(w) f} with respect to the antenna positions.
  *
+ * or_bp_rclin        eq. (4) through range compression (eq. 2) sampled on the
+ *                    range grid R_b = b dR and read back by linear interpolation:
+ *                        h_i(b) = sum_f s_if c_f exp(+j w_f b dR),  w_f = 2 (k_f - k_c)
+ *                        f(q)   = sum_i exp(+j 2 k_c R) [(1 - x) h_i(b) + x h_i(b + 1)]
+ *                    with R = |q - p'_i|, b = floor(R / dR), x = R / dR - b and c_f
+ *                    the caller's per-frequency pre-correction.
+ *
  * Complex arrays are interleaved (re, im) float64.  Points and positions are
  * (n, 3) float64 row-major.  Every loop is written out; no blocking, no
  * recurrences, one libm sin/cos per term.
@@ -104,5 +111,45 @@ void or_bp_eq4_dpos(long n_pos, const double *pos, long n_f, const double *k,
         grad[3 * i] = gx;
         grad[3 * i + 1] = gy;
         grad[3 * i + 2] = gz;
+    }
+}
+
+static void profile_at(long n_f, const double *si, const double *w, const double *c,
+                       double r, double *hre, double *him)
+{
+    double are = 0.0, aim = 0.0;
+    for (long f = 0; f < n_f; ++f) {
+        double ph = w[f] * r;
+        double cs = cos(ph), sn = sin(ph);
+        are += c[f] * (si[2 * f] * cs - si[2 * f + 1] * sn);
+        aim += c[f] * (si[2 * f] * sn + si[2 * f + 1] * cs);
+    }
+    *hre = are;
+    *him = aim;
+}
+
+void or_bp_rclin(long n_pos, const double *pos, long n_f, const double *w, const double *c,
+                 double kc, double dR, const double *s, long n_pts, const double *pts,
+                 double *out, int nthreads)
+{
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nthreads)
+    for (long q = 0; q < n_pts; ++q) {
+        double acc_re = 0.0, acc_im = 0.0;
+        for (long i = 0; i < n_pos; ++i) {
+            double R = dist3(pts + 3 * q, pos + 3 * i);
+            double t = R / dR;
+            double b = floor(t);
+            double x = t - b;
+            double h0r, h0i, h1r, h1i;
+            profile_at(n_f, s + 2 * n_f * i, w, c, b * dR, &h0r, &h0i);
+            profile_at(n_f, s + 2 * n_f * i, w, c, (b + 1.0) * dR, &h1r, &h1i);
+            double hr = (1.0 - x) * h0r + x * h1r, hi = (1.0 - x) * h0i + x * h1i;
+            double ph = 2.0 * kc * R;
+            double cs = cos(ph), sn = sin(ph);
+            acc_re += hr * cs - hi * sn;
+            acc_im += hr * sn + hi * cs;
+        }
+        out[2 * q] = acc_re;
+        out[2 * q + 1] = acc_im;
     }
 }

@@ -369,7 +369,9 @@ void range_setup(Plan &P, double rmin, double rmax)
     P.dR = kPi / (P.U * dk);
     const int W = P.W;
     const double pad = (0.5 * W + 2.0) * P.dR;
-    P.R0 = rmin - pad;
+    // the grid is anchored at R = 0 (samples at R_b = b dR), so the sampled
+    // profile does not depend on how far the window reaches
+    P.R0 = std::floor((rmin - pad) / P.dR) * P.dR;
     int64_t nr = (int64_t)std::ceil((rmax + pad - P.R0) / P.dR) + 1;
     nr = (nr + 31) / 32 * 32;
     P.Nr = nr;
@@ -675,10 +677,11 @@ namespace hh {
 namespace {
 
 template <class T>
-void upload_vec(void **dst, const std::vector<T> &v)
+void upload_vec(size_t &total, void **dst, const std::vector<T> &v)
 {
     *dst = nullptr;
     if (v.empty()) return;
+    total += v.size() * sizeof(T);
     if (hipMalloc(dst, v.size() * sizeof(T)) != hipSuccess) {
         *dst = nullptr;
         throw Error{HHFFBP_E_NOMEM, "hipMalloc failed during plan upload"};
@@ -699,18 +702,19 @@ void upload_plan(Plan &P)
     P.dev.pz.assign(S + 1, nullptr);
     P.dev.merge_blocks.assign(S + 1, nullptr);
     P.n_blocks_merge.assign(S + 1, 0);
+    P.device_bytes = 0;
     if (P.cfg.device < 0) return;  // host-only plan: geometry and sizes, no device tables
     if (hipSetDevice(P.cfg.device) != hipSuccess)
         throw Error{HHFFBP_E_DEVICE, "hipSetDevice failed"};
     DeviceBuffers &D = P.dev;
-    upload_vec(&D.B, P.Bmat);
-    upload_vec(&D.Bd, P.Bdmat);
-    upload_vec(&D.Badj, P.Badjmat);
-    upload_vec(&D.scale_mult, P.scale_mult);
-    upload_vec(&D.perm, P.perm);
-    upload_vec(&D.leaf_of_sorted, P.leaf_of_sorted);
-    upload_vec(&D.leaf_centre, P.leaf_centre);
-    upload_vec(&D.pos64, P.positions);
+    upload_vec(P.device_bytes, &D.B, P.Bmat);
+    upload_vec(P.device_bytes, &D.Bd, P.Bdmat);
+    upload_vec(P.device_bytes, &D.Badj, P.Badjmat);
+    upload_vec(P.device_bytes, &D.scale_mult, P.scale_mult);
+    upload_vec(P.device_bytes, &D.perm, P.perm);
+    upload_vec(P.device_bytes, &D.leaf_of_sorted, P.leaf_of_sorted);
+    upload_vec(P.device_bytes, &D.leaf_centre, P.leaf_centre);
+    upload_vec(P.device_bytes, &D.pos64, P.positions);
     if (S == 0) return;
     int32_t pos_cursor = 0;
     for (int d = 1; d <= S; ++d) {
@@ -792,24 +796,24 @@ void upload_plan(Plan &P)
             cbase += L.ni * L.nj;
             nodes.push_back(nd);
         }
-        upload_vec(&D.nodes[d], nodes);
-        upload_vec(&D.cols[d], cols);
+        upload_vec(P.device_bytes, &D.nodes[d], nodes);
+        upload_vec(P.device_bytes, &D.cols[d], cols);
         if (d < S) {
-            upload_vec(&D.px[d], x);
-            upload_vec(&D.py[d], y);
-            upload_vec(&D.pz[d], z);
-            upload_vec(&D.merge_blocks[d], blocks);
+            upload_vec(P.device_bytes, &D.px[d], x);
+            upload_vec(P.device_bytes, &D.py[d], y);
+            upload_vec(P.device_bytes, &D.pz[d], z);
+            upload_vec(P.device_bytes, &D.merge_blocks[d], blocks);
             P.n_blocks_merge[d] = (int64_t)blocks.size();
         } else {
-            upload_vec(&D.leafpts, lpts);
-            upload_vec(&D.leaf_blocks, blocks);
+            upload_vec(P.device_bytes, &D.leafpts, lpts);
+            upload_vec(P.device_bytes, &D.leaf_blocks, blocks);
             P.n_blocks_leaf = (int64_t)blocks.size();
             // adjoint work items: each leaf's positions in groups of 16
             std::vector<BlockItem> ab;
             for (size_t li = 0; li < nodes.size(); ++li)
                 for (int32_t p0 = nodes[li].pos_begin; p0 < nodes[li].pos_end; p0 += 16)
                     ab.push_back(BlockItem{(int32_t)li, p0});
-            upload_vec(&D.adj_blocks, ab);
+            upload_vec(P.device_bytes, &D.adj_blocks, ab);
             P.n_blocks_adj = (int64_t)ab.size();
         }
     }

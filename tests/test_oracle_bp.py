@@ -113,3 +113,51 @@ def test_position_gradient_against_central_differences():
             pm[i, a] -= h
             fd = (loss(pp) - loss(pm)) / (2 * h)
             assert abs(fd - g[i, a]) <= 1e-6 * max(1.0, np.max(np.abs(g)))
+
+
+def _rc_case():
+    from workloads import make_config
+    w = make_config(0)
+    vox = voxel_centres(w.grid_origin, w.grid_pitch, w.grid_dims)[::37]
+    k = 2 * math.pi * w.freqs_hz / C0
+    return w, vox, k
+
+
+def test_rc_linear_converges_to_eq4_at_second_order():
+    """Range compression with linear interpolation approaches eq. (4) as the
+    range oversampling U grows, with error ~ dR^2 (an index or sign slip would
+    leave an O(1) or O(dR) error), and the kernel pre-correction removes most
+    of it (a missing or wrong correction keeps the mean attenuation)."""
+    from oracle import hhffbp as OH
+    w, vox, k = _rc_case()
+    ref = native.bp_eq4(w.positions, k, w.echoes, vox)
+    e, e_raw = [], []
+    for U in (4, 8, 16, 32):
+        dR = math.pi / (U * (k.max() - k.min()))
+        e.append(OH.nrmse(native.bp_rc_linear(w.positions, k, w.echoes, vox, dR), ref))
+        e_raw.append(OH.nrmse(native.bp_rc_linear(w.positions, k, w.echoes, vox, dR,
+                                                  precorrect=False), ref))
+    for a, b in zip(e, e[1:]):
+        assert 3.3 < a / b < 4.7
+    for a, b in zip(e, e_raw):
+        assert a < b / 5
+    assert e[1] < 1e-3          # U = 8: below -60 dB
+    # the driver function is the same sum
+    assert np.array_equal(OH.direct_bp_linear(w.positions, w.freqs_hz, w.echoes, vox, 8),
+                          native.bp_rc_linear(w.positions, k, w.echoes, vox,
+                                              OH.range_step(k.min(), k.max(), 8)))
+
+
+def test_rc_linear_linearity_and_global_phase():
+    w, vox, k = _rc_case()
+    dR = math.pi / (8 * (k.max() - k.min()))
+    rng = np.random.default_rng(5)
+    s2 = rng.standard_normal(w.echoes.shape) + 1j * rng.standard_normal(w.echoes.shape)
+    f1 = native.bp_rc_linear(w.positions, k, w.echoes, vox, dR)
+    f2 = native.bp_rc_linear(w.positions, k, s2, vox, dR)
+    a, b = 0.7 - 0.2j, -1.3 + 0.5j
+    f12 = native.bp_rc_linear(w.positions, k, a * w.echoes + b * s2, vox, dR)
+    assert np.linalg.norm(f12 - (a * f1 + b * f2)) <= 1e-12 * np.linalg.norm(f12)
+    th = np.exp(0.9j)
+    fp = native.bp_rc_linear(w.positions, k, th * w.echoes, vox, dR)
+    assert np.linalg.norm(fp - th * f1) <= 1e-12 * np.linalg.norm(f1)

@@ -102,3 +102,23 @@ def test_partition_and_grids(small):
             assert np.max(np.abs(back - L.ijl[ok])) < 1e-8
     # config 0 has an empty leaf: it must be skipped, not fail
     assert any(n.empty for n in pl.levels[S])
+
+
+def test_fast_range_mode(small, direct_small):
+    """Level-1 sums through linearly interpolated range profiles: the image
+    stays within -30 dB of eq. (4) at U = 8, its distance to the eq. (4)-leaf
+    HHFFBPA falls 3-8x per doubling of U (second order or better), and S = 0 reduces to the direct sum
+    of the same form."""
+    pl = _plan(small, 2, gamma=(3.0, 3.0, 3.5))
+    ref = OH.image(pl, small.echoes, small.positions)
+    d = []
+    for U in (8, 16):
+        img = OH.image(pl, small.echoes, small.positions, range_u=U)
+        d.append(OH.nrmse(img, ref))
+        if U == 8:
+            assert 20 * np.log10(OH.nrmse(img, direct_small)) <= -30.0
+    assert 3.0 < d[0] / d[1] < 8.0 and d[0] < 1e-3
+    vox = voxel_centres(small.grid_origin, small.grid_pitch, small.grid_dims)
+    s0 = OH.image(_plan(small, 0), small.echoes, small.positions, range_u=8)
+    lin = OH.direct_bp_linear(small.positions, small.freqs_hz, small.echoes, vox, 8)
+    assert np.max(np.abs(s0.ravel() - lin)) <= 1e-12 * np.max(np.abs(lin))
