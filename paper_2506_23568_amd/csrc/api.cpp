@@ -176,6 +176,7 @@ hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info)
     info->final_pairs = P.final_pairs;
     info->plan_seconds = P.plan_seconds;
     info->storage = P.cfg.storage;
+    info->device_bytes = (int64_t)P.device_bytes;
     info->ws_scales_offset = (int64_t)P.ws_scales;
     return HHFFBP_OK;
 }

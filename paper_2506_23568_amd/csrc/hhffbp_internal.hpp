@@ -127,6 +127,7 @@ struct Plan {
     size_t ws_prof = 0, ws_posoff = 0, ws_total = 0;
     size_t ws_scales = 0, ws_amax = 0;  // per-call storage scales (float [S + 1]) and max |echo|
     size_t ws_gprof = 0, ws_gpos = 0, ws_gmax = 0, ws_total_bwd = 0;  // backward additions
+    size_t device_bytes = 0;  // plan tables uploaded to the device (owned by the plan)
     std::vector<size_t> ws_gvals;        // backward: float32 cotangents per depth
     std::vector<float> scale_mult;       // host copy of dev.scale_mult
     std::vector<size_t> ws_vals;         // per depth

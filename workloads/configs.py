@@ -1,7 +1,7 @@
 """Five synthetic handheld-scan workloads, each fully determined by a seed.
 
 Every random draw uses ``numpy.random.Generator(PCG64(seed))`` with
-``seed = 235680 + index``.  All geometry is float64 metres, frequencies are Hz.
+``seed = 235680 + index`` (index 2 for the autofocus workload).  All geometry is float64 metres, frequencies are Hz.
 
 Scales follow the paper's own experiments (mm-wave band, 0.25-0.4 m range,
 0.1-0.45 m apertures, Sec. V-A and V-C); the measured and full-wave data the
@@ -15,7 +15,8 @@ Index  name            what it is
 2      large           44 strokes + 20 dense walks (65536 positions), 128 f,
                        200 points + a 5000-scatterer slab, 256x256x128 at 1 mm
 3      grad            config 0 geometry with a smooth trajectory error
-4      autofocus       config 2 sizes with a smooth trajectory error
+4      autofocus       config 2's scene and echoes (same seed) with a smooth
+                       trajectory error on the positions handed to the imager
 """
 from __future__ import annotations
 
@@ -111,23 +112,30 @@ def _strokes(rng, n_strokes, per_stroke, half, lat_sigma):
     return np.concatenate(rows, axis=0)
 
 
-def synth_echoes(positions, freqs_hz, target_pos, target_amp, chunk=1024):
-    """Born-model echoes s(p', k) = sum_t a_t exp(-j 2 k |p_t - p'|) (eq. 1), float64."""
+def synth_echoes(positions, freqs_hz, target_pos, target_amp, chunk=1024, device=None):
+    """Born-model echoes s(p', k) = sum_t a_t exp(-j 2 k |p_t - p'|) (eq. 1), float64.
+
+    ``device`` (a torch device string, default the CPU) only chooses where the
+    float64 sums run: the formula and the seeded draws are the same, and the
+    results agree with the CPU ones to float64 rounding (~1e-15 relative)."""
     import torch
 
+    dev = torch.device(device or "cpu")
     k = torch.as_tensor(2.0 * math.pi * np.asarray(freqs_hz, float) / C0, dtype=torch.float64)
-    tp = torch.as_tensor(np.asarray(target_pos, float))
-    ta = torch.as_tensor(np.asarray(target_amp, np.complex128))
+    tp = torch.as_tensor(np.asarray(target_pos, float)).to(dev)
+    ta = torch.as_tensor(np.asarray(target_amp, np.complex128)).to(dev)
     pos = np.asarray(positions, float)
     out = np.empty((pos.shape[0], k.shape[0]), np.complex128)
+    if dev.type != "cpu":
+        chunk = max(chunk, 4096)
     for c0 in range(0, pos.shape[0], chunk):
-        p = torch.as_tensor(pos[c0:c0 + chunk])
+        p = torch.as_tensor(pos[c0:c0 + chunk]).to(dev)
         R = torch.cdist(p, tp, compute_mode="donot_use_mm_for_euclid_dist")   # (n, n_t)
-        acc = torch.empty((p.shape[0], k.shape[0]), dtype=torch.complex128)
+        acc = torch.empty((p.shape[0], k.shape[0]), dtype=torch.complex128, device=dev)
         for f in range(k.shape[0]):
-            ph = (-2.0 * k[f]) * R
+            ph = (-2.0 * float(k[f])) * R
             acc[:, f] = torch.polar(torch.ones_like(ph), ph) @ ta
-        out[c0:c0 + chunk] = acc.numpy()
+        out[c0:c0 + chunk] = acc.cpu().numpy()
     return out
 
 
@@ -150,9 +158,13 @@ def _uniform_in_box(rng, n, lo, hi):
     return rng.uniform(lo, hi, (n, 3))
 
 
-def make_config(index, synth=True, seed=None):
-    """Build workload ``index`` (0..4).  ``synth=False`` skips echo synthesis."""
-    seed = SEED_BASE + index if seed is None else seed
+def make_config(index, synth=True, seed=None, synth_device=None):
+    """Build workload ``index`` (0..4).  ``synth=False`` skips echo synthesis;
+    ``synth_device`` runs the float64 echo sums on a torch device (see
+    ``synth_echoes``)."""
+    # the autofocus workload images the large scene: same seed, then a
+    # trajectory error drawn after the scene
+    seed = SEED_BASE + (2 if index == 4 else index) if seed is None else seed
     rng = np.random.Generator(np.random.PCG64(seed))
     name = CONFIG_NAMES[index]
     noise_var = 0.0
@@ -203,7 +215,7 @@ def make_config(index, synth=True, seed=None):
                  echoes=None, stages=stages, merge_factor=q, imager_positions=imager,
                  seed=seed)
     if synth:
-        s = synth_echoes(pos, freqs, tpos, tamp)
+        s = synth_echoes(pos, freqs, tpos, tamp, device=synth_device)
         if index in (0, 3):
             # 30 dB SNR: per-sample variance = mean |s|^2 / 10^3, circular Gaussian
             noise_var = float(np.mean(np.abs(s) ** 2)) / 1e3
