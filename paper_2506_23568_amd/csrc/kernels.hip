@@ -88,9 +88,13 @@ __global__ __launch_bounds__(64) void k_scales(const uint32_t *__restrict__ amax
 // Range compression as a real GEMM, C[M x N] = scale A[perm(M) x K] B[K x N], with
 // A the echoes as interleaved reals (K = 2 Nf), B the block form of the
 // pre-corrected DFT matrix (float32, N = 2 Nr) and C the profiles (interleaved).
-// Inputs are widened to float32 in LDS; block tile 64 x 64, four waves of
-// 32 x 32, each 2 x 2 v_mfma_f32_16x16x4f32.
+// Inputs are widened to float32 in LDS, A stored k-major so that the MFMA
+// operand reads (16 consecutive rows per k) are conflict-free; block tile
+// 64 x 64, four waves of 32 x 32, each 2 x 2 v_mfma_f32_16x16x4f32.  With
+// float32 echoes, K % 8 == 0 and 16-byte aligned rows (vec) a thread stages its
+// 8 reals of A and of B with two 16-byte loads each.
 constexpr int kGemmKC = 32;
+constexpr int kGemmPad = 4;
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <int SA, int SC>
@@ -99,10 +103,10 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const typename Store<SA>::R 
                                                     int K, const float *__restrict__ B, int N,
                                                     typename Store<SC>::R *__restrict__ C,
                                                     const int32_t *__restrict__ c_perm,
-                                                    const float *__restrict__ scale)
+                                                    const float *__restrict__ scale, int vec)
 {
-    __shared__ float As[64][kGemmKC + 1];
-    __shared__ float Bs[kGemmKC][64 + 4];
+    __shared__ __align__(16) float As[kGemmKC][64 + kGemmPad];  // [k][row]
+    __shared__ __align__(16) float Bs[kGemmKC][64 + kGemmPad];  // [k][col]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
@@ -112,36 +116,53 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const typename Store<SA>::R 
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
+    // this thread's A row and k offset, B k row and column offset within a tile
+    const int ar = tid >> 2, ak = (tid & 3) * 8;
+    const int grow = row0 + ar;
+    const bool arow_ok = grow < M;
+    const int arow = arow_ok ? (perm ? perm[grow] : grow) : 0;
+    const int bk = tid >> 3, bc = (tid & 7) * 8;
+
     for (int k0 = 0; k0 < K; k0 += kGemmKC) {
-        // A tile: 64 rows x 32 k; thread t loads 8 consecutive reals of one row
-        {
-            const int r = tid >> 2, kk = (tid & 3) * 8;
-            const int grow = row0 + r;
-            const bool ok = grow < M;
-            const int arow = ok ? (perm ? perm[grow] : grow) : 0;
-            const typename Store<SA>::R *src = A + (size_t)arow * K + k0 + kk;
+        float av8[8], bv8[8];
+        const int kg = k0 + ak;
+        if constexpr (SA == HHFFBP_C64) {
+            if (vec && arow_ok && kg + 8 <= K) {
+                const float4 *src = reinterpret_cast<const float4 *>(A + (size_t)arow * K + kg);
+                const float4 u = src[0], v = src[1];
+                av8[0] = u.x; av8[1] = u.y; av8[2] = u.z; av8[3] = u.w;
+                av8[4] = v.x; av8[5] = v.y; av8[6] = v.z; av8[7] = v.w;
+            } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int kg = k0 + kk + e;
-                As[r][kk + e] = (ok && kg < K) ? Store<SA>::ldr(src[e]) : 0.0f;
+                for (int e = 0; e < 8; ++e)
+                    av8[e] = (arow_ok && kg + e < K) ? A[(size_t)arow * K + kg + e] : 0.0f;
             }
-        }
-        // B tile: 32 k x 64 cols; thread t loads 8 consecutive floats of one k row
-        {
-            const int kr = tid >> 3, cc = (tid & 7) * 8;
-            const int kg = k0 + kr;
+        } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int cg = col0 + cc + e;
-                Bs[kr][cc + e] = (kg < K && cg < N) ? B[(size_t)kg * N + cg] : 0.0f;
-            }
+            for (int e = 0; e < 8; ++e)
+                av8[e] = (arow_ok && kg + e < K) ? Store<SA>::ldr(A[(size_t)arow * K + kg + e]) : 0.0f;
         }
+        const int kb = k0 + bk, cg = col0 + bc;
+        if (vec && kb < K && cg + 8 <= N) {
+            const float4 *src = reinterpret_cast<const float4 *>(B + (size_t)kb * N + cg);
+            const float4 u = src[0], v = src[1];
+            bv8[0] = u.x; bv8[1] = u.y; bv8[2] = u.z; bv8[3] = u.w;
+            bv8[4] = v.x; bv8[5] = v.y; bv8[6] = v.z; bv8[7] = v.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                bv8[e] = (kb < K && cg + e < N) ? B[(size_t)kb * N + cg + e] : 0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) As[ak + e][ar] = av8[e];
+        *reinterpret_cast<float4 *>(&Bs[bk][bc]) = make_float4(bv8[0], bv8[1], bv8[2], bv8[3]);
+        *reinterpret_cast<float4 *>(&Bs[bk][bc + 4]) = make_float4(bv8[4], bv8[5], bv8[6], bv8[7]);
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < kGemmKC; kk += 4) {
             float av[2], bv[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = As[wr + a * 16 + (lane & 15)][kk + (lane >> 4)];
+            for (int a = 0; a < 2; ++a) av[a] = As[kk + (lane >> 4)][wr + a * 16 + (lane & 15)];
 #pragma unroll
             for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + (lane >> 4)][wc + b * 16 + (lane & 15)];
 #pragma unroll
@@ -166,6 +187,13 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const typename Store<SA>::R 
                     C[(size_t)crow * N + col] = Store<SC>::str(acc[a][b][r] * sc);
                 }
             }
+}
+
+// 16-byte staging needs K % 8 == 0, N % 4 == 0 and 16-byte aligned operands.
+inline int gemm_vec(const void *A, int K, const float *B, int N)
+{
+    return (K % 8 == 0 && N % 4 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
+            reinterpret_cast<uintptr_t>(B) % 16 == 0) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -524,7 +552,7 @@ hhffbp_status image_for_storage(const Plan &P, const void *echoes, const double 
         hipLaunchKernelGGL((k_rc_gemm<ST, ST>), grid, dim3(kBlock), 0, st,
                            (const typename Store<ST>::R *)echoes, (const int32_t *)P.dev.perm, M, K,
                            (const float *)P.dev.B, N, (typename Store<ST>::R *)prof,
-                           (const int32_t *)nullptr, scales);
+                           (const int32_t *)nullptr, scales, gemm_vec(echoes, K, (const float *)P.dev.B, N));
         if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
         if (ev) (void)hipEventRecord(*ev++, st);
     }
@@ -566,15 +594,18 @@ hipError_t launch_rc_gemm(int storage_a, const void *A, const int32_t *a_perm, i
     switch (storage_a) {
     case HHFFBP_F16:
         hipLaunchKernelGGL((k_rc_gemm<HHFFBP_F16, HHFFBP_C64>), grid, dim3(kBlock), 0, st,
-                           (const uint16_t *)A, a_perm, M, K, B, N, C, c_perm, (const float *)nullptr);
+                           (const uint16_t *)A, a_perm, M, K, B, N, C, c_perm, (const float *)nullptr,
+                           gemm_vec(A, K, B, N));
         break;
     case HHFFBP_BF16:
         hipLaunchKernelGGL((k_rc_gemm<HHFFBP_BF16, HHFFBP_C64>), grid, dim3(kBlock), 0, st,
-                           (const uint16_t *)A, a_perm, M, K, B, N, C, c_perm, (const float *)nullptr);
+                           (const uint16_t *)A, a_perm, M, K, B, N, C, c_perm, (const float *)nullptr,
+                           gemm_vec(A, K, B, N));
         break;
     default:
         hipLaunchKernelGGL((k_rc_gemm<HHFFBP_C64, HHFFBP_C64>), grid, dim3(kBlock), 0, st,
-                           (const float *)A, a_perm, M, K, B, N, C, c_perm, (const float *)nullptr);
+                           (const float *)A, a_perm, M, K, B, N, C, c_perm, (const float *)nullptr,
+                           gemm_vec(A, K, B, N));
     }
     return hipGetLastError();
 }
