@@ -239,12 +239,13 @@ const char *hhffbp_stage_name(hhffbp_plan_t plan, int32_t index);
  *
  * hhffbp_loss_grad: from stats of hhffbp_image_stats(image, clean, ...),
  * enqueued earlier on the same stream, the loss
- *     L = H(f) + sum |f - c|^2 / sum |c|^2     (second term dropped if clean = NULL)
- * into the device double *loss (if not NULL) and its cotangent in the
- * convention dL/dRe f + j dL/dIm f into the device complex64 array grad
- * (if not NULL):
- *     grad = -2 f (ln q + H) / S + 2 (f - c) / sum |c|^2
- * (voxels with f = 0 take no entropy term).  grad may alias neither input.
+ *     L = w_entropy H(f) + w_l2 sum |f - c|^2 / sum |c|^2
+ * (second term dropped if clean = NULL) into the device double *loss (if not
+ * NULL) and its cotangent in the convention dL/dRe f + j dL/dIm f into the
+ * device complex64 array grad (if not NULL):
+ *     grad = w_entropy (-2 f (ln q + H) / S) + w_l2 (2 (f - c) / sum |c|^2)
+ * (voxels with f = 0 take no entropy term).  Weights must be finite; grad may
+ * alias neither input.
  *
  * hhffbp_box_peaks: for each of n_boxes voxel boxes of a [d0][d1][d2] image
  * (z fastest), boxes = device int32 [n_boxes][6] (x_lo, x_hi, y_lo, y_hi, z_lo,
@@ -256,7 +257,8 @@ hhffbp_status hhffbp_stats_workspace_bytes(size_t *bytes);
 hhffbp_status hhffbp_image_stats(const void *image, const void *reference, int64_t n,
                                  double *stats, void *workspace, size_t ws_bytes, void *stream);
 hhffbp_status hhffbp_loss_grad(const void *image, const void *clean, int64_t n,
-                               const double *stats, double *loss, void *grad, void *stream);
+                               const double *stats, double w_entropy, double w_l2, double *loss,
+                               void *grad, void *stream);
 hhffbp_status hhffbp_box_peaks(const void *image, const int64_t dims[3], int32_t n_boxes,
                                const int32_t *boxes, int64_t *peaks, void *stream);
 

@@ -12,9 +12,12 @@ kernels make that correction a gradient method.
 
 Motion model: positions = p0 + B c, with B the first K cosine modes over the
 acquisition index, cos(pi m (i + 1/2) / N) for m = 0..K-1, one coefficient
-column per axis.  Free per-position updates (K = 0) are available too; with
-~10^5 coordinates and a few steps they follow the entropy term into
-over-sharpened images rather than towards the true trajectory.
+column per axis.  Free per-position updates (K = 0) are available too.
+
+Objective: by default the relative L2 distance to a reference image of the
+same scene (the clean-trajectory image).  The image entropy is available as a
+second term; on scenes dominated by distributed random reflectivity, lowering
+it does not lead towards the true trajectory.
 """
 import math
 
@@ -29,12 +32,14 @@ def cosine_basis(n, k, device):
     return torch.cos(t[:, None] * torch.arange(k, dtype=torch.float64, device=device)[None, :])
 
 
-def autofocus(plan, echoes, positions, steps=20, lr=1e-4, clean=None, modes=8, on_step=None):
+def autofocus(plan, echoes, positions, steps=20, lr=3e-5, clean=None, modes=16, w_entropy=0.0,
+              w_l2=1.0, on_step=None):
     """Run ``steps`` Adam steps (learning rate ``lr`` metres) on the motion model
     around ``positions`` (float64 [n_pos, 3] on the plan's device).
 
-    ``modes``: cosine modes per axis (0 = every coordinate free).  ``clean``:
-    optional complex64 image for the L2 term of the loss.  Returns (positions,
+    ``modes``: cosine modes per axis (0 = every coordinate free).  The loss is
+    w_entropy H(f) + w_l2 ||f - clean||^2 / ||clean||^2 (``clean`` an optional
+    complex64 image; without it only the entropy term).  Returns (positions,
     history); history holds, per step, the loss before the update and the
     step's device time in ms (forward, loss, backward and update).
     ``on_step(k, positions, image)`` is called after each image, before the
@@ -63,7 +68,7 @@ def autofocus(plan, echoes, positions, steps=20, lr=1e-4, clean=None, modes=8, o
         pos = current()
         plan.image(echoes, positions=pos, out=img, workspace=ws)
         st = image_stats(img, clean)
-        loss, g = loss_grad(img, clean, st)
+        loss, g = loss_grad(img, clean, st, w_entropy=w_entropy, w_l2=w_l2)
         if on_step is not None:
             on_step(k, pos, img)
         _, gp = plan.backward(echoes, g, positions=pos, want_echoes=False, workspace=ws)

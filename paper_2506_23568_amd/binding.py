@@ -98,7 +98,8 @@ def lib():
         L.hhffbp_stats_workspace_bytes.restype = ctypes.c_int
         L.hhffbp_image_stats.argtypes = [vp, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
         L.hhffbp_image_stats.restype = ctypes.c_int
-        L.hhffbp_loss_grad.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp]
+        L.hhffbp_loss_grad.argtypes = [vp, vp, ctypes.c_int64, vp, ctypes.c_double,
+                                       ctypes.c_double, vp, vp, vp]
         L.hhffbp_loss_grad.restype = ctypes.c_int
         L.hhffbp_box_peaks.argtypes = [vp, ctypes.POINTER(ctypes.c_int64 * 3), i32, vp, vp, vp]
         L.hhffbp_box_peaks.restype = ctypes.c_int
@@ -378,9 +379,10 @@ def stats_dict(stats):
     return d
 
 
-def loss_grad(image, clean=None, stats=None, want_grad=True, stream=None):
+def loss_grad(image, clean=None, stats=None, want_grad=True, stream=None, w_entropy=1.0,
+              w_l2=1.0):
     """(loss as a device float64 [1], cotangent complex64 like image or None) of
-    L = entropy + ||f - clean||^2 / ||clean||^2."""
+    L = w_entropy entropy + w_l2 ||f - clean||^2 / ||clean||^2."""
     import torch
 
     image = _c64(image, "image")
@@ -398,8 +400,8 @@ def loss_grad(image, clean=None, stats=None, want_grad=True, stream=None):
     if stream is None:
         stream = torch.cuda.current_stream(image.device).cuda_stream
     _check(lib().hhffbp_loss_grad(image.data_ptr() if n else None, cptr, n, stats.data_ptr(),
-                                  loss.data_ptr(), grad.data_ptr() if grad is not None else None,
-                                  stream))
+                                  float(w_entropy), float(w_l2), loss.data_ptr(),
+                                  grad.data_ptr() if grad is not None else None, stream))
     return loss, grad
 
 

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -316,12 +317,15 @@ hhffbp_status hhffbp_image_stats(const void *image, const void *reference, int64
 }
 
 hhffbp_status hhffbp_loss_grad(const void *image, const void *clean, int64_t n,
-                               const double *stats, double *loss, void *grad, void *stream)
+                               const double *stats, double w_entropy, double w_l2, double *loss,
+                               void *grad, void *stream)
 {
     if (n < 0) return fail(HHFFBP_E_INVALID, "hhffbp_loss_grad: n < 0");
     if (!stats || (grad && n > 0 && !image))
         return fail(HHFFBP_E_INVALID, "hhffbp_loss_grad: NULL argument");
-    const hipError_t e = hh::launch_loss_grad(image, clean, n, stats, loss, grad,
+    if (!std::isfinite(w_entropy) || !std::isfinite(w_l2))
+        return fail(HHFFBP_E_INVALID, "hhffbp_loss_grad: weights must be finite");
+    const hipError_t e = hh::launch_loss_grad(image, clean, n, stats, w_entropy, w_l2, loss, grad,
                                               (hipStream_t)stream);
     if (e != hipSuccess)
         return fail(HHFFBP_E_DEVICE, std::string("hhffbp_loss_grad: ") + hipGetErrorString(e));

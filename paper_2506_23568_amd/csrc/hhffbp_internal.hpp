@@ -169,7 +169,7 @@ size_t stats_workspace_bytes();
 hipError_t launch_image_stats(const void *image, const void *ref, int64_t n, double *stats,
                               void *ws, hipStream_t st);
 hipError_t launch_loss_grad(const void *image, const void *clean, int64_t n, const double *stats,
-                            double *loss, void *grad, hipStream_t st);
+                            double w_ent, double w_l2, double *loss, void *grad, hipStream_t st);
 hipError_t launch_box_peaks(const void *image, const int64_t dims[3], int32_t n_boxes,
                             const int32_t *boxes, int64_t *peaks, hipStream_t st);
 

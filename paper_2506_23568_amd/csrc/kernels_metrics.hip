@@ -3,7 +3,7 @@
 //
 //   k_stats_partial   one grid-stride pass: per-block float64 sums and argmax
 //   k_stats_final     one block folds the partials in a fixed order
-//   k_loss_value      L = H + sum |f - c|^2 / sum |c|^2 from the folded stats
+//   k_loss_value      L = w_ent H + w_l2 sum |f - c|^2 / sum |c|^2 from the folded stats
 //   k_loss_grad       the cotangent dL/dRe f + j dL/dIm f, elementwise
 //   k_box_peaks       argmax of |f|^2 inside each voxel box, one block per box
 //
@@ -140,24 +140,26 @@ __global__ __launch_bounds__(kRedBlock) void k_stats_final(const double *__restr
     }
 }
 
-__global__ void k_loss_value(const double *__restrict__ stats, int has_clean, double *__restrict__ loss)
+__global__ void k_loss_value(const double *__restrict__ stats, int has_clean, double w_ent,
+                             double w_l2, double *__restrict__ loss)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0)
-        loss[0] = stats[6] + (has_clean ? stats[2] / stats[1] : 0.0);
+        loss[0] = w_ent * stats[6] + (has_clean ? w_l2 * stats[2] / stats[1] : 0.0);
 }
 
-// g = -2 f (ln q + H) / S + 2 (f - c) / sum |c|^2,  q = |f|^2 / S; voxels with
-// f = 0 take no entropy term (the limit of f ln |f|^2).
+// g = w_ent (-2 f (ln q + H) / S) + w_l2 (2 (f - c) / sum |c|^2),  q = |f|^2 / S;
+// voxels with f = 0 take no entropy term (the limit of f ln |f|^2).
 template <bool CLEAN>
 __global__ __launch_bounds__(kRedBlock) void k_loss_grad(const float2 *__restrict__ f,
                                                          const float2 *__restrict__ c, int64_t n,
                                                          const double *__restrict__ stats,
+                                                         double w_ent, double w_l2,
                                                          float2 *__restrict__ grad)
 {
     const double S = stats[0], H = stats[6];
     const double lnS = S > 0.0 ? log(S) : 0.0;
-    const double invS = S > 0.0 ? 1.0 / S : 0.0;
-    const double ic2 = CLEAN ? 2.0 / stats[1] : 0.0;
+    const double invS = S > 0.0 ? w_ent / S : 0.0;
+    const double ic2 = CLEAN ? 2.0 * w_l2 / stats[1] : 0.0;
     const int64_t stride = (int64_t)gridDim.x * kRedBlock;
     for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < n; i += stride) {
         const float2 v = f[i];
@@ -225,10 +227,11 @@ hipError_t launch_image_stats(const void *image, const void *ref, int64_t n, dou
 }
 
 hipError_t launch_loss_grad(const void *image, const void *clean, int64_t n, const double *stats,
-                            double *loss, void *grad, hipStream_t st)
+                            double w_ent, double w_l2, double *loss, void *grad, hipStream_t st)
 {
     if (loss) {
-        hipLaunchKernelGGL(k_loss_value, dim3(1), dim3(64), 0, st, stats, clean ? 1 : 0, loss);
+        hipLaunchKernelGGL(k_loss_value, dim3(1), dim3(64), 0, st, stats, clean ? 1 : 0, w_ent,
+                           w_l2, loss);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -237,11 +240,12 @@ hipError_t launch_loss_grad(const void *image, const void *clean, int64_t n, con
         const unsigned g = (unsigned)(nb < 8192 ? nb : 8192);
         if (clean)
             hipLaunchKernelGGL(k_loss_grad<true>, dim3(g), dim3(kRedBlock), 0, st,
-                               (const float2 *)image, (const float2 *)clean, n, stats, (float2 *)grad);
+                               (const float2 *)image, (const float2 *)clean, n, stats, w_ent, w_l2,
+                               (float2 *)grad);
         else
             hipLaunchKernelGGL(k_loss_grad<false>, dim3(g), dim3(kRedBlock), 0, st,
-                               (const float2 *)image, (const float2 *)nullptr, n, stats,
-                               (float2 *)grad);
+                               (const float2 *)image, (const float2 *)nullptr, n, stats, w_ent,
+                               w_l2, (float2 *)grad);
     }
     return hipGetLastError();
 }

@@ -140,8 +140,9 @@ def test_reductions_validate_without_a_gpu():
     assert L.hhffbp_image_stats(dummy, None, -1, dummy, dummy, nb.value, None) == -1
     assert L.hhffbp_image_stats(dummy, None, 10, dummy, None, nb.value, None) == -5
     assert L.hhffbp_image_stats(dummy, None, 10, dummy, dummy, nb.value - 8, None) == -5
-    assert L.hhffbp_loss_grad(dummy, None, 10, None, dummy, dummy, None) == -1
-    assert L.hhffbp_loss_grad(dummy, None, -3, dummy, dummy, dummy, None) == -1
+    assert L.hhffbp_loss_grad(dummy, None, 10, None, 1.0, 1.0, dummy, dummy, None) == -1
+    assert L.hhffbp_loss_grad(dummy, None, -3, dummy, 1.0, 1.0, dummy, dummy, None) == -1
+    assert L.hhffbp_loss_grad(dummy, None, 10, dummy, float("nan"), 1.0, dummy, dummy, None) == -1
     dims = (ctypes.c_int64 * 3)(4, 0, 4)
     assert L.hhffbp_box_peaks(dummy, ctypes.byref(dims), 1, dummy, dummy, None) == -1
     dims = (ctypes.c_int64 * 3)(4, 4, 4)

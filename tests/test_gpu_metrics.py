@@ -105,3 +105,25 @@ def test_box_peaks(torch):
     print(f"  peaks {got.tolist()}", flush=True)
     assert np.array_equal(got, ref)
     assert got[0] == (3 * 29 + 4) * 41 + 5 and got[3] == -1 and got[4] == -1
+
+
+def test_weighted_loss(torch):
+    """L = w_H H + w_2 ||f - c||^2 / ||c||^2 and its cotangent: the same linear
+    combination of the oracle's two terms."""
+    from oracle import loss as OL
+    from oracle import metrics as OM
+    rng = np.random.default_rng(12)
+    n = 40000
+    f, c = _rand(rng, n), _rand(rng, n)
+    wh, w2 = 0.3, 2.5
+    loss, g = H.loss_grad(torch.from_numpy(f).cuda(), torch.from_numpy(c).cuda(), w_entropy=wh,
+                          w_l2=w2)
+    Hf = OM.entropy(f)
+    l2 = OL.loss(f, c) - Hf
+    g_full = OL.loss_cotangent(f, c)
+    fc = f.astype(np.complex128) - c.astype(np.complex128)
+    g_l2 = 2 * fc / np.sum(np.abs(c.astype(np.complex128)) ** 2)
+    ref_g = wh * (g_full - g_l2) + w2 * g_l2
+    assert abs(loss.item() - (wh * Hf + w2 * l2)) <= 1e-12 * abs(wh * Hf + w2 * l2)
+    g = g.cpu().numpy().astype(np.complex128)
+    assert np.linalg.norm(g - ref_g) <= 1e-6 * np.linalg.norm(ref_g)

@@ -130,7 +130,12 @@ def synth_echoes(positions, freqs_hz, target_pos, target_amp, chunk=1024, device
         chunk = max(chunk, 4096)
     for c0 in range(0, pos.shape[0], chunk):
         p = torch.as_tensor(pos[c0:c0 + chunk]).to(dev)
-        R = torch.cdist(p, tp, compute_mode="donot_use_mm_for_euclid_dist")   # (n, n_t)
+        if dev.type == "cpu":
+            R = torch.cdist(p, tp, compute_mode="donot_use_mm_for_euclid_dist")   # (n, n_t)
+        else:
+            # written out: float64 cdist on the GPU has returned wrong distances
+            # for rows past ~870 of a 4096 x 5200 problem on this ROCm build
+            R = torch.sqrt(((p[:, None, :] - tp[None, :, :]) ** 2).sum(-1))
         acc = torch.empty((p.shape[0], k.shape[0]), dtype=torch.complex128, device=dev)
         for f in range(k.shape[0]):
             ph = (-2.0 * float(k[f])) * R
