@@ -94,7 +94,7 @@ __global__ __launch_bounds__(64) void k_scales(const uint32_t *__restrict__ amax
 // float32 echoes, K % 8 == 0 and 16-byte aligned rows (vec) a thread stages its
 // 8 reals of A and of B with two 16-byte loads each.
 constexpr int kGemmKC = 32;
-constexpr int kGemmPad = 4;
+constexpr int kGemmPad = 16;  // row stride 80 floats: the four k groups of an MFMA operand read hit distinct banks
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <int SA, int SC>
