@@ -81,7 +81,10 @@ typedef struct {
     double grid_pitch[3];       /* voxel pitch per axis, > 0                      */
     int64_t grid_dims[3];       /* (nx, ny, nz); image index (ix*ny + iy)*nz + iz */
     int32_t mode;               /* HHFFBP_FACTORIZED or HHFFBP_DIRECT_RC          */
-    int32_t stages;             /* S >= 0: number of merge stages                 */
+    int32_t stages;             /* S >= 0: number of merge stages; S = -K (factorised
+                                   mode): the S in 1..K that minimises the operation
+                                   count of Sec. IV-B on the candidates' exact pair
+                                   counts (per-pair costs measured on MI355X)      */
     int32_t merge_factor;       /* Q = 2 (binary, alternating axes) or 4          */
     double oversample[3];       /* gamma per LLT axis (u, v, n), each in [1, 8]   */
     int32_t interp_taps;        /* T, Lagrange taps per axis: 4 or 6              */
@@ -178,6 +181,8 @@ typedef struct {
                                        stored profiles carry scale[0], depth-d
                                        subimages scale[d] (1 unless HHFFBP_F16) */
     int64_t device_bytes;           /* device memory the plan holds (its tables) */
+    double model_ms;                /* Sec. IV-B cost model: level-1 BP + interpolation,
+                                       with the per-pair costs of hhffbp_config.stages */
 } hhffbp_plan_info;
 
 hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info);

@@ -48,7 +48,7 @@ class PlanInfo(ctypes.Structure):
         ("leaf_pairs", ctypes.c_int64), ("merge_pairs", ctypes.c_int64),
         ("final_pairs", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
         ("storage", ctypes.c_int32), ("ws_scales_offset", ctypes.c_int64),
-        ("device_bytes", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64), ("model_ms", ctypes.c_double),
     ]
 
 

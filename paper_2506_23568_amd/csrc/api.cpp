@@ -54,6 +54,7 @@ hhffbp_status hhffbp_plan(const hhffbp_config *cfg, hhffbp_plan_t *out)
     try {
         h = new hhffbp_plan_s();
         h->plan.cfg = *cfg;
+        hh::choose_stages(h->plan.cfg);
         hh::build_plan_host(h->plan);
         h->plan.cfg.positions = nullptr;
         h->plan.cfg.freqs_hz = nullptr;
@@ -178,6 +179,7 @@ hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info)
     info->plan_seconds = P.plan_seconds;
     info->storage = P.cfg.storage;
     info->device_bytes = (int64_t)P.device_bytes;
+    info->model_ms = 1e3 * P.model_s;
     info->ws_scales_offset = (int64_t)P.ws_scales;
     return HHFFBP_OK;
 }

@@ -128,6 +128,7 @@ struct Plan {
     size_t ws_scales = 0, ws_amax = 0;  // per-call storage scales (float [S + 1]) and max |echo|
     size_t ws_gprof = 0, ws_gpos = 0, ws_gmax = 0, ws_total_bwd = 0;  // backward additions
     size_t device_bytes = 0;  // plan tables uploaded to the device (owned by the plan)
+    double model_s = 0.0;     // the Sec. IV-B cost model's level-1 BP + interpolation time
     std::vector<size_t> ws_gvals;        // backward: float32 cotangents per depth
     std::vector<float> scale_mult;       // host copy of dev.scale_mult
     std::vector<size_t> ws_vals;         // per depth
@@ -148,6 +149,7 @@ struct Error {
 };
 
 void build_plan_host(Plan &plan);
+void choose_stages(hhffbp_config &c);  // stages < 0: pick S by the cost model
 void upload_plan(Plan &plan);
 void release_plan(Plan &plan);
 

@@ -435,7 +435,8 @@ void validate(const hhffbp_config &c)
     if (c.grid_dims[0] * c.grid_dims[1] * c.grid_dims[2] > ((int64_t)1 << 31))
         bad("grid too large");
     if (c.mode != HHFFBP_FACTORIZED && c.mode != HHFFBP_DIRECT_RC) bad("unknown mode");
-    if (c.stages < 0 || c.stages > 8) bad("stages must be in [0, 8]");
+    if (c.stages < -8 || c.stages > 8) bad("stages must be in [-8, 8]");
+    if (c.stages < 0 && c.mode != HHFFBP_FACTORIZED) bad("automatic stages need the factorised mode");
     if (c.merge_factor != 2 && c.merge_factor != 4) bad("merge_factor must be 2 or 4");
     if (c.interp_taps != 4 && c.interp_taps != 6) bad("interp_taps must be 4 or 6");
     if (c.range_kernel == HHFFBP_RANGE_ES) {
@@ -463,6 +464,43 @@ void validate(const hhffbp_config &c)
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Sec. IV-B counts the operations of HHFFBPA as C1 N_A N_f log N_f (range
+// compression) + C2 sum_n N_SA,n N_s,n (level-1 BP) + 2 C3 sum_m,n N_s,m,n
+// (interpolation) and leaves the number of levels to a trade between cost and
+// interpolation error.  With stages = -K the plan takes the S in 1..K that
+// minimises that count on each candidate's exact pair counts (the range
+// compression term does not depend on S), with per-pair costs measured on
+// MI355X: level-1 BP 2.7 ps (ES kernel) or 1.3 ps (linear); interpolation per
+// (point, child) pair 32 ps (T = 4) or 87 ps (T = 6).
+double model_seconds(const Plan &P)
+{
+    const double c2 = (P.kernel == HHFFBP_RANGE_ES) ? 2.7e-12 : 1.3e-12;
+    const double c3 = (P.T == 4) ? 32e-12 : 87e-12;
+    return c2 * (double)P.leaf_pairs + c3 * (double)(P.merge_pairs + P.final_pairs);
+}
+
+void choose_stages(hhffbp_config &c)
+{
+    if (c.stages >= 0) return;
+    validate(c);
+    const int kmax = -c.stages;
+    int best = 1;
+    double best_cost = 0.0;
+    for (int s = 1; s <= kmax; ++s) {
+        Plan t;
+        t.cfg = c;
+        t.cfg.stages = s;
+        t.cfg.device = -1;
+        build_plan_host(t);
+        const double cost = model_seconds(t);
+        if (s == 1 || cost < best_cost) {
+            best = s;
+            best_cost = cost;
+        }
+    }
+    c.stages = best;
+}
+
 void build_plan_host(Plan &P)
 {
     auto t0 = std::chrono::steady_clock::now();
@@ -609,6 +647,7 @@ void build_plan_host(Plan &P)
             }
         P.final_pairs = P.n_vox() * (int64_t)P.compact_to_tree[1].size();
     }
+    P.model_s = model_seconds(P);
 
     // workspace layout; profiles and subimages in the storage type
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };

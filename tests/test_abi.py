@@ -47,7 +47,7 @@ def _args(w):
 
 @pytest.mark.parametrize("change,status", [
     (dict(merge_factor=3), -1), (dict(interp_taps=5), -1), (dict(range_taps=11), -1),
-    (dict(oversample=0.5), -1), (dict(stages=-1), -1),
+    (dict(oversample=0.5), -1), (dict(stages=-9), -1),
 ])
 def test_invalid_configurations_are_rejected(small, change, status):
     kw = dict(device=-1)
@@ -149,3 +149,19 @@ def test_reductions_validate_without_a_gpu():
     assert L.hhffbp_box_peaks(dummy, ctypes.byref(dims), -1, dummy, dummy, None) == -1
     assert L.hhffbp_box_peaks(None, ctypes.byref(dims), 2, dummy, dummy, None) == -1
     assert b"box_peaks" in L.hhffbp_last_error()
+
+
+def test_automatic_stages_minimise_the_cost_model(small):
+    """stages = -K picks the S in 1..K with the smallest Sec. IV-B operation
+    count (model_ms) among host plans built for each S; invalid forms fail."""
+    for rk, U in (("es", 2.0), ("linear", 8.0)):
+        kw = dict(range_kernel=rk, range_oversample=U, device=-1)
+        costs = [H.Plan(*_args(small), stages=s, **kw).info()["model_ms"] for s in (1, 2, 3)]
+        auto = H.Plan(*_args(small), stages=-3, **kw).info()
+        assert auto["stages"] == 1 + int(np.argmin(costs))
+        assert abs(auto["model_ms"] - min(costs)) <= 1e-12 + 1e-9 * min(costs)
+        assert all(c > 0 for c in costs)
+    with pytest.raises(H.HHFFBPError):
+        H.Plan(*_args(small), stages=-2, mode="direct_rc", device=-1)
+    with pytest.raises(H.HHFFBPError):
+        H.Plan(*_args(small), stages=-9, device=-1)

@@ -282,3 +282,16 @@ def test_mid_fast_range_mode_full_size(torch, mid):
         e_o = _nrmse(img.ravel()[g["index"]], g["hhffbp"])
         _say(f"  vs stored oracle HHFFBPA (eq. 4 level-1 sums) {e_o:.3e}")
         assert e_o <= 2e-3
+
+
+def test_automatic_stages_small(torch, small, oracle_small):
+    """A plan with stages = -3 is the plan of the S it chose: the same image
+    bit for bit, within -30 dB of eq. (4)."""
+    pa = H.Plan(*_args(small), stages=-3, oversample=GAMMA, interp_taps=TAPS)
+    S = pa.info()["stages"]
+    pe = H.Plan(*_args(small), stages=S, oversample=GAMMA, interp_taps=TAPS)
+    a, b = _run(torch, pa, small), _run(torch, pe, small)
+    e = _nrmse(a, oracle_small)
+    _say(f"  automatic stages: S = {S}, vs eq.4 {20 * np.log10(e):.1f} dB")
+    assert np.array_equal(a, b)
+    assert 20 * np.log10(e) <= -30.0
