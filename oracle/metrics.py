@@ -92,3 +92,39 @@ def box_peaks(f, boxes):
                     best, bi = row[k], (ix * d[1] + iy) * d[2] + lo[2] + k
         out.append(bi)
     return np.array(out, np.int64)
+
+
+def psf_metrics(x, f):
+    """Point-response metrics of a 1-D complex slice f sampled at positions x
+    (the paper's Table II reports them without definitions; readings):
+      mainlobe width  the -3 dB width of |f|^2 around its peak, linear
+                      interpolation of |f|^2 between samples
+      PSLR            10 log10(max sidelobe |f|^2 / peak |f|^2), sidelobes being
+                      the samples beyond the first local minimum on each side
+      ISLR            10 log10(sum of sidelobe |f|^2 / sum of mainlobe |f|^2)
+    Returns (width, pslr_db, islr_db)."""
+    x = np.asarray(x, float)
+    p = np.abs(np.asarray(f, np.complex128)) ** 2
+    k = int(np.argmax(p))
+    half = 0.5 * p[k]
+    # half-power crossings
+    i = k
+    while i > 0 and p[i - 1] > half:
+        i -= 1
+    xl = x[i] if i == 0 else x[i - 1] + (half - p[i - 1]) / (p[i] - p[i - 1]) * (x[i] - x[i - 1])
+    j = k
+    while j < p.size - 1 and p[j + 1] > half:
+        j += 1
+    xr = x[j] if j == p.size - 1 else x[j] + (p[j] - half) / (p[j] - p[j + 1]) * (x[j + 1] - x[j])
+    # first minima
+    a = k
+    while a > 0 and p[a - 1] < p[a]:
+        a -= 1
+    b = k
+    while b < p.size - 1 and p[b + 1] < p[b]:
+        b += 1
+    main = p[a:b + 1].sum()
+    side = np.concatenate([p[:a], p[b + 1:]])
+    pslr = 10 * np.log10(side.max() / p[k]) if side.size else -np.inf
+    islr = 10 * np.log10(side.sum() / main) if side.size else -np.inf
+    return float(xr - xl), float(pslr), float(islr)

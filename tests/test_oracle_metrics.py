@@ -84,3 +84,21 @@ def test_box_peaks_against_masked_argmax():
             continue
         assert g == int(np.argmax(np.where(m, a, -1.0).ravel()))
     assert got[1] == (2 * 7 + 3) * 11 + 4
+
+
+def test_psf_metrics_of_a_sinc():
+    """|sinc(x / rho)| sampled at rho / 100 over +-20 rho: -3 dB width 0.8859 rho,
+    PSLR -13.26 dB, ISLR from the sine integral (scipy), for sidelobes out to
+    20 rho: 10 log10((S(20) - S(1)) / S(1)), S(a) = (2/pi) Si(2 pi a)."""
+    from scipy.special import sici
+    rho = 9.7e-3
+    x = np.arange(-2000, 2001) * rho / 100
+    f = np.sinc(x / rho) * np.exp(0.3j)
+    w, pslr, islr = OM.psf_metrics(x, f)
+    S = lambda a: (2 / np.pi) * sici(2 * np.pi * a)[0]
+    assert abs(w / rho - 0.88589) < 2e-4
+    assert abs(pslr - 20 * np.log10(0.217234)) < 0.01
+    assert abs(islr - 10 * np.log10((S(20) - S(1)) / S(1))) < 0.01
+    # shifted and scaled copies measure the same
+    w2, p2, i2 = OM.psf_metrics(x + 0.03, 5.0 * f)
+    assert abs(w2 - w) < 1e-12 and abs(p2 - pslr) < 1e-9 and abs(i2 - islr) < 1e-9

@@ -17,6 +17,11 @@ Index  name            what it is
 3      grad            config 0 geometry with a smooth trajectory error
 4      autofocus       config 2's scene and echoes (same seed) with a smooth
                        trajectory error on the positions handed to the imager
+5      paper_sim       the shape of the paper's point-target simulation: a
+                       101-element linear array swept over 101 positions
+                       (0.45 m), depth and angle fluctuations, 24 f 12-15 GHz,
+                       3x3x3 points at 0.175 m spacing around (0, 0, 0.4 m),
+                       101x101x51 voxels over 0.5 m^3
 """
 from __future__ import annotations
 
@@ -27,7 +32,7 @@ import numpy as np
 
 C0 = 299792458.0  # speed of light in vacuum, m/s (the paper leaves c unstated)
 SEED_BASE = 235680
-CONFIG_NAMES = ("small", "mid", "large", "grad", "autofocus")
+CONFIG_NAMES = ("small", "mid", "large", "grad", "autofocus", "paper_sim")
 
 
 @dataclasses.dataclass
@@ -98,6 +103,33 @@ def _persistent_walk(rng, n, step, half, start=None, turn_sigma=0.3):
                 p[a] = -2 * half - p[a]
                 th = (math.pi - th) if a == 0 else -th
     return xy
+
+
+def _smooth(rng, n, amp):
+    """Sum of 3 sinusoids over the index with random frequency (0.5-3 cycles per
+    scan) and phase, scaled to max |.| = amp."""
+    t = np.arange(n) / max(n - 1, 1)
+    e = sum(rng.uniform(0.3, 1.0) * np.sin(2 * math.pi * rng.uniform(0.5, 3.0) * t
+                                           + rng.uniform(0, 2 * math.pi)) for _ in range(3))
+    return e * (amp / max(np.abs(e).max(), 1e-30))
+
+
+def _linear_array_scan(rng, n_el, n_scan, extent, depth, roll_deg, yaw_deg, lat_sigma):
+    """A linear array of n_el elements (along y) swept along x over n_scan
+    positions, with smooth lateral, depth, roll and yaw fluctuations of the
+    handheld array (scan-major order)."""
+    xs = -extent / 2 + extent * np.arange(n_scan) / (n_scan - 1) + rng.normal(0, lat_sigma, n_scan)
+    yc = _smooth(rng, n_scan, 5e-3)
+    zc = _smooth(rng, n_scan, depth)
+    roll = np.radians(_smooth(rng, n_scan, roll_deg))
+    yaw = np.radians(_smooth(rng, n_scan, yaw_deg))
+    s = -extent / 2 + extent * np.arange(n_el) / (n_el - 1)
+    pos = np.empty((n_scan, n_el, 3))
+    for j in range(n_scan):
+        pos[j, :, 0] = xs[j] - s * math.sin(yaw[j])
+        pos[j, :, 1] = yc[j] + s * math.cos(yaw[j]) * math.cos(roll[j])
+        pos[j, :, 2] = zc[j] + s * math.sin(roll[j])
+    return pos.reshape(-1, 3)
 
 
 def _strokes(rng, n_strokes, per_stroke, half, lat_sigma):
@@ -210,6 +242,18 @@ def make_config(index, synth=True, seed=None, synth_device=None):
         tpos = np.concatenate([pts, slab])
         samp = (rng.standard_normal(5000) + 1j * rng.standard_normal(5000)) / math.sqrt(2)
         tamp = np.concatenate([np.ones(200, np.complex128), samp])
+        stages, q = 3, 4
+    elif index == 5:
+        # the shape of the paper's first point-target simulation (Sec. V-A):
+        # 101 elements x 101 scan positions over ~0.45 m, depth within 8 cm
+        pos = _linear_array_scan(rng, 101, 101, 0.45, 0.03, 5.0, 3.0, 1e-3)
+        freqs = np.linspace(12e9, 15e9, 24)
+        origin, pitch, dims = _centred_grid((0.0, 0.0, 0.4), 5e-3, (101, 101, 51))
+        pitch = np.array([5e-3, 5e-3, 10e-3])
+        origin = np.array([0.0, 0.0, 0.4]) - pitch * (np.asarray(dims) - 1) / 2.0
+        g = np.array([-0.175, 0.0, 0.175])
+        tpos = np.stack(np.meshgrid(g, g, g + 0.4, indexing="ij"), -1).reshape(-1, 3)
+        tamp = np.ones(27, np.complex128)
         stages, q = 3, 4
     else:
         raise ValueError(f"unknown config {index}")
