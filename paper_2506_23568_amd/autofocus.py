@@ -72,7 +72,9 @@ def autofocus(plan, echoes, positions, steps=20, lr=3e-5, clean=None, modes=16, 
         if on_step is not None:
             on_step(k, pos, img)
         _, gp = plan.backward(echoes, g, positions=pos, want_echoes=False, workspace=ws)
-        c.grad = gp if B is None else B.T @ gp
+        # B^T gp as a reduction: the BLAS product of a 16 x N by N x 3 pair
+        # runs on a single workgroup (~1.9 ms at N = 65536)
+        c.grad = gp if B is None else (B[:, :, None] * gp[:, None, :]).sum(0)
         opt.step()
         e1.record(stream)
         torch.cuda.synchronize()
