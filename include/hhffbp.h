@@ -72,6 +72,15 @@ enum {
                                 kernel's transform (fast; ~-61 dB vs ES at U = 8) */
 };
 
+/* Interpolation weights of the merges (separable, interp_taps per axis).
+ * LAGRANGE: the Lagrange polynomial through the stencil.  BANDLIMITED: for
+ * each fractional offset x the weights minimising the squared error over all
+ * signals band-limited to |omega| <= pi / gamma per grid step, integrated over
+ * the band: the compressed subimages have unit spectral support per LLT unit
+ * (Sec. III) and gamma grid points per unit; the plan fits each weight with a
+ * degree-7 polynomial in x (error < 1e-6, checked at plan time). */
+enum { HHFFBP_INTERP_LAGRANGE = 0, HHFFBP_INTERP_BANDLIMITED = 1 };
+
 typedef struct {
     int64_t n_pos;              /* number of antenna positions, >= 1              */
     int64_t n_freq;             /* number of frequency samples, >= 2              */
@@ -94,10 +103,11 @@ typedef struct {
     int32_t storage;            /* HHFFBP_C64, HHFFBP_F16 or HHFFBP_BF16          */
     double position_slack;      /* metres the positions may move after planning  */
     int32_t device;             /* HIP device ordinal; -1 plans on the host only  */
+    int32_t interp_kernel;      /* HHFFBP_INTERP_LAGRANGE or HHFFBP_INTERP_BANDLIMITED */
 } hhffbp_config;
 
 /* Fill `cfg` with defaults: FACTORIZED, S = 3, Q = 4, gamma = (3, 3, 3.5), T = 4, ES with
- * U = 2 and W = 7, C64 storage, 5 mm slack, device 0.  Pointers and sizes are
+ * U = 2 and W = 7, C64 storage, 5 mm slack, device 0, Lagrange interpolation.  Pointers and sizes are
  * zeroed and must be set by the caller. */
 void hhffbp_config_default(hhffbp_config *cfg);
 

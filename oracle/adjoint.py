@@ -17,16 +17,16 @@ import numpy as np
 
 from . import geometry as G
 from . import native
-from .hhffbp import lagrange_weights
+from .hhffbp import axis_weights
 from .plan import lagrange_offsets, stencil_base
 
 
-def scatter_transpose(lat, t, T, coef, out):
+def scatter_transpose(lat, t, T, coef, out, kernel="lagrange", gamma=(3.0, 3.0, 3.5)):
     """Transpose of ``hhffbp.interpolate``: out[tap] += w(tap) * coef for each point."""
     offs = lagrange_offsets(T)
     base = stencil_base(t).astype(np.int64)
     frac = t - base
-    wu, wv, wn = (lagrange_weights(frac[:, a], T) for a in range(3))
+    wu, wv, wn = (axis_weights(frac[:, a], T, kernel, gamma[a]) for a in range(3))
     for a, da in enumerate(offs):
         ci = base[:, 0] + da - lat.i0
         for b, db in enumerate(offs):
@@ -53,7 +53,8 @@ def _split_to_children(plan, node, points, cot, phi_parent, child_cot):
         t = plan.gamma * G.uvn(points, child.rect, plan.kmin, plan.kmax)
         ph = G.phi(points, child.rect, plan.kmin, plan.kmax) - phi_parent
         acc = child_cot.setdefault((d + 1, ci), np.zeros(child.lattice.size, np.complex128))
-        scatter_transpose(child.lattice, t, plan.taps, np.exp(-1j * ph) * cot, acc)
+        scatter_transpose(child.lattice, t, plan.taps, np.exp(-1j * ph) * cot, acc,
+                          kernel=plan.kernel, gamma=plan.gamma)
 
 
 def leaf_cotangents(plan, grad_image):

@@ -16,9 +16,10 @@ The level-1 sum is eq. (4) itself, or (``range_u``) the fast form: range
 profiles sampled every dR = pi / (U (k_max - k_min)) on the grid R_b = b dR,
 pre-corrected for the linear kernel, and read by linear interpolation.
 
-The interpolation kernel is the separable T-tap Lagrange polynomial through
-the stencil b - T/2 + 1 .. b + T/2 on each axis, b = floor(t + 1e-9) (the
-paper does not name one).  With S = 0 the root is the single subarray and step 1 alone
+The interpolation kernel (the paper does not name one) is separable over the
+stencil b - T/2 + 1 .. b + T/2 on each axis, b = floor(t + 1e-9): the T-tap
+Lagrange polynomial, or the least-squares weights for the grid's band
+(``bandlimited_weights``).  With S = 0 the root is the single subarray and step 1 alone
 gives eq. (4) on the voxels.
 """
 from __future__ import annotations
@@ -41,8 +42,38 @@ def lagrange_weights(x, T):
     return w
 
 
-def interpolate(lat, vals, t, T, chunk=1 << 17):
-    """Separable T^3-tap Lagrange interpolation of lattice values at coordinates t.
+def bandlimited_weights(x, T, gamma):
+    """(N, T) least-squares weights for signals band-limited to |omega| <= pi / gamma
+    per lattice step: the compressed subimages have unit spectral support per
+    LLT unit (Sec. III) and a grid with gamma points per unit.  For each x they
+    minimise  int_{-W}^{W} |sum_a w_a e^{j omega a} - e^{j omega x}|^2 d omega,
+    W = pi / gamma, over the taps a = -T/2+1 .. T/2: the normal equations
+    G w = b with G_ab = int cos(omega (a - b)), b_a = int cos(omega (a - x))."""
+    W = np.pi / float(gamma)
+    o = lagrange_offsets(T).astype(float)
+
+    def integral(d):  # int_{-W}^{W} cos(omega d) d omega
+        d = np.asarray(d, float)
+        small = np.abs(d) < 1e-12
+        return np.where(small, 2 * W, 2 * np.sin(W * d) / np.where(small, 1.0, d))
+
+    G = integral(o[:, None] - o[None, :])
+    b = integral(o[None, :] - np.asarray(x, float)[:, None])
+    return np.linalg.solve(G, b.T).T
+
+
+def axis_weights(x, T, kernel, gamma):
+    """Interpolation weights of one axis: "lagrange" or "bandlimited"."""
+    if kernel == "lagrange":
+        return lagrange_weights(x, T)
+    if kernel == "bandlimited":
+        return bandlimited_weights(x, T, gamma)
+    raise ValueError(f"unknown interpolation kernel {kernel}")
+
+
+def interpolate(lat, vals, t, T, chunk=1 << 17, kernel="lagrange", gamma=(3.0, 3.0, 3.5)):
+    """Separable T^3-tap interpolation (Lagrange, or band-limited least squares
+    with the grid's oversampling ``gamma`` per axis) of lattice values at t.
 
     Raises if a stencil reaches a point that the lattice does not hold (the
     grids are built so that this cannot happen); absent points hold 0.
@@ -53,7 +84,7 @@ def interpolate(lat, vals, t, T, chunk=1 << 17):
         tc = t[c0:c0 + chunk]
         base = stencil_base(tc).astype(np.int64)
         frac = tc - base
-        wu, wv, wn = (lagrange_weights(frac[:, a], T) for a in range(3))
+        wu, wv, wn = (axis_weights(frac[:, a], T, kernel, gamma[a]) for a in range(3))
         acc = np.zeros(tc.shape[0], np.complex128)
         missing = np.zeros(tc.shape[0], bool)
         for a, da in enumerate(offs):
@@ -124,7 +155,8 @@ def merge_at(plan, node, child_vals, points):
         if child.empty:
             continue
         t = plan.gamma * G.uvn(points, child.rect, plan.kmin, plan.kmax)
-        val = interpolate(child.lattice, child_vals[(d + 1, ci)], t, plan.taps)
+        val = interpolate(child.lattice, child_vals[(d + 1, ci)], t, plan.taps,
+                          kernel=plan.kernel, gamma=plan.gamma)
         acc += val * np.exp(1j * G.phi(points, child.rect, plan.kmin, plan.kmax))
     return acc
 

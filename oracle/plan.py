@@ -241,10 +241,11 @@ class Plan:
     margin: int
     voxels: np.ndarray          # (N_vox, 3)
     dims: tuple
+    kernel: str = "lagrange"    # interpolation weights: "lagrange" or "bandlimited"
 
 
 def build_plan(positions, freqs_hz, origin, pitch, dims, stages, merge_factor,
-               gamma=3.0, taps=4, margin=0):
+               gamma=3.0, taps=4, margin=0, kernel="lagrange"):
     """Oracle plan: tree, top-down grids and their xyz preimages."""
     from workloads import voxel_centres
 
@@ -254,7 +255,9 @@ def build_plan(positions, freqs_hz, origin, pitch, dims, stages, merge_factor,
     vox = voxel_centres(origin, pitch, dims)
     z_valid = 0.5 * float(vox[:, 2].min())
     gamma = np.broadcast_to(np.asarray(gamma, float), (3,)).copy()
-    plan = Plan(levels, k, kmin, kmax, gamma, int(taps), int(margin), vox, tuple(dims))
+    if kernel not in ("lagrange", "bandlimited"):
+        raise ValueError(f"unknown interpolation kernel {kernel}")
+    plan = Plan(levels, k, kmin, kmax, gamma, int(taps), int(margin), vox, tuple(dims), kernel)
     for d in range(1, len(levels)):
         for node in levels[d]:
             if node.empty:

@@ -15,6 +15,7 @@ STATUS = {0: "ok", -1: "invalid", -2: "unsupported", -3: "nomem", -4: "device",
 MODES = {"factorized": 0, "direct_rc": 1}
 RANGE_KERNELS = {"es": 0, "linear": 1}
 STORAGE = {"c64": 0, "f16": 1, "bf16": 2}
+INTERP_KERNELS = {"lagrange": 0, "bandlimited": 1}
 
 
 class HHFFBPError(RuntimeError):
@@ -35,6 +36,7 @@ class Config(ctypes.Structure):
         ("range_kernel", ctypes.c_int32), ("range_oversample", ctypes.c_double),
         ("range_taps", ctypes.c_int32), ("storage", ctypes.c_int32),
         ("position_slack", ctypes.c_double), ("device", ctypes.c_int32),
+        ("interp_kernel", ctypes.c_int32),
     ]
 
 
@@ -128,7 +130,7 @@ class Plan:
                  mode="factorized", stages=3, merge_factor=4, oversample=(3.0, 3.0, 3.5),
                  interp_taps=4,
                  range_kernel="es", range_oversample=2.0, range_taps=7, storage="c64",
-                 position_slack=5e-3, device=0):
+                 position_slack=5e-3, device=0, interp_kernel="lagrange"):
         L = lib()
         self._pos = np.ascontiguousarray(positions, np.float64)
         self._freqs = np.ascontiguousarray(freqs_hz, np.float64)
@@ -156,6 +158,7 @@ class Plan:
         c.storage = STORAGE[storage]
         c.position_slack = float(position_slack)
         c.device = int(device)
+        c.interp_kernel = INTERP_KERNELS[interp_kernel]
         self.config = c
         self.dims = tuple(int(d) for d in grid_dims)
         self.device = int(device)

@@ -192,20 +192,54 @@ __device__ __forceinline__ void lagrange(float x, float *w)
     }
 }
 
+// Weights of the three axes at a child coordinate: Lagrange (K = LAGRANGE),
+// or the plan's band-limited polynomials (Horner in the fractional offset).
+// The stencil is symmetric (tap t at offset x is tap T-1-t at 1 - x), so the
+// plan keeps the polynomials of the first T/2 taps only.
+template <int T, int A>
+__device__ __forceinline__ void poly_weights(const InterpPoly &ip, float x, float *w)
+{
+    const float y = 1.0f - x;
+#pragma unroll
+    for (int t = 0; t < T / 2; ++t) {
+        float v = ip.c[A][t][kPolyDeg], u = ip.c[A][t][kPolyDeg];
+#pragma unroll
+        for (int d = kPolyDeg - 1; d >= 0; --d) {
+            v = fmaf(v, x, ip.c[A][t][d]);
+            u = fmaf(u, y, ip.c[A][t][d]);
+        }
+        w[t] = v;
+        w[T - 1 - t] = u;
+    }
+}
+
+template <int T, int K>
+__device__ __forceinline__ void interp_weights(const InterpPoly &ip, const ChildCoord &g, float *wu,
+                                               float *wv, float *wn)
+{
+    if constexpr (K == HHFFBP_INTERP_BANDLIMITED) {
+        poly_weights<T, 0>(ip, g.fu, wu);
+        poly_weights<T, 1>(ip, g.fv, wv);
+        poly_weights<T, 2>(ip, g.fn, wn);
+    } else {
+        lagrange<T>(g.fu, wu);
+        lagrange<T>(g.fv, wv);
+        lagrange<T>(g.fn, wn);
+    }
+}
+
 // Separable T^3 interpolation of a compressed child subimage (missing points are 0).
 // The grids are built so that every stencil of a planned point lies inside the
 // child's pencils; a pencil whose T taps along n are all present takes the
 // branch-free path (one index sum, T contiguous loads).  The guarded per-tap
 // path remains for stencils that rounding could push past a pencil end.
-template <int T, int ST = HHFFBP_C64>
+template <int T, int ST, int K>
 __device__ __forceinline__ float2 interp_child(const NodeDev &c, const ColEntry *__restrict__ cols,
                                                const typename Store<ST>::C *__restrict__ vals,
-                                               const ChildCoord &g)
+                                               const ChildCoord &g, const InterpPoly &ip)
 {
     float wu[T], wv[T], wn[T];
-    lagrange<T>(g.fu, wu);
-    lagrange<T>(g.fv, wv);
-    lagrange<T>(g.fn, wn);
+    interp_weights<T, K>(ip, g, wu, wv, wn);
     const int l0 = g.bl - T / 2 + 1;
     float are = 0.0f, aim = 0.0f;
 #pragma unroll

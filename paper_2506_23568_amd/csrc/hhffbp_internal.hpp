@@ -50,6 +50,17 @@ struct LeafPoint {
     int32_t pad;
 };
 
+// Interpolation weights of the merges: per axis (u, v, n) and tap t < T/2,
+// the coefficients of a polynomial in the fractional offset x (BANDLIMITED;
+// tap T-1-t is tap t at 1 - x), or kind = LAGRANGE (weights formed
+// directly).  Passed to kernels by value.
+constexpr int kPolyDeg = 7;
+constexpr int kMaxTaps = 6;
+struct InterpPoly {
+    int32_t kind;
+    float c[3][kMaxTaps / 2][kPolyDeg + 1];
+};
+
 // Work item of a per-node point loop: node (compact index) and first point.
 struct BlockItem {
     int32_t node, start;
@@ -129,6 +140,7 @@ struct Plan {
     size_t ws_gprof = 0, ws_gpos = 0, ws_gmax = 0, ws_total_bwd = 0;  // backward additions
     size_t device_bytes = 0;  // plan tables uploaded to the device (owned by the plan)
     double model_s = 0.0;     // the Sec. IV-B cost model's level-1 BP + interpolation time
+    InterpPoly ipoly{};       // merge interpolation weights
     std::vector<size_t> ws_gvals;        // backward: float32 cotangents per depth
     std::vector<float> scale_mult;       // host copy of dev.scale_mult
     std::vector<size_t> ws_vals;         // per depth

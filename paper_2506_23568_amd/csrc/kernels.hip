@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
 
 // Merge at depth d: parent grid points (float64 SoA) of the depth-d nodes,
 // children at depth d + 1.  Output: compressed parent values.
-template <int T, int ST>
+template <int T, int ST, int K>
 __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ parents,
                                                   const BlockItem *__restrict__ blocks,
                                                   const double *__restrict__ px,
@@ -284,8 +284,9 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
                                                   const NodeDev *__restrict__ children,
                                                   const ColEntry *__restrict__ ccols,
                                                   const typename Store<ST>::C *__restrict__ cvals,
-                                                  GeoParams gp, const float *__restrict__ scales,
-                                                  int d, typename Store<ST>::C *__restrict__ out)
+                                                  GeoParams gp, const InterpPoly ip,
+                                                  const float *__restrict__ scales, int d,
+                                                  typename Store<ST>::C *__restrict__ out)
 {
     const BlockItem blk = blocks[blockIdx.x];
     const NodeDev nd = parents[blk.node];
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
     for (int c = 0; c < nd.nchild; ++c) {
         const NodeDev ch = children[child_idx[c]];
         const ChildCoord g = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
-        const float2 v = interp_child<T, ST>(ch, ccols, cvals, g);
+        const float2 v = interp_child<T, ST, K>(ch, ccols, cvals, g, ip);
         phase_mac(v, g.phi - phip, are, aim);
     }
     const float rs = scales[d] / scales[d + 1];
@@ -311,11 +312,12 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
 }
 
 // Final stage: user voxels, children are the depth-1 nodes.
-template <int T, int ST>
+template <int T, int ST, int K>
 __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ children,
                                                   int nchild, const ColEntry *__restrict__ ccols,
                                                   const typename Store<ST>::C *__restrict__ cvals,
-                                                  GeoParams gp, const float *__restrict__ scales,
+                                                  GeoParams gp, const InterpPoly ip,
+                                                  const float *__restrict__ scales,
                                                   double ox, double oy, double oz, double sx,
                                                   double sy, double sz, int nx, int ny, int nz,
                                                   float2 *__restrict__ image)
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
     for (int c = 0; c < nchild; ++c) {
         const NodeDev ch = children[c];
         const ChildCoord g = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
-        const float2 val = interp_child<T, ST>(ch, ccols, cvals, g);
+        const float2 val = interp_child<T, ST, K>(ch, ccols, cvals, g, ip);
         phase_mac(val, g.phi, are, aim);
     }
     const float rs = 1.0f / scales[1];
@@ -472,7 +474,7 @@ hipError_t launch_bp_kernels(const Plan &P, const double *pos64, const void *pro
     return hipGetLastError();
 }
 
-template <int T, int ST>
+template <int T, int ST, int K>
 hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scales, hipStream_t st,
                          hipEvent_t *ev)
 {
@@ -480,13 +482,13 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
     GeoParams gp{P.gamma[0], P.gamma[1], P.gamma[2], P.kmin, P.kmax};
     for (int d = P.S - 1; d >= 1; --d) {
         if (P.n_blocks_merge[d] > 0) {
-            hipLaunchKernelGGL((k_merge<T, ST>), dim3(P.n_blocks_merge[d]), dim3(kBlock), 0, st,
+            hipLaunchKernelGGL((k_merge<T, ST, K>), dim3(P.n_blocks_merge[d]), dim3(kBlock), 0, st,
                                (const NodeDev *)P.dev.nodes[d],
                                (const BlockItem *)P.dev.merge_blocks[d], (const double *)P.dev.px[d],
                                (const double *)P.dev.py[d], (const double *)P.dev.pz[d],
                                (const NodeDev *)P.dev.nodes[d + 1],
                                (const ColEntry *)P.dev.cols[d + 1],
-                               (const C *)(ws + P.ws_vals[d + 1]), gp, scales, d,
+                               (const C *)(ws + P.ws_vals[d + 1]), gp, P.ipoly, scales, d,
                                (C *)(ws + P.ws_vals[d]));
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
@@ -497,9 +499,10 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
     const int nx = (int)c.grid_dims[0], ny = (int)c.grid_dims[1], nz = (int)c.grid_dims[2];
     const int64_t nv = (int64_t)nx * ny * nz;
     const int nblk = (int)((nv + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_final<T, ST>), dim3(nblk), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((k_final<T, ST, K>), dim3(nblk), dim3(kBlock), 0, st,
                        (const NodeDev *)P.dev.nodes[1], (int)P.compact_to_tree[1].size(),
-                       (const ColEntry *)P.dev.cols[1], (const C *)(ws + P.ws_vals[1]), gp, scales,
+                       (const ColEntry *)P.dev.cols[1], (const C *)(ws + P.ws_vals[1]), gp,
+                       P.ipoly, scales,
                        c.grid_origin[0], c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0],
                        c.grid_pitch[1], c.grid_pitch[2], nx, ny, nz, (float2 *)image);
     hipError_t e = hipGetLastError();
@@ -571,8 +574,12 @@ hhffbp_status image_for_storage(const Plan &P, const void *echoes, const double 
     if (e != hipSuccess) return HHFFBP_E_DEVICE;
     if (ev) (void)hipEventRecord(*ev++, st);
     if (P.S == 0) return HHFFBP_OK;
-    e = (P.T == 4) ? launch_merges<4, ST>(P, ws, image, scales, st, ev)
-                   : launch_merges<6, ST>(P, ws, image, scales, st, ev);
+    if (P.ipoly.kind == HHFFBP_INTERP_BANDLIMITED)
+        e = (P.T == 4) ? launch_merges<4, ST, HHFFBP_INTERP_BANDLIMITED>(P, ws, image, scales, st, ev)
+                       : launch_merges<6, ST, HHFFBP_INTERP_BANDLIMITED>(P, ws, image, scales, st, ev);
+    else
+        e = (P.T == 4) ? launch_merges<4, ST, HHFFBP_INTERP_LAGRANGE>(P, ws, image, scales, st, ev)
+                       : launch_merges<6, ST, HHFFBP_INTERP_LAGRANGE>(P, ws, image, scales, st, ev);
     return e == hipSuccess ? HHFFBP_OK : HHFFBP_E_DEVICE;
 }
 

@@ -39,15 +39,13 @@ __global__ __launch_bounds__(kBlock) void k_zero(float4 *__restrict__ p, int64_t
 }
 
 // Transpose of interp_child: grad[tap] += w(tap) * (gre + j gim).
-template <int T>
+template <int T, int K>
 __device__ __forceinline__ void scatter_child(const NodeDev &c, const ColEntry *__restrict__ cols,
                                               float2 *__restrict__ grad, const ChildCoord &g,
-                                              float gre, float gim)
+                                              const InterpPoly &ip, float gre, float gim)
 {
     float wu[T], wv[T], wn[T];
-    lagrange<T>(g.fu, wu);
-    lagrange<T>(g.fv, wv);
-    lagrange<T>(g.fn, wn);
+    interp_weights<T, K>(ip, g, wu, wv, wn);
 #pragma unroll
     for (int a = 0; a < T; ++a) {
         const int ci = g.bi + a - T / 2 + 1 - c.i0;
@@ -122,10 +120,11 @@ __device__ __forceinline__ float wave_sum_f(float v)
 }
 
 // Every lane of the block calls this (inactive lanes with active = false).
-template <int T>
+template <int T, int K>
 __device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c,
                                     const ColEntry *__restrict__ cols, float2 *__restrict__ grad,
-                                    const ChildCoord &g, float gre, float gim)
+                                    const ChildCoord &g, const InterpPoly &ip, float gre,
+                                    float gim)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int lo = -T / 2 + 1;
@@ -167,7 +166,7 @@ __device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c
     const long long nbox = (long long)B0 * B1 * B2;
     if (nbox > kBoxCap) {
         // box too large for LDS: direct global atomics
-        if (active) scatter_child<T>(c, cols, grad, g, gre, gim);
+        if (active) scatter_child<T, K>(c, cols, grad, g, ip, gre, gim);
         __syncthreads();
         return;
     }
@@ -180,9 +179,7 @@ __device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c
     __syncthreads();
     if (active) {
         float wu[T], wv[T], wn[T];
-        lagrange<T>(g.fu, wu);
-        lagrange<T>(g.fv, wv);
-        lagrange<T>(g.fn, wn);
+        interp_weights<T, K>(ip, g, wu, wv, wn);
         const float qre = gre * q, qim = gim * q;
         const int bi = g.bi + lo - o0, bj = g.bj + lo - o1, bl = g.bl + lo - o2;
 #pragma unroll
@@ -218,10 +215,11 @@ __device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c
     __syncthreads();
 }
 
-template <int T>
+template <int T, int K>
 __global__ __launch_bounds__(kBlock) void k_final_adj(const NodeDev *__restrict__ children,
                                                       int nchild, const ColEntry *__restrict__ ccols,
                                                       float2 *__restrict__ cgrad, GeoParams gp,
+                                                      const InterpPoly ip,
                                                       double ox, double oy, double oz, double sx,
                                                       double sy, double sz, int nx, int ny, int nz,
                                                       const float2 *__restrict__ gimg)
@@ -246,11 +244,11 @@ __global__ __launch_bounds__(kBlock) void k_final_adj(const NodeDev *__restrict_
             cc = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
             rotate_back(g, cc.phi, gre, gim);
         }
-        block_scatter_child<T>(sh, active, ch, ccols, cgrad, cc, gre, gim);
+        block_scatter_child<T, K>(sh, active, ch, ccols, cgrad, cc, ip, gre, gim);
     }
 }
 
-template <int T>
+template <int T, int K>
 __global__ __launch_bounds__(kBlock) void k_merge_adj(const NodeDev *__restrict__ parents,
                                                       const BlockItem *__restrict__ blocks,
                                                       const double *__restrict__ px,
@@ -259,7 +257,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_adj(const NodeDev *__restrict_
                                                       const float2 *__restrict__ pgrad,
                                                       const NodeDev *__restrict__ children,
                                                       const ColEntry *__restrict__ ccols,
-                                                      float2 *__restrict__ cgrad, GeoParams gp)
+                                                      float2 *__restrict__ cgrad, GeoParams gp,
+                                                      const InterpPoly ip)
 {
     __shared__ BoxShared sh;
     const BlockItem blk = blocks[blockIdx.x];
@@ -286,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_adj(const NodeDev *__restrict_
             cc = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
             rotate_back(g, cc.phi - phip, gre, gim);
         }
-        block_scatter_child<T>(sh, active, ch, ccols, cgrad, cc, gre, gim);
+        block_scatter_child<T, K>(sh, active, ch, ccols, cgrad, cc, ip, gre, gim);
     }
 }
 
@@ -511,7 +510,7 @@ hipError_t leaf_adj_dispatch(const Plan &P, bool want_s, bool want_p, const floa
     return launch_leaf_adj<KERNEL, W, false, true>(P, posoff, dprof, gleaf, gmax, gprof, gpos, st);
 }
 
-template <int T>
+template <int T, int K>
 hipError_t launch_scatters(const Plan &P, const void *grad_image, char *ws, hipStream_t st)
 {
     const hhffbp_config &c = P.cfg;
@@ -520,19 +519,19 @@ hipError_t launch_scatters(const Plan &P, const void *grad_image, char *ws, hipS
     const int64_t nv = (int64_t)nx * ny * nz;
     const unsigned ntile = (unsigned)(((nx + 3) / 4) * ((ny + 7) / 8) * ((nz + 7) / 8));
     (void)nv;
-    hipLaunchKernelGGL((k_final_adj<T>), dim3(ntile), dim3(kBlock), 0, st, (const NodeDev *)P.dev.nodes[1], (int)P.compact_to_tree[1].size(),
+    hipLaunchKernelGGL((k_final_adj<T, K>), dim3(ntile), dim3(kBlock), 0, st, (const NodeDev *)P.dev.nodes[1], (int)P.compact_to_tree[1].size(),
                        (const ColEntry *)P.dev.cols[1], (float2 *)(ws + P.ws_gvals[1]), gp,
-                       c.grid_origin[0], c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0],
+                       P.ipoly, c.grid_origin[0], c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0],
                        c.grid_pitch[1], c.grid_pitch[2], nx, ny, nz, (const float2 *)grad_image);
     hipError_t e = hipGetLastError();
     for (int d = 1; d < P.S && e == hipSuccess; ++d) {
         if (P.n_blocks_merge[d] == 0) continue;
-        hipLaunchKernelGGL((k_merge_adj<T>), dim3(P.n_blocks_merge[d]), dim3(kBlock), 0, st,
+        hipLaunchKernelGGL((k_merge_adj<T, K>), dim3(P.n_blocks_merge[d]), dim3(kBlock), 0, st,
                            (const NodeDev *)P.dev.nodes[d], (const BlockItem *)P.dev.merge_blocks[d],
                            (const double *)P.dev.px[d], (const double *)P.dev.py[d],
                            (const double *)P.dev.pz[d], (const float2 *)(ws + P.ws_gvals[d]),
                            (const NodeDev *)P.dev.nodes[d + 1], (const ColEntry *)P.dev.cols[d + 1],
-                           (float2 *)(ws + P.ws_gvals[d + 1]), gp);
+                           (float2 *)(ws + P.ws_gvals[d + 1]), gp, P.ipoly);
         e = hipGetLastError();
     }
     return e;
@@ -572,7 +571,12 @@ hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *p
         hipLaunchKernelGGL(k_zero, dim3(1024), dim3(kBlock), 0, st, (float4 *)(ws + b0), n4);
         if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
     }
-    e = (P.T == 4) ? launch_scatters<4>(P, grad_image, ws, st) : launch_scatters<6>(P, grad_image, ws, st);
+    if (P.ipoly.kind == HHFFBP_INTERP_BANDLIMITED)
+        e = (P.T == 4) ? launch_scatters<4, HHFFBP_INTERP_BANDLIMITED>(P, grad_image, ws, st)
+                       : launch_scatters<6, HHFFBP_INTERP_BANDLIMITED>(P, grad_image, ws, st);
+    else
+        e = (P.T == 4) ? launch_scatters<4, HHFFBP_INTERP_LAGRANGE>(P, grad_image, ws, st)
+                       : launch_scatters<6, HHFFBP_INTERP_LAGRANGE>(P, grad_image, ws, st);
     if (e != hipSuccess) return HHFFBP_E_DEVICE;
     const float2 *gleaf = (const float2 *)(ws + P.ws_gvals[P.S]);
     float *gmax = (float *)(ws + P.ws_gmax);

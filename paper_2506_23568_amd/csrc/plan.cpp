@@ -405,6 +405,115 @@ void range_setup(Plan &P, double rmin, double rmax)
     }
 }
 
+// ---- band-limited interpolation weights -----------------------------------
+// For signals band-limited to |omega| <= W per grid step, the weights w_a of
+// the taps o_a = a - T/2 + 1 that minimise the squared error at offset x,
+// integrated over the band, solve G w = b with
+//   G_ab = int_{-W}^{W} cos(omega (o_a - o_b)) d omega,
+//   b_a  = int_{-W}^{W} cos(omega (o_a - x)) d omega.
+double band_integral(double W, double d)
+{
+    return std::fabs(d) < 1e-12 ? 2.0 * W : 2.0 * std::sin(W * d) / d;
+}
+
+void bandlimited_weights(int T, double W, double x, double *w)
+{
+    double L[kMaxTaps][kMaxTaps] = {}, y[kMaxTaps];
+    // Cholesky factor of the (symmetric positive definite) Gram matrix
+    for (int i = 0; i < T; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double v = band_integral(W, (double)(i - j));
+            for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(v > 0.0)) throw Error{HHFFBP_E_NUMERIC, "interpolation Gram matrix not positive"};
+                L[i][i] = std::sqrt(v);
+            } else {
+                L[i][j] = v / L[j][j];
+            }
+        }
+    for (int i = 0; i < T; ++i) {
+        double v = band_integral(W, (double)(i - T / 2 + 1) - x);
+        for (int k = 0; k < i; ++k) v -= L[i][k] * y[k];
+        y[i] = v / L[i][i];
+    }
+    for (int i = T - 1; i >= 0; --i) {
+        double v = y[i];
+        for (int k = i + 1; k < T; ++k) v -= L[k][i] * w[k];
+        w[i] = v / L[i][i];
+    }
+}
+
+// Weight of tap t at offset x from the fitted polynomials (mirror symmetry
+// for the taps t >= T/2).
+double interp_poly_weight(const InterpPoly &ip, int a, int T, int t, double x)
+{
+    const int s = (t < T / 2) ? t : T - 1 - t;
+    const double y = (t < T / 2) ? x : 1.0 - x;
+    double v = 0.0;
+    for (int d = kPolyDeg; d >= 0; --d) v = v * y + (double)ip.c[a][s][d];
+    return v;
+}
+
+// Degree-kPolyDeg least-squares polynomials (modified Gram-Schmidt QR at 40
+// Chebyshev nodes of [0, 1]) for every weight of every axis; each fit, with
+// its coefficients rounded to float, is checked against the exact weights at
+// 257 offsets.
+void fit_interp_poly(Plan &P)
+{
+    InterpPoly &ip = P.ipoly;
+    std::memset(&ip, 0, sizeof(ip));
+    ip.kind = P.cfg.interp_kernel;
+    if (ip.kind != HHFFBP_INTERP_BANDLIMITED) return;
+    constexpr int K = 40, D = kPolyDeg + 1;
+    const int T = P.T;
+    double xk[K], V[K][D], R[D][D] = {};
+    for (int k = 0; k < K; ++k) {
+        xk[k] = 0.5 - 0.5 * std::cos(kPi * (k + 0.5) / K);
+        double p = 1.0;
+        for (int d = 0; d < D; ++d, p *= xk[k]) V[k][d] = p;
+    }
+    for (int d = 0; d < D; ++d) {  // V = Q R, Q stored in V
+        for (int e = 0; e < d; ++e) {
+            double r = 0.0;
+            for (int k = 0; k < K; ++k) r += V[k][e] * V[k][d];
+            R[e][d] = r;
+            for (int k = 0; k < K; ++k) V[k][d] -= r * V[k][e];
+        }
+        double nrm = 0.0;
+        for (int k = 0; k < K; ++k) nrm += V[k][d] * V[k][d];
+        R[d][d] = std::sqrt(nrm);
+        for (int k = 0; k < K; ++k) V[k][d] /= R[d][d];
+    }
+    for (int a = 0; a < 3; ++a) {
+        const double W = kPi / P.gamma[a];
+        double wk[K][kMaxTaps];
+        for (int k = 0; k < K; ++k) bandlimited_weights(T, W, xk[k], wk[k]);
+        for (int t = 0; t < T / 2; ++t) {
+            double qy[D], c[D];
+            for (int d = 0; d < D; ++d) {
+                qy[d] = 0.0;
+                for (int k = 0; k < K; ++k) qy[d] += V[k][d] * wk[k][t];
+            }
+            for (int d = D - 1; d >= 0; --d) {
+                double v = qy[d];
+                for (int e = d + 1; e < D; ++e) v -= R[d][e] * c[e];
+                c[d] = v / R[d][d];
+            }
+            for (int d = 0; d < D; ++d) ip.c[a][t][d] = (float)c[d];
+        }
+        for (int i = 0; i <= 256; ++i) {
+            const double x = i / 256.0;
+            double w[kMaxTaps];
+            bandlimited_weights(T, W, x, w);
+            for (int t = 0; t < T; ++t) {
+                const double v = interp_poly_weight(ip, a, T, t, x);
+                if (std::fabs(v - w[t]) > 1e-6)
+                    throw Error{HHFFBP_E_NUMERIC, "band-limited weight fit above 1e-6"};
+            }
+        }
+    }
+}
+
 // Distance range from points to a box (for the range window).
 void box_dist(const double *q, const double *lo, const double *hi, double *dmin, double *dmax)
 {
@@ -439,6 +548,8 @@ void validate(const hhffbp_config &c)
     if (c.stages < 0 && c.mode != HHFFBP_FACTORIZED) bad("automatic stages need the factorised mode");
     if (c.merge_factor != 2 && c.merge_factor != 4) bad("merge_factor must be 2 or 4");
     if (c.interp_taps != 4 && c.interp_taps != 6) bad("interp_taps must be 4 or 6");
+    if (c.interp_kernel != HHFFBP_INTERP_LAGRANGE && c.interp_kernel != HHFFBP_INTERP_BANDLIMITED)
+        bad("unknown interpolation kernel");
     if (c.range_kernel == HHFFBP_RANGE_ES) {
         if (c.range_taps < 4 || c.range_taps > 8) bad("range_taps must be in [4, 8]");
     } else if (c.range_kernel != HHFFBP_RANGE_LINEAR) {
@@ -514,6 +625,7 @@ void build_plan_host(Plan &P)
     P.W = (c.range_kernel == HHFFBP_RANGE_ES) ? c.range_taps : 2;
     P.U = c.range_oversample;
     P.beta = kPi * P.W * (1.0 - 1.0 / (2.0 * P.U)) * 0.98;
+    fit_interp_poly(P);
     P.positions.assign(c.positions, c.positions + 3 * c.n_pos);
     P.k.resize(c.n_freq);
     for (int64_t f = 0; f < c.n_freq; ++f) P.k[f] = 2.0 * kPi * c.freqs_hz[f] / kLight;
@@ -682,12 +794,28 @@ void build_plan_host(Plan &P)
 
     // worst-case gain from the echoes to each stage (half-precision scales):
     // profiles <= sqrt(2) Nf max|W| max|s|; a leaf sums <= members x W taps of
-    // them; a merge sums <= children x L_T^3 (L_T the Lagrange kernel's
-    // largest absolute weight sum on [0, 1)).
+    // them; a merge sums <= children x L_u L_v L_n (L_a the interpolation
+    // kernel's largest absolute weight sum on [0, 1) along axis a: 1.25 (T = 4)
+    // and 1.3906 (T = 6) for Lagrange; sampled from the fitted polynomials, with
+    // a 1% margin, for the band-limited weights).
     {
         double wmax = 0.0;
         for (size_t i = 0; i < P.Bmat.size(); ++i) wmax = std::max(wmax, (double)std::fabs(P.Bmat[i]));
-        const double lt = (P.T == 4) ? 1.25 : 1.40;
+        double lt = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            double la = (P.T == 4) ? 1.25 : 1.40;
+            if (P.ipoly.kind == HHFFBP_INTERP_BANDLIMITED) {
+                la = 0.0;
+                for (int i = 0; i <= 256; ++i) {
+                    const double x = i / 256.0;
+                    double sum = 0.0;
+                    for (int t = 0; t < P.T; ++t) sum += std::fabs(interp_poly_weight(P.ipoly, a, P.T, t, x));
+                    la = std::max(la, sum);
+                }
+                la *= 1.01;
+            }
+            lt *= la;
+        }
         P.scale_mult.assign(S + 1, 0.0f);
         const double m0 = std::sqrt(2.0) * (double)c.n_freq * wmax;
         P.scale_mult[0] = (float)m0;
@@ -699,7 +827,7 @@ void build_plan_host(Plan &P)
             for (int d = S - 1; d >= 1; --d) {
                 size_t nch = 0;
                 for (int32_t ti : P.compact_to_tree[d]) nch = std::max(nch, P.levels[d][ti].children.size());
-                m *= (double)nch * lt * lt * lt;
+                m *= (double)nch * lt;
                 P.scale_mult[d] = (float)m;
             }
         }

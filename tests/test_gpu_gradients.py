@@ -134,3 +134,25 @@ def test_autofocus_gradient_against_finite_differences(torch):
     assert abs(L.item() - L0) <= 1e-4 * abs(L0)
     assert rel <= 1e-3
     assert worst <= 1e-2
+
+
+def test_gpu_gradients_bandlimited(torch, small):
+    """The adjoint and position gradient with band-limited interpolation
+    weights against the oracle (same bars as with Lagrange's)."""
+    from oracle import adjoint as OA
+    from oracle import plan as OP
+    g3 = (2.0, 2.0, 2.5)
+    op = OP.build_plan(*_args(small), 2, 4, g3, TAPS, kernel="bandlimited")
+    pl = H.Plan(*_args(small), stages=2, oversample=g3, interp_taps=TAPS,
+                interp_kernel="bandlimited")
+    rng = np.random.default_rng(2)
+    g = rng.standard_normal(small.grid_dims) + 1j * rng.standard_normal(small.grid_dims)
+    ref_s = OA.echo_gradient(op, g, small.positions)
+    ref_p = OA.position_gradient(op, small.echoes, small.positions, g)
+    ge, gp = pl.backward(torch.from_numpy(small.echoes.astype(np.complex64)).cuda(),
+                         torch.from_numpy(g.astype(np.complex64)).cuda())
+    es = _nrmse(ge.cpu().numpy().astype(np.complex128), ref_s)
+    ep = float(np.linalg.norm(gp.cpu().numpy() - ref_p) / np.linalg.norm(ref_p))
+    _say(f"  bandlimited: echo gradient NRMSE {es:.2e}; position gradient rel {ep:.2e}")
+    assert es <= 1e-5
+    assert ep <= 1e-3

@@ -69,3 +69,20 @@ def test_loss_cotangent_against_central_differences():
         d_re = (OL.loss(f + e, fc) - OL.loss(f - e, fc)) / (2 * h)
         d_im = (OL.loss(f + 1j * e, fc) - OL.loss(f - 1j * e, fc)) / (2 * h)
         assert abs(d_re - g[v].real) < 1e-7 and abs(d_im - g[v].imag) < 1e-7
+
+
+def test_factorised_adjoint_identity_bandlimited(tiny):
+    """<A s, g> = <s, A^H g> with band-limited interpolation weights."""
+    pl, pos, ech = tiny
+    from oracle import plan as OP
+    from workloads import make_config
+    w = make_config(0)
+    sel = np.arange(0, w.n_pos, 5)[:192]
+    plb = OP.build_plan(w.positions[sel], w.freqs_hz, np.array([-0.005, -0.005, 0.245]),
+                        np.full(3, 2e-3), (6, 6, 4), 1, 4, (2.0, 2.0, 2.5), 4, kernel="bandlimited")
+    rng = np.random.default_rng(3)
+    s = rng.standard_normal(ech.shape) + 1j * rng.standard_normal(ech.shape)
+    g = rng.standard_normal(plb.dims) + 1j * rng.standard_normal(plb.dims)
+    lhs = np.vdot(g.ravel(), OH.image(plb, s, pos).ravel())
+    rhs = np.vdot(OA.echo_gradient(plb, g, pos).ravel(), s.ravel())
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
