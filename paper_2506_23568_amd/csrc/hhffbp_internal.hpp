@@ -106,7 +106,8 @@ struct DeviceBuffers {
     void *Bd = nullptr;             // range-derivative matrix (rows x j 2 k_f), [2 Nf][2 Nr]
     void *Badj = nullptr;           // conj-transposed DFT matrix, [2 Nr][2 Nf]
     void *scale_mult = nullptr;     // float [S + 1]: worst-case gain from echoes to each stage
-    std::vector<void *> merge_blocks;  // per depth 1..S-1: BlockItem[]
+    std::vector<void *> merge_blocks;  // per depth 1..S-1: BlockItem[] of 256 points (adjoint)
+    std::vector<void *> merge_blocks_fwd;  // per depth 1..S-1: BlockItem[] of 256 / Q points
 };
 
 struct Plan {
@@ -132,6 +133,7 @@ struct Plan {
     std::vector<std::vector<int32_t>> compact_to_tree;  // per depth
     std::vector<int64_t> depth_points;   // per depth
     std::vector<int64_t> n_blocks_merge; // per depth
+    std::vector<int64_t> n_blocks_merge_fwd; // per depth
     int64_t n_blocks_leaf = 0, n_blocks_adj = 0;
     int64_t leaf_pairs = 0, merge_pairs = 0, final_pairs = 0;
     // workspace layout (bytes)

@@ -274,8 +274,14 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
 }
 
 // Merge at depth d: parent grid points (float64 SoA) of the depth-d nodes,
-// children at depth d + 1.  Output: compressed parent values.
-template <int T, int ST, int K>
+// children at depth d + 1.  Output: compressed parent values.  One wave per
+// (64 parent points, child): a block of kBlock threads covers kBlock / CL
+// points, wave w interpolating child w % CL for point group w / CL, so each
+// wave's gathers stay within one child and follow its points' pencils.  The
+// children's rotated values meet in LDS and are summed in child order.  A
+// launch thus has CL times as many waves as points / 64 to hide the gathers'
+// latency.
+template <int T, int ST, int K, int CL>
 __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ parents,
                                                   const BlockItem *__restrict__ blocks,
                                                   const double *__restrict__ px,
@@ -288,30 +294,48 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
                                                   const float *__restrict__ scales, int d,
                                                   typename Store<ST>::C *__restrict__ out)
 {
+    __shared__ float2 part[kBlock];
+    // the wave index is uniform: readfirstlane lets the child's fields be scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    const int lane = (int)(threadIdx.x % 64);
+    const int c = wave % CL, grp = wave / CL;
     const BlockItem blk = blocks[blockIdx.x];
     const NodeDev nd = parents[blk.node];
-    const int p = blk.start + threadIdx.x;
-    if (p >= nd.npts) return;
-    const int gi = nd.val_base + p;
-    const double x = px[gi], y = py[gi], z = pz[gi];
-    if (!(z > 0.0)) {  // absent grid point (no preimage): holds 0
-        out[gi] = Store<ST>::st(make_float2(0.0f, 0.0f));
-        return;
+    const int p = blk.start + grp * 64 + lane;
+    const bool inside = p < nd.npts;
+    const int gi = nd.val_base + (inside ? p : 0);
+    double x = 0.0, y = 0.0, z = 0.0;
+    if (inside) {
+        x = px[gi];
+        y = py[gi];
+        z = pz[gi];
     }
-    const double phip = phi_only(nd, x, y, z, gp.kmin, gp.kmax);
+    const bool present = inside && z > 0.0;  // an absent grid point (no preimage) holds 0
     float are = 0.0f, aim = 0.0f;
-    const int32_t *child_idx = parents[blk.node].child;  // global: no dynamic index into a local copy
-    for (int c = 0; c < nd.nchild; ++c) {
-        const NodeDev ch = children[child_idx[c]];
+    if (present && c < nd.nchild) {
+        const double phip = phi_only(nd, x, y, z, gp.kmin, gp.kmax);
+        const NodeDev ch = children[parents[blk.node].child[c]];
         const ChildCoord g = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
         const float2 v = interp_child<T, ST, K>(ch, ccols, cvals, g, ip);
         phase_mac(v, g.phi - phip, are, aim);
     }
-    const float rs = scales[d] / scales[d + 1];
-    out[gi] = Store<ST>::st(make_float2(rs * are, rs * aim));
+    part[threadIdx.x] = make_float2(are, aim);
+    __syncthreads();
+    if (c == 0 && inside) {
+        float sre = 0.0f, sim = 0.0f;
+#pragma unroll
+        for (int k = 0; k < CL; ++k) {
+            const float2 q = part[(grp * CL + k) * 64 + lane];
+            sre += q.x;
+            sim += q.y;
+        }
+        const float rs = scales[d] / scales[d + 1];
+        out[gi] = Store<ST>::st(make_float2(rs * sre, rs * sim));
+    }
 }
 
-// Final stage: user voxels, children are the depth-1 nodes.
+// Final stage: user voxels, children are the depth-1 nodes; one lane per voxel
+// (the voxel grid alone gives a launch enough waves).
 template <int T, int ST, int K>
 __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ children,
                                                   int nchild, const ColEntry *__restrict__ ccols,
@@ -474,17 +498,17 @@ hipError_t launch_bp_kernels(const Plan &P, const double *pos64, const void *pro
     return hipGetLastError();
 }
 
-template <int T, int ST, int K>
+template <int T, int ST, int K, int CL>
 hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scales, hipStream_t st,
                          hipEvent_t *ev)
 {
     using C = typename Store<ST>::C;
     GeoParams gp{P.gamma[0], P.gamma[1], P.gamma[2], P.kmin, P.kmax};
     for (int d = P.S - 1; d >= 1; --d) {
-        if (P.n_blocks_merge[d] > 0) {
-            hipLaunchKernelGGL((k_merge<T, ST, K>), dim3(P.n_blocks_merge[d]), dim3(kBlock), 0, st,
-                               (const NodeDev *)P.dev.nodes[d],
-                               (const BlockItem *)P.dev.merge_blocks[d], (const double *)P.dev.px[d],
+        if (P.n_blocks_merge_fwd[d] > 0) {
+            hipLaunchKernelGGL((k_merge<T, ST, K, CL>), dim3(P.n_blocks_merge_fwd[d]), dim3(kBlock),
+                               0, st, (const NodeDev *)P.dev.nodes[d],
+                               (const BlockItem *)P.dev.merge_blocks_fwd[d], (const double *)P.dev.px[d],
                                (const double *)P.dev.py[d], (const double *)P.dev.pz[d],
                                (const NodeDev *)P.dev.nodes[d + 1],
                                (const ColEntry *)P.dev.cols[d + 1],
@@ -508,6 +532,17 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
     hipError_t e = hipGetLastError();
     if (ev && e == hipSuccess) (void)hipEventRecord(*ev, st);
     return e;
+}
+
+template <int ST, int CL>
+hipError_t dispatch_merges(const Plan &P, char *ws, void *image, const float *scales,
+                           hipStream_t st, hipEvent_t *ev)
+{
+    if (P.ipoly.kind == HHFFBP_INTERP_BANDLIMITED)
+        return (P.T == 4) ? launch_merges<4, ST, HHFFBP_INTERP_BANDLIMITED, CL>(P, ws, image, scales, st, ev)
+                          : launch_merges<6, ST, HHFFBP_INTERP_BANDLIMITED, CL>(P, ws, image, scales, st, ev);
+    return (P.T == 4) ? launch_merges<4, ST, HHFFBP_INTERP_LAGRANGE, CL>(P, ws, image, scales, st, ev)
+                      : launch_merges<6, ST, HHFFBP_INTERP_LAGRANGE, CL>(P, ws, image, scales, st, ev);
 }
 
 template <int ST>
@@ -574,12 +609,10 @@ hhffbp_status image_for_storage(const Plan &P, const void *echoes, const double 
     if (e != hipSuccess) return HHFFBP_E_DEVICE;
     if (ev) (void)hipEventRecord(*ev++, st);
     if (P.S == 0) return HHFFBP_OK;
-    if (P.ipoly.kind == HHFFBP_INTERP_BANDLIMITED)
-        e = (P.T == 4) ? launch_merges<4, ST, HHFFBP_INTERP_BANDLIMITED>(P, ws, image, scales, st, ev)
-                       : launch_merges<6, ST, HHFFBP_INTERP_BANDLIMITED>(P, ws, image, scales, st, ev);
+    if (P.Q == 4)
+        e = dispatch_merges<ST, 4>(P, ws, image, scales, st, ev);
     else
-        e = (P.T == 4) ? launch_merges<4, ST, HHFFBP_INTERP_LAGRANGE>(P, ws, image, scales, st, ev)
-                       : launch_merges<6, ST, HHFFBP_INTERP_LAGRANGE>(P, ws, image, scales, st, ev);
+        e = dispatch_merges<ST, 2>(P, ws, image, scales, st, ev);
     return e == hipSuccess ? HHFFBP_OK : HHFFBP_E_DEVICE;
 }
 

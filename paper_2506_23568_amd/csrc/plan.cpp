@@ -868,7 +868,9 @@ void upload_plan(Plan &P)
     P.dev.py.assign(S + 1, nullptr);
     P.dev.pz.assign(S + 1, nullptr);
     P.dev.merge_blocks.assign(S + 1, nullptr);
+    P.dev.merge_blocks_fwd.assign(S + 1, nullptr);
     P.n_blocks_merge.assign(S + 1, 0);
+    P.n_blocks_merge_fwd.assign(S + 1, 0);
     P.device_bytes = 0;
     if (P.cfg.device < 0) return;  // host-only plan: geometry and sizes, no device tables
     if (hipSetDevice(P.cfg.device) != hipSuccess)
@@ -887,7 +889,7 @@ void upload_plan(Plan &P)
     for (int d = 1; d <= S; ++d) {
         std::vector<NodeDev> nodes;
         std::vector<ColEntry> cols;
-        std::vector<BlockItem> blocks;
+        std::vector<BlockItem> blocks, blocks_fwd;
         std::vector<double> x, y, z;
         std::vector<LeafPoint> lpts;
         int32_t vbase = 0, cbase = 0;
@@ -924,6 +926,9 @@ void upload_plan(Plan &P)
             for (int64_t c = 0; c < (int64_t)L.ni * L.nj; ++c)
                 cols.push_back(ColEntry{(int32_t)L.off[c], L.lo[c], L.hi[c], 0});
             for (int32_t st = 0; st < nd.npts; st += 256) blocks.push_back(BlockItem{hn.compact, st});
+            // the forward merge runs one lane per (point, child): 256 / Q points a block
+            for (int32_t st = 0; st < nd.npts; st += 256 / P.Q)
+                blocks_fwd.push_back(BlockItem{hn.compact, st});
             if (d < S) {
                 for (int64_t q = 0; q < L.npts; ++q) {
                     x.push_back(L.xyz[3 * q]);
@@ -971,6 +976,8 @@ void upload_plan(Plan &P)
             upload_vec(P.device_bytes, &D.pz[d], z);
             upload_vec(P.device_bytes, &D.merge_blocks[d], blocks);
             P.n_blocks_merge[d] = (int64_t)blocks.size();
+            upload_vec(P.device_bytes, &D.merge_blocks_fwd[d], blocks_fwd);
+            P.n_blocks_merge_fwd[d] = (int64_t)blocks_fwd.size();
         } else {
             upload_vec(P.device_bytes, &D.leafpts, lpts);
             upload_vec(P.device_bytes, &D.leaf_blocks, blocks);
@@ -1004,7 +1011,7 @@ void release_plan(Plan &P)
     fr(D.Bd);
     fr(D.Badj);
     fr(D.scale_mult);
-    for (auto *v : {&D.nodes, &D.cols, &D.px, &D.py, &D.pz, &D.merge_blocks})
+    for (auto *v : {&D.nodes, &D.cols, &D.px, &D.py, &D.pz, &D.merge_blocks, &D.merge_blocks_fwd})
         for (auto &p : *v) fr(p);
 }
 
