@@ -86,6 +86,30 @@ inline int pos_chunk(int64_t Nr, size_t per_pos_header)
     return c > kPosChunkMax ? kPosChunkMax : (c < 1 ? 1 : c);
 }
 
+// XCD-aware block order.  The dispatcher hands workgroup b to XCD b mod 8, each
+// XCD with its own L2.  The logical order deals runs of RUN consecutive logical
+// blocks to the XCDs in turn, so neighbouring logical blocks, which share inputs
+// (a leaf's profiles, a parent node's children), meet in one L2.  RUN = 0 gives
+// each XCD one contiguous share: the most sharing, for blocks of equal cost (a
+// merge); a finite run keeps the XCDs balanced where block costs vary (leaves of
+// different sizes: the contiguous form measured 30% slower there).  A bijection
+// on [0, n); with a finite run the last partial round keeps the identity order.
+// Only speed depends on the dispatch order.
+constexpr int kXcds = 8;
+template <int RUN>
+__device__ __forceinline__ int xcd_block(int b, int n)
+{
+    const int x = b % kXcds, s = b / kXcds;
+    if constexpr (RUN == 0) {
+        const int per = n / kXcds, rem = n % kXcds;
+        return x * per + min(x, rem) + s;
+    } else {
+        constexpr int round = kXcds * RUN;
+        if (b >= n / round * round) return b;
+        return ((s / RUN) * kXcds + x) * RUN + s % RUN;
+    }
+}
+
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float exp2_f(float x) { return __builtin_amdgcn_exp2f(x); }

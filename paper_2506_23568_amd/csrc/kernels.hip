@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
     extern __shared__ unsigned char smem[];
     float4 *s_pos = reinterpret_cast<float4 *>(smem);
     float2 *s_prof = reinterpret_cast<float2 *>(smem + chunk * sizeof(float4));
-    const BlockItem blk = blocks[blockIdx.x];
+    const BlockItem blk = blocks[xcd_block<16>((int)blockIdx.x, (int)gridDim.x)];
     const NodeDev nd = leaves[blk.node];
     const int p = blk.start + threadIdx.x;
     const bool active = p < nd.npts;
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     const int lane = (int)(threadIdx.x % 64);
     const int c = wave % CL, grp = wave / CL;
-    const BlockItem blk = blocks[blockIdx.x];
+    const BlockItem blk = blocks[xcd_block<0>((int)blockIdx.x, (int)gridDim.x)];
     const NodeDev nd = parents[blk.node];
     const int p = blk.start + grp * 64 + lane;
     const bool inside = p < nd.npts;
