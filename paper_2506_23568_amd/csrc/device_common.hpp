@@ -110,6 +110,14 @@ __device__ __forceinline__ int xcd_block(int b, int n)
     }
 }
 
+// floor(x) as int32 in one VALU instruction (the compiler emits floor + convert)
+__device__ __forceinline__ int floor_int(float x)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float exp2_f(float x) { return __builtin_amdgcn_exp2f(x); }

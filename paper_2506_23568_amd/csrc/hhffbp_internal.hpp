@@ -141,6 +141,7 @@ struct Plan {
     size_t ws_scales = 0, ws_amax = 0;  // per-call storage scales (float [S + 1]) and max |echo|
     size_t ws_gprof = 0, ws_gpos = 0, ws_gmax = 0, ws_total_bwd = 0;  // backward additions
     size_t device_bytes = 0;  // plan tables uploaded to the device (owned by the plan)
+    double leaf_reach = 0.0;  // max |p' - c| over leaf members and their leaf centres c (z = 0), plus slack
     double model_s = 0.0;     // the Sec. IV-B cost model's level-1 BP + interpolation time
     InterpPoly ipoly{};       // merge interpolation weights
     std::vector<size_t> ws_gvals;        // backward: float32 cotangents per depth

@@ -205,7 +205,10 @@ inline int gemm_vec(const void *A, int K, const float *B, int N)
 //   g = sum_w phi_w(t) prof_i[r_first + w],   t = (|q - c| - R0)/dR + Delta R / dR
 //   acc += g exp(j 2 kc Delta R)
 // and f'(q) = acc exp(j (2 kc |q - c| - Phi(q))), the last factor precomputed.
-template <int KERNEL, int W, int ST>
+// RED = false drops the reduction of the carrier's argument to [-1/2, 1/2]
+// turn: v_sin / v_cos accept [-256, 256] turns, and the plan selects that form
+// only when 2 kc |Delta R| / 2 pi <= 2 kc max|p' - c| / 2 pi stays below 128.
+template <int KERNEL, int W, int ST, bool RED>
 __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ leaves,
                                                     const BlockItem *__restrict__ blocks,
                                                     const LeafPoint *__restrict__ pts,
@@ -227,6 +230,10 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
     const float Rc = fast_sqrt(q.dx * q.dx + q.dy * q.dy + q.dz * q.dz);
     const float frac_w = q.frac - 0.5f * W;  // tau = t - W/2 relative to the point's bin
     const int bin1 = q.bin + 1;
+    // the plan's range window holds every tap; clamping tau to [lo, hi] only keeps
+    // positions moved beyond the planned slack inside the profile
+    const float tau_lo = (float)(-bin1), tau_hi = (float)(Nr - W - bin1);
+    const float m2x = -2.0f * q.dx, m2y = -2.0f * q.dy, m2z = -2.0f * q.dz;
     float acc_re = 0.0f, acc_im = 0.0f;
     for (int c0 = nd.pos_begin; c0 < nd.pos_end; c0 += chunk) {
         const int n = min(chunk, nd.pos_end - c0);
@@ -239,27 +246,32 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
             for (int i = 0; i < n; ++i) {
                 const float4 d = s_pos[i];
                 const float ex = q.dx - d.x, ey = q.dy - d.y, ez = q.dz - d.z;
-                const float R = fast_sqrt(ex * ex + ey * ey + ez * ez);
-                const float num = d.w - 2.0f * (q.dx * d.x + q.dy * d.y + q.dz * d.z);
+                const float R = fast_sqrt(fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+                const float num = fmaf(m2x, d.x, fmaf(m2y, d.y, fmaf(m2z, d.z, d.w)));
                 const float dR = num * fast_rcp(R + Rc);
-                const float tau = fmaf(dR, inv_dR, frac_w);
-                const float fl = floorf(tau);
-                const float x = tau - fl;
-                // the plan's range window holds every tap; the clamp only keeps
-                // positions moved beyond the planned slack inside the profile
-                const int r = min(max(bin1 + (int)fl, 0), Nr - W);
-                float w[W];
-                range_weights<KERNEL, W>(x, beta_log2e, w);
+                const float tau = __builtin_amdgcn_fmed3f(fmaf(dR, inv_dR, frac_w), tau_lo, tau_hi);
+                const int r = bin1 + floor_int(tau);
+                const float x = __builtin_amdgcn_fractf(tau);
                 const float2 *pr = s_prof + i * Nr + r;
-                float gre = 0.0f, gim = 0.0f;
+                float gre, gim;
+                if constexpr (KERNEL == HHFFBP_RANGE_LINEAR) {
+                    const float2 v0 = pr[0], v1 = pr[1];
+                    gre = fmaf(x, v1.x - v0.x, v0.x);
+                    gim = fmaf(x, v1.y - v0.y, v0.y);
+                } else {
+                    float w[W];
+                    range_weights<KERNEL, W>(x, beta_log2e, w);
+                    gre = 0.0f;
+                    gim = 0.0f;
 #pragma unroll
-                for (int k = 0; k < W; ++k) {
-                    const float2 v = pr[k];
-                    gre = fmaf(w[k], v.x, gre);
-                    gim = fmaf(w[k], v.y, gim);
+                    for (int k = 0; k < W; ++k) {
+                        const float2 v = pr[k];
+                        gre = fmaf(w[k], v.x, gre);
+                        gim = fmaf(w[k], v.y, gim);
+                    }
                 }
                 float ph = dR * kc_turns;
-                ph -= rintf(ph);
+                if constexpr (RED) ph -= rintf(ph);
                 const float sn = sin_turns(ph), cs = cos_turns(ph);
                 acc_re = fmaf(gre, cs, fmaf(-gim, sn, acc_re));
                 acc_im = fmaf(gre, sn, fmaf(gim, cs, acc_im));
@@ -491,10 +503,20 @@ hipError_t launch_bp_kernels(const Plan &P, const double *pos64, const void *pro
     }
     const int chunk = pos_chunk(P.Nr, sizeof(float4));
     const size_t sh = chunk * (sizeof(float4) + P.Nr * sizeof(float2));
-    hipLaunchKernelGGL((k_leaf_bp<KERNEL, W, ST>), dim3(P.n_blocks_leaf), dim3(kBlock), sh, st,
-                       (const NodeDev *)P.dev.nodes[P.S], (const BlockItem *)P.dev.leaf_blocks,
-                       (const LeafPoint *)P.dev.leafpts, posoff, (const C *)prof, (int)P.Nr, chunk,
-                       inv_dR, beta_log2e, kc_turns, scales, P.S, (C *)(ws + P.ws_vals[P.S]));
+    // |Delta R| <= |p' - c| (triangle inequality): the carrier's argument stays
+    // below 128 turns without reduction when the plan's leaf reach allows it
+    if (P.leaf_reach * (P.kc / kPi) < 128.0)
+        hipLaunchKernelGGL((k_leaf_bp<KERNEL, W, ST, false>), dim3(P.n_blocks_leaf), dim3(kBlock), sh,
+                           st, (const NodeDev *)P.dev.nodes[P.S], (const BlockItem *)P.dev.leaf_blocks,
+                           (const LeafPoint *)P.dev.leafpts, posoff, (const C *)prof, (int)P.Nr,
+                           chunk, inv_dR, beta_log2e, kc_turns, scales, P.S,
+                           (C *)(ws + P.ws_vals[P.S]));
+    else
+        hipLaunchKernelGGL((k_leaf_bp<KERNEL, W, ST, true>), dim3(P.n_blocks_leaf), dim3(kBlock), sh,
+                           st, (const NodeDev *)P.dev.nodes[P.S], (const BlockItem *)P.dev.leaf_blocks,
+                           (const LeafPoint *)P.dev.leafpts, posoff, (const C *)prof, (int)P.Nr,
+                           chunk, inv_dR, beta_log2e, kc_turns, scales, P.S,
+                           (C *)(ws + P.ws_vals[P.S]));
     return hipGetLastError();
 }
 

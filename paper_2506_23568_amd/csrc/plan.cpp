@@ -677,15 +677,22 @@ void build_plan_host(Plan &P)
     P.perm.clear();
     P.leaf_of_sorted.clear();
     P.leaf_centre.clear();
+    P.leaf_reach = 0.0;
     for (int32_t ti : P.compact_to_tree[S]) {
         const HostNode &lf = P.levels[S][ti];
+        const double xc = 0.5 * (lf.rect.x0 + lf.rect.x1), yc = 0.5 * (lf.rect.y0 + lf.rect.y1);
         for (int32_t m : lf.members) {
             P.perm.push_back(m);
             P.leaf_of_sorted.push_back(lf.compact);
+            const double *pm = &P.positions[3 * m];
+            P.leaf_reach = std::max(P.leaf_reach, std::sqrt((pm[0] - xc) * (pm[0] - xc) +
+                                                            (pm[1] - yc) * (pm[1] - yc) + pm[2] * pm[2]));
         }
-        P.leaf_centre.push_back(0.5 * (lf.rect.x0 + lf.rect.x1));
-        P.leaf_centre.push_back(0.5 * (lf.rect.y0 + lf.rect.y1));
+        P.leaf_centre.push_back(xc);
+        P.leaf_centre.push_back(yc);
     }
+    // a member moved by up to the slack per axis stays within this distance of its leaf centre
+    P.leaf_reach += std::sqrt(3.0) * c.position_slack;
 
     // range window: all (point, position) distances the backprojection uses
     double rmin = std::numeric_limits<double>::max(), rmax = 0.0;
