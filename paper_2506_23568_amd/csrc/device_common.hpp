@@ -118,6 +118,17 @@ __device__ __forceinline__ int floor_int(float x)
     return r;
 }
 
+// Positions per staged chunk of the level-1 BP for a bin window of nrb bins:
+// as many as kLdsBudget holds (a float4 and nrb float2 each), at most 32.
+constexpr int kLeafChunkMax = 32;
+// thread-strided staging steps that cover a kLdsBudget tile of float2
+constexpr int kStageSteps = (int)((kLdsBudget / sizeof(float2) + kBlock - 1) / kBlock);
+__host__ __device__ inline int leaf_chunk(int nrb)
+{
+    const int c = (int)(kLdsBudget / (sizeof(float4) + (size_t)nrb * sizeof(float2)));
+    return c > kLeafChunkMax ? kLeafChunkMax : (c < 1 ? 1 : c);
+}
+
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float exp2_f(float x) { return __builtin_amdgcn_exp2f(x); }

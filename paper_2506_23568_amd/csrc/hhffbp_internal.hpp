@@ -66,6 +66,12 @@ struct BlockItem {
     int32_t node, start;
 };
 
+// Range bins [lo, lo + n) that a level-1 BP block can read: every tap of its
+// points for positions within the leaf's reach.
+struct BinWindow {
+    int32_t lo, n;
+};
+
 struct Rect {
     double x0, x1, y0, y1;
 };
@@ -102,6 +108,7 @@ struct DeviceBuffers {
     std::vector<void *> px, py, pz; // per depth < S: float64 SoA grid points
     void *leafpts = nullptr;        // LeafPoint[] of depth S
     void *leaf_blocks = nullptr;    // BlockItem[]
+    void *leaf_wins = nullptr;      // BinWindow[], one per leaf block
     void *adj_blocks = nullptr;     // BlockItem[]: (leaf, first sorted position of 16)
     void *Bd = nullptr;             // range-derivative matrix (rows x j 2 k_f), [2 Nf][2 Nr]
     void *Badj = nullptr;           // conj-transposed DFT matrix, [2 Nr][2 Nf]
@@ -135,6 +142,7 @@ struct Plan {
     std::vector<int64_t> n_blocks_merge; // per depth
     std::vector<int64_t> n_blocks_merge_fwd; // per depth
     int64_t n_blocks_leaf = 0, n_blocks_adj = 0;
+    int32_t leaf_win_max = 0;  // widest BinWindow of the level-1 BP blocks
     int64_t leaf_pairs = 0, merge_pairs = 0, final_pairs = 0;
     // workspace layout (bytes)
     size_t ws_prof = 0, ws_posoff = 0, ws_total = 0;

@@ -18,6 +18,7 @@
 // array carries a power-of-two scale, scales[0] for the profiles and scales[d]
 // for depth d, chosen per call from the largest echo component and the plan's
 // worst-case gain of each stage, so that no stored value can exceed 2^15.
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -211,18 +212,27 @@ inline int gemm_vec(const void *A, int K, const float *B, int N)
 template <int KERNEL, int W, int ST, bool RED>
 __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ leaves,
                                                     const BlockItem *__restrict__ blocks,
+                                                    const BinWindow *__restrict__ wins,
                                                     const LeafPoint *__restrict__ pts,
                                                     const float4 *__restrict__ posoff,
                                                     const typename Store<ST>::C *__restrict__ prof,
-                                                    int Nr, int chunk, float inv_dR,
+                                                    int Nr, float inv_dR,
                                                     float beta_log2e, float kc_turns,
                                                     const float *__restrict__ scales, int S,
                                                     typename Store<ST>::C *__restrict__ out)
 {
     extern __shared__ unsigned char smem[];
+    const int lb = xcd_block<16>((int)blockIdx.x, (int)gridDim.x);
+    const BlockItem blk = blocks[lb];
+    // only the block's bin window [r0, r0 + nrb) is staged, as many positions at a
+    // time as kLdsBudget holds
+    const BinWindow win = wins[lb];
+    const int r0 = win.lo, nrb = win.n;
+    const int chunk = leaf_chunk(nrb);
+    const int i_first = (int)threadIdx.x / nrb, t_first = (int)threadIdx.x % nrb;
+    const int di = kBlock / nrb, dt = kBlock % nrb;
     float4 *s_pos = reinterpret_cast<float4 *>(smem);
     float2 *s_prof = reinterpret_cast<float2 *>(smem + chunk * sizeof(float4));
-    const BlockItem blk = blocks[xcd_block<16>((int)blockIdx.x, (int)gridDim.x)];
     const NodeDev nd = leaves[blk.node];
     const int p = blk.start + threadIdx.x;
     const bool active = p < nd.npts;
@@ -230,17 +240,41 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
     const float Rc = fast_sqrt(q.dx * q.dx + q.dy * q.dy + q.dz * q.dz);
     const float frac_w = q.frac - 0.5f * W;  // tau = t - W/2 relative to the point's bin
     const int bin1 = q.bin + 1;
-    // the plan's range window holds every tap; clamping tau to [lo, hi] only keeps
-    // positions moved beyond the planned slack inside the profile
-    const float tau_lo = (float)(-bin1), tau_hi = (float)(Nr - W - bin1);
+    // the block's window holds every tap; clamping tau to [lo, hi] only keeps
+    // positions moved beyond the planned slack inside it
+    const float tau_lo = (float)(r0 - bin1), tau_hi = (float)(r0 + nrb - W - bin1);
     const float m2x = -2.0f * q.dx, m2y = -2.0f * q.dy, m2z = -2.0f * q.dz;
     float acc_re = 0.0f, acc_im = 0.0f;
     for (int c0 = nd.pos_begin; c0 < nd.pos_end; c0 += chunk) {
         const int n = min(chunk, nd.pos_end - c0);
         __syncthreads();
         for (int t = threadIdx.x; t < n; t += kBlock) s_pos[t] = posoff[c0 + t];
-        const typename Store<ST>::C *src = prof + (size_t)c0 * Nr;
-        for (int t = threadIdx.x; t < n * Nr; t += kBlock) s_prof[t] = Store<ST>::ld(src[t]);
+        const typename Store<ST>::C *src = prof + (size_t)c0 * Nr + r0;
+        {
+            // the n x nrb tile, element e = i nrb + t, thread-strided; (i, t) of e
+            // advances by (di, dt) per step, so no division in the loop, and the
+            // unrolled steps issue their loads together
+            const int total = n * nrb;
+            int i = i_first, t = t_first;
+            float2 v[kStageSteps];
+#pragma unroll
+            for (int k = 0; k < kStageSteps; ++k) {
+                // a step past the tile reads the tile's first element and stores nothing
+                const bool in = k * kBlock + (int)threadIdx.x < total;
+                v[k] = Store<ST>::ld(src[in ? i * Nr + t : 0]);
+                i += di;
+                t += dt;
+                if (t >= nrb) {
+                    t -= nrb;
+                    ++i;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kStageSteps; ++k)
+                if (k * kBlock + (int)threadIdx.x < total) s_prof[k * kBlock + threadIdx.x] = v[k];
+            for (int e = kStageSteps * kBlock + threadIdx.x; e < total; e += kBlock)
+                s_prof[e] = Store<ST>::ld(src[(size_t)(e / nrb) * Nr + e % nrb]);
+        }
         __syncthreads();
         if (active) {
             for (int i = 0; i < n; ++i) {
@@ -250,9 +284,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
                 const float num = fmaf(m2x, d.x, fmaf(m2y, d.y, fmaf(m2z, d.z, d.w)));
                 const float dR = num * fast_rcp(R + Rc);
                 const float tau = __builtin_amdgcn_fmed3f(fmaf(dR, inv_dR, frac_w), tau_lo, tau_hi);
-                const int r = bin1 + floor_int(tau);
+                const int r = bin1 - r0 + floor_int(tau);
                 const float x = __builtin_amdgcn_fractf(tau);
-                const float2 *pr = s_prof + i * Nr + r;
+                const float2 *pr = s_prof + i * nrb + r;
                 float gre, gim;
                 if constexpr (KERNEL == HHFFBP_RANGE_LINEAR) {
                     const float2 v0 = pr[0], v1 = pr[1];
@@ -501,21 +535,23 @@ hipError_t launch_bp_kernels(const Plan &P, const double *pos64, const void *pro
                            ny, nz, scales, (float2 *)image);
         return hipGetLastError();
     }
-    const int chunk = pos_chunk(P.Nr, sizeof(float4));
-    const size_t sh = chunk * (sizeof(float4) + P.Nr * sizeof(float2));
+    // leaf_chunk() keeps a chunk within kLdsBudget, but never below one position
+    const size_t sh = std::max(kLdsBudget, sizeof(float4) + (size_t)P.leaf_win_max * sizeof(float2));
     // |Delta R| <= |p' - c| (triangle inequality): the carrier's argument stays
     // below 128 turns without reduction when the plan's leaf reach allows it
     if (P.leaf_reach * (P.kc / kPi) < 128.0)
         hipLaunchKernelGGL((k_leaf_bp<KERNEL, W, ST, false>), dim3(P.n_blocks_leaf), dim3(kBlock), sh,
                            st, (const NodeDev *)P.dev.nodes[P.S], (const BlockItem *)P.dev.leaf_blocks,
-                           (const LeafPoint *)P.dev.leafpts, posoff, (const C *)prof, (int)P.Nr,
-                           chunk, inv_dR, beta_log2e, kc_turns, scales, P.S,
+                           (const BinWindow *)P.dev.leaf_wins, (const LeafPoint *)P.dev.leafpts,
+                           posoff, (const C *)prof, (int)P.Nr, inv_dR, beta_log2e, kc_turns,
+                           scales, P.S,
                            (C *)(ws + P.ws_vals[P.S]));
     else
         hipLaunchKernelGGL((k_leaf_bp<KERNEL, W, ST, true>), dim3(P.n_blocks_leaf), dim3(kBlock), sh,
                            st, (const NodeDev *)P.dev.nodes[P.S], (const BlockItem *)P.dev.leaf_blocks,
-                           (const LeafPoint *)P.dev.leafpts, posoff, (const C *)prof, (int)P.Nr,
-                           chunk, inv_dR, beta_log2e, kc_turns, scales, P.S,
+                           (const BinWindow *)P.dev.leaf_wins, (const LeafPoint *)P.dev.leafpts,
+                           posoff, (const C *)prof, (int)P.Nr, inv_dR, beta_log2e, kc_turns,
+                           scales, P.S,
                            (C *)(ws + P.ws_vals[P.S]));
     return hipGetLastError();
 }

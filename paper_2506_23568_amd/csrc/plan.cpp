@@ -899,6 +899,7 @@ void upload_plan(Plan &P)
         std::vector<BlockItem> blocks, blocks_fwd;
         std::vector<double> x, y, z;
         std::vector<LeafPoint> lpts;
+        std::vector<BinWindow> wins;
         int32_t vbase = 0, cbase = 0;
         for (int32_t ti : P.compact_to_tree[d]) {
             const HostNode &hn = P.levels[d][ti];
@@ -970,6 +971,40 @@ void upload_plan(Plan &P)
                     lp.pad = 0;
                     lpts.push_back(lp);
                 }
+                // per block of 256 points: the bins its taps can reach.  With
+                // |Delta R| <= reach (the leaf's largest |p' - c| plus slack), tau =
+                // Delta R / dR + frac - W/2 lies in [-reach/dR - W/2, reach/dR + 1 - W/2)
+                // and a point with bin b reads b + 1 + floor(tau) .. + W - 1.
+                double reach = 0.0;
+                for (int32_t m : hn.members) {
+                    const double *pm = &P.positions[3 * m];
+                    reach = std::max(reach, std::sqrt((pm[0] - xc) * (pm[0] - xc) +
+                                                      (pm[1] - yc) * (pm[1] - yc) + pm[2] * pm[2]));
+                }
+                reach += std::sqrt(3.0) * P.cfg.position_slack;
+                const int32_t mlo = (int32_t)std::floor(-reach / P.dR - 0.5 * P.W);
+                const int32_t mhi = (int32_t)std::floor(reach / P.dR + 1.0 - 0.5 * P.W) + P.W - 1;
+                const int32_t Nr = (int32_t)P.Nr;
+                for (int32_t st = 0; st < nd.npts; st += 256) {
+                    int32_t blo = INT32_MAX, bhi = INT32_MIN;
+                    for (int32_t q = st; q < std::min(nd.npts, st + 256); ++q) {
+                        if (!std::isfinite(L.xyz[3 * q + 2])) continue;
+                        const int32_t b1 = lpts[vbase + q].bin + 1;
+                        blo = std::min(blo, b1 + mlo);
+                        bhi = std::max(bhi, b1 + mhi);
+                    }
+                    if (blo > bhi) {  // only absent points: any W bins
+                        blo = 0;
+                        bhi = P.W - 1;
+                    }
+                    blo = std::max(blo, 0);
+                    bhi = std::min(bhi, Nr - 1);
+                    if (bhi - blo + 1 < P.W) {
+                        blo = std::max(0, std::min(blo, Nr - P.W));
+                        bhi = blo + P.W - 1;
+                    }
+                    wins.push_back(BinWindow{blo, bhi - blo + 1});
+                }
             }
             vbase += nd.npts;
             cbase += L.ni * L.nj;
@@ -988,7 +1023,10 @@ void upload_plan(Plan &P)
         } else {
             upload_vec(P.device_bytes, &D.leafpts, lpts);
             upload_vec(P.device_bytes, &D.leaf_blocks, blocks);
+            upload_vec(P.device_bytes, &D.leaf_wins, wins);
             P.n_blocks_leaf = (int64_t)blocks.size();
+            P.leaf_win_max = 0;
+            for (const BinWindow &wv : wins) P.leaf_win_max = std::max(P.leaf_win_max, wv.n);
             // adjoint work items: each leaf's positions in groups of 16
             std::vector<BlockItem> ab;
             for (size_t li = 0; li < nodes.size(); ++li)
@@ -1014,6 +1052,7 @@ void release_plan(Plan &P)
     fr(D.pos64);
     fr(D.leafpts);
     fr(D.leaf_blocks);
+    fr(D.leaf_wins);
     fr(D.adj_blocks);
     fr(D.Bd);
     fr(D.Badj);
