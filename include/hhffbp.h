@@ -193,6 +193,9 @@ typedef struct {
     int64_t device_bytes;           /* device memory the plan holds (its tables) */
     double model_ms;                /* Sec. IV-B cost model: level-1 BP + interpolation,
                                        with the per-pair costs of hhffbp_config.stages */
+    int64_t final_bricks;           /* final stage: voxel bricks of 4 x 4 x 16 */
+    int64_t final_boxed;            /* (brick, depth-1 node) pairs whose stencils fit one
+                                       staged box (the rest read the pencils directly) */
 } hhffbp_plan_info;
 
 hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info);

@@ -51,6 +51,7 @@ class PlanInfo(ctypes.Structure):
         ("final_pairs", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
         ("storage", ctypes.c_int32), ("ws_scales_offset", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64), ("model_ms", ctypes.c_double),
+        ("final_bricks", ctypes.c_int64), ("final_boxed", ctypes.c_int64),
     ]
 
 

@@ -181,6 +181,8 @@ hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info)
     info->storage = P.cfg.storage;
     info->device_bytes = (int64_t)P.device_bytes;
     info->model_ms = 1e3 * P.model_s;
+    info->final_bricks = P.n_bricks;
+    info->final_boxed = P.n_tiled;
     info->ws_scales_offset = (int64_t)P.ws_scales;
     return HHFFBP_OK;
 }

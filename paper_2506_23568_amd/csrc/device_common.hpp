@@ -121,6 +121,8 @@ __device__ __forceinline__ int floor_int(float x)
 // Positions per staged chunk of the level-1 BP for a bin window of nrb bins:
 // as many as kLdsBudget holds (a float4 and nrb float2 each), at most 32.
 constexpr int kLeafChunkMax = 32;
+// thread-strided steps that stage a final-stage box of kTileCap values
+constexpr int kStageBox = (kTileCap + kBlock - 1) / kBlock;
 // thread-strided staging steps that cover a kLdsBudget tile of float2
 constexpr int kStageSteps = (int)((kLdsBudget / sizeof(float2) + kBlock - 1) / kBlock);
 __host__ __device__ inline int leaf_chunk(int nrb)
@@ -315,6 +317,36 @@ __device__ __forceinline__ float2 interp_child(const NodeDev &c, const ColEntry 
                         sim = fmaf(wn[k], v.y, sim);
                     }
                 }
+            }
+            const float wab = wu[a] * wv[b];
+            are = fmaf(wab, sre, are);
+            aim = fmaf(wab, sim, aim);
+        }
+    }
+    return make_float2(are, aim);
+}
+
+// The T^3 taps from a dense LDS box: p points at the stencil's first tap, the
+// box holds nl values per (i, j) column and nj columns per i.  Same summation
+// order as interp_child's pencil path.
+template <int T, int K>
+__device__ __forceinline__ float2 interp_box(const float2 *p, int nj, int nl, const ChildCoord &g,
+                                             const InterpPoly &ip)
+{
+    float wu[T], wv[T], wn[T];
+    interp_weights<T, K>(ip, g, wu, wv, wn);
+    float are = 0.0f, aim = 0.0f;
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            const float2 *q = p + (a * nj + b) * nl;
+            float sre = 0.0f, sim = 0.0f;
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                const float2 v = q[k];
+                sre = fmaf(wn[k], v.x, sre);
+                sim = fmaf(wn[k], v.y, sim);
             }
             const float wab = wu[a] * wv[b];
             are = fmaf(wab, sre, are);

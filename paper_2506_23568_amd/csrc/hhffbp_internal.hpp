@@ -66,6 +66,18 @@ struct BlockItem {
     int32_t node, start;
 };
 
+// Final stage: voxels are processed in bricks of kBrickX x kBrickY x kBrickZ
+// (z fastest in a brick, as in the image), and each (brick, depth-1 node) has
+// the box of that node's lattice indices [i0, i0 + ni) x [j0, j0 + nj) x
+// [l0, l0 + nl) its stencils use, with one index of margin on every side for
+// rounding.  In LDS a box column holds 2^lsh >= nl values; ni = 0 marks a box
+// of more than kTileCap such values (the kernel then gathers from the pencils).
+constexpr int kBrickX = 4, kBrickY = 4, kBrickZ = 16;
+constexpr int kTileCap = 2048;
+struct TileBox {
+    int32_t i0, j0, l0, ni, nj, nl, lsh, pad;
+};
+
 // Range bins [lo, lo + n) that a level-1 BP block can read: every tap of its
 // points for positions within the leaf's reach.
 struct BinWindow {
@@ -109,6 +121,7 @@ struct DeviceBuffers {
     void *leafpts = nullptr;        // LeafPoint[] of depth S
     void *leaf_blocks = nullptr;    // BlockItem[]
     void *leaf_wins = nullptr;      // BinWindow[], one per leaf block
+    void *final_tiles = nullptr;    // TileBox[n_bricks][n depth-1 nodes]
     void *adj_blocks = nullptr;     // BlockItem[]: (leaf, first sorted position of 16)
     void *Bd = nullptr;             // range-derivative matrix (rows x j 2 k_f), [2 Nf][2 Nr]
     void *Badj = nullptr;           // conj-transposed DFT matrix, [2 Nr][2 Nf]
@@ -143,6 +156,8 @@ struct Plan {
     std::vector<int64_t> n_blocks_merge_fwd; // per depth
     int64_t n_blocks_leaf = 0, n_blocks_adj = 0;
     int32_t leaf_win_max = 0;  // widest BinWindow of the level-1 BP blocks
+    std::vector<TileBox> final_tiles;  // host copy, brick-major
+    int64_t n_bricks = 0, n_tiled = 0;  // final-stage bricks; (brick, node) pairs with a box
     int64_t leaf_pairs = 0, merge_pairs = 0, final_pairs = 0;
     // workspace layout (bytes)
     size_t ws_prof = 0, ws_posoff = 0, ws_total = 0;

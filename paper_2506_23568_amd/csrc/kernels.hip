@@ -380,34 +380,84 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
     }
 }
 
-// Final stage: user voxels, children are the depth-1 nodes; one lane per voxel
-// (the voxel grid alone gives a launch enough waves).
+// Final stage: user voxels, children are the depth-1 nodes; one lane per voxel,
+// a block per brick of kBrickX x kBrickY x kBrickZ voxels (lane t: z = t mod 16
+// fastest, then y, then x).  Per child, the block first stages the child's
+// values over the brick's stencil box (TileBox, from the plan) into LDS, dense
+// and zero outside the pencils: a wave per column, its lanes along n, the
+// column entry a scalar load.  A lane whose stencil lies inside the box then
+// reads its T^3 taps from LDS in the same order as the pencil path below; one
+// outside it (or a child without a box) gathers from the pencils.
 template <int T, int ST, int K>
 __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ children,
                                                   int nchild, const ColEntry *__restrict__ ccols,
                                                   const typename Store<ST>::C *__restrict__ cvals,
+                                                  const TileBox *__restrict__ tiles,
                                                   GeoParams gp, const InterpPoly ip,
                                                   const float *__restrict__ scales,
                                                   double ox, double oy, double oz, double sx,
                                                   double sy, double sz, int nx, int ny, int nz,
                                                   float2 *__restrict__ image)
 {
-    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t nv = (int64_t)nx * ny * nz;
-    if (v >= nv) return;
-    const int iz = (int)(v % nz);
-    const int iy = (int)((v / nz) % ny);
-    const int ix = (int)(v / ((int64_t)nz * ny));
+    __shared__ float2 s_tile[kTileCap];
+    const int bz = (nz + kBrickZ - 1) / kBrickZ, by = (ny + kBrickY - 1) / kBrickY;
+    const int brick = (int)blockIdx.x;
+    const int kx = brick / (by * bz), ky = (brick / bz) % by, kz = brick % bz;
+    const int t = (int)threadIdx.x;
+    const int ix = kx * kBrickX + t / (kBrickY * kBrickZ), iy = ky * kBrickY + (t / kBrickZ) % kBrickY,
+              iz = kz * kBrickZ + t % kBrickZ;
+    const bool inside = ix < nx && iy < ny && iz < nz;
     const double x = ox + ix * sx, y = oy + iy * sy, z = oz + iz * sz;
+    const int wave = __builtin_amdgcn_readfirstlane(t / 64), lane = t % 64;
     float are = 0.0f, aim = 0.0f;
     for (int c = 0; c < nchild; ++c) {
         const NodeDev ch = children[c];
-        const ChildCoord g = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
-        const float2 val = interp_child<T, ST, K>(ch, ccols, cvals, g, ip);
-        phase_mac(val, g.phi, are, aim);
+        const TileBox tb = tiles[(size_t)brick * nchild + c];
+        __syncthreads();  // the previous child's box is consumed
+        if (tb.ni > 0) {
+            // item e = (column << lsh) + l over the padded box, thread-strided;
+            // all entry loads, then all value loads, then the stores
+            const int items = (tb.ni * tb.nj) << tb.lsh;
+            const float inv_nj = 1.0f / (float)tb.nj;
+            int roff[kStageBox];
+            bool take[kStageBox];
+#pragma unroll
+            for (int k = 0; k < kStageBox; ++k) {
+                const int e = k * kBlock + t;
+                const int col = min(e >> tb.lsh, tb.ni * tb.nj - 1);
+                const int ci = (int)(((float)col + 0.5f) * inv_nj);  // exact: col, nj < 2^11
+                const int cj = col - ci * tb.nj;
+                const ColEntry en = ccols[ch.col_base + (tb.i0 + ci - ch.i0) * ch.nj + (tb.j0 + cj - ch.j0)];
+                const int l = e & ((1 << tb.lsh) - 1);
+                const int r = tb.l0 + l - en.lo;  // position in the pencil
+                take[k] = e < items && l < tb.nl && r >= 0 && r <= en.hi - en.lo;
+                roff[k] = take[k] ? ch.val_base + en.off + r : 0;
+            }
+            float2 v[kStageBox];
+#pragma unroll
+            for (int k = 0; k < kStageBox; ++k) v[k] = Store<ST>::ld(cvals[roff[k]]);
+#pragma unroll
+            for (int k = 0; k < kStageBox; ++k)
+                if (k * kBlock + t < items) s_tile[k * kBlock + t] = take[k] ? v[k] : make_float2(0.0f, 0.0f);
+        }
+        __syncthreads();
+        if (inside) {
+            const ChildCoord g = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
+            const int ti = g.bi - T / 2 + 1 - tb.i0, tj = g.bj - T / 2 + 1 - tb.j0,
+                      tl = g.bl - T / 2 + 1 - tb.l0;
+            float2 val;
+            if (tb.ni > 0 && (unsigned)ti <= (unsigned)(tb.ni - T) &&
+                (unsigned)tj <= (unsigned)(tb.nj - T) && (unsigned)tl <= (unsigned)(tb.nl - T))
+                val = interp_box<T, K>(s_tile + ((ti * tb.nj + tj) << tb.lsh) + tl, tb.nj, 1 << tb.lsh, g, ip);
+            else
+                val = interp_child<T, ST, K>(ch, ccols, cvals, g, ip);
+            phase_mac(val, g.phi, are, aim);
+        }
     }
-    const float rs = 1.0f / scales[1];
-    image[v] = make_float2(rs * are, rs * aim);
+    if (inside) {
+        const float rs = 1.0f / scales[1];
+        image[((size_t)ix * ny + iy) * nz + iz] = make_float2(rs * are, rs * aim);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -580,11 +630,11 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
     const hhffbp_config &c = P.cfg;
     const int nx = (int)c.grid_dims[0], ny = (int)c.grid_dims[1], nz = (int)c.grid_dims[2];
     const int64_t nv = (int64_t)nx * ny * nz;
-    const int nblk = (int)((nv + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_final<T, ST, K>), dim3(nblk), dim3(kBlock), 0, st,
+    (void)nv;
+    hipLaunchKernelGGL((k_final<T, ST, K>), dim3(P.n_bricks), dim3(kBlock), 0, st,
                        (const NodeDev *)P.dev.nodes[1], (int)P.compact_to_tree[1].size(),
-                       (const ColEntry *)P.dev.cols[1], (const C *)(ws + P.ws_vals[1]), gp,
-                       P.ipoly, scales,
+                       (const ColEntry *)P.dev.cols[1], (const C *)(ws + P.ws_vals[1]),
+                       (const TileBox *)P.dev.final_tiles, gp, P.ipoly, scales,
                        c.grid_origin[0], c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0],
                        c.grid_pitch[1], c.grid_pitch[2], nx, ny, nz, (float2 *)image);
     hipError_t e = hipGetLastError();

@@ -337,6 +337,61 @@ void build_lattice(Plan &P, HostNode &node, const std::vector<double> &parent_al
     L.n_absent = absent.load();
 }
 
+// Final-stage boxes: per voxel brick and depth-1 node, the bounding box of the
+// stencils (base floor(gamma w + eps) - T/2 + 1 .. + T/2) of the brick's voxels,
+// widened by one index for rounding (the kernel evaluates w in float64 with a
+// ~2e-14 relative square root) and clipped to the node's columns.
+void build_final_tiles(Plan &P)
+{
+    const hhffbp_config &c = P.cfg;
+    const int64_t nx = c.grid_dims[0], ny = c.grid_dims[1], nz = c.grid_dims[2];
+    const int64_t bx = (nx + kBrickX - 1) / kBrickX, by = (ny + kBrickY - 1) / kBrickY,
+                  bz = (nz + kBrickZ - 1) / kBrickZ;
+    const std::vector<int32_t> &d1 = P.compact_to_tree[1];
+    const int64_t nc = (int64_t)d1.size();
+    P.n_bricks = bx * by * bz;
+    P.final_tiles.assign(P.n_bricks * nc, TileBox{0, 0, 0, 0, 0, 0, 0, 0});
+    std::vector<SubarrayMap> maps;
+    for (int32_t ti : d1) maps.emplace_back(P.levels[1][ti].rect, P.kmin, P.kmax);
+    const int T = P.T, slo = -(T / 2) + 1 - 1, shi = T / 2 + 1;
+    std::atomic<int64_t> tiled{0};
+    parallel_for(P.n_bricks, 16, [&](int64_t b0, int64_t b1) {
+        for (int64_t b = b0; b < b1; ++b) {
+            const int64_t kx = b / (by * bz), ky = (b / bz) % by, kz = b % bz;
+            for (int64_t ch = 0; ch < nc; ++ch) {
+                const HostLattice &L = P.levels[1][d1[ch]].lat;
+                int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+                for (int64_t ix = kx * kBrickX; ix < std::min(nx, (kx + 1) * kBrickX); ++ix)
+                    for (int64_t iy = ky * kBrickY; iy < std::min(ny, (ky + 1) * kBrickY); ++iy)
+                        for (int64_t iz = kz * kBrickZ; iz < std::min(nz, (kz + 1) * kBrickZ); ++iz) {
+                            const double p[3] = {c.grid_origin[0] + ix * c.grid_pitch[0],
+                                                 c.grid_origin[1] + iy * c.grid_pitch[1],
+                                                 c.grid_origin[2] + iz * c.grid_pitch[2]};
+                            double w[3];
+                            maps[ch].eval(p, w, nullptr, nullptr);
+                            for (int a = 0; a < 3; ++a) {
+                                const int32_t t = (int32_t)std::floor(P.gamma[a] * w[a] + kStencilEps);
+                                lo[a] = std::min(lo[a], t + slo);
+                                hi[a] = std::max(hi[a], t + shi);
+                            }
+                        }
+                lo[0] = std::max(lo[0], L.i0);
+                hi[0] = std::min(hi[0], L.i0 + L.ni - 1);
+                lo[1] = std::max(lo[1], L.j0);
+                hi[1] = std::min(hi[1], L.j0 + L.nj - 1);
+                const int64_t ni = hi[0] - lo[0] + 1, nj = hi[1] - lo[1] + 1, nl = hi[2] - lo[2] + 1;
+                int32_t lsh = 0;
+                while ((1 << lsh) < nl) ++lsh;
+                if (ni < T || nj < T || nl < T || (ni * nj << lsh) > kTileCap) continue;
+                P.final_tiles[b * nc + ch] =
+                    TileBox{lo[0], lo[1], lo[2], (int32_t)ni, (int32_t)nj, (int32_t)nl, lsh, 0};
+                tiled.fetch_add(1);
+            }
+        }
+    });
+    P.n_tiled = tiled.load();
+}
+
 // Fourier transform of the truncated ES kernel phi(t) = exp(beta (sqrt(1 - (2t/W)^2) - 1))
 // on |t| <= W/2, at angular frequency theta (rad per bin); composite Simpson.
 double es_hat(double theta, int W, double beta)
@@ -767,6 +822,7 @@ void build_plan_host(Plan &P)
         P.final_pairs = P.n_vox() * (int64_t)P.compact_to_tree[1].size();
     }
     P.model_s = model_seconds(P);
+    if (S > 0) build_final_tiles(P);
 
     // workspace layout; profiles and subimages in the storage type
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -1024,6 +1080,7 @@ void upload_plan(Plan &P)
             upload_vec(P.device_bytes, &D.leafpts, lpts);
             upload_vec(P.device_bytes, &D.leaf_blocks, blocks);
             upload_vec(P.device_bytes, &D.leaf_wins, wins);
+            upload_vec(P.device_bytes, &D.final_tiles, P.final_tiles);
             P.n_blocks_leaf = (int64_t)blocks.size();
             P.leaf_win_max = 0;
             for (const BinWindow &wv : wins) P.leaf_win_max = std::max(P.leaf_win_max, wv.n);
@@ -1053,6 +1110,7 @@ void release_plan(Plan &P)
     fr(D.leafpts);
     fr(D.leaf_blocks);
     fr(D.leaf_wins);
+    fr(D.final_tiles);
     fr(D.adj_blocks);
     fr(D.Bd);
     fr(D.Badj);
