@@ -104,10 +104,15 @@ typedef struct {
     double position_slack;      /* metres the positions may move after planning  */
     int32_t device;             /* HIP device ordinal; -1 plans on the host only  */
     int32_t interp_kernel;      /* HHFFBP_INTERP_LAGRANGE or HHFFBP_INTERP_BANDLIMITED */
+    int32_t final_staging;      /* 1: the final stage stages each voxel brick's child
+                                   values through LDS (the default); 0: it gathers
+                                   every stencil from the pencils.  Same result bit
+                                   for bit (same summation order); 0 is for tests. */
 } hhffbp_config;
 
 /* Fill `cfg` with defaults: FACTORIZED, S = 3, Q = 4, gamma = (3, 3, 3.5), T = 4, ES with
- * U = 2 and W = 7, C64 storage, 5 mm slack, device 0, Lagrange interpolation.  Pointers and sizes are
+ * U = 2 and W = 7, C64 storage, 5 mm slack, device 0, Lagrange interpolation, final-stage
+ * staging on.  Pointers and sizes are
  * zeroed and must be set by the caller. */
 void hhffbp_config_default(hhffbp_config *cfg);
 

@@ -36,7 +36,7 @@ class Config(ctypes.Structure):
         ("range_kernel", ctypes.c_int32), ("range_oversample", ctypes.c_double),
         ("range_taps", ctypes.c_int32), ("storage", ctypes.c_int32),
         ("position_slack", ctypes.c_double), ("device", ctypes.c_int32),
-        ("interp_kernel", ctypes.c_int32),
+        ("interp_kernel", ctypes.c_int32), ("final_staging", ctypes.c_int32),
     ]
 
 
@@ -131,7 +131,7 @@ class Plan:
                  mode="factorized", stages=3, merge_factor=4, oversample=(3.0, 3.0, 3.5),
                  interp_taps=4,
                  range_kernel="es", range_oversample=2.0, range_taps=7, storage="c64",
-                 position_slack=5e-3, device=0, interp_kernel="lagrange"):
+                 position_slack=5e-3, device=0, interp_kernel="lagrange", final_staging=True):
         L = lib()
         self._pos = np.ascontiguousarray(positions, np.float64)
         self._freqs = np.ascontiguousarray(freqs_hz, np.float64)
@@ -160,6 +160,7 @@ class Plan:
         c.position_slack = float(position_slack)
         c.device = int(device)
         c.interp_kernel = INTERP_KERNELS[interp_kernel]
+        c.final_staging = 1 if final_staging else 0
         self.config = c
         self.dims = tuple(int(d) for d in grid_dims)
         self.device = int(device)

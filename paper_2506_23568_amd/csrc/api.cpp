@@ -46,6 +46,7 @@ void hhffbp_config_default(hhffbp_config *cfg)
     cfg->position_slack = 5e-3;
     cfg->device = 0;
     cfg->interp_kernel = HHFFBP_INTERP_LAGRANGE;
+    cfg->final_staging = 1;
 }
 
 hhffbp_status hhffbp_plan(const hhffbp_config *cfg, hhffbp_plan_t *out)

@@ -351,6 +351,8 @@ void build_final_tiles(Plan &P)
     const int64_t nc = (int64_t)d1.size();
     P.n_bricks = bx * by * bz;
     P.final_tiles.assign(P.n_bricks * nc, TileBox{0, 0, 0, 0, 0, 0, 0, 0});
+    P.n_tiled = 0;
+    if (!c.final_staging) return;
     std::vector<SubarrayMap> maps;
     for (int32_t ti : d1) maps.emplace_back(P.levels[1][ti].rect, P.kmin, P.kmax);
     const int T = P.T, slo = -(T / 2) + 1 - 1, shi = T / 2 + 1;
@@ -603,6 +605,7 @@ void validate(const hhffbp_config &c)
     if (c.stages < 0 && c.mode != HHFFBP_FACTORIZED) bad("automatic stages need the factorised mode");
     if (c.merge_factor != 2 && c.merge_factor != 4) bad("merge_factor must be 2 or 4");
     if (c.interp_taps != 4 && c.interp_taps != 6) bad("interp_taps must be 4 or 6");
+    if (c.final_staging != 0 && c.final_staging != 1) bad("final_staging must be 0 or 1");
     if (c.interp_kernel != HHFFBP_INTERP_LAGRANGE && c.interp_kernel != HHFFBP_INTERP_BANDLIMITED)
         bad("unknown interpolation kernel");
     if (c.range_kernel == HHFFBP_RANGE_ES) {
@@ -822,7 +825,7 @@ void build_plan_host(Plan &P)
         P.final_pairs = P.n_vox() * (int64_t)P.compact_to_tree[1].size();
     }
     P.model_s = model_seconds(P);
-    if (S > 0) build_final_tiles(P);
+    if (S > 0) build_final_tiles(P);  // with final_staging = 0 every box is left empty
 
     // workspace layout; profiles and subimages in the storage type
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };

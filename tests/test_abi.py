@@ -39,6 +39,19 @@ def test_config_default_layout():
     assert list(c.oversample) == [3.0, 3.0, 3.5]
     assert (c.range_kernel, c.range_taps, c.storage, c.device) == (0, 7, 0, 0)
     assert c.range_oversample == 2.0 and abs(c.position_slack - 5e-3) < 1e-15
+    assert (c.interp_kernel, c.final_staging) == (0, 1)
+
+
+def test_final_stage_bricks(small):
+    """Voxel bricks of 4 x 4 x 16 for the final stage; with staging off no
+    (brick, depth-1 node) pair has a box, with it on at most all of them."""
+    import math
+    on = H.Plan(*_args(small), stages=2, device=-1).info()
+    off = H.Plan(*_args(small), stages=2, device=-1, final_staging=False).info()
+    d = small.grid_dims
+    assert on["final_bricks"] == math.ceil(d[0] / 4) * math.ceil(d[1] / 4) * math.ceil(d[2] / 16)
+    assert off["final_bricks"] == on["final_bricks"] and off["final_boxed"] == 0
+    assert 0 < on["final_boxed"] <= on["final_bricks"] * 4
 
 
 def _args(w):

@@ -338,3 +338,38 @@ def test_hhffbp_bandlimited_small(torch, small, oracle_small, S, Q, T):
          f"vs eq.4 {20 * np.log10(e_bp):.1f} dB")
     assert e <= 1e-5 and worst <= 1e-5
     assert 20 * np.log10(e_bp) <= -35.0
+
+
+@pytest.mark.parametrize("storage", ["c64", "f16"])
+def test_final_staging_is_bit_exact(torch, small, storage):
+    """The final stage's LDS boxes read the same taps in the same order as the
+    pencil gathers: images with staging on and off are identical."""
+    args = (small.positions, small.freqs_hz, small.grid_origin, small.grid_pitch, small.grid_dims)
+    ech = torch.from_numpy(small.echoes.astype(np.complex64)).cuda()
+    if storage == "f16":  # half storage takes (re, im) pairs
+        ech = torch.view_as_real(ech).half().contiguous()
+    imgs = []
+    for staging in (True, False):
+        pl = H.Plan(*args, stages=2, oversample=GAMMA, interp_taps=TAPS, storage=storage,
+                    final_staging=staging)
+        imgs.append(pl.image(ech).cpu().numpy())
+    _say(f"  {storage}: boxed {H.Plan(*args, stages=2, device=-1).info()['final_boxed']} pairs")
+    assert np.array_equal(imgs[0], imgs[1])
+
+
+
+def test_final_staging_is_bit_exact_mid(torch, mid):
+    """As above on the mid workload, Lagrange weights on (3, 3, 3.5): a few
+    (brick, node) boxes exceed the cap there, so both paths meet in one image."""
+    w = mid
+    args = (w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims)
+    ech = torch.from_numpy(w.echoes.astype(np.complex64)).cuda()
+    imgs = []
+    for staging in (True, False):
+        pl = H.Plan(*args, stages=3, oversample=GAMMA, interp_taps=TAPS, range_kernel="linear",
+                    range_oversample=8.0, final_staging=staging)
+        if staging:
+            inf = pl.info()
+            _say(f"  boxed {inf['final_boxed']} of {inf['final_bricks'] * 4} (brick, node) pairs")
+        imgs.append(pl.image(ech).cpu().numpy())
+    assert np.array_equal(imgs[0], imgs[1])
