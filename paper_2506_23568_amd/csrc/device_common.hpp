@@ -238,23 +238,24 @@ __device__ __forceinline__ void lagrange(float x, float *w)
 }
 
 // Weights of the three axes at a child coordinate: Lagrange (K = LAGRANGE),
-// or the plan's band-limited polynomials (Horner in the fractional offset).
-// The stencil is symmetric (tap t at offset x is tap T-1-t at 1 - x), so the
-// plan keeps the polynomials of the first T/2 taps only.
+// or the plan's band-limited polynomials in y = x - 1/2.  The stencil is
+// symmetric (tap t at offset x is tap T-1-t at 1 - x, i.e. at -y), so with
+// w_t = E_t(y^2) + y O_t(y^2), split into even and odd parts, the mirror tap
+// is E_t - y O_t: one pair of short Horner chains for two taps.
 template <int T, int A>
 __device__ __forceinline__ void poly_weights(const InterpPoly &ip, float x, float *w)
 {
-    const float y = 1.0f - x;
+    const float y = x - 0.5f, y2 = y * y;
 #pragma unroll
     for (int t = 0; t < T / 2; ++t) {
-        float v = ip.c[A][t][kPolyDeg], u = ip.c[A][t][kPolyDeg];
+        float e = ip.c[A][t][kPolyDeg - 1], o = ip.c[A][t][kPolyDeg];
 #pragma unroll
-        for (int d = kPolyDeg - 1; d >= 0; --d) {
-            v = fmaf(v, x, ip.c[A][t][d]);
-            u = fmaf(u, y, ip.c[A][t][d]);
+        for (int d = kPolyDeg - 3; d >= 0; d -= 2) {
+            e = fmaf(e, y2, ip.c[A][t][d]);
+            o = fmaf(o, y2, ip.c[A][t][d + 1]);
         }
-        w[t] = v;
-        w[T - 1 - t] = u;
+        w[t] = fmaf(y, o, e);
+        w[T - 1 - t] = fmaf(-y, o, e);
     }
 }
 

@@ -505,16 +505,17 @@ void bandlimited_weights(int T, double W, double x, double *w)
 double interp_poly_weight(const InterpPoly &ip, int a, int T, int t, double x)
 {
     const int s = (t < T / 2) ? t : T - 1 - t;
-    const double y = (t < T / 2) ? x : 1.0 - x;
+    const double y = (t < T / 2) ? x - 0.5 : 0.5 - x;
     double v = 0.0;
     for (int d = kPolyDeg; d >= 0; --d) v = v * y + (double)ip.c[a][s][d];
     return v;
 }
 
-// Degree-kPolyDeg least-squares polynomials (modified Gram-Schmidt QR at 40
-// Chebyshev nodes of [0, 1]) for every weight of every axis; each fit, with
-// its coefficients rounded to float, is checked against the exact weights at
-// 257 offsets.
+// Degree-kPolyDeg least-squares polynomials in y = x - 1/2 (modified
+// Gram-Schmidt QR at 40 Chebyshev nodes of [0, 1]) for the weights of the
+// first T/2 taps of every axis; the mirror tap is the same polynomial at -y.
+// Each fit, with its coefficients rounded to float, is checked against the
+// exact weights at 257 offsets.
 void fit_interp_poly(Plan &P)
 {
     InterpPoly &ip = P.ipoly;
@@ -527,7 +528,7 @@ void fit_interp_poly(Plan &P)
     for (int k = 0; k < K; ++k) {
         xk[k] = 0.5 - 0.5 * std::cos(kPi * (k + 0.5) / K);
         double p = 1.0;
-        for (int d = 0; d < D; ++d, p *= xk[k]) V[k][d] = p;
+        for (int d = 0; d < D; ++d, p *= xk[k] - 0.5) V[k][d] = p;
     }
     for (int d = 0; d < D; ++d) {  // V = Q R, Q stored in V
         for (int e = 0; e < d; ++e) {
