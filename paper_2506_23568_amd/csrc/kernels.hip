@@ -31,12 +31,16 @@ namespace {
 using namespace dev;
 
 // ---------------------------------------------------------------------------
+// With `ones` set, block 0 also writes the ns storage scales, all 1 (storage
+// types without scaling), saving their own launch.
 __global__ __launch_bounds__(kBlock) void k_prep_positions(const double *__restrict__ pos64,
                                                            const int32_t *__restrict__ perm,
                                                            const int32_t *__restrict__ leaf_of,
                                                            const double *__restrict__ centre,
-                                                           int n, float4 *__restrict__ out)
+                                                           int n, float4 *__restrict__ out,
+                                                           float *__restrict__ ones, int ns)
 {
+    if (ones && blockIdx.x == 0 && (int)threadIdx.x < ns) ones[threadIdx.x] = 1.0f;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int m = perm[i], lf = leaf_of[i];
@@ -683,12 +687,15 @@ hhffbp_status image_for_storage(const Plan &P, const void *echoes, const double 
     void *prof = ws + P.ws_prof;
     float4 *posoff = (float4 *)(ws + P.ws_posoff);
     const float *scales = (const float *)(ws + P.ws_scales);
-    hipError_t e = launch_scales<ST>(P, echoes, ws, st);
-    if (e != hipSuccess) return HHFFBP_E_DEVICE;
+    // without scaling (c64, bf16) the position pass writes the unit scales itself
+    const bool fused_ones = ST != HHFFBP_F16 && P.S > 0;
+    hipError_t e = hipSuccess;
+    if (!fused_ones && (e = launch_scales<ST>(P, echoes, ws, st)) != hipSuccess) return HHFFBP_E_DEVICE;
     if (P.S > 0) {
         hipLaunchKernelGGL(k_prep_positions, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
                            pos64, (const int32_t *)P.dev.perm, (const int32_t *)P.dev.leaf_of_sorted,
-                           (const double *)P.dev.leaf_centre, n, posoff);
+                           (const double *)P.dev.leaf_centre, n, posoff,
+                           fused_ones ? (float *)(ws + P.ws_scales) : nullptr, P.S + 1);
         if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
         if (ev) (void)hipEventRecord(*ev++, st);
     }
@@ -731,7 +738,7 @@ hipError_t launch_prep(const Plan &P, const double *pos64, float4 *posoff, hipSt
     const int n = (int)P.cfg.n_pos;
     hipLaunchKernelGGL(k_prep_positions, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
                        pos64, (const int32_t *)P.dev.perm, (const int32_t *)P.dev.leaf_of_sorted,
-                       (const double *)P.dev.leaf_centre, n, posoff);
+                       (const double *)P.dev.leaf_centre, n, posoff, (float *)nullptr, 0);
     return hipGetLastError();
 }
 
