@@ -213,6 +213,26 @@ def test_positions_override(torch, small):
     assert e <= 1e-5
 
 
+@pytest.mark.parametrize("range_kernel", ["es", "linear"])
+def test_positions_moved_to_the_slack(torch, small, range_kernel):
+    """Positions moved by up to 4.9 mm per axis (the plan's slack is 5 mm): the
+    level-1 BP's range-bin windows, sized from each leaf's reach plus the slack,
+    still hold every tap; the image matches the oracle with the moved positions."""
+    from oracle import hhffbp as OH
+    from oracle import plan as OP
+    kw = dict(range_kernel="linear", range_oversample=8.0) if range_kernel == "linear" else {}
+    pl = H.Plan(*_args(small), stages=2, oversample=GAMMA, interp_taps=TAPS, **kw)
+    t = np.arange(small.n_pos)
+    moved = small.positions + 4.9e-3 * np.column_stack(
+        [np.sign(np.sin(t / 37.0)), np.sign(np.cos(t / 23.0)), np.sign(np.sin(t / 11.0))])
+    got = _run(torch, pl, small, positions=moved)
+    op = OP.build_plan(*_args(small), 2, 4, GAMMA, TAPS)
+    ref = OH.image(op, small.echoes, moved, range_u=8 if range_kernel == "linear" else None)
+    e = _nrmse(got, ref)
+    _say(f"  {range_kernel}: moved 4.9 mm per axis vs oracle {e:.3e}")
+    assert e <= 1e-5
+
+
 @pytest.fixture(scope="module")
 def mid():
     from workloads import make_config
