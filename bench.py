@@ -270,8 +270,8 @@ def main():
                          "simulation geometry with point-response metrics")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the work would shard)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the voxel "
+              "grid would be split into slabs, one per GPU)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "autofocus":
