@@ -56,7 +56,11 @@ typedef enum {
 /* Imaging mode. */
 enum {
     HHFFBP_FACTORIZED = 0,   /* HHFFBPA (Sec. IV-A); stages = 0 is one subarray */
-    HHFFBP_DIRECT_RC = 1     /* direct BPA of eq. (3) on range-compressed data   */
+    HHFFBP_DIRECT_RC = 1,    /* direct BPA of eq. (3) on range-compressed data   */
+    HHFFBP_DIRECT_EXACT = 2  /* direct BPA of eq. (4): the frequency sum per
+                                (voxel, position), no range compression; with
+                                equispaced frequencies a Horner sum in
+                                exp(j 2 dk Delta R).  Forward only.          */
 };
 
 /* Storage type of the echoes, range profiles and subimages.  Sums, phases and
@@ -89,7 +93,7 @@ typedef struct {
     double grid_origin[3];      /* centre of voxel (0,0,0), metres                */
     double grid_pitch[3];       /* voxel pitch per axis, > 0                      */
     int64_t grid_dims[3];       /* (nx, ny, nz); image index (ix*ny + iy)*nz + iz */
-    int32_t mode;               /* HHFFBP_FACTORIZED or HHFFBP_DIRECT_RC          */
+    int32_t mode;               /* HHFFBP_FACTORIZED, HHFFBP_DIRECT_RC or _EXACT  */
     int32_t stages;             /* S >= 0: number of merge stages; S = -K (factorised
                                    mode): the S in 1..K that minimises the operation
                                    count of Sec. IV-B on the candidates' exact pair

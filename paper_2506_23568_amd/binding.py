@@ -12,7 +12,7 @@ _lib = None
 
 STATUS = {0: "ok", -1: "invalid", -2: "unsupported", -3: "nomem", -4: "device",
           -5: "workspace", -6: "numeric"}
-MODES = {"factorized": 0, "direct_rc": 1}
+MODES = {"factorized": 0, "direct_rc": 1, "direct_exact": 2}
 RANGE_KERNELS = {"es": 0, "linear": 1}
 STORAGE = {"c64": 0, "f16": 1, "bf16": 2}
 INTERP_KERNELS = {"lagrange": 0, "bandlimited": 1}

@@ -115,6 +115,8 @@ struct DeviceBuffers {
     void *leaf_of_sorted = nullptr; // int32 [n_pos]
     void *leaf_centre = nullptr;    // double2 [n_leaves]
     void *pos64 = nullptr;          // double [n_pos][3], caller order
+    void *kf = nullptr;             // double [n_freq]: k_f (exact direct mode)
+    void *kf_turns = nullptr;       // float [n_freq]: k_f / pi (exact mode, general spacing)
     std::vector<void *> nodes;      // per depth: NodeDev[]
     std::vector<void *> cols;       // per depth: ColEntry[]
     std::vector<void *> px, py, pz; // per depth < S: float64 SoA grid points
@@ -137,6 +139,8 @@ struct Plan {
     // band
     std::vector<double> k;
     double kmin = 0, kmax = 0, kc = 0;
+    bool k_equispaced = false;  // k_f = k_0 + f dk to 1e-9 dk (exact direct mode's Horner sum)
+    double k0 = 0, dk = 0;
     // range profiles
     int W = 7, kernel = HHFFBP_RANGE_ES;
     double U = 2, dR = 0, R0 = 0, beta = 0;

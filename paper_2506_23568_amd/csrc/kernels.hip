@@ -566,6 +566,148 @@ __global__ __launch_bounds__(kBlock) void k_direct_bp(
     }
 }
 
+// Direct BP of eq. (4), f(p) = sum_i sum_f s_if exp(j 2 k_f |p - p'_i|), no range
+// compression.  A block is a 4 x 8 x 8 voxel tile with a float64 reference point
+// at its centre.  Per staged position the block forms c_if = s_if exp(j 2 k_f
+// R_ref) from the float64 reference distance (the phase reduced to turns in
+// float64); per voxel only Delta R = |p - p'| - R_ref enters float32, in the
+// cancellation-free form of the range-profile kernel, and
+//   f(p) += sum_f c_if exp(j 2 k_f Delta R).
+// With equispaced frequencies (EQ), k_f = k_0 + f dk, that sum is
+// exp(j 2 k_0 Delta R) sum_f c_if z^f with z = exp(j 2 dk Delta R), evaluated by
+// Horner's rule: four FMA per frequency and no trigonometry per frequency.
+struct ExactPos {
+    float dx, dy, dz;  // p' - ref
+    float rref;        // |p' - ref| (float32, as a denominator only)
+};
+
+inline int exact_chunk(int n_f)
+{
+    const size_t per = sizeof(ExactPos) + sizeof(double) + (size_t)n_f * sizeof(float2);
+    const int c = (int)(kLdsBudget / per);
+    return c > 32 ? 32 : (c < 1 ? 1 : c);
+}
+
+template <int ST, bool EQ>
+__global__ __launch_bounds__(kBlock) void k_direct_exact(
+    const double *__restrict__ pos64, int n_pos, const typename Store<ST>::C *__restrict__ echoes,
+    int n_f, const double *__restrict__ kf, const float *__restrict__ kf_turns, float k0_turns,
+    float dk_turns, int chunk, double ox, double oy, double oz, double sx, double sy, double sz,
+    int nx, int ny, int nz, float2 *__restrict__ image)
+{
+    extern __shared__ unsigned char smem[];
+    double *s_rref = reinterpret_cast<double *>(smem);
+    ExactPos *s_pos = reinterpret_cast<ExactPos *>(smem + chunk * sizeof(double));
+    float2 *s_c = reinterpret_cast<float2 *>(smem + chunk * (sizeof(double) + sizeof(ExactPos)));
+    const int tnx = (nx + 3) / 4, tny = (ny + 7) / 8;
+    const int b = blockIdx.x;
+    const int tx = b % tnx, ty = (b / tnx) % tny, tz = b / (tnx * tny);
+    const int lx = threadIdx.x >> 6, ly = (threadIdx.x >> 3) & 7, lz = threadIdx.x & 7;
+    const int ix = tx * 4 + lx, iy = ty * 8 + ly, iz = tz * 8 + lz;
+    const bool active = ix < nx && iy < ny && iz < nz;
+    const double rx = ox + (tx * 4 + 1.5) * sx, ry = oy + (ty * 8 + 3.5) * sy,
+                 rz = oz + (tz * 8 + 3.5) * sz;
+    const float ex = (float)((lx - 1.5) * sx), ey = (float)((ly - 3.5) * sy),
+                ez = (float)((lz - 3.5) * sz);
+    const float e2 = ex * ex + ey * ey + ez * ez;
+    float acc_re = 0.0f, acc_im = 0.0f;
+    for (int c0 = 0; c0 < n_pos; c0 += chunk) {
+        const int n = min(chunk, n_pos - c0);
+        __syncthreads();
+        if ((int)threadIdx.x < n) {
+            const int i = c0 + threadIdx.x;
+            const double dx = pos64[3 * i] - rx, dy = pos64[3 * i + 1] - ry,
+                         dz = pos64[3 * i + 2] - rz;
+            const double rr = sqrt(dx * dx + dy * dy + dz * dz);
+            s_rref[threadIdx.x] = rr;
+            s_pos[threadIdx.x] = ExactPos{(float)dx, (float)dy, (float)dz, (float)rr};
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < n * n_f; t += kBlock) {
+            const int i = t / n_f, f = t - i * n_f;
+            double turns = kf[f] * s_rref[i] * (1.0 / kPi);  // 2 k_f R_ref / 2 pi
+            turns -= rint(turns);
+            const float tf = (float)turns;
+            const float sn = sin_turns(tf), cs = cos_turns(tf);
+            const float2 v = Store<ST>::ld(echoes[(size_t)(c0 + i) * n_f + f]);
+            s_c[t] = make_float2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
+        }
+        __syncthreads();
+        if (active) {
+            for (int i = 0; i < n; ++i) {
+                const ExactPos sp = s_pos[i];
+                const float qx = ex - sp.dx, qy = ey - sp.dy, qz = ez - sp.dz;
+                const float R = fast_sqrt(qx * qx + qy * qy + qz * qz);
+                const float num = e2 - 2.0f * (ex * sp.dx + ey * sp.dy + ez * sp.dz);
+                const float dr = num * fast_rcp(R + sp.rref);
+                const float2 *cf = s_c + i * n_f;
+                float hre, him;
+                if constexpr (EQ) {
+                    float zt = dr * dk_turns;
+                    zt -= rintf(zt);
+                    const float zr = cos_turns(zt), zi = sin_turns(zt);
+                    hre = cf[n_f - 1].x;
+                    him = cf[n_f - 1].y;
+#pragma unroll 4
+                    for (int f = n_f - 2; f >= 0; --f) {
+                        const float2 c = cf[f];
+                        const float r = fmaf(hre, zr, fmaf(-him, zi, c.x));
+                        him = fmaf(hre, zi, fmaf(him, zr, c.y));
+                        hre = r;
+                    }
+                    float t0 = dr * k0_turns;
+                    t0 -= rintf(t0);
+                    const float cr = cos_turns(t0), ci = sin_turns(t0);
+                    const float r = hre * cr - him * ci;
+                    him = hre * ci + him * cr;
+                    hre = r;
+                } else {
+                    hre = 0.0f;
+                    him = 0.0f;
+                    for (int f = 0; f < n_f; ++f) {
+                        float tt = dr * kf_turns[f];
+                        tt -= rintf(tt);
+                        const float cr = cos_turns(tt), ci = sin_turns(tt);
+                        const float2 c = cf[f];
+                        hre = fmaf(c.x, cr, fmaf(-c.y, ci, hre));
+                        him = fmaf(c.x, ci, fmaf(c.y, cr, him));
+                    }
+                }
+                acc_re += hre;
+                acc_im += him;
+            }
+        }
+    }
+    if (active) image[((int64_t)ix * ny + iy) * nz + iz] = make_float2(acc_re, acc_im);
+}
+
+template <int ST>
+hipError_t launch_direct_exact(const Plan &P, const void *echoes, const double *pos64, void *image,
+                               hipStream_t st)
+{
+    using C = typename Store<ST>::C;
+    const hhffbp_config &c = P.cfg;
+    const int nx = (int)c.grid_dims[0], ny = (int)c.grid_dims[1], nz = (int)c.grid_dims[2];
+    const int nblk = ((nx + 3) / 4) * ((ny + 7) / 8) * ((nz + 7) / 8);
+    const int nf = (int)c.n_freq;
+    const int chunk = exact_chunk(nf);
+    const size_t sh = (size_t)chunk * (sizeof(double) + sizeof(ExactPos) + (size_t)nf * sizeof(float2));
+    const float k0t = (float)(P.k0 / kPi), dkt = (float)(P.dk / kPi);
+    if (P.k_equispaced)
+        hipLaunchKernelGGL((k_direct_exact<ST, true>), dim3(nblk), dim3(kBlock), sh, st, pos64,
+                           (int)c.n_pos, (const C *)echoes, nf, (const double *)P.dev.kf,
+                           (const float *)P.dev.kf_turns, k0t, dkt, chunk, c.grid_origin[0],
+                           c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0], c.grid_pitch[1],
+                           c.grid_pitch[2], nx, ny, nz, (float2 *)image);
+    else
+        hipLaunchKernelGGL((k_direct_exact<ST, false>), dim3(nblk), dim3(kBlock), sh, st, pos64,
+                           (int)c.n_pos, (const C *)echoes, nf, (const double *)P.dev.kf,
+                           (const float *)P.dev.kf_turns, k0t, dkt, chunk, c.grid_origin[0],
+                           c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0], c.grid_pitch[1],
+                           c.grid_pitch[2], nx, ny, nz, (float2 *)image);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 template <int KERNEL, int W, int ST>
 hipError_t launch_bp_kernels(const Plan &P, const double *pos64, const void *prof,
@@ -687,6 +829,11 @@ hhffbp_status image_for_storage(const Plan &P, const void *echoes, const double 
     void *prof = ws + P.ws_prof;
     float4 *posoff = (float4 *)(ws + P.ws_posoff);
     const float *scales = (const float *)(ws + P.ws_scales);
+    if (c.mode == HHFFBP_DIRECT_EXACT) {
+        if (launch_direct_exact<ST>(P, echoes, pos64, image, st) != hipSuccess) return HHFFBP_E_DEVICE;
+        if (ev) (void)hipEventRecord(*ev, st);
+        return HHFFBP_OK;
+    }
     // without scaling (c64, bf16) the position pass writes the unit scales itself
     const bool fused_ones = ST != HHFFBP_F16 && P.S > 0;
     hipError_t e = hipSuccess;
@@ -768,7 +915,9 @@ hipError_t launch_rc_gemm(int storage_a, const void *A, const int32_t *a_perm, i
 std::vector<std::string> Plan::stage_names() const
 {
     std::vector<std::string> n;
-    if (S == 0) {
+    if (cfg.mode == HHFFBP_DIRECT_EXACT) {
+        n = {"direct_exact"};
+    } else if (S == 0) {
         n = {"rc_gemm", "direct_bp"};
     } else {
         n = {"prep_positions", "rc_gemm", "leaf_bp"};

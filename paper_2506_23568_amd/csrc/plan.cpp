@@ -601,7 +601,8 @@ void validate(const hhffbp_config &c)
     }
     if (c.grid_dims[0] * c.grid_dims[1] * c.grid_dims[2] > ((int64_t)1 << 31))
         bad("grid too large");
-    if (c.mode != HHFFBP_FACTORIZED && c.mode != HHFFBP_DIRECT_RC) bad("unknown mode");
+    if (c.mode != HHFFBP_FACTORIZED && c.mode != HHFFBP_DIRECT_RC && c.mode != HHFFBP_DIRECT_EXACT)
+        bad("unknown mode");
     if (c.stages < -8 || c.stages > 8) bad("stages must be in [-8, 8]");
     if (c.stages < 0 && c.mode != HHFFBP_FACTORIZED) bad("automatic stages need the factorised mode");
     if (c.merge_factor != 2 && c.merge_factor != 4) bad("merge_factor must be 2 or 4");
@@ -692,6 +693,14 @@ void build_plan_host(Plan &P)
     P.kmax = *std::max_element(P.k.begin(), P.k.end());
     if (!(P.kmax > P.kmin)) throw Error{HHFFBP_E_INVALID, "need at least two distinct frequencies"};
     P.kc = 0.5 * (P.kmin + P.kmax);
+    {
+        const int64_t nf = c.n_freq;
+        P.k0 = P.k[0];
+        P.dk = (P.k[nf - 1] - P.k[0]) / (double)(nf - 1);
+        P.k_equispaced = P.dk != 0.0;
+        for (int64_t f = 0; f < nf && P.k_equispaced; ++f)
+            P.k_equispaced = std::fabs(P.k[f] - (P.k0 + (double)f * P.dk)) <= 1e-9 * std::fabs(P.dk);
+    }
 
     partition(P);
     const int S = P.S;
@@ -951,6 +960,12 @@ void upload_plan(Plan &P)
     upload_vec(P.device_bytes, &D.leaf_of_sorted, P.leaf_of_sorted);
     upload_vec(P.device_bytes, &D.leaf_centre, P.leaf_centre);
     upload_vec(P.device_bytes, &D.pos64, P.positions);
+    if (P.cfg.mode == HHFFBP_DIRECT_EXACT) {
+        std::vector<float> kt(P.k.size());
+        for (size_t f = 0; f < P.k.size(); ++f) kt[f] = (float)(P.k[f] / kPi);
+        upload_vec(P.device_bytes, &D.kf, P.k);
+        upload_vec(P.device_bytes, &D.kf_turns, kt);
+    }
     if (S == 0) return;
     int32_t pos_cursor = 0;
     for (int d = 1; d <= S; ++d) {
@@ -1111,6 +1126,8 @@ void release_plan(Plan &P)
     fr(D.leaf_of_sorted);
     fr(D.leaf_centre);
     fr(D.pos64);
+    fr(D.kf);
+    fr(D.kf_turns);
     fr(D.leafpts);
     fr(D.leaf_blocks);
     fr(D.leaf_wins);

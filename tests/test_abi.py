@@ -70,6 +70,14 @@ def test_invalid_configurations_are_rejected(small, change, status):
     assert e.value.status == status
 
 
+def test_exact_direct_mode_plans_on_the_host(small):
+    """mode = direct_exact plans without stages; an unknown mode is rejected."""
+    info = H.Plan(*_args(small), mode="direct_exact", device=-1).info()
+    assert info["stages"] == 0 and info["leaf_pairs"] == small.n_pos * int(np.prod(small.grid_dims))
+    c = H.binding.default_config()
+    assert H.binding.MODES["direct_exact"] == 2
+
+
 def test_unknown_storage_is_rejected(small):
     c = H.binding.default_config()
     pos = np.ascontiguousarray(small.positions)

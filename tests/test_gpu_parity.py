@@ -110,6 +110,40 @@ def test_direct_rc_small_vs_eq4(torch, small, oracle_small):
     assert e <= 1e-5
 
 
+def test_direct_exact_small_vs_eq4(torch, small, oracle_small):
+    """Direct BP of eq. (4) without range compression (equispaced frequencies:
+    the Horner form) against the float64 oracle on the full grid: <= 1e-5."""
+    pl = H.Plan(*_args(small), mode="direct_exact")
+    img = _run(torch, pl, small)
+    e = _nrmse(img, oracle_small)
+    _say(f"  direct_exact NRMSE {e:.3e}")
+    assert e <= 1e-5
+
+
+def test_direct_exact_general_frequencies(torch, small):
+    """Frequencies that are not equispaced (the per-frequency carrier form):
+    eq. (4) on the same grid, <= 1e-5; with f16 echoes, against eq. (4) of the
+    same rounded values, <= 1e-5."""
+    from oracle import hhffbp as OH
+    from workloads import voxel_centres
+    rng = np.random.default_rng(5)
+    f = np.sort(small.freqs_hz + rng.uniform(-0.3, 0.3, small.freqs_hz.size) *
+                (small.freqs_hz[1] - small.freqs_hz[0]))
+    args = (small.positions, f, small.grid_origin, small.grid_pitch, small.grid_dims)
+    vox = voxel_centres(small.grid_origin, small.grid_pitch, small.grid_dims)
+    ref = OH.direct_bp(small.positions, f, small.echoes, vox).reshape(small.grid_dims)
+    ech = torch.from_numpy(small.echoes.astype(np.complex64)).cuda()
+    img = H.Plan(*args, mode="direct_exact").image(ech).cpu().numpy()
+    e = _nrmse(img, ref)
+    eh = torch.view_as_real(ech).half().contiguous()
+    img_h = H.Plan(*args, mode="direct_exact", storage="f16").image(eh).cpu().numpy()
+    ref_h = OH.direct_bp(small.positions, f, torch.view_as_complex(eh.float()).cpu().numpy(),
+                         vox).reshape(small.grid_dims)
+    e_h = _nrmse(img_h, ref_h)
+    _say(f"  general spacing NRMSE {e:.3e}; f16 echoes {e_h:.3e}")
+    assert e <= 1e-5 and e_h <= 1e-5
+
+
 def test_direct_linear_fast_mode_small(torch, small, oracle_small):
     """Fast range mode (linear kernel, U = 8) against the oracle's sum of the
     same form (<= 1e-5) and against eq. (4) (<= -60 dB)."""
@@ -393,3 +427,22 @@ def test_final_staging_is_bit_exact_mid(torch, mid):
             _say(f"  boxed {inf['final_boxed']} of {inf['final_bricks'] * 4} (brick, node) pairs")
         imgs.append(pl.image(ech).cpu().numpy())
     assert np.array_equal(imgs[0], imgs[1])
+
+
+def test_direct_exact_mid_sampled(torch, mid):
+    """Exact direct BP at the mid size (16384 positions, 64 f, 128 x 128 x 64
+    voxels) against float64 eq. (4) on 512 seeded voxels: <= 1e-5."""
+    from oracle import hhffbp as OH
+    from workloads import voxel_centres
+    w = mid
+    ech = torch.from_numpy(w.echoes.astype(np.complex64)).cuda()
+    pl = H.Plan(w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims,
+                mode="direct_exact")
+    img = pl.image(ech).cpu().numpy().ravel()
+    vox = voxel_centres(w.grid_origin, w.grid_pitch, w.grid_dims)
+    sel = np.random.default_rng(17).choice(vox.shape[0], 512, replace=False)
+    ref = OH.direct_bp(w.positions, w.freqs_hz, w.echoes, vox[sel])
+    e = _nrmse(img[sel], ref)
+    _say(f"  mid direct_exact (512 voxels) NRMSE {e:.3e}")
+    assert e <= 1e-5
+
