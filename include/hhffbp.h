@@ -112,6 +112,11 @@ typedef struct {
                                    values through LDS (the default); 0: it gathers
                                    every stencil from the pencils.  Same result bit
                                    for bit (same summation order); 0 is for tests. */
+    const double *weights;      /* host [n_pos] aperture weights w_i, the measure of
+                                   dp' in eq. (4): f = sum_i w_i sum_f s_if e^{...};
+                                   NULL: unit weights.  Must be finite; read only
+                                   during hhffbp_plan.  The gradients follow:
+                                   grad_s_i carries w_i, grad_p'_i the weighted sum. */
 } hhffbp_config;
 
 /* Fill `cfg` with defaults: FACTORIZED, S = 3, Q = 4, gamma = (3, 3, 3.5), T = 4, ES with

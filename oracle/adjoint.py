@@ -81,8 +81,14 @@ def leaf_cotangents(plan, grad_image):
     return cot
 
 
-def echo_gradient(plan, grad_image, positions):
-    """grad_s = A^H g, (n_pos, n_f) complex128."""
+def echo_gradient(plan, grad_image, positions, weights=None):
+    """grad_s = A^H g, (n_pos, n_f) complex128; with aperture weights w_i row i
+    of A carries w_i, so row i of the result does too."""
+    g = _echo_gradient(plan, grad_image, positions)
+    return g if weights is None else g * np.asarray(weights, float)[:, None]
+
+
+def _echo_gradient(plan, grad_image, positions):
     positions = np.asarray(positions, float)
     n_pos, n_f = positions.shape[0], plan.k.shape[0]
     S = len(plan.levels) - 1
@@ -101,10 +107,13 @@ def echo_gradient(plan, grad_image, positions):
     return out
 
 
-def position_gradient(plan, echoes, positions, grad_image):
-    """dL/dp' for L with image cotangent g, (n_pos, 3) float64."""
+def position_gradient(plan, echoes, positions, grad_image, weights=None):
+    """dL/dp' for L with image cotangent g, (n_pos, 3) float64 (aperture
+    weights w_i scale position i's terms, as they scale its echoes)."""
     positions = np.asarray(positions, float)
     echoes = np.asarray(echoes, np.complex128)
+    if weights is not None:
+        echoes = echoes * np.asarray(weights, float)[:, None]
     S = len(plan.levels) - 1
     if S == 0:
         return native.bp_eq4_dpos(positions, plan.k, echoes, plan.voxels, grad_image)

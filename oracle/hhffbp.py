@@ -161,19 +161,29 @@ def merge_at(plan, node, child_vals, points):
     return acc
 
 
-def image(plan, echoes, positions=None, keep=False, range_u=None):
+def weighted(echoes, weights):
+    """Echoes under the aperture measure of eq. (4): with weights w_i the
+    integral over p' becomes sum_i w_i (...), the same as scaling s_i by w_i."""
+    echoes = np.asarray(echoes, np.complex128)
+    if weights is None:
+        return echoes
+    return echoes * np.asarray(weights, float)[:, None]
+
+
+def image(plan, echoes, positions=None, keep=False, range_u=None, weights=None):
     """HHFFBPA image on the voxel grid, (nx, ny, nz) complex128.
 
     ``positions`` are the antenna positions used for backprojection (the plan's
     tree and grids stay as built).  With ``keep`` the compressed subimages of
     every node are returned as well, keyed by (depth, index).  ``range_u``
     selects the range-compressed, linearly interpolated level-1 sum (see ``_bp``).
+    ``weights`` are the aperture weights of eq. (4) (None: 1).
     """
     levels = plan.levels
     if positions is None:
         raise ValueError("positions are required")
     positions = np.asarray(positions, float)
-    echoes = np.asarray(echoes, np.complex128)
+    echoes = weighted(echoes, weights)
     S = len(levels) - 1
     if S == 0:
         img = _bp(plan, positions, echoes, plan.voxels, range_u)
@@ -196,10 +206,10 @@ def image(plan, echoes, positions=None, keep=False, range_u=None):
     return (img, vals) if keep else img
 
 
-def direct_bp(positions, freqs_hz, echoes, points):
-    """Plain eq. (4) at arbitrary points (float64)."""
+def direct_bp(positions, freqs_hz, echoes, points, weights=None):
+    """Plain eq. (4) at arbitrary points (float64), aperture weights w_i (None: 1)."""
     k = 2.0 * np.pi * np.asarray(freqs_hz, float) / 299792458.0
-    return native.bp_eq4(positions, k, echoes, points)
+    return native.bp_eq4(positions, k, weighted(echoes, weights), points)
 
 
 def direct_bp_linear(positions, freqs_hz, echoes, points, U):

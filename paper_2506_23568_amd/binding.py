@@ -37,6 +37,7 @@ class Config(ctypes.Structure):
         ("range_taps", ctypes.c_int32), ("storage", ctypes.c_int32),
         ("position_slack", ctypes.c_double), ("device", ctypes.c_int32),
         ("interp_kernel", ctypes.c_int32), ("final_staging", ctypes.c_int32),
+        ("weights", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -131,7 +132,8 @@ class Plan:
                  mode="factorized", stages=3, merge_factor=4, oversample=(3.0, 3.0, 3.5),
                  interp_taps=4,
                  range_kernel="es", range_oversample=2.0, range_taps=7, storage="c64",
-                 position_slack=5e-3, device=0, interp_kernel="lagrange", final_staging=True):
+                 position_slack=5e-3, device=0, interp_kernel="lagrange", final_staging=True,
+                 weights=None):
         L = lib()
         self._pos = np.ascontiguousarray(positions, np.float64)
         self._freqs = np.ascontiguousarray(freqs_hz, np.float64)
@@ -161,6 +163,11 @@ class Plan:
         c.device = int(device)
         c.interp_kernel = INTERP_KERNELS[interp_kernel]
         c.final_staging = 1 if final_staging else 0
+        if weights is not None:
+            self._w = np.ascontiguousarray(weights, np.float64)
+            if self._w.shape != (self._pos.shape[0],):
+                raise ValueError("weights must be (n_pos,)")
+            c.weights = self._w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self.config = c
         self.dims = tuple(int(d) for d in grid_dims)
         self.device = int(device)

@@ -47,6 +47,7 @@ void hhffbp_config_default(hhffbp_config *cfg)
     cfg->device = 0;
     cfg->interp_kernel = HHFFBP_INTERP_LAGRANGE;
     cfg->final_staging = 1;
+    cfg->weights = nullptr;
 }
 
 hhffbp_status hhffbp_plan(const hhffbp_config *cfg, hhffbp_plan_t *out)

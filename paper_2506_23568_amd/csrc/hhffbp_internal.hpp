@@ -115,6 +115,7 @@ struct DeviceBuffers {
     void *leaf_of_sorted = nullptr; // int32 [n_pos]
     void *leaf_centre = nullptr;    // double2 [n_leaves]
     void *pos64 = nullptr;          // double [n_pos][3], caller order
+    void *weights = nullptr;        // float [n_pos] aperture weights, caller order (or none)
     void *kf = nullptr;             // double [n_freq]: k_f (exact direct mode)
     void *kf_turns = nullptr;       // float [n_freq]: k_f / pi (exact mode, general spacing)
     std::vector<void *> nodes;      // per depth: NodeDev[]
@@ -154,6 +155,7 @@ struct Plan {
     std::vector<int32_t> leaf_of_sorted; // compact leaf index per sorted position
     std::vector<double> leaf_centre;     // [n_leaves][2]
     std::vector<double> positions;       // caller order, [n_pos][3]
+    std::vector<float> weights;          // caller order, empty for unit weights
     std::vector<std::vector<int32_t>> compact_to_tree;  // per depth
     std::vector<int64_t> depth_points;   // per depth
     std::vector<int64_t> n_blocks_merge; // per depth
@@ -198,8 +200,11 @@ void release_plan(Plan &plan);
 // Launchers (kernels.hip, kernels_adjoint.hip).
 hipError_t launch_prep(const Plan &P, const double *pos64, float4 *posoff, hipStream_t st);
 // Range-compression GEMM with float32 output; A stored as `storage_a` reals.
+// a_w / c_w: optional per-row weights of A (indexed by A's row) and of C
+// (indexed by C's row after c_perm); NULL for none.
 hipError_t launch_rc_gemm(int storage_a, const void *A, const int32_t *a_perm, int M, int K,
-                          const float *B, int N, float *C, const int32_t *c_perm, hipStream_t st);
+                          const float *B, int N, float *C, const int32_t *c_perm, hipStream_t st,
+                          const float *a_w, const float *c_w);
 hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *positions,
                               const void *grad_image, void *grad_echoes, double *grad_positions,
                               char *ws, hipStream_t st);

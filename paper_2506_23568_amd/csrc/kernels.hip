@@ -108,7 +108,9 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const typename Store<SA>::R 
                                                     int K, const float *__restrict__ B, int N,
                                                     typename Store<SC>::R *__restrict__ C,
                                                     const int32_t *__restrict__ c_perm,
-                                                    const float *__restrict__ scale, int vec)
+                                                    const float *__restrict__ scale, int vec,
+                                                    const float *__restrict__ a_w,
+                                                    const float *__restrict__ c_w)
 {
     __shared__ __align__(16) float As[kGemmKC][64 + kGemmPad];  // [k][row]
     __shared__ __align__(16) float Bs[kGemmKC][64 + kGemmPad];  // [k][col]
@@ -126,6 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const typename Store<SA>::R 
     const int grow = row0 + ar;
     const bool arow_ok = grow < M;
     const int arow = arow_ok ? (perm ? perm[grow] : grow) : 0;
+    const float aw = a_w ? a_w[arow] : 1.0f;  // row weight of A (aperture weight of the echo row)
     const int bk = tid >> 3, bc = (tid & 7) * 8;
 
     for (int k0 = 0; k0 < K; k0 += kGemmKC) {
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const typename Store<SA>::R 
                 bv8[e] = (kb < K && cg + e < N) ? B[(size_t)kb * N + cg + e] : 0.0f;
         }
 #pragma unroll
-        for (int e = 0; e < 8; ++e) As[ak + e][ar] = av8[e];
+        for (int e = 0; e < 8; ++e) As[ak + e][ar] = av8[e] * aw;
         *reinterpret_cast<float4 *>(&Bs[bk][bc]) = make_float4(bv8[0], bv8[1], bv8[2], bv8[3]);
         *reinterpret_cast<float4 *>(&Bs[bk][bc + 4]) = make_float4(bv8[4], bv8[5], bv8[6], bv8[7]);
         __syncthreads();
@@ -189,7 +192,8 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const typename Store<SA>::R 
                 const int col = col0 + wc + b * 16 + (lane & 15);
                 if (row < M && col < N) {
                     const int crow = c_perm ? c_perm[row] : row;
-                    C[(size_t)crow * N + col] = Store<SC>::str(acc[a][b][r] * sc);
+                    const float cw = c_w ? c_w[crow] : 1.0f;
+                    C[(size_t)crow * N + col] = Store<SC>::str(acc[a][b][r] * (sc * cw));
                 }
             }
 }
@@ -583,7 +587,7 @@ struct ExactPos {
 
 inline int exact_chunk(int n_f)
 {
-    const size_t per = sizeof(ExactPos) + sizeof(double) + (size_t)n_f * sizeof(float2);
+    const size_t per = sizeof(ExactPos) + sizeof(double) + sizeof(float) + (size_t)n_f * sizeof(float2);
     const int c = (int)(kLdsBudget / per);
     return c > 32 ? 32 : (c < 1 ? 1 : c);
 }
@@ -592,13 +596,14 @@ template <int ST, bool EQ>
 __global__ __launch_bounds__(kBlock) void k_direct_exact(
     const double *__restrict__ pos64, int n_pos, const typename Store<ST>::C *__restrict__ echoes,
     int n_f, const double *__restrict__ kf, const float *__restrict__ kf_turns, float k0_turns,
-    float dk_turns, int chunk, double ox, double oy, double oz, double sx, double sy, double sz,
-    int nx, int ny, int nz, float2 *__restrict__ image)
+    float dk_turns, int chunk, const float *__restrict__ wts, double ox, double oy, double oz,
+    double sx, double sy, double sz, int nx, int ny, int nz, float2 *__restrict__ image)
 {
     extern __shared__ unsigned char smem[];
     double *s_rref = reinterpret_cast<double *>(smem);
     ExactPos *s_pos = reinterpret_cast<ExactPos *>(smem + chunk * sizeof(double));
     float2 *s_c = reinterpret_cast<float2 *>(smem + chunk * (sizeof(double) + sizeof(ExactPos)));
+    float *s_w = reinterpret_cast<float *>(s_c + (size_t)chunk * n_f);
     const int tnx = (nx + 3) / 4, tny = (ny + 7) / 8;
     const int b = blockIdx.x;
     const int tx = b % tnx, ty = (b / tnx) % tny, tz = b / (tnx * tny);
@@ -621,6 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_direct_exact(
             const double rr = sqrt(dx * dx + dy * dy + dz * dz);
             s_rref[threadIdx.x] = rr;
             s_pos[threadIdx.x] = ExactPos{(float)dx, (float)dy, (float)dz, (float)rr};
+            s_w[threadIdx.x] = wts ? wts[i] : 1.0f;
         }
         __syncthreads();
         for (int t = threadIdx.x; t < n * n_f; t += kBlock) {
@@ -629,7 +635,9 @@ __global__ __launch_bounds__(kBlock) void k_direct_exact(
             turns -= rint(turns);
             const float tf = (float)turns;
             const float sn = sin_turns(tf), cs = cos_turns(tf);
-            const float2 v = Store<ST>::ld(echoes[(size_t)(c0 + i) * n_f + f]);
+            float2 v = Store<ST>::ld(echoes[(size_t)(c0 + i) * n_f + f]);
+            v.x *= s_w[i];
+            v.y *= s_w[i];
             s_c[t] = make_float2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
         }
         __syncthreads();
@@ -691,18 +699,21 @@ hipError_t launch_direct_exact(const Plan &P, const void *echoes, const double *
     const int nblk = ((nx + 3) / 4) * ((ny + 7) / 8) * ((nz + 7) / 8);
     const int nf = (int)c.n_freq;
     const int chunk = exact_chunk(nf);
-    const size_t sh = (size_t)chunk * (sizeof(double) + sizeof(ExactPos) + (size_t)nf * sizeof(float2));
+    const size_t sh =
+        (size_t)chunk * (sizeof(double) + sizeof(ExactPos) + sizeof(float) + (size_t)nf * sizeof(float2));
     const float k0t = (float)(P.k0 / kPi), dkt = (float)(P.dk / kPi);
     if (P.k_equispaced)
         hipLaunchKernelGGL((k_direct_exact<ST, true>), dim3(nblk), dim3(kBlock), sh, st, pos64,
                            (int)c.n_pos, (const C *)echoes, nf, (const double *)P.dev.kf,
-                           (const float *)P.dev.kf_turns, k0t, dkt, chunk, c.grid_origin[0],
+                           (const float *)P.dev.kf_turns, k0t, dkt, chunk,
+                           (const float *)P.dev.weights, c.grid_origin[0],
                            c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0], c.grid_pitch[1],
                            c.grid_pitch[2], nx, ny, nz, (float2 *)image);
     else
         hipLaunchKernelGGL((k_direct_exact<ST, false>), dim3(nblk), dim3(kBlock), sh, st, pos64,
                            (int)c.n_pos, (const C *)echoes, nf, (const double *)P.dev.kf,
-                           (const float *)P.dev.kf_turns, k0t, dkt, chunk, c.grid_origin[0],
+                           (const float *)P.dev.kf_turns, k0t, dkt, chunk,
+                           (const float *)P.dev.weights, c.grid_origin[0],
                            c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0], c.grid_pitch[1],
                            c.grid_pitch[2], nx, ny, nz, (float2 *)image);
     return hipGetLastError();
@@ -852,7 +863,8 @@ hhffbp_status image_for_storage(const Plan &P, const void *echoes, const double 
         hipLaunchKernelGGL((k_rc_gemm<ST, ST>), grid, dim3(kBlock), 0, st,
                            (const typename Store<ST>::R *)echoes, (const int32_t *)P.dev.perm, M, K,
                            (const float *)P.dev.B, N, (typename Store<ST>::R *)prof,
-                           (const int32_t *)nullptr, scales, gemm_vec(echoes, K, (const float *)P.dev.B, N));
+                           (const int32_t *)nullptr, scales, gemm_vec(echoes, K, (const float *)P.dev.B, N),
+                           (const float *)P.dev.weights, (const float *)nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
         if (ev) (void)hipEventRecord(*ev++, st);
     }
@@ -890,24 +902,25 @@ hipError_t launch_prep(const Plan &P, const double *pos64, float4 *posoff, hipSt
 }
 
 hipError_t launch_rc_gemm(int storage_a, const void *A, const int32_t *a_perm, int M, int K,
-                          const float *B, int N, float *C, const int32_t *c_perm, hipStream_t st)
+                          const float *B, int N, float *C, const int32_t *c_perm, hipStream_t st,
+                          const float *a_w, const float *c_w)
 {
     dim3 grid((M + 63) / 64, (N + 63) / 64);
     switch (storage_a) {
     case HHFFBP_F16:
         hipLaunchKernelGGL((k_rc_gemm<HHFFBP_F16, HHFFBP_C64>), grid, dim3(kBlock), 0, st,
                            (const uint16_t *)A, a_perm, M, K, B, N, C, c_perm, (const float *)nullptr,
-                           gemm_vec(A, K, B, N));
+                           gemm_vec(A, K, B, N), a_w, c_w);
         break;
     case HHFFBP_BF16:
         hipLaunchKernelGGL((k_rc_gemm<HHFFBP_BF16, HHFFBP_C64>), grid, dim3(kBlock), 0, st,
                            (const uint16_t *)A, a_perm, M, K, B, N, C, c_perm, (const float *)nullptr,
-                           gemm_vec(A, K, B, N));
+                           gemm_vec(A, K, B, N), a_w, c_w);
         break;
     default:
         hipLaunchKernelGGL((k_rc_gemm<HHFFBP_C64, HHFFBP_C64>), grid, dim3(kBlock), 0, st,
                            (const float *)A, a_perm, M, K, B, N, C, c_perm, (const float *)nullptr,
-                           gemm_vec(A, K, B, N));
+                           gemm_vec(A, K, B, N), a_w, c_w);
     }
     return hipGetLastError();
 }

@@ -558,7 +558,7 @@ hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *p
     if (want_p) {
         e = launch_rc_gemm(c.storage, echoes, (const int32_t *)P.dev.perm, n,
                            (int)(2 * c.n_freq), (const float *)P.dev.Bd, (int)(2 * P.Nr),
-                           (float *)dprof, nullptr, st);
+                           (float *)dprof, nullptr, st, (const float *)P.dev.weights, nullptr);
         if (e != hipSuccess) return HHFFBP_E_DEVICE;
     }
     // clear every grid cotangent: depths 1..S are contiguous and end at the
@@ -604,7 +604,7 @@ hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *p
         // grad_s = gprof conj(W)^T, rows back to the caller's position order
         e = launch_rc_gemm(HHFFBP_C64, gprof, nullptr, n, (int)(2 * P.Nr),
                            (const float *)P.dev.Badj, (int)(2 * c.n_freq), (float *)grad_echoes,
-                           (const int32_t *)P.dev.perm, st);
+                           (const int32_t *)P.dev.perm, st, nullptr, (const float *)P.dev.weights);
         if (e != hipSuccess) return HHFFBP_E_DEVICE;
     }
     if (want_p) {

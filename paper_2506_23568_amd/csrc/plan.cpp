@@ -623,6 +623,9 @@ void validate(const hhffbp_config &c)
     double zmax = -1e300;
     for (int64_t i = 0; i < 3 * c.n_pos; ++i)
         if (!std::isfinite(c.positions[i])) bad("positions must be finite");
+    if (c.weights)
+        for (int64_t i = 0; i < c.n_pos; ++i)
+            if (!std::isfinite(c.weights[i])) bad("weights must be finite");
     for (int64_t i = 0; i < c.n_pos; ++i) zmax = std::max(zmax, c.positions[3 * i + 2]);
     for (int64_t f = 0; f < c.n_freq; ++f)
         if (!(c.freqs_hz[f] > 0) || !std::isfinite(c.freqs_hz[f])) bad("freqs_hz must be finite and > 0");
@@ -687,6 +690,8 @@ void build_plan_host(Plan &P)
     P.beta = kPi * P.W * (1.0 - 1.0 / (2.0 * P.U)) * 0.98;
     fit_interp_poly(P);
     P.positions.assign(c.positions, c.positions + 3 * c.n_pos);
+    P.weights.clear();
+    if (c.weights) P.weights.assign(c.weights, c.weights + c.n_pos);
     P.k.resize(c.n_freq);
     for (int64_t f = 0; f < c.n_freq; ++f) P.k[f] = 2.0 * kPi * c.freqs_hz[f] / kLight;
     P.kmin = *std::min_element(P.k.begin(), P.k.end());
@@ -960,6 +965,7 @@ void upload_plan(Plan &P)
     upload_vec(P.device_bytes, &D.leaf_of_sorted, P.leaf_of_sorted);
     upload_vec(P.device_bytes, &D.leaf_centre, P.leaf_centre);
     upload_vec(P.device_bytes, &D.pos64, P.positions);
+    if (!P.weights.empty()) upload_vec(P.device_bytes, &D.weights, P.weights);
     if (P.cfg.mode == HHFFBP_DIRECT_EXACT) {
         std::vector<float> kt(P.k.size());
         for (size_t f = 0; f < P.k.size(); ++f) kt[f] = (float)(P.k[f] / kPi);
@@ -1126,6 +1132,7 @@ void release_plan(Plan &P)
     fr(D.leaf_of_sorted);
     fr(D.leaf_centre);
     fr(D.pos64);
+    fr(D.weights);
     fr(D.kf);
     fr(D.kf_turns);
     fr(D.leafpts);

@@ -78,6 +78,18 @@ def test_exact_direct_mode_plans_on_the_host(small):
     assert H.binding.MODES["direct_exact"] == 2
 
 
+def test_aperture_weights_are_validated(small):
+    """Non-finite weights are rejected at plan time, a wrong length by the binding."""
+    w = np.ones(small.n_pos)
+    H.Plan(*_args(small), device=-1, weights=w)
+    w[5] = np.nan
+    with pytest.raises(H.HHFFBPError) as e:
+        H.Plan(*_args(small), device=-1, weights=w)
+    assert e.value.status == -1
+    with pytest.raises(ValueError):
+        H.Plan(*_args(small), device=-1, weights=np.ones(3))
+
+
 def test_unknown_storage_is_rejected(small):
     c = H.binding.default_config()
     pos = np.ascontiguousarray(small.positions)

@@ -156,3 +156,26 @@ def test_gpu_gradients_bandlimited(torch, small):
     _say(f"  bandlimited: echo gradient NRMSE {es:.2e}; position gradient rel {ep:.2e}")
     assert es <= 1e-5
     assert ep <= 1e-3
+
+
+def test_gpu_gradients_with_aperture_weights(torch, small):
+    """Weighted echo and position gradients against the oracle's (weights scale
+    row i of A and position i's terms): echo <= 1e-5, positions <= 1e-3."""
+    from oracle import adjoint as OA
+    from oracle import plan as OP
+    w8 = np.random.default_rng(9).uniform(0.1, 2.0, small.n_pos)
+    op = OP.build_plan(*_args(small), 2, 4, GAMMA, TAPS)
+    pl = H.Plan(*_args(small), stages=2, oversample=GAMMA, interp_taps=TAPS, weights=w8)
+    rng = np.random.default_rng(2)
+    g = rng.standard_normal(small.grid_dims) + 1j * rng.standard_normal(small.grid_dims)
+    ref_s = OA.echo_gradient(op, g, small.positions, weights=w8)
+    ref_p = OA.position_gradient(op, small.echoes, small.positions, g, weights=w8)
+    ech = torch.from_numpy(small.echoes.astype(np.complex64)).cuda()
+    gt = torch.from_numpy(g.astype(np.complex64)).cuda()
+    ge, gp = pl.backward(ech, gt)
+    es = _nrmse(ge.cpu().numpy().astype(np.complex128), ref_s)
+    gp = gp.cpu().numpy()
+    ep = float(np.linalg.norm(gp - ref_p) / np.linalg.norm(ref_p))
+    _say(f"  weighted: echo gradient NRMSE {es:.2e}; position gradient rel {ep:.2e}")
+    assert es <= 1e-5 and ep <= 1e-3
+

@@ -446,3 +446,27 @@ def test_direct_exact_mid_sampled(torch, mid):
     _say(f"  mid direct_exact (512 voxels) NRMSE {e:.3e}")
     assert e <= 1e-5
 
+
+@pytest.mark.parametrize("mode", ["factorized", "direct_exact", "direct_rc"])
+def test_aperture_weights(torch, small, mode):
+    """Aperture weights w_i (eq. (4)'s measure of dp'): the weighted image
+    against the oracle's weighted form (<= 1e-5); for the factorised mode the
+    oracle HHFFBPA with the same plan choices, for the direct modes eq. (4)."""
+    from oracle import hhffbp as OH
+    from oracle import plan as OP
+    from workloads import voxel_centres
+    w8 = np.random.default_rng(8).uniform(0.1, 2.0, small.n_pos)
+    kw = dict(stages=2, oversample=GAMMA, interp_taps=TAPS) if mode == "factorized" else {}
+    pl = H.Plan(*_args(small), mode=mode, weights=w8, **kw)
+    got = _run(torch, pl, small)
+    if mode == "factorized":
+        op = OP.build_plan(*_args(small), 2, 4, GAMMA, TAPS)
+        ref = OH.image(op, small.echoes, small.positions, weights=w8)
+    else:
+        vox = voxel_centres(small.grid_origin, small.grid_pitch, small.grid_dims)
+        ref = OH.direct_bp(small.positions, small.freqs_hz, small.echoes, vox,
+                           weights=w8).reshape(small.grid_dims)
+    e = _nrmse(got, ref)
+    _say(f"  {mode} weighted vs oracle {e:.3e}")
+    assert e <= 1e-5
+
