@@ -179,3 +179,51 @@ def test_gpu_gradients_with_aperture_weights(torch, small):
     _say(f"  weighted: echo gradient NRMSE {es:.2e}; position gradient rel {ep:.2e}")
     assert es <= 1e-5 and ep <= 1e-3
 
+
+
+def test_gpu_gradients_linear_range_mode(torch, small):
+    """The fast range mode (linear kernel, U = 8) in the backward.  Echo
+    gradient: the adjoint identity with the same mode's forward (<= 1e-5).
+    Position gradient: the kernels interpolate the range-derivative profiles
+    h' (the analytic derivative), so they give the exact gradient to the range
+    kernel's accuracy (-61 dB, ~1e-3), checked against the oracle's exact
+    position gradient (<= 5e-3); central differences of the oracle's own
+    linear form are reported beside it."""
+    from oracle import adjoint as OA
+    from oracle import hhffbp as OH
+    from oracle import plan as OP
+    kw = dict(stages=2, oversample=GAMMA, interp_taps=TAPS, range_kernel="linear",
+              range_oversample=8.0)
+    pl = H.Plan(*_args(small), **kw)
+    rng = np.random.default_rng(6)
+    s = rng.standard_normal(small.echoes.shape) + 1j * rng.standard_normal(small.echoes.shape)
+    g = rng.standard_normal(small.grid_dims) + 1j * rng.standard_normal(small.grid_dims)
+    st = torch.from_numpy(s.astype(np.complex64)).cuda()
+    gt = torch.from_numpy(g.astype(np.complex64)).cuda()
+    f = pl.image(st).cpu().numpy().astype(np.complex128)
+    ge, _ = pl.backward(None, gt, want_positions=False)
+    ge = ge.cpu().numpy().astype(np.complex128)
+    lhs = np.vdot(g.astype(np.complex64).astype(np.complex128).ravel(), f.ravel())
+    rhs = np.vdot(ge.ravel(), s.astype(np.complex64).astype(np.complex128).ravel())
+    e_adj = abs(lhs - rhs) / abs(lhs)
+    ech = torch.from_numpy(small.echoes.astype(np.complex64)).cuda()
+    _, gp = pl.backward(ech, gt)
+    gp = gp.cpu().numpy()
+    op = OP.build_plan(*_args(small), 2, 4, GAMMA, TAPS)
+    ref = OA.position_gradient(op, small.echoes, small.positions, g)
+    e_p = float(np.linalg.norm(gp - ref) / np.linalg.norm(ref))
+    coords = [(int(rng.integers(small.n_pos)), int(rng.integers(3))) for _ in range(8)]
+    h = 1e-6
+    fd, an = [], []
+    for i, a in coords:
+        pp, pm = small.positions.copy(), small.positions.copy()
+        pp[i, a] += h
+        pm[i, a] -= h
+        d = OH.image(op, small.echoes, pp, range_u=8) - OH.image(op, small.echoes, pm, range_u=8)
+        fd.append(np.real(np.vdot(g.ravel(), d.ravel())) / (2 * h))
+        an.append(gp[i, a])
+    e_fd = float(np.linalg.norm(np.array(an) - np.array(fd)) / np.linalg.norm(fd))
+    _say(f"  adjoint identity {e_adj:.2e}; position gradient vs exact {e_p:.2e}, "
+         f"vs central differences of the linear form {e_fd:.2e}")
+    assert e_adj <= 1e-5
+    assert e_p <= 5e-3
