@@ -154,6 +154,8 @@ def autofocus_report(args):
     a3 = (p_img, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims)
     kw = dict(stages=3, merge_factor=4, oversample=BENCH_GAMMA, interp_taps=TAPS,
               interp_kernel="bandlimited")
+    if args.af_range == "linear":
+        kw.update(range_kernel="linear", range_oversample=8.0)
     pos_true = torch.from_numpy(w.positions).cuda()
     pos0 = torch.from_numpy(p_img.copy()).cuda()
     ech64 = torch.from_numpy(w.echoes.astype(np.complex64)).cuda()
@@ -191,6 +193,8 @@ def autofocus_report(args):
         "config": {"workload": "autofocus: 65536 positions (44 strokes + 20 dense walks), 128 f "
                                "24-40 GHz, 256x256x128 voxels at 1 mm, 200 points + 5000-scatterer "
                                "slab, smooth trajectory error, S=3 Q=4, 20 Adam steps (lr 0.03 mm) on 16 cosine modes per axis, relative-L2 loss to the clean-trajectory image",
+                   "range_kernel": "linear U=8" if args.af_range == "linear" else "ES U=2 W=7",
+                   "interp_kernel": "bandlimited", "oversample": list(BENCH_GAMMA),
                    "parallelism": "single GPU"},
         "storage": out,
         "reference": "float32 direct BP (ES U=2 W=7) at the true positions, full grid"}), flush=True)
@@ -275,6 +279,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain copy of this size first (HBM counter scale)")
+    ap.add_argument("--af-range", choices=("es", "linear"), default="linear",
+                    help="range kernel of the autofocus workload's images")
     ap.add_argument("--workload", choices=["mid", "autofocus", "paper_sim"], default="mid",
                     help="mid: the imaging benchmark (default); autofocus: the trajectory "
                          "correction loop on the large scene; paper_sim: the paper's "
