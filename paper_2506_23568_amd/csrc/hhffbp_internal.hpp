@@ -78,6 +78,15 @@ struct TileBox {
     int32_t i0, j0, l0, ni, nj, nl, lsh, pad;
 };
 
+// Bricks of a parent grid for the merge adjoint: kBrickX x kBrickY columns
+// (i, j) x kBrickZ lattice steps l of one node's grid, with origin (i, j, l); a
+// lane's grid point is found through the node's column table (lanes outside
+// every pencil are idle).  Their stencils cover a smaller box of the child grid
+// than a run of points along the pencils does.
+struct MergeBrick {
+    int32_t node, i, j, l;
+};
+
 // Range bins [lo, lo + n) that a level-1 BP block can read: every tap of its
 // points for positions within the leaf's reach.
 struct BinWindow {
@@ -131,6 +140,7 @@ struct DeviceBuffers {
     void *scale_mult = nullptr;     // float [S + 1]: worst-case gain from echoes to each stage
     std::vector<void *> merge_blocks;  // per depth 1..S-1: BlockItem[] of 256 points (adjoint)
     std::vector<void *> merge_blocks_fwd;  // per depth 1..S-1: BlockItem[] of 256 / Q points
+    std::vector<void *> merge_bricks;      // per depth 1..S-1: MergeBrick[] (merge adjoint)
 };
 
 struct Plan {
@@ -160,6 +170,7 @@ struct Plan {
     std::vector<int64_t> depth_points;   // per depth
     std::vector<int64_t> n_blocks_merge; // per depth
     std::vector<int64_t> n_blocks_merge_fwd; // per depth
+    std::vector<std::vector<MergeBrick>> merge_bricks;  // per depth, host copy
     int64_t n_blocks_leaf = 0, n_blocks_adj = 0;
     int32_t leaf_win_max = 0;  // widest BinWindow of the level-1 BP blocks
     std::vector<TileBox> final_tiles;  // host copy, brick-major

@@ -248,9 +248,15 @@ __global__ __launch_bounds__(kBlock) void k_final_adj(const NodeDev *__restrict_
     }
 }
 
+// M_d^H on a merge brick (4 x 4 columns x 16 steps of a parent grid; lane t:
+// l = t mod 16 fastest, then j, then i): each point's cotangent is rotated by
+// Phi_child - Phi_parent and scattered into the child's grid through the
+// block's box.  Bricks keep that box, and so the number of global atomics per
+// point, smaller than runs of points along the pencils would.
 template <int T, int K>
 __global__ __launch_bounds__(kBlock) void k_merge_adj(const NodeDev *__restrict__ parents,
-                                                      const BlockItem *__restrict__ blocks,
+                                                      const ColEntry *__restrict__ pcols,
+                                                      const MergeBrick *__restrict__ bricks,
                                                       const double *__restrict__ px,
                                                       const double *__restrict__ py,
                                                       const double *__restrict__ pz,
@@ -261,11 +267,20 @@ __global__ __launch_bounds__(kBlock) void k_merge_adj(const NodeDev *__restrict_
                                                       const InterpPoly ip)
 {
     __shared__ BoxShared sh;
-    const BlockItem blk = blocks[blockIdx.x];
-    const NodeDev nd = parents[blk.node];
-    const int p = blk.start + threadIdx.x;
-    bool active = p < nd.npts;
-    const int gi = nd.val_base + (active ? p : 0);
+    const MergeBrick mb = bricks[blockIdx.x];
+    const NodeDev nd = parents[mb.node];
+    const int t = (int)threadIdx.x;
+    const int ci = mb.i + t / (kBrickY * kBrickZ) - nd.i0, cj = mb.j + (t / kBrickZ) % kBrickY - nd.j0;
+    const int l = mb.l + t % kBrickZ;
+    bool active = false;
+    int gi = 0;
+    if ((unsigned)ci < (unsigned)nd.ni && (unsigned)cj < (unsigned)nd.nj) {
+        const ColEntry pe = pcols[nd.col_base + ci * nd.nj + cj];
+        if (l >= pe.lo && l <= pe.hi) {
+            active = true;
+            gi = nd.val_base + pe.off + (l - pe.lo);
+        }
+    }
     double x = 0.0, y = 0.0, z = 1.0;
     float2 g = make_float2(0.f, 0.f);
     if (active) {
@@ -276,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_adj(const NodeDev *__restrict_
     }
     active = active && (z > 0.0) && (g.x != 0.0f || g.y != 0.0f);  // absent points hold nothing
     const double phip = active ? phi_only(nd, x, y, z, gp.kmin, gp.kmax) : 0.0;
-    const int32_t *child_idx = parents[blk.node].child;
+    const int32_t *child_idx = parents[mb.node].child;
     for (int c = 0; c < nd.nchild; ++c) {
         const NodeDev ch = children[child_idx[c]];
         ChildCoord cc{};
@@ -525,9 +540,11 @@ hipError_t launch_scatters(const Plan &P, const void *grad_image, char *ws, hipS
                        c.grid_pitch[1], c.grid_pitch[2], nx, ny, nz, (const float2 *)grad_image);
     hipError_t e = hipGetLastError();
     for (int d = 1; d < P.S && e == hipSuccess; ++d) {
-        if (P.n_blocks_merge[d] == 0) continue;
-        hipLaunchKernelGGL((k_merge_adj<T, K>), dim3(P.n_blocks_merge[d]), dim3(kBlock), 0, st,
-                           (const NodeDev *)P.dev.nodes[d], (const BlockItem *)P.dev.merge_blocks[d],
+        const int64_t nb = (int64_t)P.merge_bricks[d].size();
+        if (nb == 0) continue;
+        hipLaunchKernelGGL((k_merge_adj<T, K>), dim3(nb), dim3(kBlock), 0, st,
+                           (const NodeDev *)P.dev.nodes[d], (const ColEntry *)P.dev.cols[d],
+                           (const MergeBrick *)P.dev.merge_bricks[d],
                            (const double *)P.dev.px[d], (const double *)P.dev.py[d],
                            (const double *)P.dev.pz[d], (const float2 *)(ws + P.ws_gvals[d]),
                            (const NodeDev *)P.dev.nodes[d + 1], (const ColEntry *)P.dev.cols[d + 1],

@@ -394,6 +394,31 @@ void build_final_tiles(Plan &P)
     P.n_tiled = tiled.load();
 }
 
+// Merge bricks of depth d: per node, 4 x 4 column blocks of its grid, each cut
+// into runs of kBrickZ steps over the union of its columns' n ranges.
+void build_merge_bricks(Plan &P, int d)
+{
+    std::vector<MergeBrick> &bricks = P.merge_bricks[d];
+    bricks.clear();
+    for (int32_t ti : P.compact_to_tree[d]) {
+        const HostNode &nd = P.levels[d][ti];
+        const HostLattice &L = nd.lat;
+        for (int32_t ib = 0; ib < L.ni; ib += kBrickX)
+            for (int32_t jb = 0; jb < L.nj; jb += kBrickY) {
+                int32_t lmin = INT32_MAX, lmax = INT32_MIN;
+                for (int32_t i = ib; i < std::min(L.ni, ib + kBrickX); ++i)
+                    for (int32_t j = jb; j < std::min(L.nj, jb + kBrickY); ++j) {
+                        const int64_t cidx = (int64_t)i * L.nj + j;
+                        if (L.hi[cidx] < L.lo[cidx]) continue;
+                        lmin = std::min(lmin, L.lo[cidx]);
+                        lmax = std::max(lmax, L.hi[cidx]);
+                    }
+                for (int32_t l = lmin; lmin <= lmax && l <= lmax; l += kBrickZ)
+                    bricks.push_back(MergeBrick{nd.compact, L.i0 + ib, L.j0 + jb, l});
+            }
+    }
+}
+
 // Fourier transform of the truncated ES kernel phi(t) = exp(beta (sqrt(1 - (2t/W)^2) - 1))
 // on |t| <= W/2, at angular frequency theta (rad per bin); composite Simpson.
 double es_hat(double theta, int W, double beta)
@@ -841,6 +866,8 @@ void build_plan_host(Plan &P)
     }
     P.model_s = model_seconds(P);
     if (S > 0) build_final_tiles(P);  // with final_staging = 0 every box is left empty
+    P.merge_bricks.assign(S + 1, {});
+    for (int d = 1; d < S; ++d) build_merge_bricks(P, d);
 
     // workspace layout; profiles and subimages in the storage type
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -950,6 +977,7 @@ void upload_plan(Plan &P)
     P.dev.pz.assign(S + 1, nullptr);
     P.dev.merge_blocks.assign(S + 1, nullptr);
     P.dev.merge_blocks_fwd.assign(S + 1, nullptr);
+    P.dev.merge_bricks.assign(S + 1, nullptr);
     P.n_blocks_merge.assign(S + 1, 0);
     P.n_blocks_merge_fwd.assign(S + 1, 0);
     P.device_bytes = 0;
@@ -1100,6 +1128,7 @@ void upload_plan(Plan &P)
             upload_vec(P.device_bytes, &D.merge_blocks[d], blocks);
             P.n_blocks_merge[d] = (int64_t)blocks.size();
             upload_vec(P.device_bytes, &D.merge_blocks_fwd[d], blocks_fwd);
+            upload_vec(P.device_bytes, &D.merge_bricks[d], P.merge_bricks[d]);
             P.n_blocks_merge_fwd[d] = (int64_t)blocks_fwd.size();
         } else {
             upload_vec(P.device_bytes, &D.leafpts, lpts);
@@ -1143,7 +1172,8 @@ void release_plan(Plan &P)
     fr(D.Bd);
     fr(D.Badj);
     fr(D.scale_mult);
-    for (auto *v : {&D.nodes, &D.cols, &D.px, &D.py, &D.pz, &D.merge_blocks, &D.merge_blocks_fwd})
+    for (auto *v : {&D.nodes, &D.cols, &D.px, &D.py, &D.pz, &D.merge_blocks, &D.merge_blocks_fwd,
+                    &D.merge_bricks})
         for (auto &p : *v) fr(p);
 }
 
