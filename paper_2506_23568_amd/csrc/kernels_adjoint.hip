@@ -182,17 +182,39 @@ __device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c
         interp_weights<T, K>(ip, g, wu, wv, wn);
         const float qre = gre * q, qim = gim * q;
         const int bi = g.bi + lo - o0, bj = g.bj + lo - o1, bl = g.bl + lo - o2;
+        // Neighbouring points often share a stencil base; taken in the same tap
+        // order their atomics would hit one LDS address per instruction.  Each
+        // lane rotates its v and n tap order by lane bits (z and y neighbours of
+        // the final stage's tiles), so such lanes add to different entries at
+        // once; integer sums do not depend on the order.
+        const int rn = lane % T, rv = (lane >> 3) % T;
+        float wvr[T], wnr[T];
+        int ov[T], on[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int iv = (t + rv) % T, in = (t + rn) % T;
+            float x = wv[0], y = wn[0];
+#pragma unroll
+            for (int u = 1; u < T; ++u) {
+                x = (iv == u) ? wv[u] : x;
+                y = (in == u) ? wn[u] : y;
+            }
+            wvr[t] = x;
+            wnr[t] = y;
+            ov[t] = iv;
+            on[t] = in;
+        }
 #pragma unroll
         for (int a = 0; a < T; ++a)
 #pragma unroll
             for (int b = 0; b < T; ++b) {
-                const float wab = wu[a] * wv[b];
-                const int row = ((bi + a) * B1 + (bj + b)) * B2 + bl;
+                const float wab = wu[a] * wvr[b];
+                const int row = ((bi + a) * B1 + (bj + ov[b])) * B2 + bl;
 #pragma unroll
                 for (int k = 0; k < T; ++k) {
-                    const float w = wab * wn[k];
-                    atomicAdd(&sh.box_re[row + k], (int)rintf(w * qre));
-                    atomicAdd(&sh.box_im[row + k], (int)rintf(w * qim));
+                    const float w = wab * wnr[k];
+                    atomicAdd(&sh.box_re[row + on[k]], (int)rintf(w * qre));
+                    atomicAdd(&sh.box_im[row + on[k]], (int)rintf(w * qim));
                 }
             }
     }
