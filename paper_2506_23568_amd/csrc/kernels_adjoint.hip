@@ -526,7 +526,17 @@ hipError_t launch_leaf_adj(const Plan &P, const float4 *posoff, const float2 *dp
 {
     const size_t sh = (P_ ? (size_t)kAdjPos * P.Nr * sizeof(float2) : 0) +
                       (S_ ? (size_t)kAdjPos * (P.Nr + 1) * 2 * sizeof(unsigned long long) : 0);
-    if (sh > kLdsLimit) return hipErrorInvalidConfiguration;  // caller maps to UNSUPPORTED
+    if (sh > kLdsLimit) {
+        // beyond the default dynamic LDS: use the device's opt-in limit if it is larger
+        int dev = 0, optin = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess ||
+            sh > (size_t)optin)
+            return hipErrorInvalidConfiguration;  // caller maps to UNSUPPORTED
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_leaf_adj<KERNEL, W, S_, P_>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess)
+            return hipErrorInvalidConfiguration;
+    }
     hipLaunchKernelGGL((k_leaf_adj<KERNEL, W, S_, P_>), dim3(P.n_blocks_adj), dim3(kBlock), sh, st,
                        (const NodeDev *)P.dev.nodes[P.S], (const BlockItem *)P.dev.adj_blocks,
                        (const LeafPoint *)P.dev.leafpts, posoff, dprof, (int)P.Nr,
