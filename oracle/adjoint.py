@@ -65,8 +65,19 @@ def leaf_cotangents(plan, grad_image):
     cot = {}
     if S == 0:
         return cot
-    _split_to_children(plan, levels[0][0], plan.voxels, g, 0.0, cot)
-    for d in range(1, S):
+    if plan.root_grid:
+        # transpose of the last resample: image = exp(+j Phi_root) I_root(voxels)
+        root = levels[0][0]
+        t = plan.gamma * G.uvn(plan.voxels, root.rect, plan.kmin, plan.kmax)
+        ph = G.phi(plan.voxels, root.rect, plan.kmin, plan.kmax)
+        cot[(0, 0)] = np.zeros(root.lattice.size, np.complex128)
+        scatter_transpose(root.lattice, t, plan.taps, np.exp(-1j * ph) * g, cot[(0, 0)],
+                          kernel=plan.kernel, gamma=plan.gamma)
+        first = 0
+    else:
+        _split_to_children(plan, levels[0][0], plan.voxels, g, 0.0, cot)
+        first = 1
+    for d in range(first, S):
         for idx, node in enumerate(levels[d]):
             if node.empty:
                 continue

@@ -10,7 +10,10 @@ Test infrastructure (oracle).
    exp(+j Phi_child), and the children are summed coherently
    (f_{m,n} = sum of its children, Fig. pcsffbp).  A parent below the root is
    compressed again with its own Phi before the next merge.
-4. The root's grid is the user voxel grid; its sum is the image.
+4. The root's grid is the user voxel grid; its sum is the image.  With the
+   plan's root grid the root is merged onto its own compressed lattice like any
+   other parent, and the image is that lattice interpolated at the voxels with
+   the root's SDC reverted (one child, the root).
 
 The level-1 sum is eq. (4) itself, or (``range_u``) the fast form: range
 profiles sampled every dR = pi / (U (k_max - k_min)) on the grid R_b = b dR,
@@ -146,6 +149,14 @@ def leaf_bp_at(plan, node, echoes, positions, point_index, range_u=None):
     return out
 
 
+def resample(plan, node, vals, points):
+    """exp(+j Phi_node) I_node((u, v, n)_node(points)): a node's compressed
+    subimage, interpolated at ``points`` and with its SDC reverted."""
+    t = plan.gamma * G.uvn(points, node.rect, plan.kmin, plan.kmax)
+    val = interpolate(node.lattice, vals, t, plan.taps, kernel=plan.kernel, gamma=plan.gamma)
+    return val * np.exp(1j * G.phi(points, node.rect, plan.kmin, plan.kmax))
+
+
 def merge_at(plan, node, child_vals, points):
     """f_node(points) = sum_c exp(+j Phi_c) I_c((u, v, n)_c(points)) (uncompressed)."""
     d = node.depth
@@ -154,10 +165,7 @@ def merge_at(plan, node, child_vals, points):
         child = plan.levels[d + 1][ci]
         if child.empty:
             continue
-        t = plan.gamma * G.uvn(points, child.rect, plan.kmin, plan.kmax)
-        val = interpolate(child.lattice, child_vals[(d + 1, ci)], t, plan.taps,
-                          kernel=plan.kernel, gamma=plan.gamma)
-        acc += val * np.exp(1j * G.phi(points, child.rect, plan.kmin, plan.kmax))
+        acc += resample(plan, child, child_vals[(d + 1, ci)], points)
     return acc
 
 
@@ -192,7 +200,7 @@ def image(plan, echoes, positions=None, keep=False, range_u=None, weights=None):
     for idx, node in enumerate(levels[S]):
         if not node.empty:
             vals[(S, idx)] = leaf_bp(plan, node, echoes, positions, range_u)
-    for d in range(S - 1, 0, -1):
+    for d in range(S - 1, -1 if plan.root_grid else 0, -1):
         for idx, node in enumerate(levels[d]):
             if node.empty:
                 continue
@@ -202,7 +210,10 @@ def image(plan, echoes, positions=None, keep=False, range_u=None, weights=None):
             out = np.zeros(lat.size, np.complex128)
             out[lat.valid] = f * np.exp(-1j * G.phi(pts, node.rect, plan.kmin, plan.kmax))
             vals[(d, idx)] = out
-    img = merge_at(plan, levels[0][0], vals, plan.voxels).reshape(plan.dims)
+    if plan.root_grid:
+        img = resample(plan, levels[0][0], vals[(0, 0)], plan.voxels).reshape(plan.dims)
+    else:
+        img = merge_at(plan, levels[0][0], vals, plan.voxels).reshape(plan.dims)
     return (img, vals) if keep else img
 
 

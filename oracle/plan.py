@@ -17,6 +17,13 @@ Readings of what the paper leaves open (Sec. IV-A and Fig. pcsffbp):
   every side, then closed along n into one contiguous pencil per (i, j) column.
   Built from the root downwards, so no stencil ever reaches a missing point.
   The spacing may differ per axis: (u, v, n) = (i/gamma_u, j/gamma_v, l/gamma_n).
+* Root grid (optional).  The root's grid is the user voxel grid.  With
+  ``root_grid`` the root gets a compressed lattice of its own, built like every
+  other grid (the stencils of the voxels in the root's (u, v, n), i.e. with the
+  full aperture's rectangle), the depth-1 grids are built from its points, and
+  one more single-child resample carries it to the voxels.  Where the voxel
+  grid is finer than the full aperture's band needs, that lattice has fewer
+  points than the voxels, so the last merge does fewer interpolations.
 * Conversion (u, v, n) -> (x, y, z).  Newton's method with the analytic
   Jacobian of eq. uvw_xyz, to 1e-12 m, from a boresight starting point.  A
   stencil of a point seen at a grazing angle can reach (u, v, n) beyond the
@@ -242,10 +249,11 @@ class Plan:
     voxels: np.ndarray          # (N_vox, 3)
     dims: tuple
     kernel: str = "lagrange"    # interpolation weights: "lagrange" or "bandlimited"
+    root_grid: bool = False     # the root holds a compressed lattice (see module notes)
 
 
 def build_plan(positions, freqs_hz, origin, pitch, dims, stages, merge_factor,
-               gamma=3.0, taps=4, margin=0, kernel="lagrange"):
+               gamma=3.0, taps=4, margin=0, kernel="lagrange", root_grid=False):
     """Oracle plan: tree, top-down grids and their xyz preimages."""
     from workloads import voxel_centres
 
@@ -257,13 +265,19 @@ def build_plan(positions, freqs_hz, origin, pitch, dims, stages, merge_factor,
     gamma = np.broadcast_to(np.asarray(gamma, float), (3,)).copy()
     if kernel not in ("lagrange", "bandlimited"):
         raise ValueError(f"unknown interpolation kernel {kernel}")
-    plan = Plan(levels, k, kmin, kmax, gamma, int(taps), int(margin), vox, tuple(dims), kernel)
-    for d in range(1, len(levels)):
+    if root_grid and stages < 1:
+        raise ValueError("a root grid needs at least one stage")
+    plan = Plan(levels, k, kmin, kmax, gamma, int(taps), int(margin), vox, tuple(dims), kernel,
+                bool(root_grid))
+    for d in range(0 if root_grid else 1, len(levels)):
         for node in levels[d]:
             if node.empty:
                 continue
-            parent = levels[d - 1][node.parent]
-            ppts = vox if d == 1 else parent.lattice.xyz[parent.lattice.valid]
+            if d == 0 or (d == 1 and not root_grid):
+                ppts = vox
+            else:
+                parent = levels[d - 1][node.parent]
+                ppts = parent.lattice.xyz[parent.lattice.valid]
             t = gamma * G.uvn(ppts, node.rect, kmin, kmax)
             i0, j0, l_lo, l_hi = required_lattice(t, taps, margin)
             off, ijl = enumerate_points(i0, j0, l_lo, l_hi)

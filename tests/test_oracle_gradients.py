@@ -122,3 +122,30 @@ def test_aperture_weights(tiny):
         fm = OH.image(pl, ech, pos - dp, weights=w)
         fd = np.real(np.vdot(g.ravel(), ((fp - fm) / (2 * h)).ravel()))
         assert abs(gp[i, a] - fd) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(gp).max())
+
+
+def test_root_grid_adjoint_and_position_gradient(tiny):
+    """With a root grid (one more merge, then one resample to the voxels): the
+    adjoint identity <A s, g> = <s, A^H g>, and the position gradient against
+    central differences of the image (frozen plan, h = 1e-6 m)."""
+    pl, pos, ech = tiny
+    from oracle import plan as OP
+    from workloads import make_config
+    w = make_config(0)
+    plr = OP.build_plan(pos, w.freqs_hz, np.array([-0.005, -0.005, 0.245]), np.full(3, 2e-3),
+                        (6, 6, 4), 2, 2, (3.0, 3.0, 3.5), 4, root_grid=True)
+    assert plr.levels[0][0].lattice is not None
+    rng = np.random.default_rng(5)
+    s = rng.standard_normal(ech.shape) + 1j * rng.standard_normal(ech.shape)
+    g = rng.standard_normal(plr.dims) + 1j * rng.standard_normal(plr.dims)
+    lhs = np.vdot(g.ravel(), OH.image(plr, s, pos).ravel())
+    rhs = np.vdot(OA.echo_gradient(plr, g, pos).ravel(), s.ravel())
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+    gp = OA.position_gradient(plr, ech, pos, g)
+    h = 1e-6
+    for i, a in ((2, 1), (64, 0), (180, 2)):
+        dp = np.zeros_like(pos)
+        dp[i, a] = h
+        fd = np.real(np.vdot(g.ravel(), ((OH.image(plr, ech, pos + dp) -
+                                          OH.image(plr, ech, pos - dp)) / (2 * h)).ravel()))
+        assert abs(gp[i, a] - fd) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(gp).max())

@@ -168,3 +168,40 @@ def test_bandlimited_kernel_accuracy(small, direct_small):
         e[kern] = 20 * np.log10(OH.nrmse(OH.image(pl, small.echoes, small.positions), direct_small))
     assert e["bandlimited"] <= -35.0
     assert e["bandlimited"] <= e["lagrange"] - 8.0
+
+
+def test_root_grid(small, direct_small):
+    """A compressed lattice at the root (the full-aperture grid) plus one
+    resample to the voxels: its points map back to their (u, v, n) in the full
+    aperture's frame; their values are eq. (4) over every position, compressed
+    with the root's Phi (within the merge error); the image stays within -30 dB
+    of eq. (4) for S = 1, 2 and Q = 2, and its error falls by more than half with
+    T = 6 taps."""
+    for S, Q in ((1, 4), (2, 4), (2, 2)):
+        pl = OP.build_plan(small.positions, small.freqs_hz, small.grid_origin, small.grid_pitch,
+                           small.grid_dims, S, Q, 3.0, 4, root_grid=True)
+        img, vals = OH.image(pl, small.echoes, small.positions, keep=True)
+        assert 20 * np.log10(OH.nrmse(img, direct_small)) <= -30.0, (S, Q)
+        root = pl.levels[0][0]
+        L = root.lattice
+        ok = L.valid
+        back = G.uvn(L.xyz[ok], root.rect, pl.kmin, pl.kmax) * pl.gamma
+        assert np.max(np.abs(back - L.ijl[ok])) < 1e-8
+        # root values: eq. (4) at the points that lie in the scene box, compressed
+        box = np.all((L.xyz[ok] >= small.grid_origin) &
+                     (L.xyz[ok] <= small.grid_origin + (np.array(small.grid_dims) - 1) * small.grid_pitch),
+                     axis=1)
+        q = L.xyz[ok][box]
+        ref = OH.direct_bp(small.positions, small.freqs_hz, small.echoes, q) * \
+            np.exp(-1j * G.phi(q, root.rect, pl.kmin, pl.kmax))
+        assert 20 * np.log10(OH.nrmse(vals[(0, 0)][ok][box], ref)) <= -30.0
+        assert not np.any(vals[(0, 0)][~ok])
+    e = {}
+    for T in (4, 6):
+        pl = OP.build_plan(small.positions, small.freqs_hz, small.grid_origin, small.grid_pitch,
+                           small.grid_dims, 1, 4, 3.0, T, root_grid=True)
+        e[T] = OH.nrmse(OH.image(pl, small.echoes, small.positions), direct_small)
+    assert e[6] < 0.5 * e[4]
+    with pytest.raises(ValueError):
+        OP.build_plan(small.positions, small.freqs_hz, small.grid_origin, small.grid_pitch,
+                      small.grid_dims, 0, 4, 3.0, 4, root_grid=True)
