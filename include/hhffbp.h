@@ -117,17 +117,25 @@ typedef struct {
                                    NULL: unit weights.  Must be finite; read only
                                    during hhffbp_plan.  The gradients follow:
                                    grad_s_i carries w_i, grad_p'_i the weighted sum. */
+    int32_t root_grid;          /* 0: the root's grid is the voxel grid (Sec. IV-A; the
+                                   default).  1: the root also gets a compressed grid
+                                   in the full aperture's (u, v, n), built like every
+                                   other grid; the last merge lands on it and one
+                                   single-child interpolation takes it to the voxels.
+                                   Fewer interpolations where the voxel grid is finer
+                                   than the full aperture's band, at the error of one
+                                   more interpolation.  Needs FACTORIZED with S >= 1. */
 } hhffbp_config;
 
 /* Fill `cfg` with defaults: FACTORIZED, S = 3, Q = 4, gamma = (3, 3, 3.5), T = 4, ES with
  * U = 2 and W = 7, C64 storage, 5 mm slack, device 0, Lagrange interpolation, final-stage
- * staging on.  Pointers and sizes are
+ * staging on, no root grid.  Pointers and sizes are
  * zeroed and must be set by the caller. */
 void hhffbp_config_default(hhffbp_config *cfg);
 
 /*
  * Build a plan (Sec. IV-A): the subarray tree, the sampling grid G of every
- * subarray below the root, the (x, y, z) preimage of every grid point, the
+ * subarray below the root (and of the root with cfg->root_grid), the (x, y, z) preimage of every grid point, the
  * range window and the range-compression matrix, uploaded to `cfg->device`.
  * Runs on the host in float64.  Reads `cfg` and the host arrays it points to
  * only during the call.  On success *out receives a plan that must be released
@@ -195,21 +203,27 @@ typedef struct {
     int64_t n_range_bins;           /* N_r                                      */
     double range_lo, range_step;    /* R_0 and delta R of the profile grid (m); R_0 is a
                                        whole multiple of delta R (samples at b delta R) */
-    int64_t level_points[16];       /* grid points summed over depth d = 1..S   */
+    int64_t level_points[16];       /* grid points summed over depth d = 1..S;
+                                       [0]: the root grid's points (0 without one) */
     int64_t leaf_pairs;             /* sum over leaves of points x positions    */
-    int64_t merge_pairs;            /* (parent point, child) pairs, depths 1..S-1 */
-    int64_t final_pairs;            /* (voxel, child) pairs at the root         */
+    int64_t merge_pairs;            /* (parent point, child) pairs, depths 1..S-1
+                                       (0..S-1 with a root grid)                 */
+    int64_t final_pairs;            /* (voxel, child) pairs at the root (with a
+                                       root grid: voxels, the root its one child) */
     double plan_seconds;            /* host time spent in hhffbp_plan           */
     int32_t storage;                /* storage type of profiles and subimages   */
-    int64_t ws_scales_offset;       /* workspace byte offset of float scale[S+1]:
-                                       stored profiles carry scale[0], depth-d
-                                       subimages scale[d] (1 unless HHFFBP_F16) */
+    int64_t ws_scales_offset;       /* workspace byte offset of float scale[S+1]
+                                       (S+2 with a root grid): stored profiles
+                                       carry scale[0], depth-d subimages scale[d],
+                                       the root grid scale[S+1] (1 unless HHFFBP_F16) */
     int64_t device_bytes;           /* device memory the plan holds (its tables) */
     double model_ms;                /* Sec. IV-B cost model: level-1 BP + interpolation,
                                        with the per-pair costs of hhffbp_config.stages */
     int64_t final_bricks;           /* final stage: voxel bricks of 4 x 4 x 16 */
-    int64_t final_boxed;            /* (brick, depth-1 node) pairs whose stencils fit one
-                                       staged box (the rest read the pencils directly) */
+    int64_t final_boxed;            /* (brick, depth-1 node) pairs (with a root grid:
+                                       (brick, root)) whose stencils fit one staged
+                                       box (the rest read the pencils directly)  */
+    int32_t root_grid;              /* the plan's cfg->root_grid                */
 } hhffbp_plan_info;
 
 hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info);
@@ -224,7 +238,8 @@ hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info);
  * *ws_offset + size * point, multiplied by the depth's scale (see
  * hhffbp_plan_info.ws_scales_offset).  Arrays may be
  * NULL to query sizes only; otherwise they must hold ni * nj entries.
- * Depth 0 is the user grid and has no lattice (HHFFBP_E_INVALID); an empty
+ * Depth 0 is the root: with cfg->root_grid its grid is node (0, 0); without,
+ * the root's grid is the user grid and has no lattice (HHFFBP_E_INVALID); an empty
  * node reports npoints = 0.
  */
 hhffbp_status hhffbp_node_layout(hhffbp_plan_t plan, int32_t depth, int32_t index,

@@ -37,7 +37,7 @@ class Config(ctypes.Structure):
         ("range_taps", ctypes.c_int32), ("storage", ctypes.c_int32),
         ("position_slack", ctypes.c_double), ("device", ctypes.c_int32),
         ("interp_kernel", ctypes.c_int32), ("final_staging", ctypes.c_int32),
-        ("weights", ctypes.POINTER(ctypes.c_double)),
+        ("weights", ctypes.POINTER(ctypes.c_double)), ("root_grid", ctypes.c_int32),
     ]
 
 
@@ -53,6 +53,7 @@ class PlanInfo(ctypes.Structure):
         ("storage", ctypes.c_int32), ("ws_scales_offset", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64), ("model_ms", ctypes.c_double),
         ("final_bricks", ctypes.c_int64), ("final_boxed", ctypes.c_int64),
+        ("root_grid", ctypes.c_int32),
     ]
 
 
@@ -133,7 +134,7 @@ class Plan:
                  interp_taps=4,
                  range_kernel="es", range_oversample=2.0, range_taps=7, storage="c64",
                  position_slack=5e-3, device=0, interp_kernel="lagrange", final_staging=True,
-                 weights=None):
+                 weights=None, root_grid=False):
         L = lib()
         self._pos = np.ascontiguousarray(positions, np.float64)
         self._freqs = np.ascontiguousarray(freqs_hz, np.float64)
@@ -163,6 +164,7 @@ class Plan:
         c.device = int(device)
         c.interp_kernel = INTERP_KERNELS[interp_kernel]
         c.final_staging = 1 if final_staging else 0
+        c.root_grid = 1 if root_grid else 0
         if weights is not None:
             self._w = np.ascontiguousarray(weights, np.float64)
             if self._w.shape != (self._pos.shape[0],):
@@ -338,8 +340,11 @@ class Plan:
         if st == STORAGE["c64"]:
             return workspace[o:o + 8 * n].view(torch.complex64)
         dt = torch.float16 if st == STORAGE["f16"] else torch.bfloat16
-        so = self.info()["ws_scales_offset"]
-        scale = workspace[so + 4 * depth:so + 4 * depth + 4].view(torch.float32)
+        info = self.info()
+        so = info["ws_scales_offset"]
+        # the root grid's scale follows the depths' (slot S + 1); slot 0 is the profiles'
+        slot = info["stages"] + 1 if depth == 0 else depth
+        scale = workspace[so + 4 * slot:so + 4 * slot + 4].view(torch.float32)
         v = workspace[o:o + 4 * n].view(dt).reshape(n, 2).to(torch.float32)
         return torch.view_as_complex(v.contiguous()) / scale
 

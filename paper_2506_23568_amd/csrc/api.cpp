@@ -48,6 +48,7 @@ void hhffbp_config_default(hhffbp_config *cfg)
     cfg->interp_kernel = HHFFBP_INTERP_LAGRANGE;
     cfg->final_staging = 1;
     cfg->weights = nullptr;
+    cfg->root_grid = 0;
 }
 
 hhffbp_status hhffbp_plan(const hhffbp_config *cfg, hhffbp_plan_t *out)
@@ -175,7 +176,7 @@ hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info)
     info->n_range_bins = P.Nr;
     info->range_lo = P.R0;
     info->range_step = P.dR;
-    for (int d = 1; d <= P.S && d < 16; ++d) info->level_points[d] = P.depth_points[d];
+    for (int d = P.F; d <= P.S && d < 16; ++d) info->level_points[d] = P.depth_points[d];
     info->leaf_pairs = P.leaf_pairs;
     info->merge_pairs = P.merge_pairs;
     info->final_pairs = P.final_pairs;
@@ -186,12 +187,13 @@ hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info)
     info->final_bricks = P.n_bricks;
     info->final_boxed = P.n_tiled;
     info->ws_scales_offset = (int64_t)P.ws_scales;
+    info->root_grid = P.F == 0 ? 1 : 0;
     return HHFFBP_OK;
 }
 
 static const hh::HostNode *find_node(const hh::Plan &P, int32_t depth, int32_t index)
 {
-    if (depth < 1 || depth > P.S) return nullptr;
+    if (depth < P.F || depth > P.S) return nullptr;
     if (index < 0 || index >= (int32_t)P.levels[depth].size()) return nullptr;
     return &P.levels[depth][index];
 }

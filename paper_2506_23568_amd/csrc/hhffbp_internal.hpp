@@ -133,19 +133,22 @@ struct DeviceBuffers {
     void *leafpts = nullptr;        // LeafPoint[] of depth S
     void *leaf_blocks = nullptr;    // BlockItem[]
     void *leaf_wins = nullptr;      // BinWindow[], one per leaf block
-    void *final_tiles = nullptr;    // TileBox[n_bricks][n depth-1 nodes]
+    void *final_tiles = nullptr;    // TileBox[n_bricks][n nodes at depth F]
     void *adj_blocks = nullptr;     // BlockItem[]: (leaf, first sorted position of 16)
     void *Bd = nullptr;             // range-derivative matrix (rows x j 2 k_f), [2 Nf][2 Nr]
     void *Badj = nullptr;           // conj-transposed DFT matrix, [2 Nr][2 Nf]
-    void *scale_mult = nullptr;     // float [S + 1]: worst-case gain from echoes to each stage
-    std::vector<void *> merge_blocks;  // per depth 1..S-1: BlockItem[] of 256 points (adjoint)
-    std::vector<void *> merge_blocks_fwd;  // per depth 1..S-1: BlockItem[] of 256 / Q points
-    std::vector<void *> merge_bricks;      // per depth 1..S-1: MergeBrick[] (merge adjoint)
+    void *scale_mult = nullptr;     // float [n_scales()]: worst-case gain from echoes to each stage
+    std::vector<void *> merge_blocks;  // per depth F..S-1: BlockItem[] of 256 points (adjoint)
+    std::vector<void *> merge_blocks_fwd;  // per depth F..S-1: BlockItem[] of 256 / Q points
+    std::vector<void *> merge_bricks;      // per depth F..S-1: MergeBrick[] (merge adjoint)
 };
 
 struct Plan {
     hhffbp_config cfg{};
     int S = 0, Q = 4, T = 4;
+    // first depth with a grid: 1, or 0 when the root holds a compressed grid of
+    // its own (then the final stage resamples that one node onto the voxels)
+    int F = 1;
     double gamma[3] = {3, 3, 3};
     // band
     std::vector<double> k;
@@ -178,7 +181,7 @@ struct Plan {
     int64_t leaf_pairs = 0, merge_pairs = 0, final_pairs = 0;
     // workspace layout (bytes)
     size_t ws_prof = 0, ws_posoff = 0, ws_total = 0;
-    size_t ws_scales = 0, ws_amax = 0;  // per-call storage scales (float [S + 1]) and max |echo|
+    size_t ws_scales = 0, ws_amax = 0;  // per-call storage scales (float [n_scales()]) and max |echo|
     size_t ws_gprof = 0, ws_gpos = 0, ws_gmax = 0, ws_total_bwd = 0;  // backward additions
     size_t device_bytes = 0;  // plan tables uploaded to the device (owned by the plan)
     double leaf_reach = 0.0;  // max |p' - c| over leaf members and their leaf centres c (z = 0), plus slack
@@ -195,6 +198,10 @@ struct Plan {
     int prof_max_calls = 0, prof_calls = 0;
     std::vector<std::string> stage_names() const;
     int64_t n_vox() const { return cfg.grid_dims[0] * cfg.grid_dims[1] * cfg.grid_dims[2]; }
+    // storage-scale slot of depth d's subimages: d, except S + 1 for the root grid
+    // (slot 0 belongs to the profiles)
+    int scale_slot(int d) const { return d == 0 ? S + 1 : d; }
+    int n_scales() const { return S + 1 + (F == 0 ? 1 : 0); }
 };
 
 // Plan construction (host, float64).  Throws hh::Error on failure.

@@ -16,7 +16,7 @@
 // Echoes, profiles and subimages may be stored as half or bfloat16 pairs
 // (template parameter ST); every sum is float32.  With IEEE half each stage's
 // array carries a power-of-two scale, scales[0] for the profiles and scales[d]
-// for depth d, chosen per call from the largest echo component and the plan's
+// for depth d (scales[S + 1] for a root grid), chosen per call from the largest echo component and the plan's
 // worst-case gain of each stage, so that no stored value can exceed 2^15.
 #include <algorithm>
 #include <hip/hip_runtime.h>
@@ -345,8 +345,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
                                                   const ColEntry *__restrict__ ccols,
                                                   const typename Store<ST>::C *__restrict__ cvals,
                                                   GeoParams gp, const InterpPoly ip,
-                                                  const float *__restrict__ scales, int d,
-                                                  typename Store<ST>::C *__restrict__ out)
+                                                  const float *__restrict__ scales, int sp,
+                                                  int sc, typename Store<ST>::C *__restrict__ out)
 {
     __shared__ float2 part[kBlock];
     // the wave index is uniform: readfirstlane lets the child's fields be scalar loads
@@ -383,12 +383,13 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
             sre += q.x;
             sim += q.y;
         }
-        const float rs = scales[d] / scales[d + 1];
+        const float rs = scales[sp] / scales[sc];
         out[gi] = Store<ST>::st(make_float2(rs * sre, rs * sim));
     }
 }
 
-// Final stage: user voxels, children are the depth-1 nodes; one lane per voxel,
+// Final stage: user voxels, children are the depth-1 nodes (or the root's own
+// grid, then the only child); scales[sc] is their storage scale.  One lane per voxel,
 // a block per brick of kBrickX x kBrickY x kBrickZ voxels (lane t: z = t mod 16
 // fastest, then y, then x).  Per child, the block first stages the child's
 // values over the brick's stencil box (TileBox, from the plan) into LDS, dense
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
                                                   const typename Store<ST>::C *__restrict__ cvals,
                                                   const TileBox *__restrict__ tiles,
                                                   GeoParams gp, const InterpPoly ip,
-                                                  const float *__restrict__ scales,
+                                                  const float *__restrict__ scales, int sc,
                                                   double ox, double oy, double oz, double sx,
                                                   double sy, double sz, int nx, int ny, int nz,
                                                   float2 *__restrict__ image)
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
         }
     }
     if (inside) {
-        const float rs = 1.0f / scales[1];
+        const float rs = 1.0f / scales[sc];
         image[((size_t)ix * ny + iy) * nz + iz] = make_float2(rs * are, rs * aim);
     }
 }
@@ -769,7 +770,7 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
 {
     using C = typename Store<ST>::C;
     GeoParams gp{P.gamma[0], P.gamma[1], P.gamma[2], P.kmin, P.kmax};
-    for (int d = P.S - 1; d >= 1; --d) {
+    for (int d = P.S - 1; d >= P.F; --d) {
         if (P.n_blocks_merge_fwd[d] > 0) {
             hipLaunchKernelGGL((k_merge<T, ST, K, CL>), dim3(P.n_blocks_merge_fwd[d]), dim3(kBlock),
                                0, st, (const NodeDev *)P.dev.nodes[d],
@@ -777,8 +778,8 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
                                (const double *)P.dev.py[d], (const double *)P.dev.pz[d],
                                (const NodeDev *)P.dev.nodes[d + 1],
                                (const ColEntry *)P.dev.cols[d + 1],
-                               (const C *)(ws + P.ws_vals[d + 1]), gp, P.ipoly, scales, d,
-                               (C *)(ws + P.ws_vals[d]));
+                               (const C *)(ws + P.ws_vals[d + 1]), gp, P.ipoly, scales,
+                               P.scale_slot(d), P.scale_slot(d + 1), (C *)(ws + P.ws_vals[d]));
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -789,9 +790,9 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
     const int64_t nv = (int64_t)nx * ny * nz;
     (void)nv;
     hipLaunchKernelGGL((k_final<T, ST, K>), dim3(P.n_bricks), dim3(kBlock), 0, st,
-                       (const NodeDev *)P.dev.nodes[1], (int)P.compact_to_tree[1].size(),
-                       (const ColEntry *)P.dev.cols[1], (const C *)(ws + P.ws_vals[1]),
-                       (const TileBox *)P.dev.final_tiles, gp, P.ipoly, scales,
+                       (const NodeDev *)P.dev.nodes[P.F], (int)P.compact_to_tree[P.F].size(),
+                       (const ColEntry *)P.dev.cols[P.F], (const C *)(ws + P.ws_vals[P.F]),
+                       (const TileBox *)P.dev.final_tiles, gp, P.ipoly, scales, P.scale_slot(P.F),
                        c.grid_origin[0], c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0],
                        c.grid_pitch[1], c.grid_pitch[2], nx, ny, nz, (float2 *)image);
     hipError_t e = hipGetLastError();
@@ -815,7 +816,7 @@ hipError_t launch_scales(const Plan &P, const void *echoes, char *ws, hipStream_
 {
     float *scales = (float *)(ws + P.ws_scales);
     uint32_t *amax = (uint32_t *)(ws + P.ws_amax);
-    const int ns = P.S + 1;
+    const int ns = P.n_scales();
     if (ST == HHFFBP_F16) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, st, amax);
         const int64_t n = 2 * P.cfg.n_pos * P.cfg.n_freq;
@@ -853,7 +854,7 @@ hhffbp_status image_for_storage(const Plan &P, const void *echoes, const double 
         hipLaunchKernelGGL(k_prep_positions, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
                            pos64, (const int32_t *)P.dev.perm, (const int32_t *)P.dev.leaf_of_sorted,
                            (const double *)P.dev.leaf_centre, n, posoff,
-                           fused_ones ? (float *)(ws + P.ws_scales) : nullptr, P.S + 1);
+                           fused_ones ? (float *)(ws + P.ws_scales) : nullptr, P.n_scales());
         if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
         if (ev) (void)hipEventRecord(*ev++, st);
     }
@@ -934,7 +935,7 @@ std::vector<std::string> Plan::stage_names() const
         n = {"rc_gemm", "direct_bp"};
     } else {
         n = {"prep_positions", "rc_gemm", "leaf_bp"};
-        for (int d = S - 1; d >= 1; --d) n.push_back("merge_d" + std::to_string(d));
+        for (int d = S - 1; d >= F; --d) n.push_back("merge_d" + std::to_string(d));
         n.push_back("final");
     }
     return n;

@@ -8,7 +8,8 @@
 // with the plan frozen: only the level-1 BP depends on the positions.
 //
 //   k_zero        clear the cotangent arrays (a kernel, never a memset)
-//   k_final_adj   F^H: scatter voxel cotangents into depth-1 grids (float atomics)
+//   k_final_adj   F^H: scatter voxel cotangents into the depth-1 grids, or the
+//                 root grid when the plan has one (float atomics)
 //   k_merge_adj   M_d^H: scatter parent-grid cotangents into the children
 //   k_leaf_adj    L^H and the position gradient: one block per 16 positions of a
 //                 leaf, looping over all its grid points; the range-profile
@@ -566,12 +567,13 @@ hipError_t launch_scatters(const Plan &P, const void *grad_image, char *ws, hipS
     const int64_t nv = (int64_t)nx * ny * nz;
     const unsigned ntile = (unsigned)(((nx + 3) / 4) * ((ny + 7) / 8) * ((nz + 7) / 8));
     (void)nv;
-    hipLaunchKernelGGL((k_final_adj<T, K>), dim3(ntile), dim3(kBlock), 0, st, (const NodeDev *)P.dev.nodes[1], (int)P.compact_to_tree[1].size(),
-                       (const ColEntry *)P.dev.cols[1], (float2 *)(ws + P.ws_gvals[1]), gp,
+    hipLaunchKernelGGL((k_final_adj<T, K>), dim3(ntile), dim3(kBlock), 0, st,
+                       (const NodeDev *)P.dev.nodes[P.F], (int)P.compact_to_tree[P.F].size(),
+                       (const ColEntry *)P.dev.cols[P.F], (float2 *)(ws + P.ws_gvals[P.F]), gp,
                        P.ipoly, c.grid_origin[0], c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0],
                        c.grid_pitch[1], c.grid_pitch[2], nx, ny, nz, (const float2 *)grad_image);
     hipError_t e = hipGetLastError();
-    for (int d = 1; d < P.S && e == hipSuccess; ++d) {
+    for (int d = P.F; d < P.S && e == hipSuccess; ++d) {
         const int64_t nb = (int64_t)P.merge_bricks[d].size();
         if (nb == 0) continue;
         hipLaunchKernelGGL((k_merge_adj<T, K>), dim3(nb), dim3(kBlock), 0, st,
@@ -610,11 +612,11 @@ hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *p
                            (float *)dprof, nullptr, st, (const float *)P.dev.weights, nullptr);
         if (e != hipSuccess) return HHFFBP_E_DEVICE;
     }
-    // clear every grid cotangent: depths 1..S are contiguous and end at the
+    // clear every grid cotangent: depths F..S are contiguous and end at the
     // 256-byte aligned start of gprof (a point count may be odd, so the float4
     // clear runs to that aligned end rather than to the last point)
     {
-        const size_t b0 = P.ws_gvals[1];
+        const size_t b0 = P.ws_gvals[P.F];
         const size_t b1 = P.ws_gprof;
         const int64_t n4 = (int64_t)((b1 - b0) / sizeof(float4));
         hipLaunchKernelGGL(k_zero, dim3(1024), dim3(kBlock), 0, st, (float4 *)(ws + b0), n4);

@@ -337,7 +337,7 @@ void build_lattice(Plan &P, HostNode &node, const std::vector<double> &parent_al
     L.n_absent = absent.load();
 }
 
-// Final-stage boxes: per voxel brick and depth-1 node, the bounding box of the
+// Final-stage boxes: per voxel brick and node of depth F, the bounding box of the
 // stencils (base floor(gamma w + eps) - T/2 + 1 .. + T/2) of the brick's voxels,
 // widened by one index for rounding (the kernel evaluates w in float64 with a
 // ~2e-14 relative square root) and clipped to the node's columns.
@@ -347,21 +347,21 @@ void build_final_tiles(Plan &P)
     const int64_t nx = c.grid_dims[0], ny = c.grid_dims[1], nz = c.grid_dims[2];
     const int64_t bx = (nx + kBrickX - 1) / kBrickX, by = (ny + kBrickY - 1) / kBrickY,
                   bz = (nz + kBrickZ - 1) / kBrickZ;
-    const std::vector<int32_t> &d1 = P.compact_to_tree[1];
+    const std::vector<int32_t> &d1 = P.compact_to_tree[P.F];
     const int64_t nc = (int64_t)d1.size();
     P.n_bricks = bx * by * bz;
     P.final_tiles.assign(P.n_bricks * nc, TileBox{0, 0, 0, 0, 0, 0, 0, 0});
     P.n_tiled = 0;
     if (!c.final_staging) return;
     std::vector<SubarrayMap> maps;
-    for (int32_t ti : d1) maps.emplace_back(P.levels[1][ti].rect, P.kmin, P.kmax);
+    for (int32_t ti : d1) maps.emplace_back(P.levels[P.F][ti].rect, P.kmin, P.kmax);
     const int T = P.T, slo = -(T / 2) + 1 - 1, shi = T / 2 + 1;
     std::atomic<int64_t> tiled{0};
     parallel_for(P.n_bricks, 16, [&](int64_t b0, int64_t b1) {
         for (int64_t b = b0; b < b1; ++b) {
             const int64_t kx = b / (by * bz), ky = (b / bz) % by, kz = b % bz;
             for (int64_t ch = 0; ch < nc; ++ch) {
-                const HostLattice &L = P.levels[1][d1[ch]].lat;
+                const HostLattice &L = P.levels[P.F][d1[ch]].lat;
                 int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
                 for (int64_t ix = kx * kBrickX; ix < std::min(nx, (kx + 1) * kBrickX); ++ix)
                     for (int64_t iy = ky * kBrickY; iy < std::min(ny, (ky + 1) * kBrickY); ++iy)
@@ -633,6 +633,9 @@ void validate(const hhffbp_config &c)
     if (c.merge_factor != 2 && c.merge_factor != 4) bad("merge_factor must be 2 or 4");
     if (c.interp_taps != 4 && c.interp_taps != 6) bad("interp_taps must be 4 or 6");
     if (c.final_staging != 0 && c.final_staging != 1) bad("final_staging must be 0 or 1");
+    if (c.root_grid != 0 && c.root_grid != 1) bad("root_grid must be 0 or 1");
+    if (c.root_grid && (c.mode != HHFFBP_FACTORIZED || c.stages == 0))
+        bad("a root grid needs the factorised mode with stages != 0");
     if (c.interp_kernel != HHFFBP_INTERP_LAGRANGE && c.interp_kernel != HHFFBP_INTERP_BANDLIMITED)
         bad("unknown interpolation kernel");
     if (c.range_kernel == HHFFBP_RANGE_ES) {
@@ -706,6 +709,7 @@ void build_plan_host(Plan &P)
     const hhffbp_config &c = P.cfg;
     validate(c);
     P.S = (c.mode == HHFFBP_FACTORIZED) ? c.stages : 0;
+    P.F = (c.root_grid && P.S > 0) ? 0 : 1;
     P.Q = c.merge_factor;
     P.T = c.interp_taps;
     for (int a = 0; a < 3; ++a) P.gamma[a] = c.oversample[a];
@@ -751,12 +755,12 @@ void build_plan_host(Plan &P)
     }
     // grid points whose preimage lies below half the lowest voxel plane are absent
     P.z_valid = 0.5 * c.grid_origin[2];
-    // grids, top-down: depth d needs the points of depth d - 1
-    for (int d = 1; d <= S; ++d) {
+    // grids, top-down: depth d needs the points of depth d - 1, depth F the voxels
+    for (int d = P.F; d <= S; ++d) {
         for (auto &node : P.levels[d]) {
             if (node.empty()) continue;
             const std::vector<double> &ppts =
-                (d == 1) ? vox : P.levels[d - 1][node.parent].lat.xyz;
+                (d == P.F) ? vox : P.levels[d - 1][node.parent].lat.xyz;
             build_lattice(P, node, ppts);
         }
     }
@@ -855,19 +859,19 @@ void build_plan_host(Plan &P)
             const HostNode &lf = P.levels[S][ti];
             P.leaf_pairs += lf.lat.npts * (int64_t)lf.members.size();
         }
-        for (int d = 1; d < S; ++d)
+        for (int d = P.F; d < S; ++d)
             for (int32_t ti : P.compact_to_tree[d]) {
                 const HostNode &nd = P.levels[d][ti];
                 int nch = 0;
                 for (int32_t ch : nd.children) nch += P.levels[d + 1][ch].empty() ? 0 : 1;
                 P.merge_pairs += nd.lat.npts * nch;
             }
-        P.final_pairs = P.n_vox() * (int64_t)P.compact_to_tree[1].size();
+        P.final_pairs = P.n_vox() * (int64_t)P.compact_to_tree[P.F].size();
     }
     P.model_s = model_seconds(P);
     if (S > 0) build_final_tiles(P);  // with final_staging = 0 every box is left empty
     P.merge_bricks.assign(S + 1, {});
-    for (int d = 1; d < S; ++d) build_merge_bricks(P, d);
+    for (int d = P.F; d < S; ++d) build_merge_bricks(P, d);
 
     // workspace layout; profiles and subimages in the storage type
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -882,13 +886,13 @@ void build_plan_host(Plan &P)
     P.ws_amax = off;
     off += al(sizeof(uint32_t));
     P.ws_vals.assign(S + 1, 0);
-    for (int d = 1; d <= S; ++d) {
+    for (int d = P.F; d <= S; ++d) {
         P.ws_vals[d] = off;
         off += al((size_t)P.depth_points[d] * csz);
     }
     P.ws_total = off;
     P.ws_gvals.assign(S + 1, 0);
-    for (int d = 1; d <= S; ++d) {
+    for (int d = P.F; d <= S; ++d) {
         P.ws_gvals[d] = off;
         off += al((size_t)P.depth_points[d] * 8);
     }
@@ -924,7 +928,7 @@ void build_plan_host(Plan &P)
             }
             lt *= la;
         }
-        P.scale_mult.assign(S + 1, 0.0f);
+        P.scale_mult.assign(P.n_scales(), 0.0f);
         const double m0 = std::sqrt(2.0) * (double)c.n_freq * wmax;
         P.scale_mult[0] = (float)m0;
         if (S > 0) {
@@ -932,11 +936,11 @@ void build_plan_host(Plan &P)
             for (int32_t ti : P.compact_to_tree[S]) mem_max = std::max(mem_max, P.levels[S][ti].members.size());
             double m = m0 * (double)mem_max * (double)P.W;
             P.scale_mult[S] = (float)m;
-            for (int d = S - 1; d >= 1; --d) {
+            for (int d = S - 1; d >= P.F; --d) {
                 size_t nch = 0;
                 for (int32_t ti : P.compact_to_tree[d]) nch = std::max(nch, P.levels[d][ti].children.size());
                 m *= (double)nch * lt;
-                P.scale_mult[d] = (float)m;
+                P.scale_mult[P.scale_slot(d)] = (float)m;
             }
         }
     }
@@ -1002,7 +1006,7 @@ void upload_plan(Plan &P)
     }
     if (S == 0) return;
     int32_t pos_cursor = 0;
-    for (int d = 1; d <= S; ++d) {
+    for (int d = P.F; d <= S; ++d) {
         std::vector<NodeDev> nodes;
         std::vector<ColEntry> cols;
         std::vector<BlockItem> blocks, blocks_fwd;

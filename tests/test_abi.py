@@ -39,7 +39,7 @@ def test_config_default_layout():
     assert list(c.oversample) == [3.0, 3.0, 3.5]
     assert (c.range_kernel, c.range_taps, c.storage, c.device) == (0, 7, 0, 0)
     assert c.range_oversample == 2.0 and abs(c.position_slack - 5e-3) < 1e-15
-    assert (c.interp_kernel, c.final_staging) == (0, 1)
+    assert (c.interp_kernel, c.final_staging, c.root_grid) == (0, 1, 0)
 
 
 def test_final_stage_bricks(small):
@@ -61,6 +61,7 @@ def _args(w):
 @pytest.mark.parametrize("change,status", [
     (dict(merge_factor=3), -1), (dict(interp_taps=5), -1), (dict(range_taps=11), -1),
     (dict(oversample=0.5), -1), (dict(stages=-9), -1),
+    (dict(root_grid=True, mode="direct_rc"), -1), (dict(root_grid=True, stages=0), -1),
 ])
 def test_invalid_configurations_are_rejected(small, change, status):
     kw = dict(device=-1)
@@ -140,15 +141,23 @@ def test_host_only_plan_refuses_image(small):
         pl.node_layout(2, 0)
 
 
-@pytest.mark.parametrize("S,Q,gamma,T", [(1, 4, 3.0, 4), (2, 4, 3.0, 4), (2, 2, (2.5, 2.5, 3.0), 6)])
-def test_host_plan_matches_oracle_plan(small, S, Q, gamma, T):
+@pytest.mark.parametrize("S,Q,gamma,T,root", [
+    (1, 4, 3.0, 4, False), (2, 4, 3.0, 4, False), (2, 2, (2.5, 2.5, 3.0), 6, False),
+    (1, 4, 3.0, 4, True), (2, 2, (2.5, 2.5, 3.0), 4, True),
+])
+def test_host_plan_matches_oracle_plan(small, S, Q, gamma, T, root):
     from oracle import plan as OP
 
-    pl = H.Plan(*_args(small), stages=S, merge_factor=Q, oversample=gamma, interp_taps=T, device=-1)
-    op = OP.build_plan(*_args(small), S, Q, gamma, T)
+    pl = H.Plan(*_args(small), stages=S, merge_factor=Q, oversample=gamma, interp_taps=T,
+                device=-1, root_grid=root)
+    op = OP.build_plan(*_args(small), S, Q, gamma, T, root_grid=root)
     info = pl.info()
     assert info["n_leaves"] == sum(1 for n in op.levels[S] if not n.empty)
-    for d in range(1, S + 1):
+    assert info["root_grid"] == int(root)
+    if root:
+        assert info["level_points"][0] == op.levels[0][0].lattice.size
+        assert info["final_pairs"] == int(np.prod(small.grid_dims))
+    for d in range(0 if root else 1, S + 1):
         for i, node in enumerate(op.levels[d]):
             lay = pl.node_layout(d, i)
             if node.empty:
