@@ -156,6 +156,8 @@ def autofocus_report(args):
               interp_kernel="bandlimited")
     if args.af_range == "linear":
         kw.update(range_kernel="linear", range_oversample=8.0)
+    if args.af_root_grid == "on":
+        kw.update(root_grid=True)
     pos_true = torch.from_numpy(w.positions).cuda()
     pos0 = torch.from_numpy(p_img.copy()).cuda()
     ech64 = torch.from_numpy(w.echoes.astype(np.complex64)).cuda()
@@ -195,7 +197,7 @@ def autofocus_report(args):
                                "slab, smooth trajectory error, S=3 Q=4, 20 Adam steps (lr 0.03 mm) on 16 cosine modes per axis, relative-L2 loss to the clean-trajectory image",
                    "range_kernel": "linear U=8" if args.af_range == "linear" else "ES U=2 W=7",
                    "interp_kernel": "bandlimited", "oversample": list(BENCH_GAMMA),
-                   "parallelism": "single GPU"},
+                   "root_grid": args.af_root_grid == "on", "parallelism": "single GPU"},
         "storage": out,
         "reference": "float32 direct BP (ES U=2 W=7) at the true positions, full grid"}), flush=True)
 
@@ -281,6 +283,10 @@ def main():
                     help="run one plain copy of this size first (HBM counter scale)")
     ap.add_argument("--af-range", choices=("es", "linear"), default="linear",
                     help="range kernel of the autofocus workload's images")
+    ap.add_argument("--af-root-grid", choices=("on", "off"), default="on",
+                    help="autofocus workload: plans with a compressed root grid (the "
+                         "last merge onto the full aperture's lattice, one resample to "
+                         "the voxels)")
     ap.add_argument("--workload", choices=["mid", "autofocus", "paper_sim"], default="mid",
                     help="mid: the imaging benchmark (default); autofocus: the trajectory "
                          "correction loop on the large scene; paper_sim: the paper's "
@@ -350,6 +356,10 @@ def main():
     plan_lg = H.Plan(*args3, stages=3, merge_factor=4, oversample=GAMMA, interp_taps=TAPS,
                      range_kernel="linear", range_oversample=8.0)
     ms_lg, kernels_lg, img_lg = timed(plan_lg, max(3, args.steps // 2), 1)
+    # the benchmarked form with a compressed root grid and one resample to the voxels
+    plan_rg = H.Plan(*args3, range_kernel="linear", range_oversample=8.0, root_grid=True, **kw)
+    ms_rg, kernels_rg, img_rg = timed(plan_rg, max(3, args.steps // 2), 1)
+    info_rg = plan_rg.info()
     ref_plan = H.Plan(*args3, mode="direct_rc", range_kernel="es", range_oversample=2.0,
                       range_taps=7)
     ref = ref_plan.image(ech)
@@ -358,6 +368,7 @@ def main():
     nrmse = (torch.linalg.norm(img - ref) / nref).item()
     nrmse_es = (torch.linalg.norm(img_es - ref) / nref).item()
     nrmse_lg = (torch.linalg.norm(img_lg - ref) / nref).item()
+    nrmse_rg = (torch.linalg.norm(img_rg - ref) / nref).item()
     fast = H.Plan(*args3, mode="direct_rc", range_kernel="linear", range_oversample=8.0)
     dimg = fast.image(ech)
     torch.cuda.synchronize()
@@ -425,6 +436,13 @@ def main():
                             "mode": "Lagrange weights, gamma (3, 3, 3.5), linear U=8",
                             "kernels_ms": kernels_lg,
                             "nrmse_vs_direct_db": 20 * np.log10(nrmse_lg)},
+        "hhffbp_root_grid": {"value": w.n_vox * w.n_pos / (ms_rg * 1e-3), "ms": ms_rg,
+                             "mode": "benchmarked form with a compressed root grid",
+                             "kernels_ms": kernels_rg,
+                             "nrmse_vs_direct_db": 20 * np.log10(nrmse_rg),
+                             "root_points": info_rg["level_points"][0],
+                             "merge_pairs": info_rg["merge_pairs"],
+                             "final_pairs": info_rg["final_pairs"]},
         "direct_bp": {"value": direct_vp, "unit": "vp/s", "ms": dms, "mode": "linear U=8",
                       "nrmse_vs_es_direct_db": 20 * np.log10(d_nrmse)},
         "direct_exact": {"value": w.n_vox * w.n_pos / (ex_ms * 1e-3), "unit": "vp/s", "ms": ex_ms,

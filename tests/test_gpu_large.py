@@ -160,6 +160,42 @@ def test_large_direct_leaf_and_hhffbp(torch, large, gold):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("form", ["lagrange", "bandlimited"])
+def test_large_root_grid(torch, large, gold, form):
+    """A compressed root grid with one resample to the voxels, in the parity
+    form (Lagrange, gamma (3, 3, 3.5), ES range kernel) and in the autofocus
+    benchmark's form (band-limited, gamma (2.2, 2.2, 2.6), linear range kernel at
+    U = 8): <= -30 dB against eq. (4) on the stored sample and against GPU direct
+    BP on the full grid, and the isolated peaks where the float64 gap exceeds 1%."""
+    w = large
+    if form == "lagrange":
+        kw = dict(oversample=GAMMA)
+    else:
+        kw = dict(oversample=(2.2, 2.2, 2.6), interp_kernel="bandlimited",
+                  range_kernel="linear", range_oversample=8.0)
+    pl = H.Plan(*_args(w), stages=3, merge_factor=4, interp_taps=TAPS, root_grid=True, **kw)
+    ech = _ech(torch, w)
+    img = pl.image(ech)
+    img_d = H.Plan(*_args(w), mode="direct_rc").image(ech)
+    torch.cuda.synchronize()
+    idx = torch.from_numpy(gold["index"]).cuda()
+    hs = img.reshape(-1)[idx].cpu().numpy().astype(np.complex128)
+    uni = gold["uniform"]
+    e_hs = _nrmse(hs, gold["bp"])
+    e_hu = _nrmse(hs[uni], gold["bp"][uni])
+    e_full = (torch.linalg.norm(img - img_d) / torch.linalg.norm(img_d)).item()
+    got, want, amb, bad = _peak_checks(torch, img, gold, w, 1e-2)
+    inf = pl.info()
+    _say(f"  root grid {form}: {inf['level_points'][0]} root points; vs eq.4 sample "
+         f"{20 * np.log10(e_hs):.1f} dB, uniform part {20 * np.log10(e_hu):.1f} dB, full grid "
+         f"vs direct {20 * np.log10(e_full):.1f} dB; peaks {int((got == want).sum())}/{want.size}")
+    assert inf["root_grid"] == 1 and inf["final_pairs"] == int(np.prod(w.grid_dims))
+    assert 20 * np.log10(e_hs) <= -30 and 20 * np.log10(e_hu) <= -30
+    assert 20 * np.log10(e_full) <= -30
+    assert want.size >= 10
+    assert np.array_equal(got, want)
+
+
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 def test_large_half_storage(torch, large, gold, storage):
     w = large
@@ -196,8 +232,8 @@ def test_large_linear_mode_echo_gradient(torch, large):
     assert es <= 5e-3 and ep <= 1e-2
 
 
-@pytest.mark.parametrize("storage", ["f16", "bf16"])
-def test_autofocus_loop(torch, gold, storage):
+@pytest.mark.parametrize("storage,root_grid", [("f16", False), ("bf16", False), ("f16", True)])
+def test_autofocus_loop(torch, gold, storage, root_grid):
     """20 Adam steps (lr 0.03 mm) on a 16-mode cosine motion model of the
     positions of the autofocus workload (the large scene, imaged at positions
     with a smooth trajectory error), relative-L2 loss to the clean-trajectory
@@ -208,7 +244,7 @@ def test_autofocus_loop(torch, gold, storage):
     w = make_config(4, synth_device="cuda")
     p_img = w.imager_positions
     _say(f"  autofocus {storage}: trajectory error max {np.abs(p_img - w.positions).max() * 1e3:.2f} mm")
-    kw = dict(stages=3, merge_factor=4, oversample=GAMMA, interp_taps=TAPS)
+    kw = dict(stages=3, merge_factor=4, oversample=GAMMA, interp_taps=TAPS, root_grid=root_grid)
     pl = H.Plan(*_args(w, p_img), storage=storage, **kw)
     ech = _ech(torch, w, storage)
     pos_true = torch.from_numpy(w.positions).cuda()
@@ -236,7 +272,7 @@ def test_autofocus_loop(torch, gold, storage):
     d0 = (pos0 - pos_true).norm(dim=1).mean().item()
     d1 = (pos - pos_true).norm(dim=1).mean().item()
     ms = np.median([h["ms"] for h in hist[1:]])
-    _say(f"  autofocus {storage}: loss {hist[0]['loss']:.4f} -> {hist[-1]['loss']:.4f}; "
+    _say(f"  autofocus {storage} root grid {root_grid}: loss {hist[0]['loss']:.4f} -> {hist[-1]['loss']:.4f}; "
          f"mean position error {d0 * 1e3:.3f} -> {d1 * 1e3:.3f} mm; image vs clean eq.4 "
          f"{20 * np.log10(first['e']):.1f} -> {20 * np.log10(e_final):.1f} dB; "
          f"{ms:.2f} ms per step; peak device memory {peak / 2**30:.2f} GiB")
