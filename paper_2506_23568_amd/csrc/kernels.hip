@@ -211,6 +211,7 @@ inline int gemm_vec(const void *A, int K, const float *B, int N)
 // chunk's profiles are one contiguous block, widened to float32 on staging).
 // Per (q, i):
 //   Delta R = |q - p'_i| - |q - c| = (|delta|^2 - 2 d.delta) / (|q - p'_i| + |q - c|)
+//   with |q - p'_i| = sqrt(|q - c|^2 + |delta|^2 - 2 d.delta) (one add and a root)
 //   g = sum_w phi_w(t) prof_i[r_first + w],   t = (|q - c| - R0)/dR + Delta R / dR
 //   acc += g exp(j 2 kc Delta R)
 // and f'(q) = acc exp(j (2 kc |q - c| - Phi(q))), the last factor precomputed.
@@ -245,7 +246,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
     const int p = blk.start + threadIdx.x;
     const bool active = p < nd.npts;
     LeafPoint q = active ? pts[nd.val_base + p] : LeafPoint{0, 0, 1, 0, 0, 0, 0, 0};
-    const float Rc = fast_sqrt(q.dx * q.dx + q.dy * q.dy + q.dz * q.dz);
+    const float Rc2 = fmaf(q.dx, q.dx, fmaf(q.dy, q.dy, q.dz * q.dz));
+    const float Rc = fast_sqrt(Rc2);
     const float frac_w = q.frac - 0.5f * W;  // tau = t - W/2 relative to the point's bin
     const int bin1 = q.bin + 1;
     // the block's window holds every tap; clamping tau to [lo, hi] only keeps
@@ -285,11 +287,14 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
         }
         __syncthreads();
         if (active) {
-            for (int i = 0; i < n; ++i) {
+            // two positions per step into two accumulators, so that the two
+            // dependency chains (root, reciprocal, LDS tap reads, sine) overlap
+            auto pair_term = [&](int i, float &are, float &aim) {
                 const float4 d = s_pos[i];
-                const float ex = q.dx - d.x, ey = q.dy - d.y, ez = q.dz - d.z;
-                const float R = fast_sqrt(fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+                // |q - p'|^2 = |q - c|^2 + num: R enters only the denominator, where
+                // float32 rounding of the sum costs ~1e-8 relative of Delta R
                 const float num = fmaf(m2x, d.x, fmaf(m2y, d.y, fmaf(m2z, d.z, d.w)));
+                const float R = fast_sqrt(num + Rc2);
                 const float dR = num * fast_rcp(R + Rc);
                 const float tau = __builtin_amdgcn_fmed3f(fmaf(dR, inv_dR, frac_w), tau_lo, tau_hi);
                 const int r = bin1 - r0 + floor_int(tau);
@@ -315,9 +320,18 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
                 float ph = dR * kc_turns;
                 if constexpr (RED) ph -= rintf(ph);
                 const float sn = sin_turns(ph), cs = cos_turns(ph);
-                acc_re = fmaf(gre, cs, fmaf(-gim, sn, acc_re));
-                acc_im = fmaf(gre, sn, fmaf(gim, cs, acc_im));
+                are = fmaf(gre, cs, fmaf(-gim, sn, are));
+                aim = fmaf(gre, sn, fmaf(gim, cs, aim));
+            };
+            float bre = 0.0f, bim = 0.0f;
+            int i = 0;
+            for (; i + 1 < n; i += 2) {
+                pair_term(i, acc_re, acc_im);
+                pair_term(i + 1, bre, bim);
             }
+            if (i < n) pair_term(i, acc_re, acc_im);
+            acc_re += bre;
+            acc_im += bim;
         }
     }
     if (active) {
@@ -334,7 +348,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
 // wave's gathers stay within one child and follow its points' pencils.  The
 // children's rotated values meet in LDS and are summed in child order.  A
 // launch thus has CL times as many waves as points / 64 to hide the gathers'
-// latency.
+// latency.  Each wave restores its child's downconversion (exp(+j Phi_c));
+// the parent's (exp(-j Phi_P)) is applied once to the sum.
 template <int T, int ST, int K, int CL>
 __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ parents,
                                                   const BlockItem *__restrict__ blocks,
@@ -367,11 +382,10 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
     const bool present = inside && z > 0.0;  // an absent grid point (no preimage) holds 0
     float are = 0.0f, aim = 0.0f;
     if (present && c < nd.nchild) {
-        const double phip = phi_only(nd, x, y, z, gp.kmin, gp.kmax);
         const NodeDev ch = children[parents[blk.node].child[c]];
         const ChildCoord g = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
         const float2 v = interp_child<T, ST, K>(ch, ccols, cvals, g, ip);
-        phase_mac(v, g.phi - phip, are, aim);
+        phase_mac(v, g.phi, are, aim);
     }
     part[threadIdx.x] = make_float2(are, aim);
     __syncthreads();
@@ -383,8 +397,11 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
             sre += q.x;
             sim += q.y;
         }
+        // the parent's own downconversion, once per point rather than per child
+        float ore = 0.0f, oim = 0.0f;
+        if (present) phase_mac(make_float2(sre, sim), -phi_only(nd, x, y, z, gp.kmin, gp.kmax), ore, oim);
         const float rs = scales[sp] / scales[sc];
-        out[gi] = Store<ST>::st(make_float2(rs * sre, rs * sim));
+        out[gi] = Store<ST>::st(make_float2(rs * ore, rs * oim));
     }
 }
 
@@ -536,9 +553,9 @@ __global__ __launch_bounds__(kBlock) void k_direct_bp(
         if (active) {
             for (int i = 0; i < n; ++i) {
                 const StagedPos sp = s_pos[i];
-                const float qx = ex - sp.dx, qy = ey - sp.dy, qz = ez - sp.dz;
-                const float R = fast_sqrt(qx * qx + qy * qy + qz * qz);
+                // |q - p'|^2 = |p' - ref|^2 + num, R only in the denominator
                 const float num = e2 - 2.0f * (ex * sp.dx + ey * sp.dy + ez * sp.dz);
+                const float R = fast_sqrt(fmaf(sp.rref, sp.rref, num));
                 const float dr = num * fast_rcp(R + sp.rref);
                 const float tau = fmaf(dr, inv_dR, sp.frac);
                 const float fl = floorf(tau);
@@ -645,9 +662,9 @@ __global__ __launch_bounds__(kBlock) void k_direct_exact(
         if (active) {
             for (int i = 0; i < n; ++i) {
                 const ExactPos sp = s_pos[i];
-                const float qx = ex - sp.dx, qy = ey - sp.dy, qz = ez - sp.dz;
-                const float R = fast_sqrt(qx * qx + qy * qy + qz * qz);
+                // |q - p'|^2 = |p' - ref|^2 + num, R only in the denominator
                 const float num = e2 - 2.0f * (ex * sp.dx + ey * sp.dy + ez * sp.dz);
+                const float R = fast_sqrt(fmaf(sp.rref, sp.rref, num));
                 const float dr = num * fast_rcp(R + sp.rref);
                 const float2 *cf = s_c + i * n_f;
                 float hre, him;

@@ -424,7 +424,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_adj(
         const float gcre = q.pre_re * G.x + q.pre_im * G.y;
         const float gcim = q.pre_re * G.y - q.pre_im * G.x;
         if (gcre == 0.0f && gcim == 0.0f) continue;
-        const float Rc = fast_sqrt(q.dx * q.dx + q.dy * q.dy + q.dz * q.dz);
+        const float Rc2 = q.dx * q.dx + q.dy * q.dy + q.dz * q.dz;
+        const float Rc = fast_sqrt(Rc2);
         const float frac_w = q.frac - 0.5f * W;
         const int bin1 = q.bin + 1;
 #pragma unroll
@@ -432,8 +433,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf_adj(
             if (i < n) {  // predicated, so every ap[i] index stays a constant
                 const float4 d = s_pos[i];
                 const float ex = q.dx - d.x, ey = q.dy - d.y, ez = q.dz - d.z;
-                const float R = fast_sqrt(ex * ex + ey * ey + ez * ez);
+                // |q - p'|^2 = |q - c|^2 + num (as in the forward level-1 BP)
                 const float num = d.w - 2.0f * (q.dx * d.x + q.dy * d.y + q.dz * d.z);
+                const float R = fast_sqrt(num + Rc2);
                 const float dR = num * fast_rcp(R + Rc);
                 const float tau = fmaf(dR, inv_dR, frac_w);
                 const float fl = floorf(tau);
