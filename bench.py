@@ -34,16 +34,18 @@ BENCH_GAMMA = (2.2, 2.2, 2.6)    # band-limited interpolation grids (the timed f
 TAPS = 4
 # VALU issue peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane-ops/s
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
-# Algorithmic VALU lane-ops of one (leaf grid point, position) backprojection
-# with the 7-tap ES range kernel: num = |d|^2 - 2 q.d 3 (FMA), distance
-# |q - p'| = sqrt(|q|^2 + num) 2 (add, sqrt), Delta R = num / (|q - p'| + |q|)
-# 3 (add, reciprocal, multiply), bin coordinate 4 (FMA, clamp, floor,
-# fraction), kernel weights 6 per tap, tap sums 2 per tap, carrier 3 (scale to
-# turns, sin, cos), complex accumulate 4.
-LEAF_OPS_PER_PAIR = 3 + 2 + 3 + 4 + 6 * 7 + 2 * 7 + 3 + 4
-# ... and with the linear range kernel: the same distance, distance-difference,
-# bin, carrier and accumulate ops; v0 + x (v1 - v0) per component (4).
-LEAF_OPS_LINEAR = 3 + 2 + 3 + 4 + 4 + 3 + 4
+# Algorithmic VALU lane-ops per (leaf grid point, position) backprojection: the
+# fixed per-unit yardstick of the range-compressed form, ~25 VALU + 3
+# transcendentals per pair, itemised as distance |q - p'| 7 (3 differences, 3
+# for the squared norm, sqrt), distance difference 6 (|d|^2 - 2 q.d as 3 FMA,
+# then / (R + R_c) as add, reciprocal, multiply), bin coordinate 4 (FMA, clamp,
+# floor, fraction), range read, carrier 3 (scale to turns, sin, cos), complex
+# accumulate 4.  Range read with the 7-tap ES kernel: weights 6 per tap, tap
+# sums 2 per tap.  (The kernel itself forms |q - p'| from |q - c|^2 plus the
+# distance-difference numerator and issues fewer than this count.)
+LEAF_OPS_PER_PAIR = 7 + 6 + 4 + 6 * 7 + 2 * 7 + 3 + 4
+# ... and with the linear range kernel: v0 + x (v1 - v0) per component (4).
+LEAF_OPS_LINEAR = 7 + 6 + 4 + 4 + 3 + 4
 KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "hhffbp_internal.hpp")
 TRAFFIC_SUMMARY = "hhffbp_mid_hbm_traffic.md"
 
