@@ -310,15 +310,18 @@ def test_mid_config_full_size(torch, mid):
 
 
 # the benchmark's launch configuration: band-limited weights on a coarser grid
-BENCH_GAMMA = (2.2, 2.2, 2.6)
+# (and the autofocus workload's, one step finer)
+BENCH_GAMMA = (2.0, 2.0, 2.4)
+AF_GAMMA = (2.2, 2.2, 2.6)
 
 
-@pytest.mark.parametrize("kernel,gamma", [("lagrange", GAMMA), ("bandlimited", BENCH_GAMMA)])
+@pytest.mark.parametrize("kernel,gamma", [("lagrange", GAMMA), ("bandlimited", BENCH_GAMMA),
+                                          ("bandlimited", AF_GAMMA)])
 def test_mid_fast_range_mode_full_size(torch, mid, kernel, gamma):
     """The fast range mode at full size: 16384 positions, 64 f, 128x128x64
     voxels, S = 3, Q = 4, linear range kernel at U = 8; with Lagrange weights
-    at (3, 3, 3.5) and with the benchmark's band-limited weights at
-    (2.2, 2.2, 2.6).  Level-1 subimages at seeded grid points against the
+    at (3, 3, 3.5) and with band-limited weights at (2.0, 2.0, 2.4), the
+    benchmark's, and (2.2, 2.2, 2.6).  Level-1 subimages at seeded grid points against the
     oracle's level-1 sum of the same form (<= 1e-5); the image against GPU
     direct BP (pinned to eq. (4) by the test above) on the full grid (<= -30 dB)
     with the same isolated peaks; for the Lagrange form also against the stored
