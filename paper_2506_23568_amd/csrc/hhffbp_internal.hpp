@@ -74,6 +74,9 @@ struct BlockItem {
 // of more than kTileCap such values (the kernel then gathers from the pencils).
 constexpr int kBrickX = 4, kBrickY = 4, kBrickZ = 16;
 constexpr int kTileCap = 2048;
+// Positions per block of the level-1 adjoint (one block per leaf and kAdjPos
+// of its leaf-sorted positions).
+constexpr int kAdjPos = 8;
 struct TileBox {
     int32_t i0, j0, l0, ni, nj, nl, lsh, pad;
 };
@@ -134,7 +137,7 @@ struct DeviceBuffers {
     void *leaf_blocks = nullptr;    // BlockItem[]
     void *leaf_wins = nullptr;      // BinWindow[], one per leaf block
     void *final_tiles = nullptr;    // TileBox[n_bricks][n nodes at depth F]
-    void *adj_blocks = nullptr;     // BlockItem[]: (leaf, first sorted position of 16)
+    void *adj_blocks = nullptr;     // BlockItem[]: (leaf, first sorted position of kAdjPos)
     void *Bd = nullptr;             // range-derivative matrix (rows x j 2 k_f), [2 Nf][2 Nr]
     void *Badj = nullptr;           // conj-transposed DFT matrix, [2 Nr][2 Nf]
     void *scale_mult = nullptr;     // float [n_scales()]: worst-case gain from echoes to each stage

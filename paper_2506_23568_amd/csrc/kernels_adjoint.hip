@@ -11,7 +11,7 @@
 //   k_final_adj   F^H: scatter voxel cotangents into the depth-1 grids, or the
 //                 root grid when the plan has one (float atomics)
 //   k_merge_adj   M_d^H: scatter parent-grid cotangents into the children
-//   k_leaf_adj    L^H and the position gradient: one block per 16 positions of a
+//   k_leaf_adj    L^H and the position gradient: one block per kAdjPos positions of a
 //                 leaf, looping over all its grid points; the range-profile
 //                 cotangents accumulate in LDS and the position gradients in
 //                 registers, so each output is written exactly once
@@ -29,7 +29,6 @@ namespace hh {
 namespace {
 using namespace dev;
 
-constexpr int kAdjPos = 16;
 constexpr size_t kLdsLimit = 64 * 1024;  // dynamic LDS available without opting in
 
 __global__ __launch_bounds__(kBlock) void k_zero(float4 *__restrict__ p, int64_t n4)
@@ -364,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_gmax(const NodeDev *__restrict_
     }
 }
 
-// L^H and the position gradient for the 16 positions [p0, p0 + n) of one leaf.
+// L^H and the position gradient for the kAdjPos positions [p0, p0 + n) of one leaf.
 // For each (grid point q, position i), with gi = conj(pre_q e^{j 2 kc dR}) G_q:
 //   profile cotangent  gprof_i[r_w] += phi_w gi
 //   position gradient  grad p'_i  += Re{conj(gi) sum_w phi_w dprof_i[r_w]} * (-(q - p'_i)/|q - p'_i|)

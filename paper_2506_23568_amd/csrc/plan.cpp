@@ -1145,7 +1145,7 @@ void upload_plan(Plan &P)
             // adjoint work items: each leaf's positions in groups of 16
             std::vector<BlockItem> ab;
             for (size_t li = 0; li < nodes.size(); ++li)
-                for (int32_t p0 = nodes[li].pos_begin; p0 < nodes[li].pos_end; p0 += 16)
+                for (int32_t p0 = nodes[li].pos_begin; p0 < nodes[li].pos_end; p0 += kAdjPos)
                     ab.push_back(BlockItem{(int32_t)li, p0});
             upload_vec(P.device_bytes, &D.adj_blocks, ab);
             P.n_blocks_adj = (int64_t)ab.size();
