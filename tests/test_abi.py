@@ -196,8 +196,8 @@ def test_reductions_validate_without_a_gpu():
 def test_automatic_stages_minimise_the_cost_model(small):
     """stages = -K picks the S in 1..K with the smallest Sec. IV-B operation
     count (model_ms) among host plans built for each S; invalid forms fail."""
-    for rk, U in (("es", 2.0), ("linear", 8.0)):
-        kw = dict(range_kernel=rk, range_oversample=U, device=-1)
+    for rk, U, root in (("es", 2.0, False), ("linear", 8.0, False), ("linear", 8.0, True)):
+        kw = dict(range_kernel=rk, range_oversample=U, device=-1, root_grid=root)
         costs = [H.Plan(*_args(small), stages=s, **kw).info()["model_ms"] for s in (1, 2, 3)]
         auto = H.Plan(*_args(small), stages=-3, **kw).info()
         assert auto["stages"] == 1 + int(np.argmin(costs))
