@@ -12,9 +12,9 @@ band-limited interpolation weights on grids oversampled (2.0, 2.0, 2.4).
 A step is one hhffbp_image call: range compression, level-1 backprojection,
 the two intermediate merges and the final merge, with the echoes already
 resident in device memory.  The timed form reads the range profiles by linear
-interpolation at 8-fold range oversampling, the fast range mode that the
-direct-BP baseline uses too; the ES-kernel form (the parity mode) is timed and
-reported beside it.  The metric counts voxel x position
+interpolation at 4-fold range oversampling; the ES-kernel form (the parity
+mode) is timed and reported beside it.  The direct-BP baseline is the fastest
+linear-kernel direct mode within -30 dB of the ES direct image.  The metric counts voxel x position
 backprojections: N_vox * N_pos per step (the direct-BP work that HHFFBPA
 replaces).  Plan construction (host) is timed separately and reported as
 ``plan_ms``.  One JSON line is printed.
@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 METRIC = "voxel·position backprojections/s, HHFFBPA vs direct BP on 1 GPU at ≤−30 dB NRMSE"
 GAMMA = (3.0, 3.0, 3.5)          # Lagrange interpolation grids
 BENCH_GAMMA = (2.0, 2.0, 2.4)    # band-limited interpolation grids (the timed form)
+BENCH_U = 4.0                    # range oversampling of its linear range kernel
+DIRECT_U = (2.0, 3.0, 4.0, 8.0)  # linear-kernel direct-BP candidates for the baseline
 AF_GAMMA = (2.2, 2.2, 2.6)       # band-limited grids of the autofocus workload
 TAPS = 4
 # VALU issue peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane-ops/s
@@ -351,9 +353,9 @@ def main():
 
     # the benchmarked form: band-limited interpolation weights on grids with
     # gamma = (2.0, 2.0, 2.4), range profiles read by linear interpolation at
-    # U = 8 (the same fast range mode as the direct-BP baseline)
+    # U = 4
     t = time.time()
-    plan = H.Plan(*args3, range_kernel="linear", range_oversample=8.0, **kw)
+    plan = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, **kw)
     plan_ms = (time.time() - t) * 1e3
     info = plan.info()
     log("warm-up and timed steps")
@@ -367,7 +369,7 @@ def main():
                      range_kernel="linear", range_oversample=8.0)
     ms_lg, kernels_lg, img_lg = timed(plan_lg, max(3, args.steps // 2), 1)
     # the benchmarked form with a compressed root grid and one resample to the voxels
-    plan_rg = H.Plan(*args3, range_kernel="linear", range_oversample=8.0, root_grid=True, **kw)
+    plan_rg = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, root_grid=True, **kw)
     ms_rg, kernels_rg, img_rg = timed(plan_rg, max(3, args.steps // 2), 1)
     info_rg = plan_rg.info()
     ref_plan = H.Plan(*args3, mode="direct_rc", range_kernel="es", range_oversample=2.0,
@@ -379,18 +381,26 @@ def main():
     nrmse_es = (torch.linalg.norm(img_es - ref) / nref).item()
     nrmse_lg = (torch.linalg.norm(img_lg - ref) / nref).item()
     nrmse_rg = (torch.linalg.norm(img_rg - ref) / nref).item()
-    fast = H.Plan(*args3, mode="direct_rc", range_kernel="linear", range_oversample=8.0)
-    dimg = fast.image(ech)
-    torch.cuda.synchronize()
-    nd = 3
-    d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    d0.record(stream)
-    for _ in range(nd):
-        fast.image(ech, out=dimg)
-    d1.record(stream)
-    torch.cuda.synchronize()
-    dms = d0.elapsed_time(d1) / nd
-    d_nrmse = (torch.linalg.norm(dimg - ref) / nref).item()
+    # the direct-BP baseline: the fastest linear-kernel range mode within -30 dB
+    # of the ES direct image (itself <= 1e-5 of eq. 4)
+    candidates = {}
+    for u in DIRECT_U:
+        fast = H.Plan(*args3, mode="direct_rc", range_kernel="linear", range_oversample=u)
+        dimg = fast.image(ech)
+        torch.cuda.synchronize()
+        nd = 3
+        d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        d0.record(stream)
+        for _ in range(nd):
+            fast.image(ech, out=dimg)
+        d1.record(stream)
+        torch.cuda.synchronize()
+        candidates[f"linear U={u:g}"] = (d0.elapsed_time(d1) / nd,
+                                         (torch.linalg.norm(dimg - ref) / nref).item())
+        del fast, dimg
+    ok = {k: v for k, v in candidates.items() if 20 * np.log10(v[1]) <= -30.0}
+    d_mode = min(ok, key=lambda k: ok[k][0])
+    dms, d_nrmse = ok[d_mode]
     direct_vp = w.n_vox * w.n_pos / (dms * 1e-3)
     # eq. (4) itself, without range compression (the frequency sum per pair)
     ex_plan = H.Plan(*args3, mode="direct_exact")
@@ -435,7 +445,7 @@ def main():
                    "n_pos": w.n_pos, "n_freq": w.n_f, "grid": list(w.grid_dims),
                    "stages": 3, "merge_factor": 4, "oversample": list(BENCH_GAMMA),
                    "interp_taps": TAPS, "interp_kernel": "bandlimited",
-                   "range_kernel": "linear", "range_oversample": 8.0,
+                   "range_kernel": "linear", "range_oversample": BENCH_U,
                    "parallelism": "single GPU"},
         "nrmse_vs_direct_db": 20 * np.log10(nrmse),
         "reference": "float32 direct BP, ES range kernel U=2 W=7 (<= 1e-5 of float64 eq. 4)",
@@ -453,8 +463,10 @@ def main():
                              "root_points": info_rg["level_points"][0],
                              "merge_pairs": info_rg["merge_pairs"],
                              "final_pairs": info_rg["final_pairs"]},
-        "direct_bp": {"value": direct_vp, "unit": "vp/s", "ms": dms, "mode": "linear U=8",
-                      "nrmse_vs_es_direct_db": 20 * np.log10(d_nrmse)},
+        "direct_bp": {"value": direct_vp, "unit": "vp/s", "ms": dms, "mode": d_mode,
+                      "nrmse_vs_es_direct_db": 20 * np.log10(d_nrmse),
+                      "candidates": {k: {"ms": v[0], "nrmse_vs_es_direct_db": 20 * np.log10(v[1])}
+                                     for k, v in candidates.items()}},
         "direct_exact": {"value": w.n_vox * w.n_pos / (ex_ms * 1e-3), "unit": "vp/s", "ms": ex_ms,
                          "mode": "eq. (4): Horner sum over the 64 frequencies per pair",
                          "nrmse_vs_es_direct_db": 20 * np.log10(ex_nrmse)},

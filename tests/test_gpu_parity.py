@@ -144,34 +144,37 @@ def test_direct_exact_general_frequencies(torch, small):
     assert e <= 1e-5 and e_h <= 1e-5
 
 
-def test_direct_linear_fast_mode_small(torch, small, oracle_small):
-    """Fast range mode (linear kernel, U = 8) against the oracle's sum of the
-    same form (<= 1e-5) and against eq. (4) (<= -60 dB)."""
+@pytest.mark.parametrize("U,bound_db", [(8, -60.0), (4, -45.0), (2, -30.0)])
+def test_direct_linear_fast_mode_small(torch, small, oracle_small, U, bound_db):
+    """Fast range mode (linear kernel, U-fold range oversampling) against the
+    oracle's sum of the same form (<= 1e-5) and against eq. (4) (the linear
+    kernel's error falls as 1/U^2: <= -60, -45, -30 dB at U = 8, 4, 2)."""
     from oracle import hhffbp as OH
     from workloads import voxel_centres
-    _say("direct_rc linear U=8, config small")
+    _say(f"direct_rc linear U={U}, config small")
     vox = voxel_centres(small.grid_origin, small.grid_pitch, small.grid_dims)
-    ref = OH.direct_bp_linear(small.positions, small.freqs_hz, small.echoes, vox, 8)
-    pl = H.Plan(*_args(small), mode="direct_rc", range_kernel="linear", range_oversample=8.0)
+    ref = OH.direct_bp_linear(small.positions, small.freqs_hz, small.echoes, vox, U)
+    pl = H.Plan(*_args(small), mode="direct_rc", range_kernel="linear", range_oversample=float(U))
     img = _run(torch, pl, small)
     e = _nrmse(img.ravel(), ref)
     e4 = _nrmse(img, oracle_small)
     _say(f"  vs oracle linear {e:.3e}; vs eq.4 {20 * np.log10(e4):.1f} dB")
     assert e <= 1e-5
-    assert 20 * np.log10(e4) <= -60.0
+    assert 20 * np.log10(e4) <= bound_db
 
 
-@pytest.mark.parametrize("S,Q", [(1, 4), (2, 4), (2, 2)])
-def test_hhffbp_fast_range_mode_small(torch, small, oracle_small, S, Q):
-    """HHFFBPA with linearly interpolated range profiles (U = 8) against the
-    oracle HHFFBPA with the same level-1 sum, image and every stage <= 1e-5."""
+@pytest.mark.parametrize("S,Q,U", [(1, 4, 8), (2, 4, 8), (2, 2, 8), (2, 4, 4)])
+def test_hhffbp_fast_range_mode_small(torch, small, oracle_small, S, Q, U):
+    """HHFFBPA with linearly interpolated range profiles (U-fold range
+    oversampling) against the oracle HHFFBPA with the same level-1 sum, image
+    and every stage <= 1e-5."""
     from oracle import hhffbp as OH
     from oracle import plan as OP
-    _say(f"hhffbp fast range mode, config small S={S} Q={Q}")
+    _say(f"hhffbp fast range mode, config small S={S} Q={Q} U={U}")
     op = OP.build_plan(*_args(small), S, Q, GAMMA, TAPS)
-    ref, vals = OH.image(op, small.echoes, small.positions, keep=True, range_u=8)
+    ref, vals = OH.image(op, small.echoes, small.positions, keep=True, range_u=U)
     pl = H.Plan(*_args(small), stages=S, merge_factor=Q, oversample=GAMMA, interp_taps=TAPS,
-                range_kernel="linear", range_oversample=8.0)
+                range_kernel="linear", range_oversample=float(U))
     ws = pl._workspace(torch)
     img = _run(torch, pl, small, workspace=ws)
     e = _nrmse(img, ref)
@@ -315,13 +318,14 @@ BENCH_GAMMA = (2.0, 2.0, 2.4)
 AF_GAMMA = (2.2, 2.2, 2.6)
 
 
-@pytest.mark.parametrize("kernel,gamma", [("lagrange", GAMMA), ("bandlimited", BENCH_GAMMA),
-                                          ("bandlimited", AF_GAMMA)])
-def test_mid_fast_range_mode_full_size(torch, mid, kernel, gamma):
+@pytest.mark.parametrize("kernel,gamma,U", [("lagrange", GAMMA, 8), ("bandlimited", BENCH_GAMMA, 4),
+                                            ("bandlimited", AF_GAMMA, 8)])
+def test_mid_fast_range_mode_full_size(torch, mid, kernel, gamma, U):
     """The fast range mode at full size: 16384 positions, 64 f, 128x128x64
-    voxels, S = 3, Q = 4, linear range kernel at U = 8; with Lagrange weights
-    at (3, 3, 3.5) and with band-limited weights at (2.0, 2.0, 2.4), the
-    benchmark's, and (2.2, 2.2, 2.6).  Level-1 subimages at seeded grid points against the
+    voxels, S = 3, Q = 4, linear range kernel; Lagrange weights at (3, 3, 3.5)
+    with U = 8, band-limited weights at (2.0, 2.0, 2.4) with U = 4 (the
+    benchmark's form) and at (2.2, 2.2, 2.6) with U = 8 (the autofocus
+    workload's).  Level-1 subimages at seeded grid points against the
     oracle's level-1 sum of the same form (<= 1e-5); the image against GPU
     direct BP (pinned to eq. (4) by the test above) on the full grid (<= -30 dB)
     with the same isolated peaks; for the Lagrange form also against the stored
@@ -330,10 +334,10 @@ def test_mid_fast_range_mode_full_size(torch, mid, kernel, gamma):
     from oracle import hhffbp as OH
     from oracle import plan as OP
     w = mid
-    _say(f"mid fast range mode, {kernel} {gamma}: oracle plan")
+    _say(f"mid fast range mode, {kernel} {gamma} U={U}: oracle plan")
     op = OP.build_plan(*_args(w), 3, 4, gamma, TAPS, kernel=kernel)
     pl = H.Plan(*_args(w), stages=3, merge_factor=4, oversample=gamma, interp_taps=TAPS,
-                range_kernel="linear", range_oversample=8.0, interp_kernel=kernel)
+                range_kernel="linear", range_oversample=float(U), interp_kernel=kernel)
     ws = pl._workspace(torch)
     img = _run(torch, pl, w, workspace=ws)
     rng = np.random.default_rng(21)
@@ -341,7 +345,7 @@ def test_mid_fast_range_mode_full_size(torch, mid, kernel, gamma):
     errs, refs = [], []
     for i, n in leaves[::4]:
         sel = np.sort(rng.choice(n.lattice.size, 256, replace=False))
-        ref = OH.leaf_bp_at(op, n, w.echoes, w.positions, sel, range_u=8)
+        ref = OH.leaf_bp_at(op, n, w.echoes, w.positions, sel, range_u=U)
         got = pl.workspace_view(ws, 3, i)[torch.from_numpy(sel).cuda()].cpu().numpy()
         errs.append(got.astype(np.complex128) - ref)
         refs.append(ref)
