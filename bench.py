@@ -160,7 +160,7 @@ def autofocus_report(args):
     kw = dict(stages=3, merge_factor=4, oversample=AF_GAMMA, interp_taps=TAPS,
               interp_kernel="bandlimited")
     if args.af_range == "linear":
-        kw.update(range_kernel="linear", range_oversample=8.0)
+        kw.update(range_kernel="linear", range_oversample=args.af_u)
     if args.af_root_grid == "on":
         kw.update(root_grid=True)
     pos_true = torch.from_numpy(w.positions).cuda()
@@ -200,7 +200,7 @@ def autofocus_report(args):
         "config": {"workload": "autofocus: 65536 positions (44 strokes + 20 dense walks), 128 f "
                                "24-40 GHz, 256x256x128 voxels at 1 mm, 200 points + 5000-scatterer "
                                "slab, smooth trajectory error, S=3 Q=4, 20 Adam steps (lr 0.03 mm) on 16 cosine modes per axis, relative-L2 loss to the clean-trajectory image",
-                   "range_kernel": "linear U=8" if args.af_range == "linear" else "ES U=2 W=7",
+                   "range_kernel": f"linear U={args.af_u:g}" if args.af_range == "linear" else "ES U=2 W=7",
                    "interp_kernel": "bandlimited", "oversample": list(AF_GAMMA),
                    "root_grid": args.af_root_grid == "on", "parallelism": "single GPU"},
         "storage": out,
@@ -288,6 +288,8 @@ def main():
                     help="run one plain copy of this size first (HBM counter scale)")
     ap.add_argument("--af-range", choices=("es", "linear"), default="linear",
                     help="range kernel of the autofocus workload's images")
+    ap.add_argument("--af-u", type=float, default=4.0,
+                    help="autofocus workload: range oversampling of the linear range kernel")
     ap.add_argument("--af-root-grid", choices=("on", "off"), default="on",
                     help="autofocus workload: plans with a compressed root grid (the "
                          "last merge onto the full aperture's lattice, one resample to "

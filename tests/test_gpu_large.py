@@ -165,14 +165,14 @@ def test_large_root_grid(torch, large, gold, form):
     """A compressed root grid with one resample to the voxels, in the parity
     form (Lagrange, gamma (3, 3, 3.5), ES range kernel) and in the autofocus
     benchmark's form (band-limited, gamma (2.2, 2.2, 2.6), linear range kernel at
-    U = 8): <= -30 dB against eq. (4) on the stored sample and against GPU direct
+    U = 4): <= -30 dB against eq. (4) on the stored sample and against GPU direct
     BP on the full grid, and the isolated peaks where the float64 gap exceeds 1%."""
     w = large
     if form == "lagrange":
         kw = dict(oversample=GAMMA)
     else:
         kw = dict(oversample=(2.2, 2.2, 2.6), interp_kernel="bandlimited",
-                  range_kernel="linear", range_oversample=8.0)
+                  range_kernel="linear", range_oversample=4.0)
     pl = H.Plan(*_args(w), stages=3, merge_factor=4, interp_taps=TAPS, root_grid=True, **kw)
     ech = _ech(torch, w)
     img = pl.image(ech)
