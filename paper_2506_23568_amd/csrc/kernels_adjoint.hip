@@ -369,7 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_gmax(const NodeDev *__restrict_
 //   position gradient  grad p'_i  += Re{conj(gi) sum_w phi_w dprof_i[r_w]} * (-(q - p'_i)/|q - p'_i|)
 // where dprof holds the range profiles of the echoes weighted by j 2 k_f (the
 // range derivative of the compressed data).
-template <int KERNEL, int W, bool WANT_S, bool WANT_P>
+template <int KERNEL, int W, bool WANT_S, bool WANT_P, bool RED>
 __global__ __launch_bounds__(kBlock) void k_leaf_adj(
     const NodeDev *__restrict__ leaves, const BlockItem *__restrict__ blocks,
     const LeafPoint *__restrict__ pts, const float4 *__restrict__ posoff,
@@ -427,6 +427,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf_adj(
         const float Rc = fast_sqrt(Rc2);
         const float frac_w = q.frac - 0.5f * W;
         const int bin1 = q.bin + 1;
+        // the taps stay inside the staged profiles: clamping tau to [lo, hi] keeps
+        // r in [0, Nr - W] for positions moved beyond the planned slack
+        const float tau_lo = (float)(-bin1), tau_hi = (float)(Nr - W - bin1);
 #pragma unroll
         for (int i = 0; i < kAdjPos; ++i) {
             if (i < n) {  // predicated, so every ap[i] index stays a constant
@@ -436,14 +439,13 @@ __global__ __launch_bounds__(kBlock) void k_leaf_adj(
                 const float num = d.w - 2.0f * (q.dx * d.x + q.dy * d.y + q.dz * d.z);
                 const float R = fast_sqrt(num + Rc2);
                 const float dR = num * fast_rcp(R + Rc);
-                const float tau = fmaf(dR, inv_dR, frac_w);
-                const float fl = floorf(tau);
-                const float x = tau - fl;
-                const int r = min(max(bin1 + (int)fl, 0), Nr - W);
+                const float tau = __builtin_amdgcn_fmed3f(fmaf(dR, inv_dR, frac_w), tau_lo, tau_hi);
+                const int r = bin1 + floor_int(tau);
+                const float x = __builtin_amdgcn_fractf(tau);
                 float w[W];
                 range_weights<KERNEL, W>(x, beta_log2e, w);
                 float ph = dR * kc_turns;
-                ph -= rintf(ph);
+                if constexpr (RED) ph -= rintf(ph);
                 const float sn = sin_turns(ph), cs = cos_turns(ph);
                 const float gire = gcre * cs + gcim * sn;
                 const float giim = gcim * cs - gcre * sn;
@@ -521,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_pos_out(const float4 *__restrict__ g
     out[3 * m + 2] = (double)g.z;
 }
 
-template <int KERNEL, int W, bool S_, bool P_>
+template <int KERNEL, int W, bool S_, bool P_, bool RED>
 hipError_t launch_leaf_adj(const Plan &P, const float4 *posoff, const float2 *dprof,
                            const float2 *gleaf, const float *gmax, float2 *gprof, float4 *gpos,
                            hipStream_t st)
@@ -535,11 +537,11 @@ hipError_t launch_leaf_adj(const Plan &P, const float4 *posoff, const float2 *dp
             hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess ||
             sh > (size_t)optin)
             return hipErrorInvalidConfiguration;  // caller maps to UNSUPPORTED
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_leaf_adj<KERNEL, W, S_, P_>),
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_leaf_adj<KERNEL, W, S_, P_, RED>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess)
             return hipErrorInvalidConfiguration;
     }
-    hipLaunchKernelGGL((k_leaf_adj<KERNEL, W, S_, P_>), dim3(P.n_blocks_adj), dim3(kBlock), sh, st,
+    hipLaunchKernelGGL((k_leaf_adj<KERNEL, W, S_, P_, RED>), dim3(P.n_blocks_adj), dim3(kBlock), sh, st,
                        (const NodeDev *)P.dev.nodes[P.S], (const BlockItem *)P.dev.adj_blocks,
                        (const LeafPoint *)P.dev.leafpts, posoff, dprof, (int)P.Nr,
                        (float)(1.0 / P.dR), (float)(P.beta * 1.4426950408889634),
@@ -552,11 +554,19 @@ hipError_t leaf_adj_dispatch(const Plan &P, bool want_s, bool want_p, const floa
                              const float2 *dprof, const float2 *gleaf, const float *gmax,
                              float2 *gprof, float4 *gpos, hipStream_t st)
 {
+    // the carrier's argument needs no reduction below 128 turns, as in the forward
+    if (P.leaf_reach * (P.kc / kPi) < 128.0) {
+        if (want_s && want_p)
+            return launch_leaf_adj<KERNEL, W, true, true, false>(P, posoff, dprof, gleaf, gmax, gprof, gpos, st);
+        if (want_s)
+            return launch_leaf_adj<KERNEL, W, true, false, false>(P, posoff, dprof, gleaf, gmax, gprof, gpos, st);
+        return launch_leaf_adj<KERNEL, W, false, true, false>(P, posoff, dprof, gleaf, gmax, gprof, gpos, st);
+    }
     if (want_s && want_p)
-        return launch_leaf_adj<KERNEL, W, true, true>(P, posoff, dprof, gleaf, gmax, gprof, gpos, st);
+        return launch_leaf_adj<KERNEL, W, true, true, true>(P, posoff, dprof, gleaf, gmax, gprof, gpos, st);
     if (want_s)
-        return launch_leaf_adj<KERNEL, W, true, false>(P, posoff, dprof, gleaf, gmax, gprof, gpos, st);
-    return launch_leaf_adj<KERNEL, W, false, true>(P, posoff, dprof, gleaf, gmax, gprof, gpos, st);
+        return launch_leaf_adj<KERNEL, W, true, false, true>(P, posoff, dprof, gleaf, gmax, gprof, gpos, st);
+    return launch_leaf_adj<KERNEL, W, false, true, true>(P, posoff, dprof, gleaf, gmax, gprof, gpos, st);
 }
 
 template <int T, int K>
