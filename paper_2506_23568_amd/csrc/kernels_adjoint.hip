@@ -96,8 +96,9 @@ struct BoxShared {
     float gsum;
     float gpart[kBlock / 64];
     int ipart[kBlock / 64][6];
-    int box_re[kBoxCap];
-    int box_im[kBoxCap];
+    // one 64-bit entry per box point: real part in the high half, imaginary in
+    // the low half (see block_scatter_child)
+    unsigned long long box[kBoxCap];
 };
 
 __device__ __forceinline__ int wave_min_i(int v)
@@ -171,10 +172,7 @@ __device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c
         return;
     }
     const int nb = (int)nbox;
-    for (int t = tid; t < nb; t += kBlock) {
-        sh.box_re[t] = 0;
-        sh.box_im[t] = 0;
-    }
+    for (int t = tid; t < nb; t += kBlock) sh.box[t] = 0ull;
     const float q = 1651910204.0f / sh.gsum;  // 2^31 / 1.3
     __syncthreads();
     if (active) {
@@ -212,17 +210,23 @@ __device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c
                 const int row = ((bi + a) * B1 + (bj + ov[b])) * B2 + bl;
 #pragma unroll
                 for (int k = 0; k < T; ++k) {
+                    // re 2^32 + im in one 64-bit add: both sums stay within int32
+                    // (the scale q), so the low half is the imaginary sum exactly
+                    // and the carries it leaves make the high half the real sum
                     const float w = wab * wnr[k];
-                    atomicAdd(&sh.box_re[row + on[k]], (int)rintf(w * qre));
-                    atomicAdd(&sh.box_im[row + on[k]], (int)rintf(w * qim));
+                    const long long v = (long long)(int)rintf(w * qre) * 4294967296ll +
+                                        (long long)(int)rintf(w * qim);
+                    atomicAdd(&sh.box[row + on[k]], (unsigned long long)v);
                 }
             }
     }
     __syncthreads();
     const float inv = 1.0f / q;
     for (int t = tid; t < nb; t += kBlock) {
-        const int vr = sh.box_re[t], vi = sh.box_im[t];
-        if (vr == 0 && vi == 0) continue;
+        const long long x = (long long)sh.box[t];
+        if (x == 0) continue;
+        const int vi = (int)(unsigned)(unsigned long long)x;
+        const int vr = (int)((x - (long long)vi) >> 32);
         const int l = o2 + t % B2;
         const int j = o1 + (t / B2) % B1;
         const int i = o0 + t / (B2 * B1);
