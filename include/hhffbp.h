@@ -215,7 +215,9 @@ typedef struct {
     int64_t ws_scales_offset;       /* workspace byte offset of float scale[S+1]
                                        (S+2 with a root grid): stored profiles
                                        carry scale[0], depth-d subimages scale[d],
-                                       the root grid scale[S+1] (1 unless HHFFBP_F16) */
+                                       the root grid scale[S+1]; written by
+                                       hhffbp_image with HHFFBP_F16 storage only
+                                       (the other types store values unscaled) */
     int64_t device_bytes;           /* device memory the plan holds (its tables) */
     double model_ms;                /* Sec. IV-B cost model: level-1 BP + interpolation,
                                        with the per-pair costs of hhffbp_config.stages */
@@ -235,8 +237,8 @@ hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info);
  * holds l in [l_lo[c], l_hi[c]] contiguously from point offset col_off[c].
  * Values are complex pairs of the plan's storage type (8 bytes per point for
  * HHFFBP_C64, 4 for HHFFBP_F16 and HHFFBP_BF16) at byte offset
- * *ws_offset + size * point, multiplied by the depth's scale (see
- * hhffbp_plan_info.ws_scales_offset).  Arrays may be
+ * *ws_offset + size * point, with HHFFBP_F16 multiplied by the depth's scale
+ * (see hhffbp_plan_info.ws_scales_offset).  Arrays may be
  * NULL to query sizes only; otherwise they must hold ni * nj entries.
  * Depth 0 is the root: with cfg->root_grid its grid is node (0, 0); without,
  * the root's grid is the user grid and has no lattice (HHFFBP_E_INVALID); an empty

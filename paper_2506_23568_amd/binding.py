@@ -340,13 +340,16 @@ class Plan:
         if st == STORAGE["c64"]:
             return workspace[o:o + 8 * n].view(torch.complex64)
         dt = torch.float16 if st == STORAGE["f16"] else torch.bfloat16
+        v = workspace[o:o + 4 * n].view(dt).reshape(n, 2).to(torch.float32)
+        v = torch.view_as_complex(v.contiguous())
+        if st != STORAGE["f16"]:
+            return v  # bfloat16 values are stored unscaled
         info = self.info()
         so = info["ws_scales_offset"]
         # the root grid's scale follows the depths' (slot S + 1); slot 0 is the profiles'
         slot = info["stages"] + 1 if depth == 0 else depth
         scale = workspace[so + 4 * slot:so + 4 * slot + 4].view(torch.float32)
-        v = workspace[o:o + 4 * n].view(dt).reshape(n, 2).to(torch.float32)
-        return torch.view_as_complex(v.contiguous()) / scale
+        return v / scale
 
 
 # ---------------------------------------------------------------------------

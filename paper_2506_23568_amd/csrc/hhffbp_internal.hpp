@@ -127,6 +127,9 @@ struct DeviceBuffers {
     void *leaf_of_sorted = nullptr; // int32 [n_pos]
     void *leaf_centre = nullptr;    // double2 [n_leaves]
     void *pos64 = nullptr;          // double [n_pos][3], caller order
+    void *posoff = nullptr;         // float4 [n_pos]: the plan positions' leaf offsets and
+                                    // squared norms (as k_prep_positions writes them)
+    void *unit_scales = nullptr;    // float [n_scales()] of 1: storage scales of c64, bf16
     void *weights = nullptr;        // float [n_pos] aperture weights, caller order (or none)
     void *kf = nullptr;             // double [n_freq]: k_f (exact direct mode)
     void *kf_turns = nullptr;       // float [n_freq]: k_f / pi (exact mode, general spacing)

@@ -863,16 +863,24 @@ hhffbp_status image_for_storage(const Plan &P, const void *echoes, const double 
         if (ev) (void)hipEventRecord(*ev, st);
         return HHFFBP_OK;
     }
-    // without scaling (c64, bf16) the position pass writes the unit scales itself
-    const bool fused_ones = ST != HHFFBP_F16 && P.S > 0;
+    // Factorised plans: without scaling (c64, bf16) the storage scales are the
+    // plan's unit array, and at the plan's own positions the leaf offsets are the
+    // plan's too, so such an image starts with the range compression.
+    const bool unit = ST != HHFFBP_F16 && P.S > 0;
     hipError_t e = hipSuccess;
-    if (!fused_ones && (e = launch_scales<ST>(P, echoes, ws, st)) != hipSuccess) return HHFFBP_E_DEVICE;
+    if (unit)
+        scales = (const float *)P.dev.unit_scales;
+    else if ((e = launch_scales<ST>(P, echoes, ws, st)) != hipSuccess)
+        return HHFFBP_E_DEVICE;
     if (P.S > 0) {
-        hipLaunchKernelGGL(k_prep_positions, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
-                           pos64, (const int32_t *)P.dev.perm, (const int32_t *)P.dev.leaf_of_sorted,
-                           (const double *)P.dev.leaf_centre, n, posoff,
-                           fused_ones ? (float *)(ws + P.ws_scales) : nullptr, P.n_scales());
-        if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
+        if (pos64 == (const double *)P.dev.pos64) {
+            posoff = (float4 *)P.dev.posoff;
+        } else {
+            hipLaunchKernelGGL(k_prep_positions, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                               pos64, (const int32_t *)P.dev.perm, (const int32_t *)P.dev.leaf_of_sorted,
+                               (const double *)P.dev.leaf_centre, n, posoff, (float *)nullptr, 0);
+            if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
+        }
         if (ev) (void)hipEventRecord(*ev++, st);
     }
     {

@@ -1151,6 +1151,20 @@ void upload_plan(Plan &P)
             P.n_blocks_adj = (int64_t)ab.size();
         }
     }
+    // images at the plan's own positions read their leaf offsets from the plan,
+    // formed once here by the same kernel that forms them for other positions
+    upload_vec(P.device_bytes, &D.unit_scales, std::vector<float>((size_t)P.n_scales(), 1.0f));
+    {
+        const size_t bytes = (size_t)P.cfg.n_pos * sizeof(float4);
+        if (hipMalloc(&D.posoff, bytes) != hipSuccess) {
+            D.posoff = nullptr;
+            throw Error{HHFFBP_E_NOMEM, "hipMalloc failed during plan upload"};
+        }
+        P.device_bytes += bytes;
+        if (launch_prep(P, (const double *)D.pos64, (float4 *)D.posoff, nullptr) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess)
+            throw Error{HHFFBP_E_DEVICE, "position offsets failed during plan upload"};
+    }
 }
 
 void release_plan(Plan &P)
@@ -1165,6 +1179,8 @@ void release_plan(Plan &P)
     fr(D.leaf_of_sorted);
     fr(D.leaf_centre);
     fr(D.pos64);
+    fr(D.posoff);
+    fr(D.unit_scales);
     fr(D.weights);
     fr(D.kf);
     fr(D.kf_turns);
