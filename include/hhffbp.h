@@ -137,8 +137,10 @@ void hhffbp_config_default(hhffbp_config *cfg);
  * Build a plan (Sec. IV-A): the subarray tree, the sampling grid G of every
  * subarray below the root (and of the root with cfg->root_grid), the (x, y, z) preimage of every grid point, the
  * range window and the range-compression matrix, uploaded to `cfg->device`.
- * Runs on the host in float64.  Reads `cfg` and the host arrays it points to
- * only during the call.  On success *out receives a plan that must be released
+ * Runs on the host in float64; one small kernel on the device's null stream
+ * forms the plan positions' leaf offsets, and the call waits for it.  Reads
+ * `cfg` and the host arrays it points to only during the call.  On success
+ * *out receives a plan that must be released
  * with hhffbp_plan_destroy.  With cfg->device = -1 nothing touches a GPU: the
  * plan holds its host tables only (for inspection) and hhffbp_image refuses it.  Errors: HHFFBP_E_INVALID (non-finite input, empty
  * grid, grid not in front of the aperture, unsupported Q/T/W/U/gamma),

@@ -1162,7 +1162,7 @@ void upload_plan(Plan &P)
         }
         P.device_bytes += bytes;
         if (launch_prep(P, (const double *)D.pos64, (float4 *)D.posoff, nullptr) != hipSuccess ||
-            hipDeviceSynchronize() != hipSuccess)
+            hipStreamSynchronize(nullptr) != hipSuccess)
             throw Error{HHFFBP_E_DEVICE, "position offsets failed during plan upload"};
     }
 }
