@@ -177,6 +177,27 @@ hhffbp_status hhffbp_image(hhffbp_plan_t plan, const void *echoes, const double 
                            void *image, void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * Form the image without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same work and result as hhffbp_image, bit for bit,
+ * with the workspace taken from a static array that the library holds on each
+ * device it runs on (HHFFBP_NOALLOC_WORKSPACE_BYTES bytes, kept from the
+ * module's load until the process ends).  The call itself allocates nothing:
+ * no hipMalloc, hipFree or allocating library routine.
+ *   echoes, positions, image   as for hhffbp_image (caller-owned, device)
+ * Every such call on one device shares that device's array, which keeps the
+ * last call's contents: calls that may overlap on one device (other streams,
+ * other threads) race and must be ordered by the caller.  hhffbp_profile_begin
+ * does not apply to these calls.  Errors: HHFFBP_E_INVALID (NULL echoes or
+ * image), HHFFBP_E_WORKSPACE (the plan needs more than
+ * HHFFBP_NOALLOC_WORKSPACE_BYTES of workspace; nothing is launched),
+ * HHFFBP_E_DEVICE.
+ */
+#define HHFFBP_NOALLOC_WORKSPACE_BYTES ((size_t)256 << 20)
+hhffbp_status hhffbp_image_noalloc(hhffbp_plan_t plan, const void *echoes,
+                                   const double *positions, void *image, void *stream);
+
+/*
  * Gradients of a real loss L(image) with respect to the echoes and the antenna
  * positions (autofocus of handheld motion errors, Sec. I), with the plan frozen:
  * the tree and grids stay as planned and only the level-1 backprojection

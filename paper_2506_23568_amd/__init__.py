@@ -7,7 +7,7 @@ library has not been built the import still succeeds, but every call raises.
 """
 from .binding import (  # noqa: F401
     Plan, HHFFBPError, lib, library_path, STATUS, MODES, RANGE_KERNELS, STORAGE,
-    STATS_FIELDS, image_stats, stats_dict, loss_grad, box_peaks,
+    STATS_FIELDS, NOALLOC_WORKSPACE_BYTES, image_stats, stats_dict, loss_grad, box_peaks,
 )
 
 __all__ = ["Plan", "HHFFBPError", "lib", "library_path", "hhffbp_image", "image_stats",

@@ -16,6 +16,8 @@ MODES = {"factorized": 0, "direct_rc": 1, "direct_exact": 2}
 RANGE_KERNELS = {"es": 0, "linear": 1}
 STORAGE = {"c64": 0, "f16": 1, "bf16": 2}
 INTERP_KERNELS = {"lagrange": 0, "bandlimited": 1}
+# HHFFBP_NOALLOC_WORKSPACE_BYTES of include/hhffbp.h
+NOALLOC_WORKSPACE_BYTES = 256 << 20
 
 
 class HHFFBPError(RuntimeError):
@@ -80,6 +82,8 @@ def lib():
         L.hhffbp_workspace_bytes.restype = ctypes.c_int
         L.hhffbp_image.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.hhffbp_image.restype = ctypes.c_int
+        L.hhffbp_image_noalloc.argtypes = [vp, vp, vp, vp, vp]
+        L.hhffbp_image_noalloc.restype = ctypes.c_int
         L.hhffbp_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.hhffbp_backward.restype = ctypes.c_int
         L.hhffbp_get_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
@@ -285,6 +289,25 @@ class Plan:
             stream = torch.cuda.current_stream(echoes.device).cuda_stream
         _check(lib().hhffbp_image(self._h, echoes.data_ptr(), pptr, out.data_ptr(),
                                   workspace.data_ptr(), workspace.numel(), stream))
+        return out
+
+    def image_noalloc(self, echoes, positions=None, out=None, stream=None):
+        """As ``image``, with the library's own per-device workspace
+        (hhffbp_image_noalloc): calls on one device share it and must not overlap."""
+        import torch
+
+        echoes = self._check_echoes(echoes)
+        if out is None:
+            out = torch.empty(self.dims, dtype=torch.complex64, device=echoes.device)
+        pptr = None
+        if positions is not None:
+            if positions.dtype != torch.float64 or tuple(positions.shape) != (self.config.n_pos, 3):
+                raise TypeError("positions must be float64 (n_pos, 3) on the device")
+            positions = positions.contiguous()
+            pptr = positions.data_ptr()
+        if stream is None:
+            stream = torch.cuda.current_stream(echoes.device).cuda_stream
+        _check(lib().hhffbp_image_noalloc(self._h, echoes.data_ptr(), pptr, out.data_ptr(), stream))
         return out
 
     def backward(self, echoes, grad_image, positions=None, want_echoes=True, want_positions=True,

@@ -159,6 +159,37 @@ hhffbp_status hhffbp_image(hhffbp_plan_t plan, const void *echoes, const double 
     return HHFFBP_OK;
 }
 
+hhffbp_status hhffbp_image_noalloc(hhffbp_plan_t plan, const void *echoes,
+                                   const double *positions, void *image, void *stream)
+{
+    if (!plan || !echoes || !image)
+        return fail(HHFFBP_E_INVALID, "hhffbp_image_noalloc: NULL argument");
+    const hh::Plan &P = plan->plan;
+    if (P.cfg.device < 0)
+        return fail(HHFFBP_E_DEVICE, "hhffbp_image_noalloc: host-only plan (device < 0)");
+    if (P.ws_total > HHFFBP_NOALLOC_WORKSPACE_BYTES)
+        return fail(HHFFBP_E_WORKSPACE, "hhffbp_image_noalloc: the plan needs " +
+                                            std::to_string(P.ws_total) +
+                                            " bytes of workspace, more than the library's " +
+                                            std::to_string(HHFFBP_NOALLOC_WORKSPACE_BYTES));
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(HHFFBP_E_DEVICE, "hipGetDevice failed");
+    if (cur != P.cfg.device && hipSetDevice(P.cfg.device) != hipSuccess)
+        return fail(HHFFBP_E_DEVICE, "hipSetDevice failed");
+    char *ws = nullptr;
+    hipError_t e = hh::noalloc_workspace(P.cfg.device, &ws);
+    hhffbp_status st = HHFFBP_E_DEVICE;
+    if (e == hipSuccess)
+        st = hh::launch_image(P, echoes, positions, image, ws, (hipStream_t)stream, nullptr);
+    if (cur != P.cfg.device) (void)hipSetDevice(cur);
+    if (e != hipSuccess)
+        return fail(HHFFBP_E_DEVICE, std::string("hhffbp_image_noalloc: workspace address: ") +
+                                         hipGetErrorString(e));
+    if (st != HHFFBP_OK) return fail(st, std::string("hhffbp_image_noalloc: launch failed: ") +
+                                             hipGetErrorString(hipGetLastError()));
+    return HHFFBP_OK;
+}
+
 hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info)
 {
     if (!plan || !info) return fail(HHFFBP_E_INVALID, "hhffbp_get_plan_info: NULL argument");

@@ -236,6 +236,9 @@ hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *p
 // `stream` before the first stage and after each stage.
 hhffbp_status launch_image(const Plan &plan, const void *echoes, const double *positions,
                            void *image, char *ws, hipStream_t stream, hipEvent_t *events);
+// Device address of the library-held workspace of hhffbp_image_noalloc on
+// `device`, which must be the current device (kernels.hip).
+hipError_t noalloc_workspace(int device, char **ptr);
 
 // Image reductions (kernels_metrics.hip); no plan, current device.
 size_t stats_workspace_bytes();

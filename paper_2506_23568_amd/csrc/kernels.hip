@@ -22,9 +22,16 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "device_common.hpp"
 #include "hhffbp_internal.hpp"
+
+// Workspace of hhffbp_image_noalloc: one array per device, held from the
+// module's load until the process ends, shared by every such call on that
+// device.  In host code `scratch` names a host-side stand-in; the device
+// address comes from hipGetSymbolAddress (noalloc_workspace below).
+static __device__ __align__(256) unsigned char scratch[HHFFBP_NOALLOC_WORKSPACE_BYTES];
 
 namespace hh {
 namespace {
@@ -964,6 +971,26 @@ std::vector<std::string> Plan::stage_names() const
         n.push_back("final");
     }
     return n;
+}
+
+// The device address of this device's `scratch`, looked up once per device
+// with that device current and kept; later calls reuse it.
+hipError_t noalloc_workspace(int device, char **ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256 != 0) return hipErrorInvalidValue;
+        addr[device] = p;
+    }
+    *ptr = static_cast<char *>(addr[device]);
+    return hipSuccess;
 }
 
 hhffbp_status launch_image(const Plan &P, const void *echoes, const double *positions,

@@ -207,3 +207,15 @@ def test_automatic_stages_minimise_the_cost_model(small):
         H.Plan(*_args(small), stages=-2, mode="direct_rc", device=-1)
     with pytest.raises(H.HHFFBPError):
         H.Plan(*_args(small), stages=-9, device=-1)
+
+
+def test_host_only_plan_refuses_images(small):
+    """A host-only plan (device = -1) holds no device tables: hhffbp_image and
+    hhffbp_image_noalloc return HHFFBP_E_DEVICE before touching a GPU."""
+    pl = H.Plan(*_args(small), stages=2, device=-1)
+    L = H.lib()
+    dummy = ctypes.c_void_p(256)  # never dereferenced: the calls stop at the plan check
+    st = L.hhffbp_image_noalloc(pl._h, dummy, None, dummy, None)
+    assert st == -4 and b"host-only" in L.hhffbp_last_error()
+    st = L.hhffbp_image(pl._h, dummy, None, dummy, dummy, 1 << 30, None)
+    assert st == -4
