@@ -217,6 +217,100 @@ def image(plan, echoes, positions=None, keep=False, range_u=None, weights=None):
     return (img, vals) if keep else img
 
 
+def stencil_points(lat, t, T):
+    """Point indices (unique, ascending) of every tap of the T^3 stencils around
+    the lattice coordinates t (N, 3); raises if a tap lies outside the lattice."""
+    base = stencil_base(t).astype(np.int64)
+    offs = lagrange_offsets(T)
+    out = []
+    for da in offs:
+        ci = base[:, 0] + da - lat.i0
+        for db in offs:
+            cj = base[:, 1] + db - lat.j0
+            inside = (ci >= 0) & (ci < lat.ni) & (cj >= 0) & (cj < lat.nj)
+            if not inside.all():
+                raise RuntimeError("a stencil reaches outside the grid's columns")
+            lo, hi, of = lat.l_lo[ci, cj], lat.l_hi[ci, cj], lat.off[ci, cj]
+            for dc in offs:
+                ll = base[:, 2] + dc
+                if np.any((ll < lo) | (ll > hi)):
+                    raise RuntimeError("a stencil reaches outside a grid pencil")
+                out.append(of + ll - lo)
+    return np.unique(np.concatenate(out)) if out else np.zeros(0, np.int64)
+
+
+def image_at(plan, echoes, positions, voxel_index, range_u=None, weights=None, keep=False):
+    """The HHFFBPA image of ``image`` at the voxels ``voxel_index`` (linear, z
+    fastest) only.  The same steps in the same order, restricted to the grid
+    points those voxels need: at each depth, from the root down, the points of
+    every stencil that the needed points of the depth above reach (for depth 1,
+    or the root's own grid, the voxels' stencils); then leaf sums at the
+    needed leaf points, and merges at the needed points of each depth, from the
+    leaves up.  Values no needed point reads are never formed (NaN in the work
+    arrays, so that reading one would show in the result).  With ``keep`` also
+    returns {(depth, node): (point indices, compressed values)} of every depth."""
+    levels = plan.levels
+    positions = np.asarray(positions, float)
+    echoes = weighted(echoes, weights)
+    S = len(levels) - 1
+    vi = np.asarray(voxel_index, np.int64)
+    vox = plan.voxels[vi]
+    if S == 0:
+        return _bp(plan, positions, echoes, vox, range_u)
+    top = 0 if plan.root_grid else 1
+
+    def coords(node, pts):
+        return plan.gamma * G.uvn(pts, node.rect, plan.kmin, plan.kmax)
+
+    need = {}
+    for d in range(top, S + 1):
+        for idx, node in enumerate(levels[d]):
+            if node.empty:
+                continue
+            if d == top:
+                pts = vox
+            else:
+                par = levels[d - 1][node.parent]
+                sel = need[(d - 1, node.parent)]
+                sel = sel[par.lattice.valid[sel]]
+                pts = par.lattice.xyz[sel]
+            need[(d, idx)] = stencil_points(node.lattice, coords(node, pts), plan.taps)
+
+    def work_array(node, sel, values):
+        lat = node.lattice
+        a = np.where(lat.valid, np.nan, 0.0).astype(np.complex128)
+        a[sel] = values
+        return a
+
+    vals = {}
+    for idx, node in enumerate(levels[S]):
+        if not node.empty:
+            sel = need[(S, idx)]
+            vals[(S, idx)] = work_array(node, sel,
+                                        leaf_bp_at(plan, node, echoes, positions, sel, range_u))
+    for d in range(S - 1, top - 1, -1):
+        for idx, node in enumerate(levels[d]):
+            if node.empty:
+                continue
+            lat = node.lattice
+            sel = need[(d, idx)]
+            ok = lat.valid[sel]
+            pts = lat.xyz[sel[ok]]
+            f = np.zeros(sel.size, np.complex128)
+            f[ok] = merge_at(plan, node, vals, pts) * np.exp(
+                -1j * G.phi(pts, node.rect, plan.kmin, plan.kmax))
+            vals[(d, idx)] = work_array(node, sel, f)
+    if plan.root_grid:
+        img = resample(plan, levels[0][0], vals[(0, 0)], vox)
+    else:
+        img = merge_at(plan, levels[0][0], vals, vox)
+    if not np.all(np.isfinite(img)):
+        raise RuntimeError("a stencil read a grid value that was not formed")
+    if keep:
+        return img, {key: (sel, vals[key][sel]) for key, sel in need.items()}
+    return img
+
+
 def direct_bp(positions, freqs_hz, echoes, points, weights=None):
     """Plain eq. (4) at arbitrary points (float64), aperture weights w_i (None: 1)."""
     k = 2.0 * np.pi * np.asarray(freqs_hz, float) / 299792458.0
