@@ -71,7 +71,7 @@ struct Store<HHFFBP_BF16> {
     static __device__ __forceinline__ R str(float v) { return f32_to_bf16(v); }
 };
 
-constexpr int kBlock = 256;
+constexpr int kBlock = kBlockThreads;
 constexpr int kPosChunkMax = 16;
 constexpr size_t kLdsBudget = 20 * 1024;  // dynamic LDS per block
 
@@ -260,18 +260,70 @@ __device__ __forceinline__ void poly_weights(const InterpPoly &ip, float x, floa
 }
 
 template <int T, int K>
+__device__ __forceinline__ void interp_weights3(const InterpPoly &ip, float fu, float fv, float fn,
+                                                float *wu, float *wv, float *wn)
+{
+    if constexpr (K == HHFFBP_INTERP_BANDLIMITED) {
+        poly_weights<T, 0>(ip, fu, wu);
+        poly_weights<T, 1>(ip, fv, wv);
+        poly_weights<T, 2>(ip, fn, wn);
+    } else {
+        lagrange<T>(fu, wu);
+        lagrange<T>(fv, wv);
+        lagrange<T>(fn, wn);
+    }
+}
+
+template <int T, int K>
 __device__ __forceinline__ void interp_weights(const InterpPoly &ip, const ChildCoord &g, float *wu,
                                                float *wv, float *wn)
 {
-    if constexpr (K == HHFFBP_INTERP_BANDLIMITED) {
-        poly_weights<T, 0>(ip, g.fu, wu);
-        poly_weights<T, 1>(ip, g.fv, wv);
-        poly_weights<T, 2>(ip, g.fn, wn);
-    } else {
-        lagrange<T>(g.fu, wu);
-        lagrange<T>(g.fv, wv);
-        lagrange<T>(g.fn, wn);
+    interp_weights3<T, K>(ip, g.fu, g.fv, g.fn, wu, wv, wn);
+}
+
+// Separable T^3 interpolation at a plan-time record (InterpIdx): the stencil's
+// first column (ci0, cj0) of the child's lattice and first n index l0.  Every
+// tap lies inside the child's pencils (checked when the records were built),
+// so each of the T^2 columns gives T contiguous values from its base
+// colbase[col] = off - lo alone (4 bytes a column instead of a column entry).
+template <int T, int ST>
+__device__ __forceinline__ float2 interp_rec(const NodeDev &c, const int32_t *__restrict__ colbase,
+                                             const typename Store<ST>::C *__restrict__ vals, int ci0,
+                                             int cj0, int l0, const float *wu, const float *wv,
+                                             const float *wn)
+{
+    const int32_t *crow = colbase + c.col_base + ci0 * c.nj + cj0;
+    const typename Store<ST>::C *base = vals + (c.val_base + l0);
+    float are = 0.0f, aim = 0.0f;
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            const typename Store<ST>::C *p = base + crow[a * c.nj + b];
+            float sre = 0.0f, sim = 0.0f;
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                const float2 v = Store<ST>::ld(p[k]);
+                sre = fmaf(wn[k], v.x, sre);
+                sim = fmaf(wn[k], v.y, sim);
+            }
+            const float wab = wu[a] * wv[b];
+            are = fmaf(wab, sre, are);
+            aim = fmaf(wab, sim, aim);
+        }
+        // one stencil row (T columns, T^2 values) in flight at a time: hoisting
+        // every gather costs registers and occupancy, not latency
+        __builtin_amdgcn_sched_barrier(0);
     }
+    return make_float2(are, aim);
+}
+
+// acc += v exp(j 2 pi turns), turns in [-1/2, 1/2]
+__device__ __forceinline__ void rotate_mac(float2 v, float turns, float &are, float &aim)
+{
+    const float sn = sin_turns(turns), cs = cos_turns(turns);
+    are = fmaf(v.x, cs, fmaf(-v.y, sn, are));
+    aim = fmaf(v.x, sn, fmaf(v.y, cs, aim));
 }
 
 // Separable T^3 interpolation of a compressed child subimage (missing points are 0).
@@ -329,13 +381,11 @@ __device__ __forceinline__ float2 interp_child(const NodeDev &c, const ColEntry 
 
 // The T^3 taps from a dense LDS box: p points at the stencil's first tap, the
 // box holds nl values per (i, j) column and nj columns per i.  Same summation
-// order as interp_child's pencil path.
-template <int T, int K>
-__device__ __forceinline__ float2 interp_box(const float2 *p, int nj, int nl, const ChildCoord &g,
-                                             const InterpPoly &ip)
+// order as interp_rec and interp_child's pencil path.
+template <int T>
+__device__ __forceinline__ float2 interp_box(const float2 *p, int nj, int nl, const float *wu,
+                                             const float *wv, const float *wn)
 {
-    float wu[T], wv[T], wn[T];
-    interp_weights<T, K>(ip, g, wu, wv, wn);
     float are = 0.0f, aim = 0.0f;
 #pragma unroll
     for (int a = 0; a < T; ++a) {

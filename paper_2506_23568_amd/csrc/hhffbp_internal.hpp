@@ -17,6 +17,8 @@ constexpr double kPi = 3.14159265358979323846;
 // point seen by a child that shares an edge with it (Q = 2) sits on a child node
 // up to rounding; the offset makes every code path choose the same stencil.
 constexpr double kStencilEps = 1e-9;
+// Threads of every imaging kernel's block (four waves of 64).
+constexpr int kBlockThreads = 256;
 
 // One non-empty subarray as the kernels see it.  Rectangles are the cell
 // rectangles of the bisection (aperture plane z' = 0).
@@ -90,6 +92,27 @@ struct MergeBrick {
     int32_t node, i, j, l;
 };
 
+// Interpolation record of one (point, child) pair of a merge or of the final
+// stage, formed at plan time in float64 with the same arithmetic that builds
+// the grids (Sec. III maps, stencil base floor(gamma w + kStencilEps)):
+//   cij    first stencil column (ci | cj << 16) relative to the child's lattice
+//          columns (i0, j0); kNoPair: the pair contributes nothing (an absent
+//          parent point, a padding lane, no such child)
+//   l0     first stencil index along n
+//   fu, fv, fn   fractional lattice coordinates in [0, 1]
+//   turns  phase in turns, reduced to [-1/2, 1/2]: Phi_child - Phi_parent in a
+//          merge (restores the child's downconversion and applies the parent's),
+//          Phi_child in the final stage
+// Every stencil is checked at plan time to lie inside the child's pencils.
+struct InterpIdx {
+    uint32_t cij;
+    int32_t l0;
+};
+struct InterpGeo {
+    float fu, fv, fn, turns;
+};
+constexpr uint32_t kNoPair = 0xffffffffu;
+
 // Range bins [lo, lo + n) that a level-1 BP block can read: every tap of its
 // points for positions within the leaf's reach.
 struct BinWindow {
@@ -135,6 +158,8 @@ struct DeviceBuffers {
     void *kf_turns = nullptr;       // float [n_freq]: k_f / pi (exact mode, general spacing)
     std::vector<void *> nodes;      // per depth: NodeDev[]
     std::vector<void *> cols;       // per depth: ColEntry[]
+    std::vector<void *> colbase;    // per depth: int32 off - lo per column (the value index of
+                                    // lattice point l of column c is val_base + colbase[c] + l)
     std::vector<void *> px, py, pz; // per depth < S: float64 SoA grid points
     void *leafpts = nullptr;        // LeafPoint[] of depth S
     void *leaf_blocks = nullptr;    // BlockItem[]
@@ -147,6 +172,10 @@ struct DeviceBuffers {
     std::vector<void *> merge_blocks;  // per depth F..S-1: BlockItem[] of 256 points (adjoint)
     std::vector<void *> merge_blocks_fwd;  // per depth F..S-1: BlockItem[] of 256 / Q points
     std::vector<void *> merge_bricks;      // per depth F..S-1: MergeBrick[] (merge adjoint)
+    std::vector<void *> merge_idx, merge_geo;  // per depth F..S-1: InterpIdx[], InterpGeo[] of
+                                               // the forward merge, [block][lane]
+    void *final_idx = nullptr;      // InterpIdx[n_bricks][nodes at depth F][kBlockThreads]
+    void *final_geo = nullptr;      // InterpGeo[n_bricks][nodes at depth F][kBlockThreads]
 };
 
 struct Plan {

@@ -12,7 +12,9 @@
 // Precision plan.  Large distances (~0.3 m) never enter float32 phases directly:
 // leaf BP works with distance differences to the leaf centre, direct BP with
 // differences to a per-tile reference point whose own distance is float64, and
-// the merge geometry ((u, v, n) and Phi of each child) is evaluated in float64.
+// the merge geometry ((u, v, n) and Phi of each child at each point) is formed
+// once per plan in float64 on the host: the merges and the final stage read
+// per-pair records of stencil, fractions and a phase already reduced to turns.
 // Echoes, profiles and subimages may be stored as half or bfloat16 pairs
 // (template parameter ST); every sum is float32.  With IEEE half each stage's
 // array carries a power-of-two scale, scales[0] for the profiles and scales[d]
@@ -348,25 +350,25 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
     }
 }
 
-// Merge at depth d: parent grid points (float64 SoA) of the depth-d nodes,
-// children at depth d + 1.  Output: compressed parent values.  One wave per
-// (64 parent points, child): a block of kBlock threads covers kBlock / CL
-// points, wave w interpolating child w % CL for point group w / CL, so each
-// wave's gathers stay within one child and follow its points' pencils.  The
-// children's rotated values meet in LDS and are summed in child order.  A
-// launch thus has CL times as many waves as points / 64 to hide the gathers'
-// latency.  Each wave restores its child's downconversion (exp(+j Phi_c));
-// the parent's (exp(-j Phi_P)) is applied once to the sum.
+// Merge at depth d: parent grid points of the depth-d nodes, children at
+// depth d + 1.  Output: compressed parent values.  One wave per (64 parent
+// points, child): a block of kBlock threads covers kBlock / CL points, wave w
+// interpolating child w % CL for point group w / CL, so each wave's gathers
+// stay within one child and follow its points' pencils.  Each lane reads its
+// pair's plan-time record (stencil, fractions, and the phase Phi_c - Phi_P
+// that restores the child's downconversion and applies the parent's), so the
+// kernel holds no geometry; the rotated children meet in LDS and are summed in
+// child order.  A launch thus has CL times as many waves as points / 64 to
+// hide the gathers' latency.
 template <int T, int ST, int K, int CL>
 __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ parents,
                                                   const BlockItem *__restrict__ blocks,
-                                                  const double *__restrict__ px,
-                                                  const double *__restrict__ py,
-                                                  const double *__restrict__ pz,
+                                                  const InterpIdx *__restrict__ ridx,
+                                                  const InterpGeo *__restrict__ rgeo,
                                                   const NodeDev *__restrict__ children,
-                                                  const ColEntry *__restrict__ ccols,
+                                                  const int32_t *__restrict__ ccolbase,
                                                   const typename Store<ST>::C *__restrict__ cvals,
-                                                  GeoParams gp, const InterpPoly ip,
+                                                  const InterpPoly ip,
                                                   const float *__restrict__ scales, int sp,
                                                   int sc, typename Store<ST>::C *__restrict__ out)
 {
@@ -375,28 +377,28 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     const int lane = (int)(threadIdx.x % 64);
     const int c = wave % CL, grp = wave / CL;
-    const BlockItem blk = blocks[xcd_block<0>((int)blockIdx.x, (int)gridDim.x)];
-    const NodeDev nd = parents[blk.node];
+    const int lb = xcd_block<0>((int)blockIdx.x, (int)gridDim.x);
+    const BlockItem blk = blocks[lb];
+    // the parent's fields one by one: a copy of the whole node would go through
+    // scratch memory, as child[c] is indexed at run time
+    const NodeDev *nd = parents + blk.node;
+    const int npts = nd->npts, vbase = nd->val_base;
     const int p = blk.start + grp * 64 + lane;
-    const bool inside = p < nd.npts;
-    const int gi = nd.val_base + (inside ? p : 0);
-    double x = 0.0, y = 0.0, z = 0.0;
-    if (inside) {
-        x = px[gi];
-        y = py[gi];
-        z = pz[gi];
-    }
-    const bool present = inside && z > 0.0;  // an absent grid point (no preimage) holds 0
+    const size_t r = (size_t)lb * kBlock + threadIdx.x;
+    const InterpIdx ix = ridx[r];
     float are = 0.0f, aim = 0.0f;
-    if (present && c < nd.nchild) {
-        const NodeDev ch = children[parents[blk.node].child[c]];
-        const ChildCoord g = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
-        const float2 v = interp_child<T, ST, K>(ch, ccols, cvals, g, ip);
-        phase_mac(v, g.phi, are, aim);
+    if (ix.cij != kNoPair) {
+        const InterpGeo g = rgeo[r];
+        const NodeDev ch = children[nd->child[c]];
+        float wu[T], wv[T], wn[T];
+        interp_weights3<T, K>(ip, g.fu, g.fv, g.fn, wu, wv, wn);
+        const float2 v = interp_rec<T, ST>(ch, ccolbase, cvals, (int)(ix.cij & 0xffffu),
+                                           (int)(ix.cij >> 16), ix.l0, wu, wv, wn);
+        rotate_mac(v, g.turns, are, aim);
     }
     part[threadIdx.x] = make_float2(are, aim);
     __syncthreads();
-    if (c == 0 && inside) {
+    if (c == 0 && p < npts) {
         float sre = 0.0f, sim = 0.0f;
 #pragma unroll
         for (int k = 0; k < CL; ++k) {
@@ -404,11 +406,9 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
             sre += q.x;
             sim += q.y;
         }
-        // the parent's own downconversion, once per point rather than per child
-        float ore = 0.0f, oim = 0.0f;
-        if (present) phase_mac(make_float2(sre, sim), -phi_only(nd, x, y, z, gp.kmin, gp.kmax), ore, oim);
+        // an absent parent point (no preimage) has no pairs and holds 0
         const float rs = scales[sp] / scales[sc];
-        out[gi] = Store<ST>::st(make_float2(rs * ore, rs * oim));
+        out[vbase + p] = Store<ST>::st(make_float2(rs * sre, rs * sim));
     }
 }
 
@@ -419,17 +419,21 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
 // values over the brick's stencil box (TileBox, from the plan) into LDS, dense
 // and zero outside the pencils: a wave per column, its lanes along n, the
 // column entry a scalar load.  A lane whose stencil lies inside the box then
-// reads its T^3 taps from LDS in the same order as the pencil path below; one
-// outside it (or a child without a box) gathers from the pencils.
+// reads its T^3 taps from LDS in the same order as the pencil path; one
+// outside it (or a child without a box) gathers from the pencils.  Each
+// (voxel, child) pair's stencil, fractions and phase Phi_c come from its
+// plan-time record.
 template <int T, int ST, int K>
 __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ children,
                                                   int nchild, const ColEntry *__restrict__ ccols,
+                                                  const int32_t *__restrict__ ccolbase,
                                                   const typename Store<ST>::C *__restrict__ cvals,
                                                   const TileBox *__restrict__ tiles,
-                                                  GeoParams gp, const InterpPoly ip,
+                                                  const InterpIdx *__restrict__ ridx,
+                                                  const InterpGeo *__restrict__ rgeo,
+                                                  const InterpPoly ip,
                                                   const float *__restrict__ scales, int sc,
-                                                  double ox, double oy, double oz, double sx,
-                                                  double sy, double sz, int nx, int ny, int nz,
+                                                  int nx, int ny, int nz,
                                                   float2 *__restrict__ image)
 {
     __shared__ float2 s_tile[kTileCap];
@@ -440,8 +444,6 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
     const int ix = kx * kBrickX + t / (kBrickY * kBrickZ), iy = ky * kBrickY + (t / kBrickZ) % kBrickY,
               iz = kz * kBrickZ + t % kBrickZ;
     const bool inside = ix < nx && iy < ny && iz < nz;
-    const double x = ox + ix * sx, y = oy + iy * sy, z = oz + iz * sz;
-    const int wave = __builtin_amdgcn_readfirstlane(t / 64), lane = t % 64;
     float are = 0.0f, aim = 0.0f;
     for (int c = 0; c < nchild; ++c) {
         const NodeDev ch = children[c];
@@ -462,9 +464,9 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
                 const int cj = col - ci * tb.nj;
                 const ColEntry en = ccols[ch.col_base + (tb.i0 + ci - ch.i0) * ch.nj + (tb.j0 + cj - ch.j0)];
                 const int l = e & ((1 << tb.lsh) - 1);
-                const int r = tb.l0 + l - en.lo;  // position in the pencil
-                take[k] = e < items && l < tb.nl && r >= 0 && r <= en.hi - en.lo;
-                roff[k] = take[k] ? ch.val_base + en.off + r : 0;
+                const int rr = tb.l0 + l - en.lo;  // position in the pencil
+                take[k] = e < items && l < tb.nl && rr >= 0 && rr <= en.hi - en.lo;
+                roff[k] = take[k] ? ch.val_base + en.off + rr : 0;
             }
             float2 v[kStageBox];
 #pragma unroll
@@ -474,17 +476,22 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
                 if (k * kBlock + t < items) s_tile[k * kBlock + t] = take[k] ? v[k] : make_float2(0.0f, 0.0f);
         }
         __syncthreads();
-        if (inside) {
-            const ChildCoord g = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
-            const int ti = g.bi - T / 2 + 1 - tb.i0, tj = g.bj - T / 2 + 1 - tb.j0,
-                      tl = g.bl - T / 2 + 1 - tb.l0;
+        const size_t r = ((size_t)brick * nchild + c) * kBlock + t;
+        const InterpIdx rx = ridx[r];
+        if (inside && rx.cij != kNoPair) {
+            const InterpGeo g = rgeo[r];
+            const int ci0 = (int)(rx.cij & 0xffffu), cj0 = (int)(rx.cij >> 16);
+            float wu[T], wv[T], wn[T];
+            interp_weights3<T, K>(ip, g.fu, g.fv, g.fn, wu, wv, wn);
+            const int ti = ci0 + ch.i0 - tb.i0, tj = cj0 + ch.j0 - tb.j0, tl = rx.l0 - tb.l0;
             float2 val;
             if (tb.ni > 0 && (unsigned)ti <= (unsigned)(tb.ni - T) &&
                 (unsigned)tj <= (unsigned)(tb.nj - T) && (unsigned)tl <= (unsigned)(tb.nl - T))
-                val = interp_box<T, K>(s_tile + ((ti * tb.nj + tj) << tb.lsh) + tl, tb.nj, 1 << tb.lsh, g, ip);
+                val = interp_box<T>(s_tile + ((ti * tb.nj + tj) << tb.lsh) + tl, tb.nj, 1 << tb.lsh,
+                                    wu, wv, wn);
             else
-                val = interp_child<T, ST, K>(ch, ccols, cvals, g, ip);
-            phase_mac(val, g.phi, are, aim);
+                val = interp_rec<T, ST>(ch, ccolbase, cvals, ci0, cj0, rx.l0, wu, wv, wn);
+            rotate_mac(val, g.turns, are, aim);
         }
     }
     if (inside) {
@@ -793,16 +800,15 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
                          hipEvent_t *ev)
 {
     using C = typename Store<ST>::C;
-    GeoParams gp{P.gamma[0], P.gamma[1], P.gamma[2], P.kmin, P.kmax};
     for (int d = P.S - 1; d >= P.F; --d) {
         if (P.n_blocks_merge_fwd[d] > 0) {
             hipLaunchKernelGGL((k_merge<T, ST, K, CL>), dim3(P.n_blocks_merge_fwd[d]), dim3(kBlock),
                                0, st, (const NodeDev *)P.dev.nodes[d],
-                               (const BlockItem *)P.dev.merge_blocks_fwd[d], (const double *)P.dev.px[d],
-                               (const double *)P.dev.py[d], (const double *)P.dev.pz[d],
+                               (const BlockItem *)P.dev.merge_blocks_fwd[d],
+                               (const InterpIdx *)P.dev.merge_idx[d], (const InterpGeo *)P.dev.merge_geo[d],
                                (const NodeDev *)P.dev.nodes[d + 1],
-                               (const ColEntry *)P.dev.cols[d + 1],
-                               (const C *)(ws + P.ws_vals[d + 1]), gp, P.ipoly, scales,
+                               (const int32_t *)P.dev.colbase[d + 1],
+                               (const C *)(ws + P.ws_vals[d + 1]), P.ipoly, scales,
                                P.scale_slot(d), P.scale_slot(d + 1), (C *)(ws + P.ws_vals[d]));
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
@@ -811,14 +817,12 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
     }
     const hhffbp_config &c = P.cfg;
     const int nx = (int)c.grid_dims[0], ny = (int)c.grid_dims[1], nz = (int)c.grid_dims[2];
-    const int64_t nv = (int64_t)nx * ny * nz;
-    (void)nv;
     hipLaunchKernelGGL((k_final<T, ST, K>), dim3(P.n_bricks), dim3(kBlock), 0, st,
                        (const NodeDev *)P.dev.nodes[P.F], (int)P.compact_to_tree[P.F].size(),
-                       (const ColEntry *)P.dev.cols[P.F], (const C *)(ws + P.ws_vals[P.F]),
-                       (const TileBox *)P.dev.final_tiles, gp, P.ipoly, scales, P.scale_slot(P.F),
-                       c.grid_origin[0], c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0],
-                       c.grid_pitch[1], c.grid_pitch[2], nx, ny, nz, (float2 *)image);
+                       (const ColEntry *)P.dev.cols[P.F], (const int32_t *)P.dev.colbase[P.F],
+                       (const C *)(ws + P.ws_vals[P.F]), (const TileBox *)P.dev.final_tiles, (const InterpIdx *)P.dev.final_idx,
+                       (const InterpGeo *)P.dev.final_geo, P.ipoly, scales, P.scale_slot(P.F), nx, ny,
+                       nz, (float2 *)image);
     hipError_t e = hipGetLastError();
     if (ev && e == hipSuccess) (void)hipEventRecord(*ev, st);
     return e;

@@ -663,7 +663,111 @@ void validate(const hhffbp_config &c)
         bad("factorised imaging needs the grid at z > 0");
 }
 
+// Interpolation record of the pair (point p, child with map mc and grid Lc), with
+// the parent's SDC phase phi_parent (0 in the final stage).  The lattice
+// coordinates and stencil base are those build_lattice used to build Lc, so
+// every stencil lies inside Lc's pencils; that is checked here.
+void pair_record(const Plan &P, const SubarrayMap &mc, const HostLattice &Lc, const double *p,
+                 double phi_parent, InterpIdx &ix, InterpGeo &g)
+{
+    double w[3], phic;
+    mc.eval(p, w, &phic, nullptr);
+    int32_t base[3];
+    float frac[3];
+    for (int a = 0; a < 3; ++a) {
+        const double t = P.gamma[a] * w[a];
+        const double b = std::floor(t + kStencilEps);
+        base[a] = (int32_t)b;
+        frac[a] = (float)(t - b);
+    }
+    const int h = P.T / 2 - 1;
+    const int32_t ci0 = base[0] - h - Lc.i0, cj0 = base[1] - h - Lc.j0, l0 = base[2] - h;
+    bool ok = ci0 >= 0 && ci0 + P.T <= Lc.ni && cj0 >= 0 && cj0 + P.T <= Lc.nj && Lc.ni < 65536 &&
+              Lc.nj < 65536;
+    for (int a = 0; ok && a < P.T; ++a)
+        for (int b = 0; ok && b < P.T; ++b) {
+            const int64_t c = (int64_t)(ci0 + a) * Lc.nj + (cj0 + b);
+            ok = Lc.lo[c] <= l0 && l0 + P.T - 1 <= Lc.hi[c];
+        }
+    if (!ok) throw Error{HHFFBP_E_NUMERIC, "an interpolation stencil reaches outside its grid"};
+    double turns = (phic - phi_parent) * (0.5 / kPi);
+    turns -= std::rint(turns);
+    ix.cij = (uint32_t)ci0 | ((uint32_t)cj0 << 16);
+    ix.l0 = l0;
+    g = InterpGeo{frac[0], frac[1], frac[2], (float)turns};
+}
+
 }  // namespace
+
+// Records of the forward merge at depth d, in the order of its lanes: block k
+// of `blocks` (a node's points from `start`), thread t: wave t / 64 takes child
+// (t / 64) mod Q of point start + (t / 64) / Q * 64 + t mod 64.
+void merge_records(const Plan &P, int d, const std::vector<BlockItem> &blocks,
+                   std::vector<InterpIdx> &idx, std::vector<InterpGeo> &geo)
+{
+    const int nb = (int)blocks.size();
+    idx.assign((size_t)nb * kBlockThreads, InterpIdx{kNoPair, 0});
+    geo.assign((size_t)nb * kBlockThreads, InterpGeo{0, 0, 0, 0});
+    std::vector<SubarrayMap> maps_c;
+    std::vector<const HostLattice *> lats_c;
+    for (int32_t ti : P.compact_to_tree[d + 1]) {
+        maps_c.emplace_back(P.levels[d + 1][ti].rect, P.kmin, P.kmax);
+        lats_c.push_back(&P.levels[d + 1][ti].lat);
+    }
+    parallel_for(nb, 16, [&](int64_t b0, int64_t b1) {
+        for (int64_t k = b0; k < b1; ++k) {
+            const BlockItem bk = blocks[k];
+            const HostNode &hn = P.levels[d][P.compact_to_tree[d][bk.node]];
+            const SubarrayMap mp(hn.rect, P.kmin, P.kmax);
+            std::vector<int32_t> ch;  // compact indices of the non-empty children, in order
+            for (int32_t c : hn.children)
+                if (!P.levels[d + 1][c].empty()) ch.push_back(P.levels[d + 1][c].compact);
+            for (int t = 0; t < kBlockThreads; ++t) {
+                const int wave = t / 64, c = wave % P.Q;
+                const int64_t p = bk.start + (int64_t)(wave / P.Q) * 64 + t % 64;
+                if (p >= hn.lat.npts || c >= (int)ch.size()) continue;
+                const double *x = &hn.lat.xyz[3 * p];
+                if (!std::isfinite(x[2])) continue;  // absent parent point: value 0
+                double w[3], phip;
+                mp.eval(x, w, &phip, nullptr);
+                pair_record(P, maps_c[ch[c]], *lats_c[ch[c]], x, phip, idx[k * kBlockThreads + t],
+                            geo[k * kBlockThreads + t]);
+            }
+        }
+    });
+}
+
+// Records of the final stage: brick b (as the final kernel numbers them), node c
+// of depth F, lane t: voxel (kx 4 + t / 64, ky 4 + (t / 16) mod 4, kz 16 + t mod 16).
+void final_records(const Plan &P, std::vector<InterpIdx> &idx, std::vector<InterpGeo> &geo)
+{
+    const hhffbp_config &c = P.cfg;
+    const int64_t nx = c.grid_dims[0], ny = c.grid_dims[1], nz = c.grid_dims[2];
+    const int64_t by = (ny + kBrickY - 1) / kBrickY, bz = (nz + kBrickZ - 1) / kBrickZ;
+    const std::vector<int32_t> &nodes = P.compact_to_tree[P.F];
+    const int64_t nc = (int64_t)nodes.size();
+    idx.assign((size_t)(P.n_bricks * nc) * kBlockThreads, InterpIdx{kNoPair, 0});
+    geo.assign((size_t)(P.n_bricks * nc) * kBlockThreads, InterpGeo{0, 0, 0, 0});
+    std::vector<SubarrayMap> maps;
+    for (int32_t ti : nodes) maps.emplace_back(P.levels[P.F][ti].rect, P.kmin, P.kmax);
+    parallel_for(P.n_bricks, 16, [&](int64_t b0, int64_t b1) {
+        for (int64_t b = b0; b < b1; ++b) {
+            const int64_t kx = b / (by * bz), ky = (b / bz) % by, kz = b % bz;
+            for (int t = 0; t < kBlockThreads; ++t) {
+                const int64_t ix = kx * kBrickX + t / (kBrickY * kBrickZ),
+                              iy = ky * kBrickY + (t / kBrickZ) % kBrickY, iz = kz * kBrickZ + t % kBrickZ;
+                if (ix >= nx || iy >= ny || iz >= nz) continue;
+                const double p[3] = {c.grid_origin[0] + ix * c.grid_pitch[0],
+                                     c.grid_origin[1] + iy * c.grid_pitch[1],
+                                     c.grid_origin[2] + iz * c.grid_pitch[2]};
+                for (int64_t ch = 0; ch < nc; ++ch) {
+                    const size_t r = (size_t)((b * nc + ch) * kBlockThreads + t);
+                    pair_record(P, maps[ch], P.levels[P.F][nodes[ch]].lat, p, 0.0, idx[r], geo[r]);
+                }
+            }
+        }
+    });
+}
 
 // ---------------------------------------------------------------------------
 // Sec. IV-B counts the operations of HHFFBPA as C1 N_A N_f log N_f (range
@@ -976,12 +1080,15 @@ void upload_plan(Plan &P)
     const int S = P.S;
     P.dev.nodes.assign(S + 1, nullptr);
     P.dev.cols.assign(S + 1, nullptr);
+    P.dev.colbase.assign(S + 1, nullptr);
     P.dev.px.assign(S + 1, nullptr);
     P.dev.py.assign(S + 1, nullptr);
     P.dev.pz.assign(S + 1, nullptr);
     P.dev.merge_blocks.assign(S + 1, nullptr);
     P.dev.merge_blocks_fwd.assign(S + 1, nullptr);
     P.dev.merge_bricks.assign(S + 1, nullptr);
+    P.dev.merge_idx.assign(S + 1, nullptr);
+    P.dev.merge_geo.assign(S + 1, nullptr);
     P.n_blocks_merge.assign(S + 1, 0);
     P.n_blocks_merge_fwd.assign(S + 1, 0);
     P.device_bytes = 0;
@@ -1009,6 +1116,7 @@ void upload_plan(Plan &P)
     for (int d = P.F; d <= S; ++d) {
         std::vector<NodeDev> nodes;
         std::vector<ColEntry> cols;
+        std::vector<int32_t> colbase;
         std::vector<BlockItem> blocks, blocks_fwd;
         std::vector<double> x, y, z;
         std::vector<LeafPoint> lpts;
@@ -1045,7 +1153,10 @@ void upload_plan(Plan &P)
                 nd.pos_end = pos_cursor;
             }
             for (int64_t c = 0; c < (int64_t)L.ni * L.nj; ++c)
+            {
                 cols.push_back(ColEntry{(int32_t)L.off[c], L.lo[c], L.hi[c], 0});
+                colbase.push_back((int32_t)L.off[c] - L.lo[c]);
+            }
             for (int32_t st = 0; st < nd.npts; st += 256) blocks.push_back(BlockItem{hn.compact, st});
             // the forward merge runs one lane per (point, child): 256 / Q points a block
             for (int32_t st = 0; st < nd.npts; st += 256 / P.Q)
@@ -1125,6 +1236,7 @@ void upload_plan(Plan &P)
         }
         upload_vec(P.device_bytes, &D.nodes[d], nodes);
         upload_vec(P.device_bytes, &D.cols[d], cols);
+        upload_vec(P.device_bytes, &D.colbase[d], colbase);
         if (d < S) {
             upload_vec(P.device_bytes, &D.px[d], x);
             upload_vec(P.device_bytes, &D.py[d], y);
@@ -1134,6 +1246,11 @@ void upload_plan(Plan &P)
             upload_vec(P.device_bytes, &D.merge_blocks_fwd[d], blocks_fwd);
             upload_vec(P.device_bytes, &D.merge_bricks[d], P.merge_bricks[d]);
             P.n_blocks_merge_fwd[d] = (int64_t)blocks_fwd.size();
+            std::vector<InterpIdx> ridx;
+            std::vector<InterpGeo> rgeo;
+            merge_records(P, d, blocks_fwd, ridx, rgeo);
+            upload_vec(P.device_bytes, &D.merge_idx[d], ridx);
+            upload_vec(P.device_bytes, &D.merge_geo[d], rgeo);
         } else {
             upload_vec(P.device_bytes, &D.leafpts, lpts);
             upload_vec(P.device_bytes, &D.leaf_blocks, blocks);
@@ -1150,6 +1267,13 @@ void upload_plan(Plan &P)
             upload_vec(P.device_bytes, &D.adj_blocks, ab);
             P.n_blocks_adj = (int64_t)ab.size();
         }
+    }
+    {
+        std::vector<InterpIdx> ridx;
+        std::vector<InterpGeo> rgeo;
+        final_records(P, ridx, rgeo);
+        upload_vec(P.device_bytes, &D.final_idx, ridx);
+        upload_vec(P.device_bytes, &D.final_geo, rgeo);
     }
     // images at the plan's own positions read their leaf offsets from the plan,
     // formed once here by the same kernel that forms them for other positions
@@ -1192,8 +1316,10 @@ void release_plan(Plan &P)
     fr(D.Bd);
     fr(D.Badj);
     fr(D.scale_mult);
-    for (auto *v : {&D.nodes, &D.cols, &D.px, &D.py, &D.pz, &D.merge_blocks, &D.merge_blocks_fwd,
-                    &D.merge_bricks})
+    fr(D.final_idx);
+    fr(D.final_geo);
+    for (auto *v : {&D.nodes, &D.cols, &D.colbase, &D.px, &D.py, &D.pz, &D.merge_blocks, &D.merge_blocks_fwd,
+                    &D.merge_bricks, &D.merge_idx, &D.merge_geo})
         for (auto &p : *v) fr(p);
 }
 
