@@ -2,26 +2,34 @@
 """Throughput of HHFFBPA against direct backprojection on one MI355X.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+                    [--workload large|mid|autofocus|paper_sim]
 
-Workload: 16384 handheld positions (64 serpentine strokes over 0.3 x 0.3 m,
-2 mm lateral and 1 mm depth jitter), 64 frequencies 24-40 GHz, a 128x128x64
-voxel grid at 1.5 mm centred 0.3 m in front of the aperture, 50 point targets
-and a 10x10x10 scatterer cube; HHFFBPA with 3 merge stages of factor 4,
-band-limited interpolation weights on grids oversampled (2.0, 2.0, 2.4).
+Default workload ("HHFFBPA large"): 65536 handheld positions (44 serpentine
+strokes over 0.3 x 0.3 m plus 20 persistent walks in the central 80 mm,
+0.5-3.7 samples/mm^2), 128 frequencies 24-40 GHz, a 256x256x128 voxel grid at
+1 mm centred 0.3 m in front of the aperture, 200 point targets and a
+5000-scatterer slab of complex-normal amplitudes; float32 (complex64) storage.
+The timed form: HHFFBPA with 4 merge stages of factor 4 onto a compressed root
+grid with one resample to the voxels, band-limited interpolation weights on
+grids oversampled (2.2, 2.2, 2.6), range profiles at 4-fold range oversampling
+read by linear interpolation.  The mid workload (16384 positions, 64 f,
+128x128x64 voxels, 3 stages onto the voxel grid) is reported beside it.
 
-A step is one hhffbp_image call: range compression, level-1 backprojection,
-the two intermediate merges and the final merge, with the echoes already
-resident in device memory.  The timed form reads the range profiles by linear
-interpolation at 4-fold range oversampling; the ES-kernel form (the parity
-mode) is timed and reported beside it.  The direct-BP baseline is the fastest
-linear-kernel direct mode within -30 dB of the ES direct image.  The metric counts voxel x position
-backprojections: N_vox * N_pos per step (the direct-BP work that HHFFBPA
-replaces).  Plan construction (host) is timed separately and reported as
-``plan_ms``.  One JSON line is printed.
+A step is one hhffbp_image call: range compression, level-1 backprojection, the
+merges and the final resample, with the echoes already resident in device
+memory.  The metric counts voxel x position backprojections: N_vox * N_pos per
+step (the direct-BP work that HHFFBPA replaces).  Plan construction (host) is
+timed separately (``plan_ms``).  Beside the timed form: the ES parity mode on the
+same grids, half and bfloat16 storage, and the direct-BP baseline (the fastest
+linear-kernel direct mode within -30 dB of the ES direct image) and eq. (4)
+itself.  Errors are NRMSE against GPU ES direct BP on the full grid (itself
+<= 1e-5 of float64 eq. (4)) and, for the large workload, against float64 eq. (4)
+on the stored stratified voxel sample.  One JSON line is printed.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -29,77 +37,134 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "voxel·position backprojections/s, HHFFBPA vs direct BP on 1 GPU at ≤−30 dB NRMSE"
-GAMMA = (3.0, 3.0, 3.5)          # Lagrange interpolation grids
-BENCH_GAMMA = (2.0, 2.0, 2.4)    # band-limited interpolation grids (the timed form)
+BL_GAMMA = (2.2, 2.2, 2.6)       # band-limited interpolation grids (the timed form)
 BENCH_U = 4.0                    # range oversampling of its linear range kernel
 DIRECT_U = (2.0, 3.0, 4.0, 8.0)  # linear-kernel direct-BP candidates for the baseline
-AF_GAMMA = (2.2, 2.2, 2.6)       # band-limited grids of the autofocus workload
+AF_GAMMA = BL_GAMMA              # band-limited grids of the autofocus workload
 TAPS = 4
-# VALU issue peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane-ops/s
+# the timed form per workload index: stages and root grid
+TIMED = {2: dict(stages=4, root_grid=True), 1: dict(stages=3, root_grid=False)}
+WORKLOAD_NAME = {
+    2: "HHFFBPA large: 65536 handheld positions (44 serpentine strokes + 20 dense walks, "
+       "0.5-3.7 samples/mm^2), 128 f 24-40 GHz, 256x256x128 voxels at 1 mm, 200 points + "
+       "5000-scatterer slab at 0.33 m",
+    1: "HHFFBPA mid: 16384 handheld positions (64 serpentine strokes, 0.3x0.3 m), 64 f "
+       "24-40 GHz, 128x128x64 voxels at 1.5 mm, 50 points + 10x10x10 cube at 0.3 m",
+}
+# Peaks of MI355X (256 CUs at 2.4 GHz): VALU issue 256 x 4 SIMD x 16 lanes x 2.4 GHz
+# lane-ops/s (packed FP32 disabled, every VALU op one lane-op); FP32 MFMA
+# 157.3 TFLOP/s; vector L1 64 B/clk/CU; HBM 8 TB/s.
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
-# Algorithmic VALU lane-ops per (leaf grid point, position) backprojection: the
-# fixed per-unit yardstick of the range-compressed form, ~25 VALU + 3
-# transcendentals per pair, itemised as distance |q - p'| 7 (3 differences, 3
-# for the squared norm, sqrt), distance difference 6 (|d|^2 - 2 q.d as 3 FMA,
-# then / (R + R_c) as add, reciprocal, multiply), bin coordinate 4 (FMA, clamp,
-# floor, fraction), range read, carrier 3 (scale to turns, sin, cos), complex
-# accumulate 4.  Range read with the 7-tap ES kernel: weights 6 per tap, tap
-# sums 2 per tap.  (The kernel itself forms |q - p'| from |q - c|^2 plus the
+MFMA_F32_PEAK = 157.3e12
+L1_PEAK_BPS = 256 * 64 * 2.4e9
+HBM_PEAK_BPS = 8.0e12
+# Algorithmic VALU lane-ops per (leaf grid point, position) backprojection, the
+# fixed yardstick of the range-compressed form (~25 VALU + 3 transcendentals):
+# distance |q - p'| 7 (3 differences, 3 for the squared norm, sqrt), distance
+# difference 6 (|d|^2 - 2 q.d as 3 FMA, then / (R + R_c) as add, reciprocal,
+# multiply), bin coordinate 4 (FMA, clamp, floor, fraction), carrier 3 (scale to
+# turns, sin, cos), complex accumulate 4; range read with the 7-tap ES kernel:
+# weights 6 per tap, tap sums 2 per tap; with the linear kernel v0 + x (v1 - v0)
+# per component (4).  (The kernel forms |q - p'| from |q - c|^2 plus the
 # distance-difference numerator and issues fewer than this count.)
 LEAF_OPS_PER_PAIR = 7 + 6 + 4 + 6 * 7 + 2 * 7 + 3 + 4
-# ... and with the linear range kernel: v0 + x (v1 - v0) per component (4).
 LEAF_OPS_LINEAR = 7 + 6 + 4 + 4 + 3 + 4
+# Algorithmic VALU lane-ops per (point, child) interpolation of a merge or the
+# final stage (T = 4, band-limited weights, geometry from the plan's records):
+# weights 54 (per axis y = x - 1/2, y^2, two 3-FMA Horner chains per tap pair
+# and the even/odd combination), taps 176 (64 x 2 FMA, and per column the
+# weight product and 2 FMA), rotation by the pair's phase 6 (sin, cos, 4 FMA).
+INTERP_OPS_PER_PAIR = 54 + 176 + 6
 KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "hhffbp_internal.hpp")
-TRAFFIC_SUMMARY = "hhffbp_mid_hbm_traffic.md"
+TRAFFIC_SUMMARY = "hhffbp_large_hbm_traffic.md"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def oracle_cpu_baseline(w, target_s=15.0):
-    """The float64 oracle's eq. (4) on seeded voxels of the same workload.
+def host_description():
+    """nproc, the usable cores and the CPU model of this host."""
+    out = {"nproc": os.cpu_count(), "usable_cores": len(os.sched_getaffinity(0))}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                             "CPU(s)"):
+                out[k.strip()] = v.strip()
+    except Exception:
+        pass
+    return out
 
-    The sample grows by 4x until one pass takes >= 2 s, then is sized for about
-    ``target_s`` seconds of oracle work; only the last pass is reported."""
+
+def oracle_cpu_baseline(w, index, target_s=12.0):
+    """The float64 oracle on the host cores: eq. (4) on voxels of the stored
+    stratified sample (large: the point targets' boxes and seeded uniform voxels
+    of tests/golden/large_oracle.npz; mid: seeded voxels), on all the threads the
+    oracle uses and on one; and the oracle HHFFBPA on one 4x4x4 voxel brick,
+    through the cone of grid points its stencils reach (oracle.hhffbp.image_at)."""
     import numpy as np
 
     from oracle import hhffbp as OH
     from oracle import native
+    from oracle import plan as OP
     from workloads import voxel_centres
 
     vox = voxel_centres(w.grid_origin, w.grid_pitch, w.grid_dims)
-    nv = vox.shape[0]
+    if index == 2:
+        pool = np.load(os.path.join(ROOT, "tests", "golden", "large_oracle.npz"))["index"]
+        what = "the stored stratified sample (target boxes + seeded uniform voxels)"
+    else:
+        pool = np.arange(vox.shape[0])
+        what = "seeded voxels"
     rng = np.random.default_rng(3)
+    cores = native._nthreads()
     n = 8
     while True:
-        sel = rng.choice(nv, n, replace=False)
+        sel = rng.choice(pool, n, replace=False)
         t = time.time()
         OH.direct_bp(w.positions, w.freqs_hz, w.echoes, vox[sel])
         dt = time.time() - t
-        if dt >= 2.0 or n >= nv:
+        if dt >= 1.5 or n >= pool.size:
             break
-        n = min(nv, 4 * n)
-    n2 = int(min(nv, max(n, round(n * target_s / max(dt, 1e-3)))))
-    sel = rng.choice(nv, n2, replace=False)
+        n = min(pool.size, 4 * n)
+    n2 = int(min(pool.size, max(n, round(n * target_s / max(dt, 1e-3)))))
+    sel = rng.choice(pool, n2, replace=False)
     t = time.time()
     OH.direct_bp(w.positions, w.freqs_hz, w.echoes, vox[sel])
     dt = time.time() - t
-    cores = native._nthreads()
-    # the same sum on one thread (the paper's CPU figures are single-threaded),
-    # on a sample sized for about a third of the time above
-    n1 = int(max(8, min(nv, round(n2 / cores / 3))))
-    sel1 = rng.choice(nv, n1, replace=False)
+    n1 = int(max(8, min(pool.size, round(n2 / cores / 3))))
+    sel1 = rng.choice(pool, n1, replace=False)
     k = 2.0 * np.pi * np.asarray(w.freqs_hz, float) / 299792458.0
     t = time.time()
     native.bp_eq4(w.positions, k, w.echoes, vox[sel1], nthreads=1)
     dt1 = time.time() - t
-    return {"value": n2 * w.n_pos / dt, "unit": "vp/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"float64 eq. (4) on {n2} seeded voxels x {w.n_pos} positions x "
-                      f"{w.n_f} frequencies of the same workload ({dt:.1f} s)",
+    # the oracle HHFFBPA (timed form's grid choices, S = 3 onto the voxel grid) on
+    # one brick of 64 voxels at the grid centre
+    t = time.time()
+    op = OP.build_plan(w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims, 3, 4,
+                       BL_GAMMA, TAPS, kernel="bandlimited")
+    plan_s = time.time() - t
+    d = np.asarray(w.grid_dims)
+    c = d // 2 - 2
+    r = np.arange(4)
+    bx = [((c[0] + a) * d[1] + c[1] + b) * d[2] + c[2] + e for a in r for b in r for e in r]
+    t = time.time()
+    OH.image_at(op, w.echoes, w.positions, np.array(bx), range_u=BENCH_U)
+    dth = time.time() - t
+    return {"value": n2 * w.n_pos / dt, "unit": "vp/s", "cores": cores, "kind": "oracle",
+            "sample": f"float64 eq. (4) on {n2} voxels of {what} x {w.n_pos} positions x "
+                      f"{w.n_f} frequencies ({dt:.1f} s)",
             "value_1thread": n1 * w.n_pos / dt1,
-            "sample_1thread": f"{n1} seeded voxels on one thread ({dt1:.1f} s)"}
+            "sample_1thread": f"{n1} voxels of the same sample on one thread ({dt1:.1f} s)",
+            "hhffbp_oracle": {"value": 64 * w.n_pos / dth, "unit": "vp/s", "seconds": dth,
+                              "plan_seconds": plan_s,
+                              "sample": "oracle HHFFBPA (S=3, band-limited (2.2, 2.2, 2.6), "
+                                        "linear U=4) on one 4x4x4 voxel brick through its "
+                                        "stencil cone; a cone does not amortise the level-1 "
+                                        "sums over the image as a whole image does"},
+            "host": host_description()}
 
 
 def kernel_source_hash():
@@ -278,12 +343,232 @@ def paper_sim_report(args):
                           "bpa_s": 187.52, "hhffbpa_s": 3.02, "table": "III"}}), flush=True)
 
 
+def imaging_report(args, index):
+    """The imaging benchmark on workload ``index`` (2: large, 1: mid); returns
+    the JSON record (see the module docstring)."""
+    import numpy as np
+    import torch
+
+    import paper_2506_23568_amd as H
+    from workloads import make_config
+
+    log(f"synthesising workload {index} (float64 sums on the GPU)")
+    w = make_config(index, synth_device="cuda")
+    args3 = (w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims)
+    dev = torch.device("cuda:0")
+    ech = torch.from_numpy(w.echoes.astype(np.complex64)).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    vp = w.n_vox * w.n_pos
+    form = dict(merge_factor=4, oversample=BL_GAMMA, interp_taps=TAPS, interp_kernel="bandlimited",
+                **TIMED[index])
+
+    def timed(plan, e, steps, warmup):
+        """(ms per image over ``steps`` calls, per-stage ms, image).  The timed
+        region holds the images alone; the per-stage times come from the same
+        number of images right after it, with a HIP event on the launch stream
+        after each stage (events between the kernels cost ~5 us each, so they
+        stay out of the timed region)."""
+        ws = plan._workspace(torch)
+        img = torch.empty(w.grid_dims, dtype=torch.complex64, device=dev)
+        for _ in range(warmup):
+            plan.image(e, out=img, workspace=ws)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.image(e, out=img, workspace=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        if args.only_timed:
+            return ms, {}, img
+        plan.profile_begin(steps)
+        for _ in range(steps):
+            plan.image(e, out=img, workspace=ws)
+        torch.cuda.synchronize()
+        st = plan.profile_end()
+        return ms, {k: v[0] / max(v[1], 1) for k, v in st.items()}, img
+
+    t = time.time()
+    plan = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, **form)
+    plan_ms = (time.time() - t) * 1e3
+    info = plan.info()
+    log("warm-up and timed steps")
+    ms, kernels_ms, img = timed(plan, ech, args.steps, args.warmup)
+    value = vp / (ms * 1e-3)
+    rec = {
+        "metric": METRIC, "value": value, "unit": "vp/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD_NAME[index], "n_pos": w.n_pos, "n_freq": w.n_f,
+                   "grid": list(w.grid_dims), "merge_factor": 4, "oversample": list(BL_GAMMA),
+                   "interp_taps": TAPS, "interp_kernel": "bandlimited", "range_kernel": "linear",
+                   "range_oversample": BENCH_U, "storage": "c64", "parallelism": "single GPU",
+                   **TIMED[index]},
+        "plan_ms": plan_ms, "kernels_ms": kernels_ms,
+        "work": {"leaf_pairs": info["leaf_pairs"], "merge_pairs": info["merge_pairs"],
+                 "final_pairs": info["final_pairs"], "level_points": info["level_points"],
+                 "n_range_bins": info["n_range_bins"], "plan_device_bytes": info["device_bytes"]},
+    }
+    if args.only_timed:
+        return rec
+
+    log("references: ES direct BP (full grid) and the float64 sample")
+    ref = H.Plan(*args3, mode="direct_rc", range_kernel="es", range_oversample=2.0,
+                 range_taps=7).image(ech)
+    torch.cuda.synchronize()
+    nref = torch.linalg.norm(ref)
+    sample = None
+    if index == 2:
+        g = np.load(os.path.join(ROOT, "tests", "golden", "large_oracle.npz"))
+        sample = (torch.from_numpy(g["index"]).to(dev), g["bp"])
+
+    def errors(im):
+        out = {"nrmse_vs_direct_db": 20 * np.log10((torch.linalg.norm(im - ref) / nref).item())}
+        if sample is not None:
+            s = im.reshape(-1)[sample[0]].cpu().numpy().astype(np.complex128)
+            out["nrmse_vs_fp64_sample_db"] = float(
+                20 * np.log10(np.linalg.norm(s - sample[1]) / np.linalg.norm(sample[1])))
+        return out
+
+    rec.update(errors(img))
+
+    def roofline_rows(kms, inf, leaf_ops, val_bytes):
+        """Per-kernel achieved rate against its bound, from the per-stage times."""
+        rows = {}
+        lms = kms.get("leaf_bp")
+        if lms:
+            a = inf["leaf_pairs"] * leaf_ops / (lms * 1e-3)
+            rows["leaf_bp"] = {"bound": "alu", "ms": lms, "ops_per_pair": leaf_ops,
+                               "pairs": inf["leaf_pairs"], "achieved": a / 1e12,
+                               "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+                               "frac": a / VALU_PEAK_OPS}
+        rms = kms.get("rc_gemm")
+        if rms:
+            fl = 2.0 * w.n_pos * (2 * w.n_f) * (2 * inf["n_range_bins"])
+            rows["rc_gemm"] = {"bound": "mfma", "ms": rms, "flop": fl,
+                               "achieved": fl / (rms * 1e-3) / 1e12, "peak": MFMA_F32_PEAK / 1e12,
+                               "unit": "TFLOP/s", "frac": fl / (rms * 1e-3) / MFMA_F32_PEAK}
+        # interpolation kernels: VALU by the algorithmic count, and the gathers
+        # through the vector L1 (16 column bases of 4 B, 64 taps, the 24-B record)
+        gb = 16 * 4 + 64 * val_bytes + 24
+        mpairs = {}
+        for name, t in kms.items():
+            if name.startswith("merge_d") or name == "final":
+                mpairs[name] = t
+        for name, t in mpairs.items():
+            pairs = inf["final_pairs"] if name == "final" else None
+            if pairs is None:
+                # pairs of the merge at depth d: that depth's points x children
+                pairs = inf["merge_pairs_depth"][int(name[len("merge_d"):])]
+            if not pairs:
+                continue
+            va = pairs * INTERP_OPS_PER_PAIR / (t * 1e-3)
+            ga = pairs * gb / (t * 1e-3)
+            rows[name] = {"bound": "alu", "ms": t, "pairs": pairs,
+                          "ops_per_pair": INTERP_OPS_PER_PAIR, "achieved": va / 1e12,
+                          "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+                          "frac": va / VALU_PEAK_OPS, "gather_bytes_per_pair": gb,
+                          "gather_frac_of_l1": ga / L1_PEAK_BPS}
+        return rows
+
+    kern = roofline_rows(kernels_ms, info, LEAF_OPS_LINEAR, 8)
+    lr = kern["leaf_bp"]
+    # algorithmic bytes of the level-1 BP: profiles + leaf points (32 B) + antenna
+    # offsets (16 B) in, subimages out (8 B per point)
+    pts = info["level_points"][-1]
+    rec["roofline"] = {"kernel": "leaf_bp", "bound": "alu", "achieved": lr["achieved"],
+                       "peak": lr["peak"], "unit": "Tops/s", "frac": lr["frac"],
+                       "traffic": measured_traffic("leaf_bp"),
+                       "ops_per_pair": LEAF_OPS_LINEAR, "pairs_per_launch": info["leaf_pairs"],
+                       "avg_launch_ms": lr["ms"],
+                       "algorithmic_bytes": w.n_pos * info["n_range_bins"] * 8 + pts * 32
+                       + w.n_pos * 16 + pts * 8}
+    rec["kernels_roofline"] = kern
+
+    log("parity mode (ES range kernel), half storage and the S = 3 voxel-root form")
+    extra = {}
+    pl_es = H.Plan(*args3, range_kernel="es", range_oversample=2.0, range_taps=7, **form)
+    ms_es, k_es, img_es = timed(pl_es, ech, max(3, args.steps // 2), 1)
+    extra["hhffbp_es"] = {"value": vp / (ms_es * 1e-3), "ms": ms_es, "kernels_ms": k_es,
+                          "mode": "ES U=2 W=7 (parity mode), same grids", **errors(img_es)}
+    del pl_es, img_es
+    for st in ("f16", "bf16"):
+        pl_h = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, storage=st, **form)
+        eh = H.Plan.pack_echoes(ech, st)
+        ms_h, k_h, img_h = timed(pl_h, eh, max(3, args.steps // 2), 1)
+        extra[f"hhffbp_{st}"] = {
+            "value": vp / (ms_h * 1e-3), "ms": ms_h, "kernels_ms": k_h,
+            "mode": f"{st} storage of echoes, profiles and subimages, f32 arithmetic",
+            "nrmse_vs_f32_storage": (torch.linalg.norm(img_h - img) / torch.linalg.norm(img)).item(),
+            **errors(img_h)}
+        del pl_h, eh, img_h
+    alt = dict(form, stages=3, root_grid=False) if index == 2 else dict(form, stages=4, root_grid=True)
+    pl_a = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, **alt)
+    ms_a, k_a, img_a = timed(pl_a, ech, max(3, args.steps // 2), 1)
+    extra["hhffbp_alt"] = {"value": vp / (ms_a * 1e-3), "ms": ms_a, "kernels_ms": k_a,
+                           "mode": f"S={alt['stages']}, root grid {alt['root_grid']}",
+                           **errors(img_a)}
+    del pl_a, img_a
+    torch.cuda.empty_cache()
+
+    log("direct-BP baselines")
+    candidates = {}
+    for u in DIRECT_U:
+        fast = H.Plan(*args3, mode="direct_rc", range_kernel="linear", range_oversample=u)
+        dimg = fast.image(ech)
+        torch.cuda.synchronize()
+        nd = 2 if index == 2 else 3
+        d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        d0.record(stream)
+        for _ in range(nd):
+            fast.image(ech, out=dimg)
+        d1.record(stream)
+        torch.cuda.synchronize()
+        candidates[f"linear U={u:g}"] = (d0.elapsed_time(d1) / nd,
+                                         (torch.linalg.norm(dimg - ref) / nref).item())
+        del fast, dimg
+    ok = {k: v for k, v in candidates.items() if 20 * np.log10(v[1]) <= -30.0}
+    d_mode = min(ok, key=lambda k: ok[k][0])
+    dms, d_nrmse = ok[d_mode]
+    direct_vp = vp / (dms * 1e-3)
+    ex_plan = H.Plan(*args3, mode="direct_exact")
+    ex_img = ex_plan.image(ech)
+    torch.cuda.synchronize()
+    x0, x1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    x0.record(stream)
+    ex_plan.image(ech, out=ex_img)
+    x1.record(stream)
+    torch.cuda.synchronize()
+    ex_ms = x0.elapsed_time(x1)
+    ex_err = errors(ex_img)
+    del ex_img, ex_plan
+    rec.update({
+        "reference": "float32 direct BP, ES range kernel U=2 W=7 (<= 1e-5 of float64 eq. 4), "
+                     "full grid" + ("; float64 eq. (4) on the stored stratified sample of "
+                                    "22212 voxels" if index == 2 else ""),
+        **extra,
+        "direct_bp": {"value": direct_vp, "unit": "vp/s", "ms": dms, "mode": d_mode,
+                      "nrmse_vs_es_direct_db": 20 * np.log10(d_nrmse),
+                      "candidates": {k: {"ms": v[0], "nrmse_vs_es_direct_db": 20 * np.log10(v[1])}
+                                     for k, v in candidates.items()}},
+        "direct_exact": {"value": vp / (ex_ms * 1e-3), "unit": "vp/s", "ms": ex_ms,
+                         "mode": f"eq. (4): Horner sum over the {w.n_f} frequencies per pair",
+                         **ex_err},
+        "speedup_vs_direct": value / direct_vp,
+    })
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-timed", action="store_true",
+                    help="time the benchmarked form alone (no references, no other forms): "
+                         "for kernel traces and counter runs")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain copy of this size first (HBM counter scale)")
     ap.add_argument("--af-range", choices=("es", "linear"), default="linear",
@@ -294,10 +579,12 @@ def main():
                     help="autofocus workload: plans with a compressed root grid (the "
                          "last merge onto the full aperture's lattice, one resample to "
                          "the voxels)")
-    ap.add_argument("--workload", choices=["mid", "autofocus", "paper_sim"], default="mid",
-                    help="mid: the imaging benchmark (default); autofocus: the trajectory "
-                         "correction loop on the large scene; paper_sim: the paper's "
-                         "simulation geometry with point-response metrics")
+    ap.add_argument("--workload", choices=["large", "mid", "autofocus", "paper_sim"],
+                    default="large",
+                    help="large: the imaging benchmark (default; the mid workload is "
+                         "reported beside it); mid: the mid workload alone; autofocus: "
+                         "the trajectory correction loop on the large scene; paper_sim: "
+                         "the paper's simulation geometry with point-response metrics")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (the voxel "
@@ -311,174 +598,26 @@ def main():
         paper_sim_report(args)
         return
 
-    import numpy as np
     import torch
-
-    import paper_2506_23568_amd as H
-    from workloads import make_config
 
     if args.copy_mib > 0:
         copy_probe(torch, args.copy_mib)
-    log("synthesising the workload")
-    w = make_config(1)
-    args3 = (w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims)
-    dev = torch.device("cuda:0")
-    ech = torch.from_numpy(w.echoes.astype(np.complex64)).to(dev)
-    stream = torch.cuda.current_stream(dev)
-    kw = dict(stages=3, merge_factor=4, oversample=BENCH_GAMMA, interp_taps=TAPS,
-              interp_kernel="bandlimited")
-
-    def timed(plan, steps, warmup):
-        """(ms per image over ``steps`` calls, per-stage ms, image).  The timed
-        region holds the images alone; the per-stage times come from the same
-        number of images right after it, with a HIP event on the launch stream
-        after each stage (events between the kernels cost ~5 us each, so they
-        stay out of the timed region)."""
-        ws = plan._workspace(torch)
-        img = torch.empty(w.grid_dims, dtype=torch.complex64, device=dev)
-        for _ in range(warmup):
-            plan.image(ech, out=img, workspace=ws)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(steps):
-            plan.image(ech, out=img, workspace=ws)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        plan.profile_begin(steps)
-        for _ in range(steps):
-            plan.image(ech, out=img, workspace=ws)
-        torch.cuda.synchronize()
-        st = plan.profile_end()
-        return ms, {k: v[0] / max(v[1], 1) for k, v in st.items()}, img
-
-    # the benchmarked form: band-limited interpolation weights on grids with
-    # gamma = (2.0, 2.0, 2.4), range profiles read by linear interpolation at
-    # U = 4
-    t = time.time()
-    plan = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, **kw)
-    plan_ms = (time.time() - t) * 1e3
-    info = plan.info()
-    log("warm-up and timed steps")
-    ms, kernels_ms, img = timed(plan, args.steps, args.warmup)
-    value = w.n_vox * w.n_pos / (ms * 1e-3)
-
-    log("parity-mode HHFFBPA (ES range kernel), the Lagrange form and the direct-BP references")
-    plan_es = H.Plan(*args3, range_kernel="es", range_oversample=2.0, range_taps=7, **kw)
-    ms_es, kernels_es, img_es = timed(plan_es, max(3, args.steps // 2), 1)
-    plan_lg = H.Plan(*args3, stages=3, merge_factor=4, oversample=GAMMA, interp_taps=TAPS,
-                     range_kernel="linear", range_oversample=8.0)
-    ms_lg, kernels_lg, img_lg = timed(plan_lg, max(3, args.steps // 2), 1)
-    # the benchmarked form with a compressed root grid and one resample to the voxels
-    plan_rg = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, root_grid=True, **kw)
-    ms_rg, kernels_rg, img_rg = timed(plan_rg, max(3, args.steps // 2), 1)
-    info_rg = plan_rg.info()
-    ref_plan = H.Plan(*args3, mode="direct_rc", range_kernel="es", range_oversample=2.0,
-                      range_taps=7)
-    ref = ref_plan.image(ech)
-    torch.cuda.synchronize()
-    nref = torch.linalg.norm(ref)
-    nrmse = (torch.linalg.norm(img - ref) / nref).item()
-    nrmse_es = (torch.linalg.norm(img_es - ref) / nref).item()
-    nrmse_lg = (torch.linalg.norm(img_lg - ref) / nref).item()
-    nrmse_rg = (torch.linalg.norm(img_rg - ref) / nref).item()
-    # the direct-BP baseline: the fastest linear-kernel range mode within -30 dB
-    # of the ES direct image (itself <= 1e-5 of eq. 4)
-    candidates = {}
-    for u in DIRECT_U:
-        fast = H.Plan(*args3, mode="direct_rc", range_kernel="linear", range_oversample=u)
-        dimg = fast.image(ech)
-        torch.cuda.synchronize()
-        nd = 3
-        d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        d0.record(stream)
-        for _ in range(nd):
-            fast.image(ech, out=dimg)
-        d1.record(stream)
-        torch.cuda.synchronize()
-        candidates[f"linear U={u:g}"] = (d0.elapsed_time(d1) / nd,
-                                         (torch.linalg.norm(dimg - ref) / nref).item())
-        del fast, dimg
-    ok = {k: v for k, v in candidates.items() if 20 * np.log10(v[1]) <= -30.0}
-    d_mode = min(ok, key=lambda k: ok[k][0])
-    dms, d_nrmse = ok[d_mode]
-    direct_vp = w.n_vox * w.n_pos / (dms * 1e-3)
-    # eq. (4) itself, without range compression (the frequency sum per pair)
-    ex_plan = H.Plan(*args3, mode="direct_exact")
-    ex_img = ex_plan.image(ech)
-    torch.cuda.synchronize()
-    x0, x1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    x0.record(stream)
-    ex_plan.image(ech, out=ex_img)
-    x1.record(stream)
-    torch.cuda.synchronize()
-    ex_ms = x0.elapsed_time(x1)
-    ex_nrmse = (torch.linalg.norm(ex_img - ref) / nref).item()
-    del ex_img
-
-    def leaf_roofline(kms, inf, ops, kernel):
-        lms = kms.get("leaf_bp", float("nan"))
-        pts = inf["level_points"][-1]
-        a = inf["leaf_pairs"] * ops / (lms * 1e-3) / 1e12
-        pk = VALU_PEAK_OPS / 1e12
-        return {"kernel": kernel, "bound": "alu", "achieved": a, "peak": pk, "unit": "Tops/s",
-                "frac": a / pk, "traffic": measured_traffic(kernel), "ops_per_pair": ops,
-                "pairs_per_launch": inf["leaf_pairs"], "avg_launch_ms": lms,
-                # profiles + leaf points (32 B) + antenna offsets (16 B) in, subimages out
-                "algorithmic_bytes": w.n_pos * inf["n_range_bins"] * 8 + pts * 32
-                + w.n_pos * 16 + pts * 8}
-
-    roofline = leaf_roofline(kernels_ms, info, LEAF_OPS_LINEAR, "leaf_bp")
-    roofline_es = leaf_roofline(kernels_es, plan_es.info(), LEAF_OPS_PER_PAIR, "leaf_bp_es")
-
+    index = 2 if args.workload == "large" else 1
+    rec = imaging_report(args, index)
+    if index == 2 and not args.only_timed:
+        log("the mid workload beside it")
+        mid = imaging_report(args, 1)
+        rec["mid"] = {k: mid[k] for k in ("value", "ms_per_step", "config", "kernels_ms",
+                                          "kernels_roofline", "nrmse_vs_direct_db", "work",
+                                          "direct_bp", "speedup_vs_direct")}
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.only_timed:
         log("oracle CPU baseline")
-        cpu = oracle_cpu_baseline(w)
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "vp/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "HHFFBPA mid: 16384 handheld positions (64 serpentine strokes, "
-                               "0.3x0.3 m), 64 f 24-40 GHz, 128x128x64 voxels at 1.5 mm, "
-                               "50 points + 10x10x10 cube at 0.3 m",
-                   "n_pos": w.n_pos, "n_freq": w.n_f, "grid": list(w.grid_dims),
-                   "stages": 3, "merge_factor": 4, "oversample": list(BENCH_GAMMA),
-                   "interp_taps": TAPS, "interp_kernel": "bandlimited",
-                   "range_kernel": "linear", "range_oversample": BENCH_U,
-                   "parallelism": "single GPU"},
-        "nrmse_vs_direct_db": 20 * np.log10(nrmse),
-        "reference": "float32 direct BP, ES range kernel U=2 W=7 (<= 1e-5 of float64 eq. 4)",
-        "hhffbp_es": {"value": w.n_vox * w.n_pos / (ms_es * 1e-3), "ms": ms_es,
-                      "mode": "ES U=2 W=7 (parity mode), same grids", "kernels_ms": kernels_es,
-                      "nrmse_vs_direct_db": 20 * np.log10(nrmse_es), "roofline": roofline_es},
-        "hhffbp_lagrange": {"value": w.n_vox * w.n_pos / (ms_lg * 1e-3), "ms": ms_lg,
-                            "mode": "Lagrange weights, gamma (3, 3, 3.5), linear U=8",
-                            "kernels_ms": kernels_lg,
-                            "nrmse_vs_direct_db": 20 * np.log10(nrmse_lg)},
-        "hhffbp_root_grid": {"value": w.n_vox * w.n_pos / (ms_rg * 1e-3), "ms": ms_rg,
-                             "mode": "benchmarked form with a compressed root grid",
-                             "kernels_ms": kernels_rg,
-                             "nrmse_vs_direct_db": 20 * np.log10(nrmse_rg),
-                             "root_points": info_rg["level_points"][0],
-                             "merge_pairs": info_rg["merge_pairs"],
-                             "final_pairs": info_rg["final_pairs"]},
-        "direct_bp": {"value": direct_vp, "unit": "vp/s", "ms": dms, "mode": d_mode,
-                      "nrmse_vs_es_direct_db": 20 * np.log10(d_nrmse),
-                      "candidates": {k: {"ms": v[0], "nrmse_vs_es_direct_db": 20 * np.log10(v[1])}
-                                     for k, v in candidates.items()}},
-        "direct_exact": {"value": w.n_vox * w.n_pos / (ex_ms * 1e-3), "unit": "vp/s", "ms": ex_ms,
-                         "mode": "eq. (4): Horner sum over the 64 frequencies per pair",
-                         "nrmse_vs_es_direct_db": 20 * np.log10(ex_nrmse)},
-        "speedup_vs_direct": value / direct_vp,
-        "plan_ms": plan_ms, "kernels_ms": kernels_ms,
-        "work": {"leaf_pairs": info["leaf_pairs"], "merge_pairs": info["merge_pairs"],
-                 "final_pairs": info["final_pairs"], "level_points": info["level_points"][1:]},
-        "roofline": roofline, "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+        from workloads import make_config
+        w = make_config(index, synth_device="cuda")
+        cpu = oracle_cpu_baseline(w, index)
+    rec["cpu_baseline"] = cpu
+    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":

@@ -249,6 +249,15 @@ typedef struct {
                                        (brick, root)) whose stencils fit one staged
                                        box (the rest read the pencils directly)  */
     int32_t root_grid;              /* the plan's cfg->root_grid                */
+    int64_t merge_pairs_depth[16];  /* (parent point, child) pairs of the merge at depth d
+                                       (d < S; with a root grid d = 0 is the merge onto
+                                       it); their sum is merge_pairs              */
+    double level_estimate[16];      /* per depth d = 0..S: gamma_u gamma_v gamma_n times
+                                       the integral of |det J| over the voxel box, J the
+                                       Jacobian of (u, v, n) of eq. uvw_xyz, summed over
+                                       the depth's nodes: the sample count of Sec. IV-B
+                                       (eq. 4_subimgsmppresimp) before the interpolation
+                                       stencils' halos (midpoint rule on <= 32^3 cells) */
 } hhffbp_plan_info;
 
 hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info);

@@ -55,7 +55,8 @@ class PlanInfo(ctypes.Structure):
         ("storage", ctypes.c_int32), ("ws_scales_offset", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64), ("model_ms", ctypes.c_double),
         ("final_bricks", ctypes.c_int64), ("final_boxed", ctypes.c_int64),
-        ("root_grid", ctypes.c_int32),
+        ("root_grid", ctypes.c_int32), ("merge_pairs_depth", ctypes.c_int64 * 16),
+        ("level_estimate", ctypes.c_double * 16),
     ]
 
 
@@ -203,6 +204,8 @@ class Plan:
         _check(lib().hhffbp_get_plan_info(self._h, ctypes.byref(i)))
         out = {f: getattr(i, f) for f, _ in PlanInfo._fields_}
         out["level_points"] = list(i.level_points)[:i.stages + 1]
+        out["merge_pairs_depth"] = list(i.merge_pairs_depth)[:i.stages]
+        out["level_estimate"] = list(i.level_estimate)[:i.stages + 1]
         return out
 
     def node_layout(self, depth, index):

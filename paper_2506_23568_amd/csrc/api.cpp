@@ -219,6 +219,10 @@ hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info)
     info->final_boxed = P.n_tiled;
     info->ws_scales_offset = (int64_t)P.ws_scales;
     info->root_grid = P.F == 0 ? 1 : 0;
+    for (int d = 0; d < (int)P.merge_pairs_depth.size() && d < 16; ++d)
+        info->merge_pairs_depth[d] = P.merge_pairs_depth[d];
+    for (int d = 0; d < (int)P.level_estimate.size() && d < 16; ++d)
+        info->level_estimate[d] = P.level_estimate[d];
     return HHFFBP_OK;
 }
 

@@ -214,6 +214,8 @@ struct Plan {
     std::vector<TileBox> final_tiles;  // host copy, brick-major
     int64_t n_bricks = 0, n_tiled = 0;  // final-stage bricks; (brick, node) pairs with a box
     int64_t leaf_pairs = 0, merge_pairs = 0, final_pairs = 0;
+    std::vector<int64_t> merge_pairs_depth;  // per depth < S
+    std::vector<double> level_estimate;      // per depth: gamma^3 * integral of |det J| over the voxels
     // workspace layout (bytes)
     size_t ws_prof = 0, ws_posoff = 0, ws_total = 0;
     size_t ws_scales = 0, ws_amax = 0;  // per-call storage scales (float [n_scales()]) and max |echo|

@@ -417,8 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
 // a block per brick of kBrickX x kBrickY x kBrickZ voxels (lane t: z = t mod 16
 // fastest, then y, then x).  Per child, the block first stages the child's
 // values over the brick's stencil box (TileBox, from the plan) into LDS, dense
-// and zero outside the pencils: a wave per column, its lanes along n, the
-// column entry a scalar load.  A lane whose stencil lies inside the box then
+// and zero outside the pencils, thread-strided over the box's items.  A lane whose stencil lies inside the box then
 // reads its T^3 taps from LDS in the same order as the pencil path; one
 // outside it (or a child without a box) gathers from the pencils.  Each
 // (voxel, child) pair's stencil, fractions and phase Phi_c come from its
@@ -436,7 +435,9 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
                                                   int nx, int ny, int nz,
                                                   float2 *__restrict__ image)
 {
-    __shared__ float2 s_tile[kTileCap];
+    // box columns 2^lsh + 1 values apart: a power-of-two stride would put the
+    // same n index of every column into one LDS bank
+    __shared__ float2 s_tile[kTileCap + kTileCap / 4];
     const int bz = (nz + kBrickZ - 1) / kBrickZ, by = (ny + kBrickY - 1) / kBrickY;
     const int brick = (int)blockIdx.x;
     const int kx = brick / (by * bz), ky = (brick / bz) % by, kz = brick % bz;
@@ -473,7 +474,8 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
             for (int k = 0; k < kStageBox; ++k) v[k] = Store<ST>::ld(cvals[roff[k]]);
 #pragma unroll
             for (int k = 0; k < kStageBox; ++k)
-                if (k * kBlock + t < items) s_tile[k * kBlock + t] = take[k] ? v[k] : make_float2(0.0f, 0.0f);
+                if (k * kBlock + t < items)
+                    s_tile[k * kBlock + t + ((k * kBlock + t) >> tb.lsh)] = take[k] ? v[k] : make_float2(0.0f, 0.0f);
         }
         __syncthreads();
         const size_t r = ((size_t)brick * nchild + c) * kBlock + t;
@@ -487,8 +489,8 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
             float2 val;
             if (tb.ni > 0 && (unsigned)ti <= (unsigned)(tb.ni - T) &&
                 (unsigned)tj <= (unsigned)(tb.nj - T) && (unsigned)tl <= (unsigned)(tb.nl - T))
-                val = interp_box<T>(s_tile + ((ti * tb.nj + tj) << tb.lsh) + tl, tb.nj, 1 << tb.lsh,
-                                    wu, wv, wn);
+                val = interp_box<T>(s_tile + (ti * tb.nj + tj) * ((1 << tb.lsh) + 1) + tl, tb.nj,
+                                    (1 << tb.lsh) + 1, wu, wv, wn);
             else
                 val = interp_rec<T, ST>(ch, ccolbase, cvals, ci0, cj0, rx.l0, wu, wv, wn);
             rotate_mac(val, g.turns, are, aim);

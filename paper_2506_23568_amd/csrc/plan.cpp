@@ -611,6 +611,54 @@ void box_dist(const double *q, const double *lo, const double *hi, double *dmin,
     *dmax = std::sqrt(s1);
 }
 
+// Per depth: gamma_u gamma_v gamma_n times the integral of |det J| over the
+// voxel box, summed over the depth's non-empty nodes (Sec. IV-B's sample count
+// of a subimage grid, eq. 4_subimgsmppresimp), by the midpoint rule on cells of
+// s_a voxels per axis (at most 32 cells per axis).
+void level_estimates(Plan &P)
+{
+    const hhffbp_config &c = P.cfg;
+    P.level_estimate.assign(P.S + 1, 0.0);
+    int64_t st[3], nc[3];
+    for (int a = 0; a < 3; ++a) {
+        st[a] = std::max<int64_t>(1, (c.grid_dims[a] + 31) / 32);
+        nc[a] = (c.grid_dims[a] + st[a] - 1) / st[a];
+    }
+    std::vector<std::pair<int, int32_t>> nodes;  // (depth, tree index) of the non-empty nodes
+    for (int d = 0; d <= P.S; ++d)
+        for (int32_t ti = 0; ti < (int32_t)P.levels[d].size(); ++ti)
+            if (!P.levels[d][ti].empty()) nodes.emplace_back(d, ti);
+    std::vector<double> part(nodes.size(), 0.0);
+    parallel_for((int64_t)nodes.size(), 1, [&](int64_t b0, int64_t b1) {
+        for (int64_t q = b0; q < b1; ++q) {
+            const SubarrayMap map(P.levels[nodes[q].first][nodes[q].second].rect, P.kmin, P.kmax);
+            double acc = 0.0;
+            for (int64_t i = 0; i < nc[0]; ++i)
+                for (int64_t j = 0; j < nc[1]; ++j)
+                    for (int64_t k = 0; k < nc[2]; ++k) {
+                        // the cell [i s, min((i + 1) s, n)) along each axis, at its centre
+                        const int64_t lo[3] = {i * st[0], j * st[1], k * st[2]};
+                        double p[3], vol = 1.0;
+                        for (int a = 0; a < 3; ++a) {
+                            const int64_t n = std::min(st[a], c.grid_dims[a] - lo[a]);
+                            p[a] = c.grid_origin[a] +
+                                   ((double)lo[a] + 0.5 * (double)(n - 1)) * c.grid_pitch[a];
+                            vol *= (double)n * c.grid_pitch[a];
+                        }
+                        double w[3], J[9];
+                        map.eval(p, w, nullptr, J);
+                        const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) -
+                                           J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                                           J[2] * (J[3] * J[7] - J[4] * J[6]);
+                        acc += std::fabs(det) * vol;
+                    }
+            part[(size_t)q] = acc;
+        }
+    });
+    const double g3 = P.gamma[0] * P.gamma[1] * P.gamma[2];
+    for (size_t q = 0; q < nodes.size(); ++q) P.level_estimate[nodes[q].first] += g3 * part[q];
+}
+
 void validate(const hhffbp_config &c)
 {
     auto bad = [](const std::string &m) { throw Error{HHFFBP_E_INVALID, m}; };
@@ -963,13 +1011,16 @@ void build_plan_host(Plan &P)
             const HostNode &lf = P.levels[S][ti];
             P.leaf_pairs += lf.lat.npts * (int64_t)lf.members.size();
         }
+        P.merge_pairs_depth.assign(S + 1, 0);
         for (int d = P.F; d < S; ++d)
             for (int32_t ti : P.compact_to_tree[d]) {
                 const HostNode &nd = P.levels[d][ti];
                 int nch = 0;
                 for (int32_t ch : nd.children) nch += P.levels[d + 1][ch].empty() ? 0 : 1;
                 P.merge_pairs += nd.lat.npts * nch;
+                P.merge_pairs_depth[d] += nd.lat.npts * nch;
             }
+        level_estimates(P);
         P.final_pairs = P.n_vox() * (int64_t)P.compact_to_tree[P.F].size();
     }
     P.model_s = model_seconds(P);
