@@ -503,6 +503,15 @@ def imaging_report(args, index):
             "nrmse_vs_f32_storage": (torch.linalg.norm(img_h - img) / torch.linalg.norm(img)).item(),
             **errors(img_h)}
         del pl_h, eh, img_h
+    # the fused range compression + level-1 BP (one kernel, profiles in LDS)
+    pl_f = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, range_fused=True, **form)
+    ms_f, k_f, img_f = timed(pl_f, ech, max(3, args.steps // 2), 1)
+    extra["hhffbp_fused"] = {
+        "value": vp / (ms_f * 1e-3), "ms": ms_f, "kernels_ms": k_f,
+        "mode": "range compression fused into the level-1 BP (range_fused), same plan",
+        "nrmse_vs_two_kernel_form": (torch.linalg.norm(img_f - img) / torch.linalg.norm(img)).item(),
+        **errors(img_f)}
+    del pl_f, img_f
     alt = dict(form, stages=3, root_grid=False) if index == 2 else dict(form, stages=4, root_grid=True)
     pl_a = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, **alt)
     ms_a, k_a, img_a = timed(pl_a, ech, max(3, args.steps // 2), 1)

@@ -125,6 +125,16 @@ typedef struct {
                                    Fewer interpolations where the voxel grid is finer
                                    than the full aperture's band, at the error of one
                                    more interpolation.  Needs FACTORIZED with S >= 1. */
+    int32_t range_fused;        /* 0: range compression (eq. 2) as its own MFMA GEMM
+                                   writing every profile to the workspace, then the
+                                   level-1 BP (the default).  1: one kernel per block
+                                   of 1024 leaf points forms the profiles of its bin
+                                   window from the echoes on MFMA into LDS and
+                                   backprojects them, with no profile array; the
+                                   blocks of a leaf each form its profiles.  Needs
+                                   FACTORIZED with S >= 1, the linear range kernel
+                                   and C64 storage, and an image only: hhffbp_backward
+                                   returns HHFFBP_E_UNSUPPORTED for such a plan.     */
 } hhffbp_config;
 
 /* Fill `cfg` with defaults: FACTORIZED, S = 3, Q = 4, gamma = (3, 3, 3.5), T = 4, ES with
@@ -165,8 +175,9 @@ hhffbp_status hhffbp_workspace_bytes(hhffbp_plan_t plan, int32_t with_backward,
  *               of cfg->positions.
  *   positions   device float64 [n_pos][3] to backproject with, or NULL for
  *               the plan's own positions.  The tree and grids stay as planned;
- *               positions must stay within cfg->position_slack of the planned
- *               ones for the range window to hold them.
+ *               each coordinate is clamped to within cfg->position_slack of the
+ *               planned one, the box the range windows hold (see
+ *               hhffbp_check_positions).
  *   image       device complex64 [nx][ny][nz] (z fastest), overwritten.
  *   workspace   device, at least hhffbp_workspace_bytes(plan, 0) bytes,
  *               256-byte aligned; its contents on entry do not matter.
@@ -196,6 +207,23 @@ hhffbp_status hhffbp_image(hhffbp_plan_t plan, const void *echoes, const double 
 #define HHFFBP_NOALLOC_WORKSPACE_BYTES ((size_t)256 << 20)
 hhffbp_status hhffbp_image_noalloc(hhffbp_plan_t plan, const void *echoes,
                                    const double *positions, void *image, void *stream);
+
+/*
+ * Check device positions against the plan's slack: the plan's range windows and
+ * carrier form hold for positions within cfg->position_slack of the planned ones
+ * along each axis (hhffbp_image and hhffbp_backward clamp every coordinate into
+ * that box, so their results are those of the clamped positions).
+ *   positions   device float64 [n_pos][3], as for hhffbp_image
+ *   n_outside   host, optional: receives the number of positions with a coordinate
+ *               beyond the slack (or not finite)
+ * Enqueues one kernel and a 4-byte-per-256-positions copy on `stream` and waits
+ * for the stream.  Calls on one plan must not overlap (they share the plan's
+ * count buffer).  Returns HHFFBP_OK when every position is inside, and
+ * HHFFBP_E_INVALID (with *n_outside set) when any is not; HHFFBP_E_DEVICE on a
+ * HIP failure.
+ */
+hhffbp_status hhffbp_check_positions(hhffbp_plan_t plan, const double *positions,
+                                     int64_t *n_outside, void *stream);
 
 /*
  * Gradients of a real loss L(image) with respect to the echoes and the antenna

@@ -23,7 +23,7 @@ import math
 
 import torch
 
-from .binding import image_stats, loss_grad
+from .binding import HHFFBPError, image_stats, loss_grad
 
 
 def cosine_basis(n, k, device):
@@ -66,6 +66,13 @@ def autofocus(plan, echoes, positions, steps=20, lr=3e-5, clean=None, modes=16, 
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         pos = current()
+        # the plan's windows hold positions within its slack; beyond it the
+        # kernels clamp, so stop rather than descend on clamped positions
+        n_out = plan.check_positions(pos)
+        if n_out:
+            raise HHFFBPError(-1, f"autofocus step {k}: {n_out} positions moved beyond the plan's "
+                                  f"slack of {plan.config.position_slack} m; plan again around "
+                                  "the current positions")
         plan.image(echoes, positions=pos, out=img, workspace=ws)
         st = image_stats(img, clean)
         loss, g = loss_grad(img, clean, st, w_entropy=w_entropy, w_l2=w_l2)

@@ -40,6 +40,7 @@ class Config(ctypes.Structure):
         ("position_slack", ctypes.c_double), ("device", ctypes.c_int32),
         ("interp_kernel", ctypes.c_int32), ("final_staging", ctypes.c_int32),
         ("weights", ctypes.POINTER(ctypes.c_double)), ("root_grid", ctypes.c_int32),
+        ("range_fused", ctypes.c_int32),
     ]
 
 
@@ -85,6 +86,8 @@ def lib():
         L.hhffbp_image.restype = ctypes.c_int
         L.hhffbp_image_noalloc.argtypes = [vp, vp, vp, vp, vp]
         L.hhffbp_image_noalloc.restype = ctypes.c_int
+        L.hhffbp_check_positions.argtypes = [vp, vp, ctypes.POINTER(i64), vp]
+        L.hhffbp_check_positions.restype = ctypes.c_int
         L.hhffbp_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.hhffbp_backward.restype = ctypes.c_int
         L.hhffbp_get_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
@@ -139,7 +142,7 @@ class Plan:
                  interp_taps=4,
                  range_kernel="es", range_oversample=2.0, range_taps=7, storage="c64",
                  position_slack=5e-3, device=0, interp_kernel="lagrange", final_staging=True,
-                 weights=None, root_grid=False):
+                 weights=None, root_grid=False, range_fused=False):
         L = lib()
         self._pos = np.ascontiguousarray(positions, np.float64)
         self._freqs = np.ascontiguousarray(freqs_hz, np.float64)
@@ -170,6 +173,7 @@ class Plan:
         c.interp_kernel = INTERP_KERNELS[interp_kernel]
         c.final_staging = 1 if final_staging else 0
         c.root_grid = 1 if root_grid else 0
+        c.range_fused = 1 if range_fused else 0
         if weights is not None:
             self._w = np.ascontiguousarray(weights, np.float64)
             if self._w.shape != (self._pos.shape[0],):
@@ -273,6 +277,29 @@ class Plan:
         dt = torch.float16 if storage == "f16" else torch.bfloat16
         return torch.view_as_real(echoes_c.to(torch.complex64)).to(dt).contiguous()
 
+    def _check_positions_tensor(self, positions):
+        import torch
+
+        if (not positions.is_cuda or positions.dtype != torch.float64
+                or tuple(positions.shape) != (self.config.n_pos, 3)):
+            raise TypeError("positions must be float64 (n_pos, 3) on the device")
+        return positions.contiguous()
+
+    def check_positions(self, positions, stream=None):
+        """Number of device positions with a coordinate beyond the plan's slack
+        (hhffbp_check_positions; waits for the stream).  Images and gradients
+        clamp such coordinates into the slack box."""
+        import torch
+
+        positions = self._check_positions_tensor(positions)
+        if stream is None:
+            stream = torch.cuda.current_stream(positions.device).cuda_stream
+        n = ctypes.c_int64(0)
+        st = lib().hhffbp_check_positions(self._h, positions.data_ptr(), ctypes.byref(n), stream)
+        if st not in (0, -1):
+            _check(st)
+        return int(n.value)
+
     def image(self, echoes, positions=None, out=None, workspace=None, stream=None):
         """Image from device echoes (storage layout, see pack_echoes); complex64 (nx, ny, nz)."""
         import torch
@@ -284,9 +311,7 @@ class Plan:
             workspace = self._workspace(torch)
         pptr = None
         if positions is not None:
-            if positions.dtype != torch.float64 or tuple(positions.shape) != (self.config.n_pos, 3):
-                raise TypeError("positions must be float64 (n_pos, 3) on the device")
-            positions = positions.contiguous()
+            positions = self._check_positions_tensor(positions)
             pptr = positions.data_ptr()
         if stream is None:
             stream = torch.cuda.current_stream(echoes.device).cuda_stream
@@ -304,9 +329,7 @@ class Plan:
             out = torch.empty(self.dims, dtype=torch.complex64, device=echoes.device)
         pptr = None
         if positions is not None:
-            if positions.dtype != torch.float64 or tuple(positions.shape) != (self.config.n_pos, 3):
-                raise TypeError("positions must be float64 (n_pos, 3) on the device")
-            positions = positions.contiguous()
+            positions = self._check_positions_tensor(positions)
             pptr = positions.data_ptr()
         if stream is None:
             stream = torch.cuda.current_stream(echoes.device).cuda_stream
@@ -332,7 +355,7 @@ class Plan:
             eptr = echoes.data_ptr()
         pptr = None
         if positions is not None:
-            positions = positions.contiguous()
+            positions = self._check_positions_tensor(positions)
             pptr = positions.data_ptr()
         if workspace is None:
             workspace = self._workspace(torch, backward=True)

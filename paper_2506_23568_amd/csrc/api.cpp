@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "hhffbp_internal.hpp"
 
@@ -49,6 +50,7 @@ void hhffbp_config_default(hhffbp_config *cfg)
     cfg->final_staging = 1;
     cfg->weights = nullptr;
     cfg->root_grid = 0;
+    cfg->range_fused = 0;
 }
 
 hhffbp_status hhffbp_plan(const hhffbp_config *cfg, hhffbp_plan_t *out)
@@ -110,6 +112,8 @@ hhffbp_status hhffbp_backward(hhffbp_plan_t plan, const void *echoes, const doub
     if (P.cfg.device < 0) return fail(HHFFBP_E_DEVICE, "hhffbp_backward: host-only plan");
     if (P.S < 1)
         return fail(HHFFBP_E_UNSUPPORTED, "hhffbp_backward: needs a factorised plan with stages >= 1");
+    if (P.cfg.range_fused)
+        return fail(HHFFBP_E_UNSUPPORTED, "hhffbp_backward: not for a plan with range_fused");
     if (!grad_echoes && !grad_positions) return HHFFBP_OK;
     if (grad_positions && !echoes)
         return fail(HHFFBP_E_INVALID, "hhffbp_backward: the position gradient needs the echoes");
@@ -187,6 +191,38 @@ hhffbp_status hhffbp_image_noalloc(hhffbp_plan_t plan, const void *echoes,
                                          hipGetErrorString(e));
     if (st != HHFFBP_OK) return fail(st, std::string("hhffbp_image_noalloc: launch failed: ") +
                                              hipGetErrorString(hipGetLastError()));
+    return HHFFBP_OK;
+}
+
+hhffbp_status hhffbp_check_positions(hhffbp_plan_t plan, const double *positions,
+                                     int64_t *n_outside, void *stream)
+{
+    if (!plan || !positions) return fail(HHFFBP_E_INVALID, "hhffbp_check_positions: NULL argument");
+    const hh::Plan &P = plan->plan;
+    if (P.cfg.device < 0)
+        return fail(HHFFBP_E_DEVICE, "hhffbp_check_positions: host-only plan (device < 0)");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(HHFFBP_E_DEVICE, "hipGetDevice failed");
+    if (cur != P.cfg.device && hipSetDevice(P.cfg.device) != hipSuccess)
+        return fail(HHFFBP_E_DEVICE, "hipSetDevice failed");
+    const size_t nb = (size_t)((P.cfg.n_pos + hh::kBlockThreads - 1) / hh::kBlockThreads);
+    std::vector<int32_t> counts(nb, 0);
+    hipError_t e = hh::launch_check_positions(P, positions, (int32_t *)P.dev.check_counts,
+                                              (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(counts.data(), P.dev.check_counts, nb * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (cur != P.cfg.device) (void)hipSetDevice(cur);
+    if (e != hipSuccess)
+        return fail(HHFFBP_E_DEVICE, std::string("hhffbp_check_positions: ") + hipGetErrorString(e));
+    int64_t tot = 0;
+    for (int32_t c : counts) tot += c;
+    if (n_outside) *n_outside = tot;
+    if (tot > 0)
+        return fail(HHFFBP_E_INVALID, "hhffbp_check_positions: " + std::to_string(tot) +
+                                          " positions lie beyond the planned slack of " +
+                                          std::to_string(P.cfg.position_slack) + " m");
     return HHFFBP_OK;
 }
 

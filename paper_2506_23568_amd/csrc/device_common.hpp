@@ -110,6 +110,14 @@ __device__ __forceinline__ int xcd_block(int b, int n)
     }
 }
 
+// xcd_block with a run length known only at launch (the same bijection).
+__device__ __forceinline__ int xcd_block_run(int b, int n, int run)
+{
+    const int x = b % kXcds, s = b / kXcds, round = kXcds * run;
+    if (b >= n / round * round) return b;
+    return ((s / run) * kXcds + x) * run + s % run;
+}
+
 // floor(x) as int32 in one VALU instruction (the compiler emits floor + convert)
 __device__ __forceinline__ int floor_int(float x)
 {

@@ -113,6 +113,9 @@ struct InterpGeo {
 };
 constexpr uint32_t kNoPair = 0xffffffffu;
 
+// Leaf points per block of the fused range-compression + level-1 BP kernel.
+constexpr int kFusedPoints = 1024;
+
 // Range bins [lo, lo + n) that a level-1 BP block can read: every tap of its
 // points for positions within the leaf's reach.
 struct BinWindow {
@@ -150,6 +153,7 @@ struct DeviceBuffers {
     void *leaf_of_sorted = nullptr; // int32 [n_pos]
     void *leaf_centre = nullptr;    // double2 [n_leaves]
     void *pos64 = nullptr;          // double [n_pos][3], caller order
+    void *check_counts = nullptr;   // int32 [blocks of kBlockThreads positions]: hhffbp_check_positions
     void *posoff = nullptr;         // float4 [n_pos]: the plan positions' leaf offsets and
                                     // squared norms (as k_prep_positions writes them)
     void *unit_scales = nullptr;    // float [n_scales()] of 1: storage scales of c64, bf16
@@ -164,6 +168,8 @@ struct DeviceBuffers {
     void *leafpts = nullptr;        // LeafPoint[] of depth S
     void *leaf_blocks = nullptr;    // BlockItem[]
     void *leaf_wins = nullptr;      // BinWindow[], one per leaf block
+    void *fused_blocks = nullptr;   // BlockItem[] of kFusedPoints leaf points (range_fused)
+    void *fused_wins = nullptr;     // BinWindow[], one per fused block
     void *final_tiles = nullptr;    // TileBox[n_bricks][n nodes at depth F]
     void *adj_blocks = nullptr;     // BlockItem[]: (leaf, first sorted position of kAdjPos)
     void *Bd = nullptr;             // range-derivative matrix (rows x j 2 k_f), [2 Nf][2 Nr]
@@ -209,7 +215,8 @@ struct Plan {
     std::vector<int64_t> n_blocks_merge; // per depth
     std::vector<int64_t> n_blocks_merge_fwd; // per depth
     std::vector<std::vector<MergeBrick>> merge_bricks;  // per depth, host copy
-    int64_t n_blocks_leaf = 0, n_blocks_adj = 0;
+    int64_t n_blocks_leaf = 0, n_blocks_adj = 0, n_blocks_fused = 0;
+    int32_t fused_win_max = 0;  // widest BinWindow of the fused blocks
     int32_t leaf_win_max = 0;  // widest BinWindow of the level-1 BP blocks
     std::vector<TileBox> final_tiles;  // host copy, brick-major
     int64_t n_bricks = 0, n_tiled = 0;  // final-stage bricks; (brick, node) pairs with a box
@@ -254,6 +261,9 @@ void release_plan(Plan &plan);
 
 // Launchers (kernels.hip, kernels_adjoint.hip).
 hipError_t launch_prep(const Plan &P, const double *pos64, float4 *posoff, hipStream_t st);
+// Per block of kBlockThreads positions, the count beyond the slack box into counts.
+hipError_t launch_check_positions(const Plan &P, const double *pos64, int32_t *counts,
+                                  hipStream_t st);
 // Range-compression GEMM with float32 output; A stored as `storage_a` reals.
 // a_w / c_w: optional per-row weights of A (indexed by A's row) and of C
 // (indexed by C's row after c_perm); NULL for none.

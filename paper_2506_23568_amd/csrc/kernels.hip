@@ -40,24 +40,56 @@ namespace {
 using namespace dev;
 
 // ---------------------------------------------------------------------------
-// With `ones` set, block 0 also writes the ns storage scales, all 1 (storage
-// types without scaling), saving their own launch.
+// Position pass: each antenna's offset from its leaf centre (float64 ->
+// float32) and its squared norm, in leaf-sorted order.  The plan's range
+// windows and its choice of carrier form hold for positions within `slack` of
+// the planned ones along each axis; a coordinate beyond that is clamped to the
+// slack box, so that every later kernel stays inside its windows (the image is
+// then that of the clamped positions: hhffbp_check_positions reports such
+// positions).
 __global__ __launch_bounds__(kBlock) void k_prep_positions(const double *__restrict__ pos64,
+                                                           const double *__restrict__ plan64,
+                                                           double slack,
                                                            const int32_t *__restrict__ perm,
                                                            const int32_t *__restrict__ leaf_of,
                                                            const double *__restrict__ centre,
-                                                           int n, float4 *__restrict__ out,
-                                                           float *__restrict__ ones, int ns)
+                                                           int n, float4 *__restrict__ out)
 {
-    if (ones && blockIdx.x == 0 && (int)threadIdx.x < ns) ones[threadIdx.x] = 1.0f;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int m = perm[i], lf = leaf_of[i];
-    const double dx = pos64[3 * m] - centre[2 * lf];
-    const double dy = pos64[3 * m + 1] - centre[2 * lf + 1];
-    const double dz = pos64[3 * m + 2];
+    double p[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double q = plan64[3 * m + a];
+        p[a] = fmin(fmax(pos64[3 * m + a], q - slack), q + slack);
+    }
+    const double dx = p[0] - centre[2 * lf];
+    const double dy = p[1] - centre[2 * lf + 1];
+    const double dz = p[2];
     const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
     out[i] = make_float4(fx, fy, fz, fx * fx + fy * fy + fz * fz);
+}
+
+// Positions with a coordinate outside [q - slack, q + slack] around the planned
+// one q (the box k_prep_positions clamps to), or not finite: the count of each
+// block of kBlock positions into counts[block].
+__global__ __launch_bounds__(kBlock) void k_check_positions(const double *__restrict__ pos64,
+                                                            const double *__restrict__ plan64,
+                                                            double slack, int n,
+                                                            int32_t *__restrict__ counts)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    bool out = false;
+    if (i < n) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double p = pos64[3 * i + a], q = plan64[3 * i + a];
+            out = out || !(p >= q - slack && p <= q + slack);
+        }
+    }
+    const int c = __syncthreads_count(out);
+    if (threadIdx.x == 0) counts[blockIdx.x] = c;
 }
 
 // ---------------------------------------------------------------------------
@@ -124,7 +156,12 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const typename Store<SA>::R 
     __shared__ __align__(16) float As[kGemmKC][64 + kGemmPad];  // [k][row]
     __shared__ __align__(16) float Bs[kGemmKC][64 + kGemmPad];  // [k][col]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
+    // a 1-D grid: the column tiles of one row tile are consecutive logical
+    // blocks dealt to one XCD, so its rows of A come from HBM once and from
+    // that XCD's L2 for the other column tiles
+    const int ncb = (N + 63) / 64;
+    const int lb = xcd_block_run((int)blockIdx.x, (int)gridDim.x, ncb);
+    const int row0 = (lb / ncb) * 64, col0 = (lb % ncb) * 64;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     v4f acc[2][2];
 #pragma unroll
@@ -348,6 +385,118 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
         out[nd.val_base + p] = Store<ST>::st(make_float2(rs * (acc_re * q.pre_re - acc_im * q.pre_im),
                                                          rs * (acc_re * q.pre_im + acc_im * q.pre_re)));
     }
+}
+
+// ---------------------------------------------------------------------------
+// Level-1 BP with the range compression fused in (eq. 2 and Sec. IV-A; the
+// plan's range_fused option, linear range kernel, complex64).  A block of
+// kFusedPoints threads takes as many points of one leaf.  Per chunk of
+// kFusedChunk of the leaf's positions it forms their profiles over the block's
+// bin window straight from the echoes, P[i][b] = w_i sum_f s_if W[f][b]
+// (block-real, on v_mfma_f32_16x16x4f32: the echo rows in LDS k-major, W read
+// from global memory), into LDS, and then backprojects them as k_leaf_bp does
+// with the linear kernel.  No profile array exists; every block of a leaf
+// forms the leaf's profiles over its own window.
+constexpr int kFusedChunk = 16;
+constexpr int kFusedWaves = kFusedPoints / 64;
+
+inline size_t fused_lds_bytes(int K, int win_max)
+{
+    const int Kp = (K + 3) & ~3;
+    return ((size_t)Kp * kFusedChunk + (size_t)kFusedChunk * 2 * win_max) * sizeof(float) +
+           kFusedChunk * sizeof(float4);
+}
+
+template <bool RED>
+__global__ __launch_bounds__(kFusedPoints) void k_leaf_bp_fused(
+    const NodeDev *__restrict__ leaves, const BlockItem *__restrict__ blocks,
+    const BinWindow *__restrict__ wins, const LeafPoint *__restrict__ pts,
+    const float4 *__restrict__ posoff, const float *__restrict__ echoes,
+    const int32_t *__restrict__ perm, const float *__restrict__ aw, int K,
+    const float *__restrict__ B, int Nr, float inv_dR, float kc_turns, float2 *__restrict__ out)
+{
+    extern __shared__ unsigned char smem[];
+    const int lb = xcd_block<4>((int)blockIdx.x, (int)gridDim.x);
+    const BlockItem blk = blocks[lb];
+    const BinWindow win = wins[lb];
+    const int r0 = win.lo, nrb = win.n, ncol = 2 * nrb, ldb = 2 * Nr;
+    const int Kp = (K + 3) & ~3;
+    float *As = reinterpret_cast<float *>(smem);         // [Kp][kFusedChunk], k-major
+    float *Ps = As + (size_t)Kp * kFusedChunk;           // [kFusedChunk][2 nrb], block-real
+    float4 *s_pos = reinterpret_cast<float4 *>(Ps + (size_t)kFusedChunk * ncol);
+    const int tid = (int)threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const NodeDev nd = leaves[blk.node];
+    const int p = blk.start + tid;
+    const bool active = p < nd.npts;
+    LeafPoint q = active ? pts[nd.val_base + p] : LeafPoint{0, 0, 1, 0, 0, 0, 0, 0};
+    const float Rc2 = fmaf(q.dx, q.dx, fmaf(q.dy, q.dy, q.dz * q.dz));
+    const float Rc = fast_sqrt(Rc2);
+    const float frac_w = q.frac - 1.0f;  // tau = t - W/2 (W = 2) relative to the point's bin
+    const int bin1 = q.bin + 1;
+    const float tau_lo = (float)(r0 - bin1), tau_hi = (float)(r0 + nrb - 2 - bin1);
+    const float m2x = -2.0f * q.dx, m2y = -2.0f * q.dy, m2z = -2.0f * q.dz;
+    float acc_re = 0.0f, acc_im = 0.0f;
+    for (int c0 = nd.pos_begin; c0 < nd.pos_end; c0 += kFusedChunk) {
+        const int n = min(kFusedChunk, nd.pos_end - c0);
+        __syncthreads();  // the previous chunk's profiles are consumed
+        // echo rows of the chunk (weighted), k-major: As[k][i]; rows past n are 0
+        for (int t = tid; t < kFusedChunk * Kp; t += kFusedPoints) {
+            const int i = t / Kp, k = t - i * Kp;
+            float v = 0.0f;
+            if (i < n && k < K) {
+                const int row = perm[c0 + i];
+                v = echoes[(size_t)row * K + k] * (aw ? aw[row] : 1.0f);
+            }
+            As[k * kFusedChunk + i] = v;
+        }
+        if (tid < kFusedChunk)
+            s_pos[tid] = tid < n ? posoff[c0 + tid] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        __syncthreads();
+        // profiles: C[16][ncol] = A[16][K] W[K][2 r0 .. 2 r0 + ncol), one 16-column
+        // tile per wave at a time
+        for (int ct = wave; ct * 16 < ncol; ct += kFusedWaves) {
+            const int col = ct * 16 + (lane & 15);
+            const bool cin = col < ncol;
+            const float *bcol = B + 2 * r0 + (cin ? col : 0);
+            v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+            for (int k = 0; k < Kp; k += 4) {
+                const int kk = k + (lane >> 4);
+                const float a = As[kk * kFusedChunk + (lane & 15)];
+                const float b = (cin && kk < K) ? bcol[(size_t)kk * ldb] : 0.0f;
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+            }
+            if (cin) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Ps[(4 * (lane >> 4) + r) * ncol + col] = acc[r];
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const float2 *prof = reinterpret_cast<const float2 *>(Ps);
+            for (int i = 0; i < n; ++i) {
+                const float4 d = s_pos[i];
+                const float num = fmaf(m2x, d.x, fmaf(m2y, d.y, fmaf(m2z, d.z, d.w)));
+                const float R = fast_sqrt(num + Rc2);
+                const float dR = num * fast_rcp(R + Rc);
+                const float tau = __builtin_amdgcn_fmed3f(fmaf(dR, inv_dR, frac_w), tau_lo, tau_hi);
+                const int r = bin1 - r0 + floor_int(tau);
+                const float x = __builtin_amdgcn_fractf(tau);
+                const float2 v0 = prof[i * nrb + r], v1 = prof[i * nrb + r + 1];
+                const float gre = fmaf(x, v1.x - v0.x, v0.x);
+                const float gim = fmaf(x, v1.y - v0.y, v0.y);
+                float ph = dR * kc_turns;
+                if constexpr (RED) ph -= rintf(ph);
+                const float sn = sin_turns(ph), cs = cos_turns(ph);
+                acc_re = fmaf(gre, cs, fmaf(-gim, sn, acc_re));
+                acc_im = fmaf(gre, sn, fmaf(gim, cs, acc_im));
+            }
+        }
+    }
+    if (active)
+        out[nd.val_base + p] = make_float2(acc_re * q.pre_re - acc_im * q.pre_im,
+                                           acc_re * q.pre_im + acc_im * q.pre_re);
 }
 
 // Merge at depth d: parent grid points of the depth-d nodes, children at
@@ -889,16 +1038,44 @@ hhffbp_status image_for_storage(const Plan &P, const void *echoes, const double 
         if (pos64 == (const double *)P.dev.pos64) {
             posoff = (float4 *)P.dev.posoff;
         } else {
-            hipLaunchKernelGGL(k_prep_positions, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
-                               pos64, (const int32_t *)P.dev.perm, (const int32_t *)P.dev.leaf_of_sorted,
-                               (const double *)P.dev.leaf_centre, n, posoff, (float *)nullptr, 0);
-            if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
+            if ((e = launch_prep(P, pos64, posoff, st)) != hipSuccess) return HHFFBP_E_DEVICE;
         }
         if (ev) (void)hipEventRecord(*ev++, st);
     }
+    if (P.cfg.range_fused) {
+        if constexpr (ST == HHFFBP_C64) {
+            const int K = (int)(2 * c.n_freq);
+            const size_t sh = fused_lds_bytes(K, P.fused_win_max);
+            const float inv_dR = (float)(1.0 / P.dR);
+            const float kc_turns = (float)(P.kc / kPi);
+            if (P.leaf_reach * (P.kc / kPi) < 128.0)
+                hipLaunchKernelGGL((k_leaf_bp_fused<false>), dim3(P.n_blocks_fused), dim3(kFusedPoints),
+                                   sh, st, (const NodeDev *)P.dev.nodes[P.S],
+                                   (const BlockItem *)P.dev.fused_blocks, (const BinWindow *)P.dev.fused_wins,
+                                   (const LeafPoint *)P.dev.leafpts, posoff, (const float *)echoes,
+                                   (const int32_t *)P.dev.perm, (const float *)P.dev.weights, K,
+                                   (const float *)P.dev.B, (int)P.Nr, inv_dR, kc_turns,
+                                   (float2 *)(ws + P.ws_vals[P.S]));
+            else
+                hipLaunchKernelGGL((k_leaf_bp_fused<true>), dim3(P.n_blocks_fused), dim3(kFusedPoints),
+                                   sh, st, (const NodeDev *)P.dev.nodes[P.S],
+                                   (const BlockItem *)P.dev.fused_blocks, (const BinWindow *)P.dev.fused_wins,
+                                   (const LeafPoint *)P.dev.leafpts, posoff, (const float *)echoes,
+                                   (const int32_t *)P.dev.perm, (const float *)P.dev.weights, K,
+                                   (const float *)P.dev.B, (int)P.Nr, inv_dR, kc_turns,
+                                   (float2 *)(ws + P.ws_vals[P.S]));
+            if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
+            if (ev) (void)hipEventRecord(*ev++, st);
+            e = (P.Q == 4) ? dispatch_merges<ST, 4>(P, ws, image, scales, st, ev)
+                           : dispatch_merges<ST, 2>(P, ws, image, scales, st, ev);
+            return e == hipSuccess ? HHFFBP_OK : HHFFBP_E_DEVICE;
+        } else {
+            return HHFFBP_E_UNSUPPORTED;
+        }
+    }
     {
         const int M = n, K = (int)(2 * c.n_freq), N = (int)(2 * P.Nr);
-        dim3 grid((M + 63) / 64, (N + 63) / 64);
+        dim3 grid(((M + 63) / 64) * ((N + 63) / 64));
         hipLaunchKernelGGL((k_rc_gemm<ST, ST>), grid, dim3(kBlock), 0, st,
                            (const typename Store<ST>::R *)echoes, (const int32_t *)P.dev.perm, M, K,
                            (const float *)P.dev.B, N, (typename Store<ST>::R *)prof,
@@ -935,8 +1112,18 @@ hipError_t launch_prep(const Plan &P, const double *pos64, float4 *posoff, hipSt
 {
     const int n = (int)P.cfg.n_pos;
     hipLaunchKernelGGL(k_prep_positions, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
-                       pos64, (const int32_t *)P.dev.perm, (const int32_t *)P.dev.leaf_of_sorted,
-                       (const double *)P.dev.leaf_centre, n, posoff, (float *)nullptr, 0);
+                       pos64, (const double *)P.dev.pos64, P.cfg.position_slack,
+                       (const int32_t *)P.dev.perm, (const int32_t *)P.dev.leaf_of_sorted,
+                       (const double *)P.dev.leaf_centre, n, posoff);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_positions(const Plan &P, const double *pos64, int32_t *counts,
+                                  hipStream_t st)
+{
+    const int n = (int)P.cfg.n_pos;
+    hipLaunchKernelGGL(k_check_positions, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                       pos64, (const double *)P.dev.pos64, P.cfg.position_slack, n, counts);
     return hipGetLastError();
 }
 
@@ -944,7 +1131,7 @@ hipError_t launch_rc_gemm(int storage_a, const void *A, const int32_t *a_perm, i
                           const float *B, int N, float *C, const int32_t *c_perm, hipStream_t st,
                           const float *a_w, const float *c_w)
 {
-    dim3 grid((M + 63) / 64, (N + 63) / 64);
+    dim3 grid(((M + 63) / 64) * ((N + 63) / 64));
     switch (storage_a) {
     case HHFFBP_F16:
         hipLaunchKernelGGL((k_rc_gemm<HHFFBP_F16, HHFFBP_C64>), grid, dim3(kBlock), 0, st,
@@ -971,6 +1158,10 @@ std::vector<std::string> Plan::stage_names() const
         n = {"direct_exact"};
     } else if (S == 0) {
         n = {"rc_gemm", "direct_bp"};
+    } else if (cfg.range_fused) {
+        n = {"prep_positions", "leaf_bp_fused"};
+        for (int d = S - 1; d >= F; --d) n.push_back("merge_d" + std::to_string(d));
+        n.push_back("final");
     } else {
         n = {"prep_positions", "rc_gemm", "leaf_bp"};
         for (int d = S - 1; d >= F; --d) n.push_back("merge_d" + std::to_string(d));

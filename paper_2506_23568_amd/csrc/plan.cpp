@@ -682,6 +682,11 @@ void validate(const hhffbp_config &c)
     if (c.interp_taps != 4 && c.interp_taps != 6) bad("interp_taps must be 4 or 6");
     if (c.final_staging != 0 && c.final_staging != 1) bad("final_staging must be 0 or 1");
     if (c.root_grid != 0 && c.root_grid != 1) bad("root_grid must be 0 or 1");
+    if (c.range_fused != 0 && c.range_fused != 1) bad("range_fused must be 0 or 1");
+    if (c.range_fused && (c.mode != HHFFBP_FACTORIZED || c.stages == 0 ||
+                          c.range_kernel != HHFFBP_RANGE_LINEAR || c.storage != HHFFBP_C64))
+        bad("range_fused needs the factorised mode with stages != 0, the linear range kernel "
+            "and C64 storage");
     if (c.root_grid && (c.mode != HHFFBP_FACTORIZED || c.stages == 0))
         bad("a root grid needs the factorised mode with stages != 0");
     if (c.interp_kernel != HHFFBP_INTERP_LAGRANGE && c.interp_kernel != HHFFBP_INTERP_BANDLIMITED)
@@ -1033,7 +1038,8 @@ void build_plan_host(Plan &P)
     const size_t csz = (c.storage == HHFFBP_C64) ? 8 : 4;
     size_t off = 0;
     P.ws_prof = off;
-    off += al((size_t)c.n_pos * P.Nr * 8);  // also the backward's float32 range-derivative profiles
+    if (!c.range_fused)  // the fused level-1 BP keeps its profiles in LDS
+        off += al((size_t)c.n_pos * P.Nr * 8);  // also the backward's float32 range-derivative profiles
     P.ws_posoff = off;
     off += al((size_t)c.n_pos * 16);
     P.ws_scales = off;
@@ -1060,7 +1066,7 @@ void build_plan_host(Plan &P)
     P.ws_total_bwd = off;
 
     // worst-case gain from the echoes to each stage (half-precision scales):
-    // profiles <= sqrt(2) Nf max|W| max|s|; a leaf sums <= members x W taps of
+    // profiles <= sqrt(2) Nf max|W| max|w_i| max|s| (w_i the aperture weights); a leaf sums <= members x W taps of
     // them; a merge sums <= children x L_u L_v L_n (L_a the interpolation
     // kernel's largest absolute weight sum on [0, 1) along axis a: 1.25 (T = 4)
     // and 1.3906 (T = 6) for Lagrange; sampled from the fitted polynomials, with
@@ -1084,7 +1090,10 @@ void build_plan_host(Plan &P)
             lt *= la;
         }
         P.scale_mult.assign(P.n_scales(), 0.0f);
-        const double m0 = std::sqrt(2.0) * (double)c.n_freq * wmax;
+        // the aperture weights scale each echo row before the range compression
+        double wt = P.weights.empty() ? 1.0 : 0.0;
+        for (float v : P.weights) wt = std::max(wt, (double)std::fabs(v));
+        const double m0 = std::sqrt(2.0) * (double)c.n_freq * wmax * wt;
         P.scale_mult[0] = (float)m0;
         if (S > 0) {
             size_t mem_max = 0;
@@ -1155,6 +1164,8 @@ void upload_plan(Plan &P)
     upload_vec(P.device_bytes, &D.leaf_of_sorted, P.leaf_of_sorted);
     upload_vec(P.device_bytes, &D.leaf_centre, P.leaf_centre);
     upload_vec(P.device_bytes, &D.pos64, P.positions);
+    upload_vec(P.device_bytes, &D.check_counts,
+               std::vector<int32_t>((size_t)((P.cfg.n_pos + kBlockThreads - 1) / kBlockThreads), 0));
     if (!P.weights.empty()) upload_vec(P.device_bytes, &D.weights, P.weights);
     if (P.cfg.mode == HHFFBP_DIRECT_EXACT) {
         std::vector<float> kt(P.k.size());
@@ -1171,7 +1182,8 @@ void upload_plan(Plan &P)
         std::vector<BlockItem> blocks, blocks_fwd;
         std::vector<double> x, y, z;
         std::vector<LeafPoint> lpts;
-        std::vector<BinWindow> wins;
+        std::vector<BinWindow> wins, fused_wins;
+        std::vector<BlockItem> fused_blocks;
         int32_t vbase = 0, cbase = 0;
         for (int32_t ti : P.compact_to_tree[d]) {
             const HostNode &hn = P.levels[d][ti];
@@ -1260,9 +1272,10 @@ void upload_plan(Plan &P)
                 const int32_t mlo = (int32_t)std::floor(-reach / P.dR - 0.5 * P.W);
                 const int32_t mhi = (int32_t)std::floor(reach / P.dR + 1.0 - 0.5 * P.W) + P.W - 1;
                 const int32_t Nr = (int32_t)P.Nr;
-                for (int32_t st = 0; st < nd.npts; st += 256) {
+                // the window of the block of points [st, st + len)
+                auto window = [&](int32_t st, int32_t len) {
                     int32_t blo = INT32_MAX, bhi = INT32_MIN;
-                    for (int32_t q = st; q < std::min(nd.npts, st + 256); ++q) {
+                    for (int32_t q = st; q < std::min(nd.npts, st + len); ++q) {
                         if (!std::isfinite(L.xyz[3 * q + 2])) continue;
                         const int32_t b1 = lpts[vbase + q].bin + 1;
                         blo = std::min(blo, b1 + mlo);
@@ -1278,8 +1291,14 @@ void upload_plan(Plan &P)
                         blo = std::max(0, std::min(blo, Nr - P.W));
                         bhi = blo + P.W - 1;
                     }
-                    wins.push_back(BinWindow{blo, bhi - blo + 1});
-                }
+                    return BinWindow{blo, bhi - blo + 1};
+                };
+                for (int32_t st = 0; st < nd.npts; st += 256) wins.push_back(window(st, 256));
+                if (P.cfg.range_fused)
+                    for (int32_t st = 0; st < nd.npts; st += kFusedPoints) {
+                        fused_blocks.push_back(BlockItem{hn.compact, st});
+                        fused_wins.push_back(window(st, kFusedPoints));
+                    }
             }
             vbase += nd.npts;
             cbase += L.ni * L.nj;
@@ -1306,6 +1325,18 @@ void upload_plan(Plan &P)
             upload_vec(P.device_bytes, &D.leafpts, lpts);
             upload_vec(P.device_bytes, &D.leaf_blocks, blocks);
             upload_vec(P.device_bytes, &D.leaf_wins, wins);
+            upload_vec(P.device_bytes, &D.fused_blocks, fused_blocks);
+            upload_vec(P.device_bytes, &D.fused_wins, fused_wins);
+            P.n_blocks_fused = (int64_t)fused_blocks.size();
+            P.fused_win_max = 0;
+            for (const BinWindow &wv : fused_wins) P.fused_win_max = std::max(P.fused_win_max, wv.n);
+            // the fused kernel's LDS: 16 echo rows of 2 Nf (rounded up to 4), 16
+            // profiles over the widest window, 16 position offsets
+            const size_t kp = (size_t)((2 * P.cfg.n_freq + 3) / 4 * 4);
+            if (P.cfg.range_fused &&
+                (kp * 16 + 16 * 2 * (size_t)P.fused_win_max) * 4 + 16 * 16 > 65536)
+                throw Error{HHFFBP_E_UNSUPPORTED,
+                            "range_fused: the echo rows and profile window exceed 64 KB of LDS"};
             upload_vec(P.device_bytes, &D.final_tiles, P.final_tiles);
             P.n_blocks_leaf = (int64_t)blocks.size();
             P.leaf_win_max = 0;
@@ -1354,6 +1385,7 @@ void release_plan(Plan &P)
     fr(D.leaf_of_sorted);
     fr(D.leaf_centre);
     fr(D.pos64);
+    fr(D.check_counts);
     fr(D.posoff);
     fr(D.unit_scales);
     fr(D.weights);
@@ -1362,6 +1394,8 @@ void release_plan(Plan &P)
     fr(D.leafpts);
     fr(D.leaf_blocks);
     fr(D.leaf_wins);
+    fr(D.fused_blocks);
+    fr(D.fused_wins);
     fr(D.final_tiles);
     fr(D.adj_blocks);
     fr(D.Bd);

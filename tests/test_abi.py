@@ -39,7 +39,7 @@ def test_config_default_layout():
     assert list(c.oversample) == [3.0, 3.0, 3.5]
     assert (c.range_kernel, c.range_taps, c.storage, c.device) == (0, 7, 0, 0)
     assert c.range_oversample == 2.0 and abs(c.position_slack - 5e-3) < 1e-15
-    assert (c.interp_kernel, c.final_staging, c.root_grid) == (0, 1, 0)
+    assert (c.interp_kernel, c.final_staging, c.root_grid, c.range_fused) == (0, 1, 0, 0)
 
 
 def test_final_stage_bricks(small):
@@ -62,6 +62,9 @@ def _args(w):
     (dict(merge_factor=3), -1), (dict(interp_taps=5), -1), (dict(range_taps=11), -1),
     (dict(oversample=0.5), -1), (dict(stages=-9), -1),
     (dict(root_grid=True, mode="direct_rc"), -1), (dict(root_grid=True, stages=0), -1),
+    (dict(range_fused=True), -1),  # the ES range kernel
+    (dict(range_fused=True, range_kernel="linear", storage="f16"), -1),
+    (dict(range_fused=True, range_kernel="linear", mode="direct_rc"), -1),
 ])
 def test_invalid_configurations_are_rejected(small, change, status):
     kw = dict(device=-1)

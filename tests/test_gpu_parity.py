@@ -249,6 +249,30 @@ def test_positions_moved_to_the_slack(torch, small, range_kernel):
     assert e <= 1e-5
 
 
+def test_positions_beyond_the_slack(torch, small):
+    """Positions moved past the plan's 5 mm slack: hhffbp_check_positions counts
+    exactly the moved ones and returns HHFFBP_E_INVALID, the image is the one of
+    the positions clamped to the slack box (bit for bit), and a position inside
+    the box passes the check."""
+    pl = H.Plan(*_args(small), stages=2, oversample=GAMMA, interp_taps=TAPS)
+    rng = np.random.default_rng(13)
+    moved = small.positions.copy()
+    idx = rng.choice(small.n_pos, 37, replace=False)
+    moved[idx, rng.integers(0, 3, idx.size)] += rng.choice([-1.0, 1.0], idx.size) * 7e-3
+    dev_moved = torch.from_numpy(moved).cuda()
+    assert pl.check_positions(dev_moved) == idx.size
+    with pytest.raises(H.HHFFBPError) as e:
+        H.binding._check(H.lib().hhffbp_check_positions(pl._h, dev_moved.data_ptr(), None, None))
+    assert e.value.status == -1
+    s = pl.config.position_slack
+    clamped = np.clip(moved, small.positions - s, small.positions + s)
+    assert pl.check_positions(torch.from_numpy(clamped).cuda()) == 0
+    a = _run(torch, pl, small, positions=moved)
+    b = _run(torch, pl, small, positions=clamped)
+    _say(f"  {idx.size} positions moved 7 mm: counted, image equal to the clamped positions'")
+    assert np.array_equal(a, b)
+
+
 @pytest.fixture(scope="module")
 def mid():
     from workloads import make_config
@@ -398,6 +422,56 @@ def test_mid_bandlimited_vs_stored_oracle(torch, mid, mid_fp64_boxes, form):
     _check_peaks(w, img, mid_fp64_boxes, 50)
 
 
+@pytest.mark.parametrize("S,Q", [(2, 4), (2, 2)])
+def test_fused_range_compression_small(torch, small, oracle_small, S, Q):
+    """The fused range compression + level-1 BP (range_fused): image and every
+    stage against the oracle HHFFBPA of the same form (linear kernel, U = 4)
+    <= 1e-5, and against the two-kernel form of the same plan <= 1e-6."""
+    from oracle import hhffbp as OH
+    from oracle import plan as OP
+    g = (2.2, 2.2, 2.6)
+    kw = dict(stages=S, merge_factor=Q, oversample=g, interp_taps=TAPS, interp_kernel="bandlimited",
+              range_kernel="linear", range_oversample=4.0)
+    op = OP.build_plan(*_args(small), S, Q, g, TAPS, kernel="bandlimited")
+    ref, vals = OH.image(op, small.echoes, small.positions, keep=True, range_u=4)
+    pf = H.Plan(*_args(small), range_fused=True, **kw)
+    ws = pf._workspace(torch)
+    img = _run(torch, pf, small, workspace=ws)
+    worst = max(_nrmse(pf.workspace_view(ws, d, i).cpu().numpy().astype(np.complex128), v)
+                for (d, i), v in vals.items())
+    two = _run(torch, H.Plan(*_args(small), **kw), small)
+    e, e2 = _nrmse(img, ref), _nrmse(img, two)
+    _say(f"  fused S={S} Q={Q}: vs oracle {e:.3e}, worst stage {worst:.3e}, vs two kernels {e2:.3e}")
+    assert e <= 1e-5 and worst <= 1e-5 and e2 <= 1e-6
+    with pytest.raises(H.HHFFBPError) as err:
+        pf.backward(torch.from_numpy(small.echoes.astype(np.complex64)).cuda(),
+                    torch.zeros(small.grid_dims, dtype=torch.complex64, device="cuda"))
+    assert err.value.status == -2
+
+
+def test_fused_range_compression_mid(torch, mid):
+    """The fused form on the mid workload's benchmarked plan choices against the
+    stored oracle HHFFBPA (linear U = 4): image samples and every depth <= 1e-5."""
+    g = np.load(os.path.join(GOLDEN, "mid_bandlimited_oracle.npz"))
+    w = mid
+    pl = H.Plan(*_args(w), stages=3, merge_factor=4, oversample=BENCH_GAMMA, interp_taps=TAPS,
+                interp_kernel="bandlimited", range_kernel="linear",
+                range_oversample=float(g["range_u"]), range_fused=True)
+    ws = pl._workspace(torch)
+    img = _run(torch, pl, w, workspace=ws)
+    e = _nrmse(img.ravel()[g["index"]], g["linear_image"])
+    worst = 0.0
+    for d in (1, 2, 3):
+        node, point, val = g[f"linear_d{d}_node"], g[f"linear_d{d}_point"], g[f"linear_d{d}_value"]
+        v = np.zeros(val.size, np.complex128)
+        for n in np.unique(node):
+            sel = node == n
+            v[sel] = pl.workspace_view(ws, d, int(n))[torch.from_numpy(point[sel]).cuda()].cpu().numpy()
+        worst = max(worst, _nrmse(v, val))
+    _say(f"  fused mid: image vs oracle {e:.3e}, worst depth {worst:.3e}")
+    assert e <= 1e-5 and worst <= 1e-5
+
+
 def test_automatic_stages_small(torch, small, oracle_small):
     """A plan with stages = -3 is the plan of the S it chose: the same image
     bit for bit, within -30 dB of eq. (4)."""
@@ -486,6 +560,25 @@ def test_direct_exact_mid_sampled(torch, mid):
     e = _nrmse(img[sel], ref)
     _say(f"  mid direct_exact (512 voxels) NRMSE {e:.3e}")
     assert e <= 1e-5
+
+
+def test_aperture_weights_half_storage(torch, small):
+    """IEEE-half storage with aperture weights up to 8: the per-stage scales
+    include the largest weight, so nothing overflows; against the oracle's
+    weighted HHFFBPA of the same half-precision echoes, <= 1e-3."""
+    from oracle import hhffbp as OH
+    from oracle import plan as OP
+    w8 = np.random.default_rng(9).uniform(0.5, 8.0, small.n_pos)
+    pl = H.Plan(*_args(small), stages=2, oversample=GAMMA, interp_taps=TAPS, weights=w8,
+                storage="f16")
+    ech = H.Plan.pack_echoes(torch.from_numpy(small.echoes), "f16").cuda()
+    got = pl.image(ech).cpu().numpy()
+    eh = torch.view_as_complex(ech.float().contiguous()).cpu().numpy().astype(np.complex128)
+    op = OP.build_plan(*_args(small), 2, 4, GAMMA, TAPS)
+    ref = OH.image(op, eh, small.positions, weights=w8)
+    e = _nrmse(got, ref)
+    _say(f"  f16 storage, weights up to 8: vs oracle {e:.3e}, finite {np.isfinite(got).all()}")
+    assert np.isfinite(got).all() and e <= 1e-3
 
 
 @pytest.mark.parametrize("mode", ["factorized", "direct_exact", "direct_rc"])
