@@ -167,64 +167,13 @@ __device__ __forceinline__ void range_weights(float x, float beta_log2e, float *
 }
 
 // ---------------------------------------------------------------------------
-// Child coordinates and SDC phase at a point, float64 (Sec. III, eq. uvw_xyz,
-// eq. sdc_phi); the continuous lattice coordinate t = gamma (u, v, n) is split
-// into an integer base floor(t) and a float32 fraction.
+// A stencil in a child's lattice: base indices floor(t) of the continuous
+// lattice coordinate t = gamma (u, v, n) (Sec. III, eq. uvw_xyz) and the
+// fractions t - floor(t).
 struct ChildCoord {
     int bi, bj, bl;
     float fu, fv, fn;
-    double phi;
 };
-
-// Square root of a positive float64 to ~2e-14 relative: the float32 reciprocal
-// square root as a seed, one Newton step in float64, times x.  The merge
-// geometry needs ~1e-12 relative (lattice coordinates to ~1e-11 of a step,
-// phases to ~1e-12 rad); correctly rounded sqrt costs several times more.
-__device__ __forceinline__ double sqrt_pos(double x)
-{
-    double r = (double)__builtin_amdgcn_rsqf((float)x);
-    r = r * fma(-0.5 * x, r * r, 1.5);
-    return x * r;
-}
-
-__device__ __forceinline__ double phi_only(const NodeDev &c, double x, double y, double z,
-                                           double kmin, double kmax)
-{
-    const double zz = z * z;
-    const double dx0 = x - c.x0, dx1 = x - c.x1, dy0 = y - c.y0, dy1 = y - c.y1;
-    const double r = sqrt_pos(dx0 * dx0 + dy0 * dy0 + zz) + sqrt_pos(dx0 * dx0 + dy1 * dy1 + zz) +
-                     sqrt_pos(dx1 * dx1 + dy0 * dy0 + zz) + sqrt_pos(dx1 * dx1 + dy1 * dy1 + zz);
-    return 0.25 * (kmax * sqrt_pos(r * r - c.d2) + kmin * r);
-}
-
-__device__ __forceinline__ ChildCoord child_coord(const NodeDev &c, double x, double y, double z,
-                                                  double gu, double gv, double gn, double kmin,
-                                                  double kmax)
-{
-    const double zz = z * z;
-    const double cx = fmin(fmax(x, c.x0), c.x1), cy = fmin(fmax(y, c.y0), c.y1);
-    const double dx0 = x - c.x0, dx1 = x - c.x1, dy0 = y - c.y0, dy1 = y - c.y1;
-    const double ex = x - cx, ey = y - cy;
-    const double ru0 = sqrt_pos(dx0 * dx0 + ey * ey + zz), ru1 = sqrt_pos(dx1 * dx1 + ey * ey + zz);
-    const double rv0 = sqrt_pos(ex * ex + dy0 * dy0 + zz), rv1 = sqrt_pos(ex * ex + dy1 * dy1 + zz);
-    const double r = sqrt_pos(dx0 * dx0 + dy0 * dy0 + zz) + sqrt_pos(dx0 * dx0 + dy1 * dy1 + zz) +
-                     sqrt_pos(dx1 * dx1 + dy0 * dy0 + zz) + sqrt_pos(dx1 * dx1 + dy1 * dy1 + zz);
-    const double s = sqrt_pos(r * r - c.d2);
-    const double tu = gu * (kmax / kPi) * (ru0 - ru1);
-    const double tv = gv * (kmax / kPi) * (rv0 - rv1);
-    const double tn = gn * (kmax * s - kmin * r) * (0.25 / kPi);
-    ChildCoord o;
-    const double fu = floor(tu + kStencilEps), fv = floor(tv + kStencilEps),
-                 fn = floor(tn + kStencilEps);
-    o.bi = (int)fu;
-    o.bj = (int)fv;
-    o.bl = (int)fn;
-    o.fu = (float)(tu - fu);
-    o.fv = (float)(tv - fv);
-    o.fn = (float)(tn - fn);
-    o.phi = 0.25 * (kmax * s + kmin * r);
-    return o;
-}
 
 // Lagrange weights on nodes -T/2+1 .. T/2 at x in [0, 1).
 template <int T>
@@ -334,62 +283,9 @@ __device__ __forceinline__ void rotate_mac(float2 v, float turns, float &are, fl
     aim = fmaf(v.x, sn, fmaf(v.y, cs, aim));
 }
 
-// Separable T^3 interpolation of a compressed child subimage (missing points are 0).
-// The grids are built so that every stencil of a planned point lies inside the
-// child's pencils; a pencil whose T taps along n are all present takes the
-// branch-free path (one index sum, T contiguous loads).  The guarded per-tap
-// path remains for stencils that rounding could push past a pencil end.
-template <int T, int ST, int K>
-__device__ __forceinline__ float2 interp_child(const NodeDev &c, const ColEntry *__restrict__ cols,
-                                               const typename Store<ST>::C *__restrict__ vals,
-                                               const ChildCoord &g, const InterpPoly &ip)
-{
-    float wu[T], wv[T], wn[T];
-    interp_weights<T, K>(ip, g, wu, wv, wn);
-    const int l0 = g.bl - T / 2 + 1;
-    float are = 0.0f, aim = 0.0f;
-#pragma unroll
-    for (int a = 0; a < T; ++a) {
-        const int ci = g.bi + a - T / 2 + 1 - c.i0;
-        if ((unsigned)ci >= (unsigned)c.ni) continue;
-#pragma unroll
-        for (int b = 0; b < T; ++b) {
-            const int cj = g.bj + b - T / 2 + 1 - c.j0;
-            if ((unsigned)cj >= (unsigned)c.nj) continue;
-            const ColEntry e = cols[c.col_base + ci * c.nj + cj];
-            const int rel = l0 - e.lo;
-            const typename Store<ST>::C *colv = vals + (c.val_base + e.off);
-            float sre = 0.0f, sim = 0.0f;
-            if (rel >= 0 && rel + T - 1 <= e.hi - e.lo) {
-                const typename Store<ST>::C *p = colv + rel;
-#pragma unroll
-                for (int k = 0; k < T; ++k) {
-                    const float2 v = Store<ST>::ld(p[k]);
-                    sre = fmaf(wn[k], v.x, sre);
-                    sim = fmaf(wn[k], v.y, sim);
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < T; ++k) {
-                    const int r = rel + k;
-                    if (r >= 0 && r <= e.hi - e.lo) {
-                        const float2 v = Store<ST>::ld(colv[r]);
-                        sre = fmaf(wn[k], v.x, sre);
-                        sim = fmaf(wn[k], v.y, sim);
-                    }
-                }
-            }
-            const float wab = wu[a] * wv[b];
-            are = fmaf(wab, sre, are);
-            aim = fmaf(wab, sim, aim);
-        }
-    }
-    return make_float2(are, aim);
-}
-
 // The T^3 taps from a dense LDS box: p points at the stencil's first tap, the
 // box holds nl values per (i, j) column and nj columns per i.  Same summation
-// order as interp_rec and interp_child's pencil path.
+// order as interp_rec.
 template <int T>
 __device__ __forceinline__ float2 interp_box(const float2 *p, int nj, int nl, const float *wu,
                                              const float *wv, const float *wn)
@@ -414,20 +310,6 @@ __device__ __forceinline__ float2 interp_box(const float2 *p, int nj, int nl, co
     }
     return make_float2(are, aim);
 }
-
-__device__ __forceinline__ void phase_mac(float2 v, double phase, float &are, float &aim)
-{
-    double t = phase * (0.5 / kPi);
-    t -= rint(t);
-    const float tf = (float)t;
-    const float sn = sin_turns(tf), cs = cos_turns(tf);
-    are = fmaf(v.x, cs, fmaf(-v.y, sn, are));
-    aim = fmaf(v.x, sn, fmaf(v.y, cs, aim));
-}
-
-struct GeoParams {
-    double gu, gv, gn, kmin, kmax;
-};
 
 
 }  // namespace dev

@@ -31,7 +31,9 @@ struct NodeDev {
     int32_t nchild;             // non-empty children (compact indices at depth + 1)
     int32_t child[4];
     int32_t pos_begin, pos_end; // leaves: range in leaf-sorted position order
-    int32_t pad0, pad1;
+    int32_t fwd_block0;         // depths F..S-1: the node's first block of the forward merge
+                                // (its points p lie in block fwd_block0 + p / (256 / Q))
+    int32_t pad1;
 };
 
 // One pencil (column) of a lattice: l in [lo, hi] stored from value offset `off`
@@ -164,7 +166,6 @@ struct DeviceBuffers {
     std::vector<void *> cols;       // per depth: ColEntry[]
     std::vector<void *> colbase;    // per depth: int32 off - lo per column (the value index of
                                     // lattice point l of column c is val_base + colbase[c] + l)
-    std::vector<void *> px, py, pz; // per depth < S: float64 SoA grid points
     void *leafpts = nullptr;        // LeafPoint[] of depth S
     void *leaf_blocks = nullptr;    // BlockItem[]
     void *leaf_wins = nullptr;      // BinWindow[], one per leaf block
@@ -230,6 +231,7 @@ struct Plan {
     size_t device_bytes = 0;  // plan tables uploaded to the device (owned by the plan)
     double leaf_reach = 0.0;  // max |p' - c| over leaf members and their leaf centres c (z = 0), plus slack
     double model_s = 0.0;     // the Sec. IV-B cost model's level-1 BP + interpolation time
+    size_t adj_lds_max = 0;   // dynamic LDS per block the level-1 adjoint may use (plan time)
     InterpPoly ipoly{};       // merge interpolation weights
     std::vector<size_t> ws_gvals;        // backward: float32 cotangents per depth
     std::vector<float> scale_mult;       // host copy of dev.scale_mult
@@ -270,6 +272,9 @@ hipError_t launch_check_positions(const Plan &P, const double *pos64, int32_t *c
 hipError_t launch_rc_gemm(int storage_a, const void *A, const int32_t *a_perm, int M, int K,
                           const float *B, int N, float *C, const int32_t *c_perm, hipStream_t st,
                           const float *a_w, const float *c_w);
+// Plan time: the dynamic LDS the level-1 adjoint may use (adj_lds_max) and the
+// opt-in of its instances that need more than the default (kernels_adjoint.hip).
+hipError_t prepare_backward(Plan &P);
 hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *positions,
                               const void *grad_image, void *grad_echoes, double *grad_positions,
                               char *ws, hipStream_t st);

@@ -38,7 +38,8 @@ __global__ __launch_bounds__(kBlock) void k_zero(float4 *__restrict__ p, int64_t
         p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-// Transpose of interp_child: grad[tap] += w(tap) * (gre + j gim).
+// Transpose of the separable interpolation: grad[tap] += w(tap) * (gre + j gim),
+// taps outside the child's pencils skipped.
 template <int T, int K>
 __device__ __forceinline__ void scatter_child(const NodeDev &c, const ColEntry *__restrict__ cols,
                                               float2 *__restrict__ grad, const ChildCoord &g,
@@ -70,15 +71,27 @@ __device__ __forceinline__ void scatter_child(const NodeDev &c, const ColEntry *
     }
 }
 
-// (gre + j gim) = v exp(-j phase)
-__device__ __forceinline__ void rotate_back(float2 v, double phase, float &gre, float &gim)
+// (gre + j gim) = v exp(-j 2 pi turns), turns in [-1/2, 1/2]
+__device__ __forceinline__ void rotate_back(float2 v, float turns, float &gre, float &gim)
 {
-    double t = phase * (0.5 / kPi);
-    t -= rint(t);
-    const float tf = (float)t;
-    const float sn = sin_turns(tf), cs = cos_turns(tf);
+    const float sn = sin_turns(turns), cs = cos_turns(turns);
     gre = v.x * cs + v.y * sn;
     gim = v.y * cs - v.x * sn;
+}
+
+// The stencil base and fractions of a plan-time record (InterpIdx, InterpGeo)
+// as the child coordinates the scatter takes.
+template <int T>
+__device__ __forceinline__ ChildCoord record_coord(const NodeDev &c, InterpIdx ix, const InterpGeo &g)
+{
+    ChildCoord cc;
+    cc.bi = (int)(ix.cij & 0xffffu) + c.i0 + T / 2 - 1;
+    cc.bj = (int)(ix.cij >> 16) + c.j0 + T / 2 - 1;
+    cc.bl = ix.l0 + T / 2 - 1;
+    cc.fu = g.fu;
+    cc.fv = g.fv;
+    cc.fn = g.fn;
+    return cc;
 }
 
 // --- block-aggregated scatter --------------------------------------------
@@ -182,10 +195,11 @@ __device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c
         const int bi = g.bi + lo - o0, bj = g.bj + lo - o1, bl = g.bl + lo - o2;
         // Neighbouring points often share a stencil base; taken in the same tap
         // order their atomics would hit one LDS address per instruction.  Each
-        // lane rotates its v and n tap order by lane bits (z and y neighbours of
-        // the final stage's tiles), so such lanes add to different entries at
-        // once; integer sums do not depend on the order.
-        const int rn = lane % T, rv = (lane >> 3) % T;
+        // lane rotates its v and n tap order by lane bits (the z and y
+        // neighbours of the 4 x 4 x 16 bricks: z = lane mod 16, y = lane / 16),
+        // so such lanes add to different entries at once; integer sums do not
+        // depend on the order.
+        const int rn = lane % T, rv = (lane >> 4) % T;
         float wvr[T], wnr[T];
         int ov[T], on[T];
 #pragma unroll
@@ -241,92 +255,101 @@ __device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c
     __syncthreads();
 }
 
+// F^H: a block per brick of the final stage (4 x 4 x 16 voxels, numbered and
+// laid out as k_final's); each voxel's cotangent is rotated by -Phi_child and
+// scattered into the child's grid through the block's box, with the stencil,
+// fractions and phase of the forward's plan-time record of that (voxel, child).
 template <int T, int K>
 __global__ __launch_bounds__(kBlock) void k_final_adj(const NodeDev *__restrict__ children,
                                                       int nchild, const ColEntry *__restrict__ ccols,
-                                                      float2 *__restrict__ cgrad, GeoParams gp,
-                                                      const InterpPoly ip,
-                                                      double ox, double oy, double oz, double sx,
-                                                      double sy, double sz, int nx, int ny, int nz,
+                                                      float2 *__restrict__ cgrad,
+                                                      const InterpIdx *__restrict__ ridx,
+                                                      const InterpGeo *__restrict__ rgeo,
+                                                      const InterpPoly ip, int nx, int ny, int nz,
                                                       const float2 *__restrict__ gimg)
 {
     __shared__ BoxShared sh;
-    // a block is a 4 x 8 x 8 voxel tile
-    const int tnx = (nx + 3) / 4, tny = (ny + 7) / 8;
-    const int b = blockIdx.x;
-    const int tx = b % tnx, ty = (b / tnx) % tny, tz = b / (tnx * tny);
-    const int ix = tx * 4 + (threadIdx.x >> 6), iy = ty * 8 + ((threadIdx.x >> 3) & 7),
-              iz = tz * 8 + (threadIdx.x & 7);
+    const int bz = (nz + kBrickZ - 1) / kBrickZ, by = (ny + kBrickY - 1) / kBrickY;
+    const int brick = (int)blockIdx.x;
+    const int kx = brick / (by * bz), ky = (brick / bz) % by, kz = brick % bz;
+    const int t = (int)threadIdx.x;
+    const int ix = kx * kBrickX + t / (kBrickY * kBrickZ), iy = ky * kBrickY + (t / kBrickZ) % kBrickY,
+              iz = kz * kBrickZ + t % kBrickZ;
     bool active = ix < nx && iy < ny && iz < nz;
     float2 g = make_float2(0.f, 0.f);
     if (active) g = gimg[((int64_t)ix * ny + iy) * nz + iz];
     active = active && (g.x != 0.0f || g.y != 0.0f);
-    const double x = ox + ix * sx, y = oy + iy * sy, z = oz + iz * sz;
     for (int c = 0; c < nchild; ++c) {
         const NodeDev ch = children[c];
+        const size_t r = ((size_t)brick * nchild + c) * kBlock + t;
+        const InterpIdx rx = ridx[r];
+        const bool on = active && rx.cij != kNoPair;
         ChildCoord cc{};
         float gre = 0.0f, gim = 0.0f;
-        if (active) {
-            cc = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
-            rotate_back(g, cc.phi, gre, gim);
+        if (on) {
+            const InterpGeo rg = rgeo[r];
+            cc = record_coord<T>(ch, rx, rg);
+            rotate_back(g, rg.turns, gre, gim);
         }
-        block_scatter_child<T, K>(sh, active, ch, ccols, cgrad, cc, ip, gre, gim);
+        block_scatter_child<T, K>(sh, on, ch, ccols, cgrad, cc, ip, gre, gim);
     }
 }
 
 // M_d^H on a merge brick (4 x 4 columns x 16 steps of a parent grid; lane t:
 // l = t mod 16 fastest, then j, then i): each point's cotangent is rotated by
-// Phi_child - Phi_parent and scattered into the child's grid through the
-// block's box.  Bricks keep that box, and so the number of global atomics per
-// point, smaller than runs of points along the pencils would.
+// -(Phi_child - Phi_parent) and scattered into the child's grid through the
+// block's box.  The stencil, fractions and phase are the forward's plan-time
+// record of that (point, child): block fwd_block0 + p / (256 / Q) of the
+// forward merge, wave (p mod (256 / Q)) / 64 * Q + c, lane p mod 64.  Bricks
+// keep the box, and so the number of global atomics per point, smaller than
+// runs of points along the pencils would.
 template <int T, int K>
 __global__ __launch_bounds__(kBlock) void k_merge_adj(const NodeDev *__restrict__ parents,
                                                       const ColEntry *__restrict__ pcols,
                                                       const MergeBrick *__restrict__ bricks,
-                                                      const double *__restrict__ px,
-                                                      const double *__restrict__ py,
-                                                      const double *__restrict__ pz,
                                                       const float2 *__restrict__ pgrad,
                                                       const NodeDev *__restrict__ children,
                                                       const ColEntry *__restrict__ ccols,
-                                                      float2 *__restrict__ cgrad, GeoParams gp,
+                                                      float2 *__restrict__ cgrad,
+                                                      const InterpIdx *__restrict__ ridx,
+                                                      const InterpGeo *__restrict__ rgeo, int Q,
                                                       const InterpPoly ip)
 {
     __shared__ BoxShared sh;
     const MergeBrick mb = bricks[blockIdx.x];
-    const NodeDev nd = parents[mb.node];
+    const NodeDev *ndp = parents + mb.node;
+    const int ni = ndp->ni, nj = ndp->nj, i0 = ndp->i0, j0 = ndp->j0, col_base = ndp->col_base;
+    const int val_base = ndp->val_base, nchild = ndp->nchild, fb0 = ndp->fwd_block0;
     const int t = (int)threadIdx.x;
-    const int ci = mb.i + t / (kBrickY * kBrickZ) - nd.i0, cj = mb.j + (t / kBrickZ) % kBrickY - nd.j0;
+    const int ci = mb.i + t / (kBrickY * kBrickZ) - i0, cj = mb.j + (t / kBrickZ) % kBrickY - j0;
     const int l = mb.l + t % kBrickZ;
     bool active = false;
-    int gi = 0;
-    if ((unsigned)ci < (unsigned)nd.ni && (unsigned)cj < (unsigned)nd.nj) {
-        const ColEntry pe = pcols[nd.col_base + ci * nd.nj + cj];
+    int p = 0;
+    if ((unsigned)ci < (unsigned)ni && (unsigned)cj < (unsigned)nj) {
+        const ColEntry pe = pcols[col_base + ci * nj + cj];
         if (l >= pe.lo && l <= pe.hi) {
             active = true;
-            gi = nd.val_base + pe.off + (l - pe.lo);
+            p = pe.off + (l - pe.lo);
         }
     }
-    double x = 0.0, y = 0.0, z = 1.0;
     float2 g = make_float2(0.f, 0.f);
-    if (active) {
-        x = px[gi];
-        y = py[gi];
-        z = pz[gi];
-        g = pgrad[gi];
-    }
-    active = active && (z > 0.0) && (g.x != 0.0f || g.y != 0.0f);  // absent points hold nothing
-    const double phip = active ? phi_only(nd, x, y, z, gp.kmin, gp.kmax) : 0.0;
-    const int32_t *child_idx = parents[mb.node].child;
-    for (int c = 0; c < nd.nchild; ++c) {
-        const NodeDev ch = children[child_idx[c]];
+    if (active) g = pgrad[val_base + p];
+    active = active && (g.x != 0.0f || g.y != 0.0f);
+    const int pb = kBlock / Q;
+    const size_t rbase = (size_t)(fb0 + p / pb) * kBlock + (size_t)((p % pb) / 64 * Q) * 64 + p % 64;
+    for (int c = 0; c < nchild; ++c) {
+        const NodeDev ch = children[ndp->child[c]];
+        InterpIdx rx{kNoPair, 0};
+        if (active) rx = ridx[rbase + (size_t)c * 64];
+        const bool on = active && rx.cij != kNoPair;  // absent parent points hold nothing
         ChildCoord cc{};
         float gre = 0.0f, gim = 0.0f;
-        if (active) {
-            cc = child_coord(ch, x, y, z, gp.gu, gp.gv, gp.gn, gp.kmin, gp.kmax);
-            rotate_back(g, cc.phi - phip, gre, gim);
+        if (on) {
+            const InterpGeo rg = rgeo[rbase + (size_t)c * 64];
+            cc = record_coord<T>(ch, rx, rg);
+            rotate_back(g, rg.turns, gre, gim);
         }
-        block_scatter_child<T, K>(sh, active, ch, ccols, cgrad, cc, ip, gre, gim);
+        block_scatter_child<T, K>(sh, on, ch, ccols, cgrad, cc, ip, gre, gim);
     }
 }
 
@@ -527,30 +550,53 @@ __global__ __launch_bounds__(kBlock) void k_pos_out(const float4 *__restrict__ g
     out[3 * m + 2] = (double)g.z;
 }
 
+template <bool S_, bool P_>
+size_t leaf_adj_lds(const Plan &P)
+{
+    return (P_ ? (size_t)kAdjPos * P.Nr * sizeof(float2) : 0) +
+           (S_ ? (size_t)kAdjPos * (P.Nr + 1) * 2 * sizeof(unsigned long long) : 0);
+}
+
 template <int KERNEL, int W, bool S_, bool P_, bool RED>
 hipError_t launch_leaf_adj(const Plan &P, const float4 *posoff, const float2 *dprof,
                            const float2 *gleaf, const float *gmax, float2 *gprof, float4 *gpos,
                            hipStream_t st)
 {
-    const size_t sh = (P_ ? (size_t)kAdjPos * P.Nr * sizeof(float2) : 0) +
-                      (S_ ? (size_t)kAdjPos * (P.Nr + 1) * 2 * sizeof(unsigned long long) : 0);
-    if (sh > kLdsLimit) {
-        // beyond the default dynamic LDS: use the device's opt-in limit if it is larger
-        int dev = 0, optin = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess ||
-            sh > (size_t)optin)
-            return hipErrorInvalidConfiguration;  // caller maps to UNSUPPORTED
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_leaf_adj<KERNEL, W, S_, P_, RED>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess)
-            return hipErrorInvalidConfiguration;
-    }
+    const size_t sh = leaf_adj_lds<S_, P_>(P);
+    // beyond the default dynamic LDS the plan has opted the kernel in, up to the
+    // device's per-block limit (prepare_backward)
+    if (sh > P.adj_lds_max) return hipErrorInvalidConfiguration;  // caller maps to UNSUPPORTED
     hipLaunchKernelGGL((k_leaf_adj<KERNEL, W, S_, P_, RED>), dim3(P.n_blocks_adj), dim3(kBlock), sh, st,
                        (const NodeDev *)P.dev.nodes[P.S], (const BlockItem *)P.dev.adj_blocks,
                        (const LeafPoint *)P.dev.leafpts, posoff, dprof, (int)P.Nr,
                        (float)(1.0 / P.dR), (float)(P.beta * 1.4426950408889634),
                        (float)(P.kc / kPi), gleaf, gmax, gprof, gpos);
     return hipGetLastError();
+}
+
+template <int KERNEL, int W, bool S_, bool P_, bool RED>
+hipError_t leaf_adj_optin_one(const Plan &P)
+{
+    const size_t sh = leaf_adj_lds<S_, P_>(P);
+    if (sh <= kLdsLimit || sh > P.adj_lds_max) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_leaf_adj<KERNEL, W, S_, P_, RED>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+}
+
+template <int KERNEL, int W>
+hipError_t leaf_adj_optin(const Plan &P)
+{
+    hipError_t e = hipSuccess;
+    if (P.leaf_reach * (P.kc / kPi) < 128.0) {
+        if (e == hipSuccess) e = leaf_adj_optin_one<KERNEL, W, true, true, false>(P);
+        if (e == hipSuccess) e = leaf_adj_optin_one<KERNEL, W, true, false, false>(P);
+        if (e == hipSuccess) e = leaf_adj_optin_one<KERNEL, W, false, true, false>(P);
+    } else {
+        if (e == hipSuccess) e = leaf_adj_optin_one<KERNEL, W, true, true, true>(P);
+        if (e == hipSuccess) e = leaf_adj_optin_one<KERNEL, W, true, false, true>(P);
+        if (e == hipSuccess) e = leaf_adj_optin_one<KERNEL, W, false, true, true>(P);
+    }
+    return e;
 }
 
 template <int KERNEL, int W>
@@ -577,16 +623,12 @@ template <int T, int K>
 hipError_t launch_scatters(const Plan &P, const void *grad_image, char *ws, hipStream_t st)
 {
     const hhffbp_config &c = P.cfg;
-    GeoParams gp{P.gamma[0], P.gamma[1], P.gamma[2], P.kmin, P.kmax};
     const int nx = (int)c.grid_dims[0], ny = (int)c.grid_dims[1], nz = (int)c.grid_dims[2];
-    const int64_t nv = (int64_t)nx * ny * nz;
-    const unsigned ntile = (unsigned)(((nx + 3) / 4) * ((ny + 7) / 8) * ((nz + 7) / 8));
-    (void)nv;
-    hipLaunchKernelGGL((k_final_adj<T, K>), dim3(ntile), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((k_final_adj<T, K>), dim3(P.n_bricks), dim3(kBlock), 0, st,
                        (const NodeDev *)P.dev.nodes[P.F], (int)P.compact_to_tree[P.F].size(),
-                       (const ColEntry *)P.dev.cols[P.F], (float2 *)(ws + P.ws_gvals[P.F]), gp,
-                       P.ipoly, c.grid_origin[0], c.grid_origin[1], c.grid_origin[2], c.grid_pitch[0],
-                       c.grid_pitch[1], c.grid_pitch[2], nx, ny, nz, (const float2 *)grad_image);
+                       (const ColEntry *)P.dev.cols[P.F], (float2 *)(ws + P.ws_gvals[P.F]),
+                       (const InterpIdx *)P.dev.final_idx, (const InterpGeo *)P.dev.final_geo,
+                       P.ipoly, nx, ny, nz, (const float2 *)grad_image);
     hipError_t e = hipGetLastError();
     for (int d = P.F; d < P.S && e == hipSuccess; ++d) {
         const int64_t nb = (int64_t)P.merge_bricks[d].size();
@@ -594,16 +636,36 @@ hipError_t launch_scatters(const Plan &P, const void *grad_image, char *ws, hipS
         hipLaunchKernelGGL((k_merge_adj<T, K>), dim3(nb), dim3(kBlock), 0, st,
                            (const NodeDev *)P.dev.nodes[d], (const ColEntry *)P.dev.cols[d],
                            (const MergeBrick *)P.dev.merge_bricks[d],
-                           (const double *)P.dev.px[d], (const double *)P.dev.py[d],
-                           (const double *)P.dev.pz[d], (const float2 *)(ws + P.ws_gvals[d]),
+                           (const float2 *)(ws + P.ws_gvals[d]),
                            (const NodeDev *)P.dev.nodes[d + 1], (const ColEntry *)P.dev.cols[d + 1],
-                           (float2 *)(ws + P.ws_gvals[d + 1]), gp, P.ipoly);
+                           (float2 *)(ws + P.ws_gvals[d + 1]), (const InterpIdx *)P.dev.merge_idx[d],
+                           (const InterpGeo *)P.dev.merge_geo[d], P.Q, P.ipoly);
         e = hipGetLastError();
     }
     return e;
 }
 
 }  // namespace
+
+hipError_t prepare_backward(Plan &P)
+{
+    P.adj_lds_max = kLdsLimit;
+    if (P.S < 1 || P.cfg.range_fused) return hipSuccess;
+    int dev = 0, optin = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev);
+    if (e != hipSuccess) return e;
+    P.adj_lds_max = std::max(kLdsLimit, (size_t)optin);
+    if (P.kernel == HHFFBP_RANGE_LINEAR) return leaf_adj_optin<HHFFBP_RANGE_LINEAR, 2>(P);
+    switch (P.W) {
+    case 4: return leaf_adj_optin<HHFFBP_RANGE_ES, 4>(P);
+    case 5: return leaf_adj_optin<HHFFBP_RANGE_ES, 5>(P);
+    case 6: return leaf_adj_optin<HHFFBP_RANGE_ES, 6>(P);
+    case 7: return leaf_adj_optin<HHFFBP_RANGE_ES, 7>(P);
+    case 8: return leaf_adj_optin<HHFFBP_RANGE_ES, 8>(P);
+    default: return hipSuccess;
+    }
+}
 
 hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *positions,
                               const void *grad_image, void *grad_echoes, double *grad_positions,

@@ -829,12 +829,13 @@ void final_records(const Plan &P, std::vector<InterpIdx> &idx, std::vector<Inter
 // interpolation error.  With stages = -K the plan takes the S in 1..K that
 // minimises that count on each candidate's exact pair counts (the range
 // compression term does not depend on S), with per-pair costs measured on
-// MI355X: level-1 BP 2.7 ps (ES kernel) or 1.3 ps (linear); interpolation per
-// (point, child) pair 32 ps (T = 4) or 87 ps (T = 6).
+// MI355X with this build (mid and large workloads, complex64): level-1 BP
+// 0.85 ps (linear range kernel) or 2.3 ps (ES); interpolation per (point,
+// child) pair, merges and final stage alike, 23 ps (T = 4) or 55 ps (T = 6).
 double model_seconds(const Plan &P)
 {
-    const double c2 = (P.kernel == HHFFBP_RANGE_ES) ? 2.7e-12 : 1.3e-12;
-    const double c3 = (P.T == 4) ? 32e-12 : 87e-12;
+    const double c2 = (P.kernel == HHFFBP_RANGE_ES) ? 2.3e-12 : 0.85e-12;
+    const double c3 = (P.T == 4) ? 23e-12 : 55e-12;
     return c2 * (double)P.leaf_pairs + c3 * (double)(P.merge_pairs + P.final_pairs);
 }
 
@@ -1141,9 +1142,6 @@ void upload_plan(Plan &P)
     P.dev.nodes.assign(S + 1, nullptr);
     P.dev.cols.assign(S + 1, nullptr);
     P.dev.colbase.assign(S + 1, nullptr);
-    P.dev.px.assign(S + 1, nullptr);
-    P.dev.py.assign(S + 1, nullptr);
-    P.dev.pz.assign(S + 1, nullptr);
     P.dev.merge_blocks.assign(S + 1, nullptr);
     P.dev.merge_blocks_fwd.assign(S + 1, nullptr);
     P.dev.merge_bricks.assign(S + 1, nullptr);
@@ -1180,7 +1178,6 @@ void upload_plan(Plan &P)
         std::vector<ColEntry> cols;
         std::vector<int32_t> colbase;
         std::vector<BlockItem> blocks, blocks_fwd;
-        std::vector<double> x, y, z;
         std::vector<LeafPoint> lpts;
         std::vector<BinWindow> wins, fused_wins;
         std::vector<BlockItem> fused_blocks;
@@ -1222,15 +1219,10 @@ void upload_plan(Plan &P)
             }
             for (int32_t st = 0; st < nd.npts; st += 256) blocks.push_back(BlockItem{hn.compact, st});
             // the forward merge runs one lane per (point, child): 256 / Q points a block
+            nd.fwd_block0 = (int32_t)blocks_fwd.size();
             for (int32_t st = 0; st < nd.npts; st += 256 / P.Q)
                 blocks_fwd.push_back(BlockItem{hn.compact, st});
-            if (d < S) {
-                for (int64_t q = 0; q < L.npts; ++q) {
-                    x.push_back(L.xyz[3 * q]);
-                    y.push_back(L.xyz[3 * q + 1]);
-                    z.push_back(L.xyz[3 * q + 2]);
-                }
-            } else {
+            if (d == S) {
                 const SubarrayMap map(hn.rect, P.kmin, P.kmax);
                 const double xc = 0.5 * (hn.rect.x0 + hn.rect.x1), yc = 0.5 * (hn.rect.y0 + hn.rect.y1);
                 for (int64_t q = 0; q < L.npts; ++q) {
@@ -1308,9 +1300,6 @@ void upload_plan(Plan &P)
         upload_vec(P.device_bytes, &D.cols[d], cols);
         upload_vec(P.device_bytes, &D.colbase[d], colbase);
         if (d < S) {
-            upload_vec(P.device_bytes, &D.px[d], x);
-            upload_vec(P.device_bytes, &D.py[d], y);
-            upload_vec(P.device_bytes, &D.pz[d], z);
             upload_vec(P.device_bytes, &D.merge_blocks[d], blocks);
             P.n_blocks_merge[d] = (int64_t)blocks.size();
             upload_vec(P.device_bytes, &D.merge_blocks_fwd[d], blocks_fwd);
@@ -1371,6 +1360,8 @@ void upload_plan(Plan &P)
             hipStreamSynchronize(nullptr) != hipSuccess)
             throw Error{HHFFBP_E_DEVICE, "position offsets failed during plan upload"};
     }
+    if (prepare_backward(P) != hipSuccess)
+        throw Error{HHFFBP_E_DEVICE, "setting the level-1 adjoint's LDS limit failed"};
 }
 
 void release_plan(Plan &P)
@@ -1403,7 +1394,7 @@ void release_plan(Plan &P)
     fr(D.scale_mult);
     fr(D.final_idx);
     fr(D.final_geo);
-    for (auto *v : {&D.nodes, &D.cols, &D.colbase, &D.px, &D.py, &D.pz, &D.merge_blocks, &D.merge_blocks_fwd,
+    for (auto *v : {&D.nodes, &D.cols, &D.colbase, &D.merge_blocks, &D.merge_blocks_fwd,
                     &D.merge_bricks, &D.merge_idx, &D.merge_geo})
         for (auto &p : *v) fr(p);
 }
