@@ -7,7 +7,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIBPATH = os.path.join(_HERE, "libhhffbp.so")
+# HHFFBP_LIBRARY may name another build of the same library (the sanitized host
+# build of tests/sanitized_suite.py)
+_LIBPATH = os.environ.get("HHFFBP_LIBRARY") or os.path.join(_HERE, "libhhffbp.so")
 _lib = None
 
 STATUS = {0: "ok", -1: "invalid", -2: "unsupported", -3: "nomem", -4: "device",

@@ -118,6 +118,15 @@ __device__ __forceinline__ int xcd_block_run(int b, int n, int run)
     return ((s / run) * kXcds + x) * run + s % run;
 }
 
+// base[i] through a 32-bit unsigned byte offset from a wave-uniform base, so the
+// load can take the scalar base + 32-bit vector offset form instead of a 64-bit
+// address per lane.  The caller keeps i * sizeof(T) below 2^32.
+template <class T>
+__device__ __forceinline__ T ld_u32(const T *__restrict__ base, uint32_t i)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + i * (uint32_t)sizeof(T));
+}
+
 // floor(x) as int32 in one VALU instruction (the compiler emits floor + convert)
 __device__ __forceinline__ int floor_int(float x)
 {

@@ -82,7 +82,8 @@ constexpr int kTileCap = 2048;
 // of its leaf-sorted positions).
 constexpr int kAdjPos = 8;
 struct TileBox {
-    int32_t i0, j0, l0, ni, nj, nl, lsh, pad;
+    int32_t i0, j0, l0, ni, nj, nl, lsh;
+    int32_t inv_nj;  // ceil(2^22 / nj): column c of the box is (c * inv_nj >> 22, c mod nj)
 };
 
 // Bricks of a parent grid for the merge adjoint: kBrickX x kBrickY columns

@@ -601,26 +601,27 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
         __syncthreads();  // the previous child's box is consumed
         if (tb.ni > 0) {
             // item e = (column << lsh) + l over the padded box, thread-strided;
-            // all entry loads, then all value loads, then the stores
+            // all entry loads, then all value loads, then the stores.  Indices
+            // are 32-bit offsets from the child's (uniform) arrays.
             const int items = (tb.ni * tb.nj) << tb.lsh;
-            const float inv_nj = 1.0f / (float)tb.nj;
-            int roff[kStageBox];
+            const ColEntry *ccol = ccols + ch.col_base + (tb.i0 - ch.i0) * ch.nj + (tb.j0 - ch.j0);
+            const typename Store<ST>::C *cv = cvals + ch.val_base;
+            uint32_t roff[kStageBox];
             bool take[kStageBox];
 #pragma unroll
             for (int k = 0; k < kStageBox; ++k) {
                 const int e = k * kBlock + t;
                 const int col = min(e >> tb.lsh, tb.ni * tb.nj - 1);
-                const int ci = (int)(((float)col + 0.5f) * inv_nj);  // exact: col, nj < 2^11
-                const int cj = col - ci * tb.nj;
-                const ColEntry en = ccols[ch.col_base + (tb.i0 + ci - ch.i0) * ch.nj + (tb.j0 + cj - ch.j0)];
+                const int ci = (col * tb.inv_nj) >> 22, cj = col - ci * tb.nj;
+                const ColEntry en = ld_u32(ccol, (uint32_t)(ci * ch.nj + cj));
                 const int l = e & ((1 << tb.lsh) - 1);
                 const int rr = tb.l0 + l - en.lo;  // position in the pencil
-                take[k] = e < items && l < tb.nl && rr >= 0 && rr <= en.hi - en.lo;
-                roff[k] = take[k] ? ch.val_base + en.off + rr : 0;
+                take[k] = e < items && l < tb.nl && (unsigned)rr <= (unsigned)(en.hi - en.lo);
+                roff[k] = take[k] ? (uint32_t)(en.off + rr) : 0u;
             }
             float2 v[kStageBox];
 #pragma unroll
-            for (int k = 0; k < kStageBox; ++k) v[k] = Store<ST>::ld(cvals[roff[k]]);
+            for (int k = 0; k < kStageBox; ++k) v[k] = Store<ST>::ld(ld_u32(cv, roff[k]));
 #pragma unroll
             for (int k = 0; k < kStageBox; ++k)
                 if (k * kBlock + t < items)

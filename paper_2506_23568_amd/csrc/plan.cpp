@@ -385,8 +385,11 @@ void build_final_tiles(Plan &P)
                 int32_t lsh = 0;
                 while ((1 << lsh) < nl) ++lsh;
                 if (ni < T || nj < T || nl < T || (ni * nj << lsh) > kTileCap) continue;
+                // exact integer quotient of a column index c < 2^11 by nj < 2^11:
+                // c * ceil(2^22 / nj) >> 22 errs by < c / 2^22 < 1 / nj
+                const int32_t inv_nj = (int32_t)(((1 << 22) + nj - 1) / nj);
                 P.final_tiles[b * nc + ch] =
-                    TileBox{lo[0], lo[1], lo[2], (int32_t)ni, (int32_t)nj, (int32_t)nl, lsh, 0};
+                    TileBox{lo[0], lo[1], lo[2], (int32_t)ni, (int32_t)nj, (int32_t)nl, lsh, inv_nj};
                 tiled.fetch_add(1);
             }
         }
