@@ -222,7 +222,7 @@ def autofocus_report(args):
     w = make_config(4, synth_device="cuda")
     p_img = w.imager_positions
     a3 = (p_img, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims)
-    kw = dict(stages=3, merge_factor=4, oversample=AF_GAMMA, interp_taps=TAPS,
+    kw = dict(stages=args.af_stages, merge_factor=4, oversample=AF_GAMMA, interp_taps=TAPS,
               interp_kernel="bandlimited")
     if args.af_range == "linear":
         kw.update(range_kernel="linear", range_oversample=args.af_u)
@@ -236,8 +236,12 @@ def autofocus_report(args):
     clean = H.Plan(*a3, **kw).image(ech64, positions=pos_true)
     nref = torch.linalg.norm(ref)
     out = {}
+    work = None
     for storage in ("f16", "bf16"):
         pl = H.Plan(*a3, storage=storage, **kw)
+        if work is None:
+            info = pl.info()
+            work = {k: info[k] for k in ("leaf_pairs", "merge_pairs", "final_pairs")}
         ech = H.Plan.pack_echoes(torch.from_numpy(w.echoes), storage).cuda()
         e0 = (torch.linalg.norm(pl.image(ech, positions=pos0) - ref) / nref).item()
         torch.cuda.synchronize()
@@ -264,11 +268,11 @@ def autofocus_report(args):
         "vs_baseline": None, "dtype": "f16 storage, f32 arithmetic", "data": "synthetic",
         "config": {"workload": "autofocus: 65536 positions (44 strokes + 20 dense walks), 128 f "
                                "24-40 GHz, 256x256x128 voxels at 1 mm, 200 points + 5000-scatterer "
-                               "slab, smooth trajectory error, S=3 Q=4, 20 Adam steps (lr 0.03 mm) on 16 cosine modes per axis, relative-L2 loss to the clean-trajectory image",
+                               f"slab, smooth trajectory error, S={args.af_stages} Q=4, 20 Adam steps (lr 0.03 mm) on 16 cosine modes per axis, relative-L2 loss to the clean-trajectory image",
                    "range_kernel": f"linear U={args.af_u:g}" if args.af_range == "linear" else "ES U=2 W=7",
                    "interp_kernel": "bandlimited", "oversample": list(AF_GAMMA),
                    "root_grid": args.af_root_grid == "on", "parallelism": "single GPU"},
-        "storage": out,
+        "storage": out, "work": work,
         "reference": "float32 direct BP (ES U=2 W=7) at the true positions, full grid"}), flush=True)
 
 
@@ -584,6 +588,8 @@ def main():
                     help="range kernel of the autofocus workload's images")
     ap.add_argument("--af-u", type=float, default=4.0,
                     help="autofocus workload: range oversampling of the linear range kernel")
+    ap.add_argument("--af-stages", type=int, default=4,
+                    help="autofocus workload: merge stages S")
     ap.add_argument("--af-root-grid", choices=("on", "off"), default="on",
                     help="autofocus workload: plans with a compressed root grid (the "
                          "last merge onto the full aperture's lattice, one resample to "

@@ -117,6 +117,7 @@ struct InterpGeo {
 constexpr uint32_t kNoPair = 0xffffffffu;
 
 // Leaf points per block of the fused range-compression + level-1 BP kernel.
+constexpr int kAbsmaxParts = 1024;  // blocks of the echo max-reduction
 constexpr int kFusedPoints = 1024;
 
 // Range bins [lo, lo + n) that a level-1 BP block can read: every tap of its
@@ -227,7 +228,8 @@ struct Plan {
     std::vector<double> level_estimate;      // per depth: gamma^3 * integral of |det J| over the voxels
     // workspace layout (bytes)
     size_t ws_prof = 0, ws_posoff = 0, ws_total = 0;
-    size_t ws_scales = 0, ws_amax = 0;  // per-call storage scales (float [n_scales()]) and max |echo|
+    size_t ws_scales = 0, ws_amax = 0;  // per-call storage scales (float [n_scales()]) and
+                                        // per-block max |echo| (float [kAbsmaxParts])
     size_t ws_gprof = 0, ws_gpos = 0, ws_gmax = 0, ws_total_bwd = 0;  // backward additions
     size_t device_bytes = 0;  // plan tables uploaded to the device (owned by the plan)
     double leaf_reach = 0.0;  // max |p' - c| over leaf members and their leaf centres c (z = 0), plus slack

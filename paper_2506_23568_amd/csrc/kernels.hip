@@ -93,34 +93,59 @@ __global__ __launch_bounds__(kBlock) void k_check_positions(const double *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Scales for half storage.  k_absmax: the largest |component| of the echoes
-// (non-negative float bits order like unsigned integers).  k_scales:
-// scale_k = 2^-ceil(log2(m mult_k / 2^15)), mult_k the worst-case gain from the
-// echoes to stage k; without a mult (other storage types) every scale is 1.
-__global__ __launch_bounds__(kBlock) void k_zero_u32(uint32_t *p) { if (threadIdx.x == 0) *p = 0u; }
-
+// Scales for half storage.  k_absmax: the largest |component| of the echoes,
+// one partial maximum per block (plain stores: no contended atomics).
+// k_scales folds the partials and sets scale_k = 2^-ceil(log2(m mult_k / 2^15)),
+// mult_k the worst-case gain from the echoes to stage k; without a mult (other
+// storage types) every scale is 1.
 template <int ST>
 __global__ __launch_bounds__(kBlock) void k_absmax(const typename Store<ST>::R *__restrict__ a,
-                                                   int64_t n, uint32_t *__restrict__ out)
+                                                   int64_t n, int64_t n16, float *__restrict__ part)
 {
+    // the first n16 * 16 bytes as 16-byte loads (the caller checks alignment), the rest singly
+    constexpr int per = 16 / (int)sizeof(typename Store<ST>::R);
+    __shared__ float s_m[kBlock / 64];
     float m = 0.0f;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock)
+    const int64_t g0 = (int64_t)blockIdx.x * kBlock + threadIdx.x, gs = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = g0; i < n16; i += gs) {
+        const uint4 u = reinterpret_cast<const uint4 *>(a)[i];
+        const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if constexpr (per == 4) {
+                m = fmaxf(m, fabsf(__uint_as_float(w4[e])));
+            } else {
+                m = fmaxf(m, fabsf(Store<ST>::ldr((uint16_t)(w4[e] & 0xffffu))));
+                m = fmaxf(m, fabsf(Store<ST>::ldr((uint16_t)(w4[e] >> 16))));
+            }
+        }
+    }
+    for (int64_t i = n16 * per + g0; i < n; i += gs)
         m = fmaxf(m, fabsf(Store<ST>::ldr(a[i])));
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 1; w < kBlock / 64; ++w) m = fmaxf(m, s_m[w]);
+        part[blockIdx.x] = m;
+    }
 }
 
-__global__ __launch_bounds__(64) void k_scales(const uint32_t *__restrict__ amax,
+__global__ __launch_bounds__(64) void k_scales(const float *__restrict__ part, int nparts,
                                                const float *__restrict__ mult, int n,
                                                float *__restrict__ scales)
 {
     const int k = threadIdx.x;
+    float m = 0.0f;
+    for (int i = k; i < nparts; i += 64) m = fmaxf(m, part[i]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     if (k >= n) return;
     float s = 1.0f;
     if (mult) {
-        const float b = __uint_as_float(*amax) * mult[k];
+        const float b = m * mult[k];
         if (b > 0.0f && isfinite(b)) {
             int e = (int)ceilf(log2f(b)) - 15;
             e = max(-100, min(100, e));
@@ -192,9 +217,20 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const typename Store<SA>::R 
                     av8[e] = (arow_ok && kg + e < K) ? A[(size_t)arow * K + kg + e] : 0.0f;
             }
         } else {
+            if (vec && arow_ok && kg + 8 <= K) {
+                // eight half-width reals in one 16-byte load
+                const uint4 u = *reinterpret_cast<const uint4 *>(A + (size_t)arow * K + kg);
+                const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
-                av8[e] = (arow_ok && kg + e < K) ? Store<SA>::ldr(A[(size_t)arow * K + kg + e]) : 0.0f;
+                for (int e = 0; e < 4; ++e) {
+                    av8[2 * e] = Store<SA>::ldr((uint16_t)(w4[e] & 0xffffu));
+                    av8[2 * e + 1] = Store<SA>::ldr((uint16_t)(w4[e] >> 16));
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    av8[e] = (arow_ok && kg + e < K) ? Store<SA>::ldr(A[(size_t)arow * K + kg + e]) : 0.0f;
+            }
         }
         const int kb = k0 + bk, cg = col0 + bc;
         if (vec && kb < K && cg + 8 <= N) {
@@ -228,20 +264,49 @@ __global__ __launch_bounds__(kBlock) void k_rc_gemm(const typename Store<SA>::R 
         __syncthreads();
     }
     const float sc = scale ? scale[0] : 1.0f;
+    if constexpr (SC == HHFFBP_C64) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = row0 + wr + a * 16 + 4 * (lane >> 4) + r;
-                const int col = col0 + wc + b * 16 + (lane & 15);
-                if (row < M && col < N) {
-                    const int crow = c_perm ? c_perm[row] : row;
-                    const float cw = c_w ? c_w[crow] : 1.0f;
-                    C[(size_t)crow * N + col] = Store<SC>::str(acc[a][b][r] * (sc * cw));
+                for (int r = 0; r < 4; ++r) {
+                    const int row = row0 + wr + a * 16 + 4 * (lane >> 4) + r;
+                    const int col = col0 + wc + b * 16 + (lane & 15);
+                    if (row < M && col < N) {
+                        const int crow = c_perm ? c_perm[row] : row;
+                        const float cw = c_w ? c_w[crow] : 1.0f;
+                        C[(size_t)crow * N + col] = Store<SC>::str(acc[a][b][r] * (sc * cw));
+                    }
                 }
-            }
+    } else {
+        // Half-width output in 4-byte pairs: lanes 2m and 2m + 1 hold adjacent
+        // columns of the same rows; they swap one value per row pair, the even
+        // lane then writing both columns of row r and the odd lane both columns
+        // of row r + 1 (N = 2 Nr is even, so a pair never straddles the edge).
+        const bool odd = lane & 1;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int rp = 0; rp < 4; rp += 2) {
+                    const float send = odd ? acc[a][b][rp] : acc[a][b][rp + 1];
+                    const float got = __shfl_xor(send, 1, 64);
+                    const int r = rp + (odd ? 1 : 0);
+                    const float own = odd ? acc[a][b][rp + 1] : acc[a][b][rp];
+                    const float lo = odd ? got : own, hi = odd ? own : got;
+                    const int row = row0 + wr + a * 16 + 4 * (lane >> 4) + r;
+                    const int colp = col0 + wc + b * 16 + (lane & 14);
+                    if (row < M && colp < N) {
+                        const int crow = c_perm ? c_perm[row] : row;
+                        const float s2 = sc * (c_w ? c_w[crow] : 1.0f);
+                        const uint32_t v = (uint32_t)Store<SC>::str(lo * s2) |
+                                           ((uint32_t)Store<SC>::str(hi * s2) << 16);
+                        *reinterpret_cast<uint32_t *>(C + (size_t)crow * N + colp) = v;
+                    }
+                }
+    }
 }
 
 // 16-byte staging needs K % 8 == 0, N % 4 == 0 and 16-byte aligned operands.
@@ -995,18 +1060,19 @@ template <int ST>
 hipError_t launch_scales(const Plan &P, const void *echoes, char *ws, hipStream_t st)
 {
     float *scales = (float *)(ws + P.ws_scales);
-    uint32_t *amax = (uint32_t *)(ws + P.ws_amax);
+    float *part = (float *)(ws + P.ws_amax);
     const int ns = P.n_scales();
     if (ST == HHFFBP_F16) {
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, st, amax);
         const int64_t n = 2 * P.cfg.n_pos * P.cfg.n_freq;
-        const int nb = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
+        const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kAbsmaxParts, (n + kBlock - 1) / kBlock));
+        const int64_t per = 16 / (int64_t)sizeof(typename Store<ST>::R);
+        const int64_t n16 = reinterpret_cast<uintptr_t>(echoes) % 16 == 0 ? n / per : 0;
         hipLaunchKernelGGL((k_absmax<ST>), dim3(nb), dim3(kBlock), 0, st,
-                           (const typename Store<ST>::R *)echoes, n, amax);
-        hipLaunchKernelGGL(k_scales, dim3(1), dim3(64), 0, st, (const uint32_t *)amax,
+                           (const typename Store<ST>::R *)echoes, n, n16, part);
+        hipLaunchKernelGGL(k_scales, dim3(1), dim3(64), 0, st, (const float *)part, nb,
                            (const float *)P.dev.scale_mult, ns, scales);
     } else {
-        hipLaunchKernelGGL(k_scales, dim3(1), dim3(64), 0, st, (const uint32_t *)amax,
+        hipLaunchKernelGGL(k_scales, dim3(1), dim3(64), 0, st, (const float *)nullptr, 0,
                            (const float *)nullptr, ns, scales);
     }
     return hipGetLastError();

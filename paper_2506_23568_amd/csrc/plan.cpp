@@ -1049,7 +1049,7 @@ void build_plan_host(Plan &P)
     P.ws_scales = off;
     off += al(64 * sizeof(float));
     P.ws_amax = off;
-    off += al(sizeof(uint32_t));
+    off += al(kAbsmaxParts * sizeof(float));
     P.ws_vals.assign(S + 1, 0);
     for (int d = P.F; d <= S; ++d) {
         P.ws_vals[d] = off;
