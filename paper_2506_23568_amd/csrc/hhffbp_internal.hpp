@@ -171,6 +171,7 @@ struct DeviceBuffers {
     void *leafpts = nullptr;        // LeafPoint[] of depth S
     void *leaf_blocks = nullptr;    // BlockItem[]
     void *leaf_wins = nullptr;      // BinWindow[], one per leaf block
+    void *leaf_order = nullptr;     // int32[n_blocks_leaf_phys]: workgroup -> leaf block, -1 idle
     void *fused_blocks = nullptr;   // BlockItem[] of kFusedPoints leaf points (range_fused)
     void *fused_wins = nullptr;     // BinWindow[], one per fused block
     void *final_tiles = nullptr;    // TileBox[n_bricks][n nodes at depth F]
@@ -219,6 +220,7 @@ struct Plan {
     std::vector<int64_t> n_blocks_merge_fwd; // per depth
     std::vector<std::vector<MergeBrick>> merge_bricks;  // per depth, host copy
     int64_t n_blocks_leaf = 0, n_blocks_adj = 0, n_blocks_fused = 0;
+    int64_t n_blocks_leaf_phys = 0;  // workgroups of the level-1 BP launch (leaf_order)
     int32_t fused_win_max = 0;  // widest BinWindow of the fused blocks
     int32_t leaf_win_max = 0;  // widest BinWindow of the level-1 BP blocks
     std::vector<TileBox> final_tiles;  // host copy, brick-major

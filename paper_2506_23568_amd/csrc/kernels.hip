@@ -331,6 +331,7 @@ inline int gemm_vec(const void *A, int K, const float *B, int N)
 // only when 2 kc |Delta R| / 2 pi <= 2 kc max|p' - c| / 2 pi stays below 128.
 template <int KERNEL, int W, int ST, bool RED>
 __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ leaves,
+                                                    const int32_t *__restrict__ order,
                                                     const BlockItem *__restrict__ blocks,
                                                     const BinWindow *__restrict__ wins,
                                                     const LeafPoint *__restrict__ pts,
@@ -342,7 +343,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
                                                     typename Store<ST>::C *__restrict__ out)
 {
     extern __shared__ unsigned char smem[];
-    const int lb = xcd_block<16>((int)blockIdx.x, (int)gridDim.x);
+    // the plan's workgroup -> block map keeps each leaf's blocks on one XCD
+    const int lb = order[blockIdx.x];
+    if (lb < 0) return;
     const BlockItem blk = blocks[lb];
     // only the block's bin window [r0, r0 + nrb) is staged, as many positions at a
     // time as kLdsBudget holds
@@ -996,15 +999,17 @@ hipError_t launch_bp_kernels(const Plan &P, const double *pos64, const void *pro
     // |Delta R| <= |p' - c| (triangle inequality): the carrier's argument stays
     // below 128 turns without reduction when the plan's leaf reach allows it
     if (P.leaf_reach * (P.kc / kPi) < 128.0)
-        hipLaunchKernelGGL((k_leaf_bp<KERNEL, W, ST, false>), dim3(P.n_blocks_leaf), dim3(kBlock), sh,
-                           st, (const NodeDev *)P.dev.nodes[P.S], (const BlockItem *)P.dev.leaf_blocks,
+        hipLaunchKernelGGL((k_leaf_bp<KERNEL, W, ST, false>), dim3(P.n_blocks_leaf_phys), dim3(kBlock), sh,
+                           st, (const NodeDev *)P.dev.nodes[P.S], (const int32_t *)P.dev.leaf_order,
+                           (const BlockItem *)P.dev.leaf_blocks,
                            (const BinWindow *)P.dev.leaf_wins, (const LeafPoint *)P.dev.leafpts,
                            posoff, (const C *)prof, (int)P.Nr, inv_dR, beta_log2e, kc_turns,
                            scales, P.S,
                            (C *)(ws + P.ws_vals[P.S]));
     else
-        hipLaunchKernelGGL((k_leaf_bp<KERNEL, W, ST, true>), dim3(P.n_blocks_leaf), dim3(kBlock), sh,
-                           st, (const NodeDev *)P.dev.nodes[P.S], (const BlockItem *)P.dev.leaf_blocks,
+        hipLaunchKernelGGL((k_leaf_bp<KERNEL, W, ST, true>), dim3(P.n_blocks_leaf_phys), dim3(kBlock), sh,
+                           st, (const NodeDev *)P.dev.nodes[P.S], (const int32_t *)P.dev.leaf_order,
+                           (const BlockItem *)P.dev.leaf_blocks,
                            (const BinWindow *)P.dev.leaf_wins, (const LeafPoint *)P.dev.leafpts,
                            posoff, (const C *)prof, (int)P.Nr, inv_dR, beta_log2e, kc_turns,
                            scales, P.S,

@@ -1137,6 +1137,44 @@ void upload_vec(size_t &total, void **dst, const std::vector<T> &v)
         throw Error{HHFFBP_E_DEVICE, "hipMemcpy failed during plan upload"};
 }
 
+// Workgroup -> leaf block of the level-1 BP.  The dispatcher deals workgroup b
+// to XCD b mod 8; every block of one leaf is placed on one XCD, so the leaf's
+// range profiles come from HBM once and from that XCD's L2 for its other
+// blocks.  Leaves go to XCDs largest first, each to the least loaded one (work =
+// blocks x positions); slots an XCD does not fill hold -1 (the workgroup exits).
+std::vector<int32_t> leaf_block_order(const std::vector<BlockItem> &blocks,
+                                      const std::vector<NodeDev> &leaves)
+{
+    constexpr int kXcds = 8;
+    struct Run {
+        int32_t first, count;
+        double work;
+    };
+    std::vector<Run> runs;
+    for (int32_t b = 0; b < (int32_t)blocks.size(); ++b) {
+        if (b == 0 || blocks[b].node != blocks[b - 1].node) runs.push_back(Run{b, 0, 0.0});
+        ++runs.back().count;
+    }
+    for (Run &r : runs) {
+        const NodeDev &nd = leaves[blocks[r.first].node];
+        r.work = (double)r.count * (double)std::max(1, nd.pos_end - nd.pos_begin);
+    }
+    std::stable_sort(runs.begin(), runs.end(), [](const Run &a, const Run &b) { return a.work > b.work; });
+    std::vector<std::vector<int32_t>> lists(kXcds);
+    std::vector<double> load(kXcds, 0.0);
+    for (const Run &r : runs) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[x] += r.work;
+        for (int32_t k = 0; k < r.count; ++k) lists[x].push_back(r.first + k);
+    }
+    size_t slots = 0;
+    for (const auto &l : lists) slots = std::max(slots, l.size());
+    std::vector<int32_t> order(slots * kXcds, -1);
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t s = 0; s < lists[x].size(); ++s) order[s * kXcds + x] = lists[x][s];
+    return order;
+}
+
 }  // namespace
 
 void upload_plan(Plan &P)
@@ -1331,9 +1369,12 @@ void upload_plan(Plan &P)
                             "range_fused: the echo rows and profile window exceed 64 KB of LDS"};
             upload_vec(P.device_bytes, &D.final_tiles, P.final_tiles);
             P.n_blocks_leaf = (int64_t)blocks.size();
+            const std::vector<int32_t> order = leaf_block_order(blocks, nodes);
+            upload_vec(P.device_bytes, &D.leaf_order, order);
+            P.n_blocks_leaf_phys = (int64_t)order.size();
             P.leaf_win_max = 0;
             for (const BinWindow &wv : wins) P.leaf_win_max = std::max(P.leaf_win_max, wv.n);
-            // adjoint work items: each leaf's positions in groups of 16
+            // adjoint work items: each leaf's positions in groups of kAdjPos
             std::vector<BlockItem> ab;
             for (size_t li = 0; li < nodes.size(); ++li)
                 for (int32_t p0 = nodes[li].pos_begin; p0 < nodes[li].pos_end; p0 += kAdjPos)
@@ -1388,6 +1429,7 @@ void release_plan(Plan &P)
     fr(D.leafpts);
     fr(D.leaf_blocks);
     fr(D.leaf_wins);
+    fr(D.leaf_order);
     fr(D.fused_blocks);
     fr(D.fused_wins);
     fr(D.final_tiles);
