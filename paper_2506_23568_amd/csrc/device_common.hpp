@@ -138,8 +138,9 @@ __device__ __forceinline__ int floor_int(float x)
 // Positions per staged chunk of the level-1 BP for a bin window of nrb bins:
 // as many as kLdsBudget holds (a float4 and nrb float2 each), at most 32.
 constexpr int kLeafChunkMax = 32;
-// thread-strided steps that stage a final-stage box of kTileCap values
-constexpr int kStageBox = (kTileCap + kBlock - 1) / kBlock;
+// thread-strided steps per round of the final stage's box staging (a box of
+// up to kTileCap values takes (kTileCap / kBlock) / kStageRound rounds)
+constexpr int kStageRound = 4;
 // thread-strided staging steps that cover a kLdsBudget tile of float2
 constexpr int kStageSteps = (int)((kLdsBudget / sizeof(float2) + kBlock - 1) / kBlock);
 __host__ __device__ inline int leaf_chunk(int nrb)

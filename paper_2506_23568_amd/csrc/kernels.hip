@@ -668,32 +668,38 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
         const TileBox tb = tiles[(size_t)brick * nchild + c];
         __syncthreads();  // the previous child's box is consumed
         if (tb.ni > 0) {
-            // item e = (column << lsh) + l over the padded box, thread-strided;
-            // all entry loads, then all value loads, then the stores.  Indices
-            // are 32-bit offsets from the child's (uniform) arrays.
+            // item e = (column << lsh) + l over the padded box, thread-strided,
+            // in rounds of kStageRound items per thread (a uniform trip count: a
+            // small box takes one round); per round all entry loads, then all
+            // value loads, then the stores.  Indices are 32-bit offsets from the
+            // child's (uniform) arrays.
             const int items = (tb.ni * tb.nj) << tb.lsh;
             const ColEntry *ccol = ccols + ch.col_base + (tb.i0 - ch.i0) * ch.nj + (tb.j0 - ch.j0);
             const typename Store<ST>::C *cv = cvals + ch.val_base;
-            uint32_t roff[kStageBox];
-            bool take[kStageBox];
+#pragma unroll 1
+            for (int e0 = 0; e0 < items; e0 += kStageRound * kBlock) {
+                uint32_t roff[kStageRound];
+                bool take[kStageRound];
 #pragma unroll
-            for (int k = 0; k < kStageBox; ++k) {
-                const int e = k * kBlock + t;
-                const int col = min(e >> tb.lsh, tb.ni * tb.nj - 1);
-                const int ci = (col * tb.inv_nj) >> 22, cj = col - ci * tb.nj;
-                const ColEntry en = ld_u32(ccol, (uint32_t)(ci * ch.nj + cj));
-                const int l = e & ((1 << tb.lsh) - 1);
-                const int rr = tb.l0 + l - en.lo;  // position in the pencil
-                take[k] = e < items && l < tb.nl && (unsigned)rr <= (unsigned)(en.hi - en.lo);
-                roff[k] = take[k] ? (uint32_t)(en.off + rr) : 0u;
+                for (int k = 0; k < kStageRound; ++k) {
+                    const int e = e0 + k * kBlock + t;
+                    const int col = min(e >> tb.lsh, tb.ni * tb.nj - 1);
+                    const int ci = (col * tb.inv_nj) >> 22, cj = col - ci * tb.nj;
+                    const ColEntry en = ld_u32(ccol, (uint32_t)(ci * ch.nj + cj));
+                    const int l = e & ((1 << tb.lsh) - 1);
+                    const int rr = tb.l0 + l - en.lo;  // position in the pencil
+                    take[k] = e < items && l < tb.nl && (unsigned)rr <= (unsigned)(en.hi - en.lo);
+                    roff[k] = take[k] ? (uint32_t)(en.off + rr) : 0u;
+                }
+                float2 v[kStageRound];
+#pragma unroll
+                for (int k = 0; k < kStageRound; ++k) v[k] = Store<ST>::ld(ld_u32(cv, roff[k]));
+#pragma unroll
+                for (int k = 0; k < kStageRound; ++k) {
+                    const int e = e0 + k * kBlock + t;
+                    if (e < items) s_tile[e + (e >> tb.lsh)] = take[k] ? v[k] : make_float2(0.0f, 0.0f);
+                }
             }
-            float2 v[kStageBox];
-#pragma unroll
-            for (int k = 0; k < kStageBox; ++k) v[k] = Store<ST>::ld(ld_u32(cv, roff[k]));
-#pragma unroll
-            for (int k = 0; k < kStageBox; ++k)
-                if (k * kBlock + t < items)
-                    s_tile[k * kBlock + t + ((k * kBlock + t) >> tb.lsh)] = take[k] ? v[k] : make_float2(0.0f, 0.0f);
         }
         __syncthreads();
         const size_t r = ((size_t)brick * nchild + c) * kBlock + t;
