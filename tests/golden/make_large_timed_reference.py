@@ -1,8 +1,13 @@
-"""Write tests/golden/large_bandlimited_oracle.npz: the float64 oracle HHFFBPA of
-the 65536-position, 128-frequency, 256x256x128-voxel handheld workload with the
-benchmarked plan choices (S = 3, Q = 4, band-limited weights, T = 4,
-gamma = (2.2, 2.2, 2.6)) on 16 voxel bricks of 4 x 4 x 4 (8 around point
-targets, 8 seeded), in two forms of the level-1 sum:
+"""Write the float64 oracle HHFFBPA of the 65536-position, 128-frequency,
+256x256x128-voxel handheld workload with band-limited weights (T = 4, gamma =
+(2.2, 2.2, 2.6), Q = 4) on 16 voxel bricks of 4 x 4 x 4 (8 around point
+targets, 8 seeded):
+
+* tests/golden/large_bandlimited_oracle.npz: S = 3 onto the voxel grid (default);
+* tests/golden/large_s4_root_oracle.npz: S = 4 with a compressed root grid, the
+  benchmarked form (``--stages 4 --root-grid``);
+
+each in two forms of the level-1 sum:
 
 * "linear": range profiles at U = 4 read by linear interpolation (the timed form);
 * "eq4":    eq. (4) itself (what the ES parity mode approximates to ~1e-6).
@@ -10,11 +15,14 @@ targets, 8 seeded), in two forms of the level-1 sum:
 The oracle evaluates only the bricks' cones (oracle.hhffbp.image_at): the grid
 points their stencils reach, depth by depth.  Stored per form: the bricks'
 voxels and up to 4096 seeded points of every depth of the cones (node, point,
-compressed value).  Calls only oracle/ and workloads/; run from the repository
-root (CPU echo synthesis takes ~20 minutes on 8 cores):
+compressed value); with a root grid depth 0 is the root's lattice.  Calls only
+oracle/ and workloads/; run from the repository root (CPU echo synthesis takes
+~20 minutes on 8 cores):
 
     python tests/golden/make_large_timed_reference.py
+    python tests/golden/make_large_timed_reference.py --stages 4 --root-grid
 """
+import argparse
 import os
 import sys
 import time
@@ -30,7 +38,6 @@ from workloads import make_config  # noqa: E402
 
 GAMMA = (2.2, 2.2, 2.6)
 TAPS = 4
-STAGES = 3
 RANGE_U = 4
 
 
@@ -57,22 +64,31 @@ def bricks(w, rng):
 
 
 def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--stages", type=int, default=3)
+    ap.add_argument("--root-grid", action="store_true")
+    args = ap.parse_args()
+    stages, root = args.stages, args.root_grid
+    name = "large_bandlimited_oracle.npz" if (stages, root) == (3, False) else \
+        f"large_s{stages}{'_root' if root else ''}_oracle.npz"
     t0 = time.time()
     w = make_config(2)
     print(f"echoes {time.time() - t0:.0f} s", flush=True)
     pl = OP.build_plan(w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims,
-                       STAGES, 4, GAMMA, TAPS, kernel="bandlimited")
+                       stages, 4, GAMMA, TAPS, kernel="bandlimited", root_grid=root)
     print(f"plan {time.time() - t0:.0f} s", flush=True)
     index = bricks(w, np.random.default_rng(37))
-    store = dict(index=index, gamma=np.array(GAMMA), taps=TAPS, stages=STAGES, range_u=RANGE_U)
+    store = dict(index=index, gamma=np.array(GAMMA), taps=TAPS, stages=stages, range_u=RANGE_U,
+                 root_grid=root)
+    top = 0 if root else 1
     for form, ru in (("linear", RANGE_U), ("eq4", None)):
         img, kept = OH.image_at(pl, w.echoes, w.positions, index, range_u=ru, keep=True)
         print(f"{form} cone {time.time() - t0:.0f} s: "
               + ", ".join(f"depth {d} {sum(v[0].size for k, v in kept.items() if k[0] == d)}"
-                          for d in range(1, STAGES + 1)), flush=True)
+                          for d in range(top, stages + 1)), flush=True)
         store[f"{form}_image"] = img
         rng = np.random.default_rng(41)
-        for d in range(1, STAGES + 1):
+        for d in range(top, stages + 1):
             keys = sorted(k for k in kept if k[0] == d)
             node = np.concatenate([np.full(kept[k][0].size, k[1], np.int64) for k in keys])
             point = np.concatenate([kept[k][0] for k in keys]).astype(np.int64)
@@ -81,7 +97,7 @@ def main():
             store[f"{form}_d{d}_node"] = node[pick]
             store[f"{form}_d{d}_point"] = point[pick]
             store[f"{form}_d{d}_value"] = val[pick]
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "large_bandlimited_oracle.npz")
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), name)
     np.savez_compressed(out, **store)
     print(f"wrote {out}: {index.size} voxels", flush=True)
 

@@ -190,24 +190,29 @@ def test_large_peaks(torch, large, gold, form):
     assert r["matched"] == r["compared"]
 
 
+@pytest.mark.parametrize("stored", ["large_bandlimited_oracle.npz", "large_s4_root_oracle.npz"])
 @pytest.mark.parametrize("form", ["linear", "eq4"])
-def test_large_bandlimited_vs_stored_oracle(torch, large, form):
-    """The benchmarked plan choices at full size against the stored oracle
-    HHFFBPA of the same choices (tests/golden/make_large_timed_reference.py) on
-    voxel bricks and on sampled grid points of every depth of their cones: the
-    linear range kernel at U = 4 (the timed form) against the oracle's linear
-    form, the ES parity mode against the oracle with eq. (4) level-1 sums; NRMSE
-    <= 1e-5 and no value off by more than 5e-5 of the reference's RMS."""
-    path = os.path.join(os.path.dirname(GOLDEN), "large_bandlimited_oracle.npz")
+def test_large_bandlimited_vs_stored_oracle(torch, large, form, stored):
+    """Band-limited plans at full size against the stored oracle HHFFBPA of the
+    same choices (tests/golden/make_large_timed_reference.py): S = 3 onto the
+    voxel grid, and the benchmarked form, S = 4 with a compressed root grid; on
+    voxel bricks and on sampled grid points of every depth of their cones (the
+    root's lattice included).  The linear range kernel at U = 4 (the timed form)
+    against the oracle's linear form, the ES parity mode against the oracle with
+    eq. (4) level-1 sums; NRMSE <= 1e-5 and no value off by more than 5e-5 of the
+    reference's RMS."""
+    path = os.path.join(os.path.dirname(GOLDEN), stored)
     if not os.path.exists(path):
         pytest.skip("stored oracle values missing (tests/golden/make_large_timed_reference.py)")
     g = np.load(path)
     assert tuple(g["gamma"]) == BL_GAMMA and int(g["taps"]) == TAPS
+    stages = int(g["stages"])
+    root = bool(g["root_grid"]) if "root_grid" in g.files else False
     w = large
     kw = dict(range_kernel="linear", range_oversample=float(g["range_u"])) if form == "linear" \
         else dict(range_kernel="es", range_oversample=2.0, range_taps=7)
-    pl = H.Plan(*_args(w), stages=3, merge_factor=4, oversample=BL_GAMMA, interp_taps=TAPS,
-                interp_kernel="bandlimited", **kw)
+    pl = H.Plan(*_args(w), stages=stages, merge_factor=4, oversample=BL_GAMMA, interp_taps=TAPS,
+                interp_kernel="bandlimited", root_grid=root, **kw)
     ws = pl._workspace(torch)
     img = pl.image(_ech(torch, w), workspace=ws)
     torch.cuda.synchronize()
@@ -216,7 +221,7 @@ def test_large_bandlimited_vs_stored_oracle(torch, large, form):
     e, m = _nrmse(got, ref), _max_rel(got, ref)
     _say(f"  {form}: image at {ref.size} voxels vs oracle NRMSE {e:.3e}, max/rms {m:.3e}")
     assert e <= 1e-5 and m <= 5e-5
-    for d in (1, 2, 3):
+    for d in range(0 if root else 1, stages + 1):
         node, point, val = g[f"{form}_d{d}_node"], g[f"{form}_d{d}_point"], g[f"{form}_d{d}_value"]
         v = np.zeros(val.size, np.complex128)
         for n in np.unique(node):
