@@ -32,7 +32,8 @@ struct NodeDev {
     int32_t child[4];
     int32_t pos_begin, pos_end; // leaves: range in leaf-sorted position order
     int32_t fwd_block0;         // depths F..S-1: the node's first block of the forward merge
-                                // (its points p lie in block fwd_block0 + p / (256 / Q))
+                                // (the point in lane slot s of its merge order lies in block
+                                // fwd_block0 + s / (256 / Q))
     int32_t pad1;
 };
 
@@ -182,6 +183,8 @@ struct DeviceBuffers {
     std::vector<void *> merge_blocks;  // per depth F..S-1: BlockItem[] of 256 points (adjoint)
     std::vector<void *> merge_blocks_fwd;  // per depth F..S-1: BlockItem[] of 256 / Q points
     std::vector<void *> merge_bricks;      // per depth F..S-1: MergeBrick[] (merge adjoint)
+    std::vector<void *> merge_order;       // per depth F..S-1: int32 per point, lane slot -> point
+    std::vector<void *> merge_rank;        // per depth F..S-1: int32 per point, point -> lane slot
     std::vector<void *> merge_idx, merge_geo;  // per depth F..S-1: InterpIdx[], InterpGeo[] of
                                                // the forward merge, [block][lane]
     void *final_idx = nullptr;      // InterpIdx[n_bricks][nodes at depth F][kBlockThreads]
@@ -219,6 +222,9 @@ struct Plan {
     std::vector<int64_t> n_blocks_merge; // per depth
     std::vector<int64_t> n_blocks_merge_fwd; // per depth
     std::vector<std::vector<MergeBrick>> merge_bricks;  // per depth, host copy
+    // per depth F..S-1 and non-empty node (compact order): the node's points in
+    // the order the forward merge's lanes take them (see build_merge_order)
+    std::vector<std::vector<std::vector<int32_t>>> merge_order;
     int64_t n_blocks_leaf = 0, n_blocks_adj = 0, n_blocks_fused = 0;
     int64_t n_blocks_leaf_phys = 0;  // workgroups of the level-1 BP launch (leaf_order)
     int32_t fused_win_max = 0;  // widest BinWindow of the fused blocks

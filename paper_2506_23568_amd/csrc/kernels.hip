@@ -569,7 +569,8 @@ __global__ __launch_bounds__(kFusedPoints) void k_leaf_bp_fused(
 
 // Merge at depth d: parent grid points of the depth-d nodes, children at
 // depth d + 1.  Output: compressed parent values.  One wave per (64 parent
-// points, child): a block of kBlock threads covers kBlock / CL points, wave w
+// points, child), the points taken in the node's merge order (order: lane slot
+// -> point): a block of kBlock threads covers kBlock / CL points, wave w
 // interpolating child w % CL for point group w / CL, so each wave's gathers
 // stay within one child and follow its points' pencils.  Each lane reads its
 // pair's plan-time record (stencil, fractions, and the phase Phi_c - Phi_P
@@ -580,6 +581,7 @@ __global__ __launch_bounds__(kFusedPoints) void k_leaf_bp_fused(
 template <int T, int ST, int K, int CL>
 __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ parents,
                                                   const BlockItem *__restrict__ blocks,
+                                                  const int32_t *__restrict__ order,
                                                   const InterpIdx *__restrict__ ridx,
                                                   const InterpGeo *__restrict__ rgeo,
                                                   const NodeDev *__restrict__ children,
@@ -600,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
     // scratch memory, as child[c] is indexed at run time
     const NodeDev *nd = parents + blk.node;
     const int npts = nd->npts, vbase = nd->val_base;
-    const int p = blk.start + grp * 64 + lane;
+    const int slot = blk.start + grp * 64 + lane;  // the point is order[vbase + slot]
     const size_t r = (size_t)lb * kBlock + threadIdx.x;
     const InterpIdx ix = ridx[r];
     float are = 0.0f, aim = 0.0f;
@@ -615,7 +617,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
     }
     part[threadIdx.x] = make_float2(are, aim);
     __syncthreads();
-    if (c == 0 && p < npts) {
+    if (c == 0 && slot < npts) {
+        const int p = order[vbase + slot];
         float sre = 0.0f, sim = 0.0f;
 #pragma unroll
         for (int k = 0; k < CL; ++k) {
@@ -1033,6 +1036,7 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
             hipLaunchKernelGGL((k_merge<T, ST, K, CL>), dim3(P.n_blocks_merge_fwd[d]), dim3(kBlock),
                                0, st, (const NodeDev *)P.dev.nodes[d],
                                (const BlockItem *)P.dev.merge_blocks_fwd[d],
+                               (const int32_t *)P.dev.merge_order[d],
                                (const InterpIdx *)P.dev.merge_idx[d], (const InterpGeo *)P.dev.merge_geo[d],
                                (const NodeDev *)P.dev.nodes[d + 1],
                                (const int32_t *)P.dev.colbase[d + 1],

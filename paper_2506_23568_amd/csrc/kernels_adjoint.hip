@@ -299,8 +299,9 @@ __global__ __launch_bounds__(kBlock) void k_final_adj(const NodeDev *__restrict_
 // l = t mod 16 fastest, then j, then i): each point's cotangent is rotated by
 // -(Phi_child - Phi_parent) and scattered into the child's grid through the
 // block's box.  The stencil, fractions and phase are the forward's plan-time
-// record of that (point, child): block fwd_block0 + p / (256 / Q) of the
-// forward merge, wave (p mod (256 / Q)) / 64 * Q + c, lane p mod 64.  Bricks
+// record of that (point, child): with s the point's lane slot in the node's
+// merge order (rank), block fwd_block0 + s / (256 / Q) of the forward merge,
+// wave (s mod (256 / Q)) / 64 * Q + c, lane s mod 64.  Bricks
 // keep the box, and so the number of global atomics per point, smaller than
 // runs of points along the pencils would.
 template <int T, int K>
@@ -312,7 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_adj(const NodeDev *__restrict_
                                                       const ColEntry *__restrict__ ccols,
                                                       float2 *__restrict__ cgrad,
                                                       const InterpIdx *__restrict__ ridx,
-                                                      const InterpGeo *__restrict__ rgeo, int Q,
+                                                      const InterpGeo *__restrict__ rgeo,
+                                                      const int32_t *__restrict__ rank, int Q,
                                                       const InterpPoly ip)
 {
     __shared__ BoxShared sh;
@@ -335,8 +337,10 @@ __global__ __launch_bounds__(kBlock) void k_merge_adj(const NodeDev *__restrict_
     float2 g = make_float2(0.f, 0.f);
     if (active) g = pgrad[val_base + p];
     active = active && (g.x != 0.0f || g.y != 0.0f);
+    // the forward merge's lane slot of this point, and its records
+    const int s = active ? rank[val_base + p] : 0;
     const int pb = kBlock / Q;
-    const size_t rbase = (size_t)(fb0 + p / pb) * kBlock + (size_t)((p % pb) / 64 * Q) * 64 + p % 64;
+    const size_t rbase = (size_t)(fb0 + s / pb) * kBlock + (size_t)((s % pb) / 64 * Q) * 64 + s % 64;
     for (int c = 0; c < nchild; ++c) {
         const NodeDev ch = children[ndp->child[c]];
         InterpIdx rx{kNoPair, 0};
@@ -639,7 +643,8 @@ hipError_t launch_scatters(const Plan &P, const void *grad_image, char *ws, hipS
                            (const float2 *)(ws + P.ws_gvals[d]),
                            (const NodeDev *)P.dev.nodes[d + 1], (const ColEntry *)P.dev.cols[d + 1],
                            (float2 *)(ws + P.ws_gvals[d + 1]), (const InterpIdx *)P.dev.merge_idx[d],
-                           (const InterpGeo *)P.dev.merge_geo[d], P.Q, P.ipoly);
+                           (const InterpGeo *)P.dev.merge_geo[d],
+                           (const int32_t *)P.dev.merge_rank[d], P.Q, P.ipoly);
         e = hipGetLastError();
     }
     return e;

@@ -422,6 +422,62 @@ void build_merge_bricks(Plan &P, int d)
     }
 }
 
+// Lane order of the forward merge at depth d (a wave takes 64 consecutive
+// entries).  Below the root: storage order, runs along the pencils.  Onto the
+// root's own lattice (d = 0): its points grouped in bricks of 2 x 4 x 8 lattice
+// steps (i, j, l), bricks in (i, j, l) order, points within a brick in (i, j, l)
+// order.  There the children's frames are tilted most against the parent's
+// (their centres are a quarter aperture off), so a run along one parent pencil
+// crosses many child columns, and a compact group of points reaches fewer L1
+// lines per gather instruction (measured on the large workload: 0.129 ->
+// 0.102 ms; the deeper merges ran 3-5% slower in brick order).
+void build_merge_order(Plan &P, int d)
+{
+    constexpr int kBi = 2, kBj = 4, kBl = 8;
+    const std::vector<int32_t> &nodes = P.compact_to_tree[d];
+    auto &out = P.merge_order[d];
+    out.assign(nodes.size(), {});
+    parallel_for((int64_t)nodes.size(), 1, [&](int64_t n0, int64_t n1) {
+        for (int64_t n = n0; n < n1; ++n) {
+            const HostLattice &L = P.levels[d][nodes[n]].lat;
+            std::vector<int32_t> &o = out[n];
+            o.resize((size_t)L.npts);
+            if (d > 0) {
+                for (int64_t k = 0; k < L.npts; ++k) o[k] = (int32_t)k;
+                continue;
+            }
+            struct Key {
+                int64_t k;
+                int32_t p;
+            };
+            std::vector<Key> keys;
+            keys.reserve((size_t)L.npts);
+            int32_t lmin = INT32_MAX, lmax = INT32_MIN;
+            for (size_t c = 0; c < L.lo.size(); ++c)
+                if (L.hi[c] >= L.lo[c]) {
+                    lmin = std::min(lmin, L.lo[c]);
+                    lmax = std::max(lmax, L.hi[c]);
+                }
+            const int64_t nbj = (L.nj + kBj - 1) / kBj, nbl = (int64_t)(lmax - lmin) / kBl + 1;
+            for (int32_t i = 0; i < L.ni; ++i)
+                for (int32_t j = 0; j < L.nj; ++j) {
+                    const int64_t c = (int64_t)i * L.nj + j;
+                    for (int32_t l = L.lo[c]; l <= L.hi[c]; ++l) {
+                        const int64_t dl = l - lmin;
+                        const int64_t brick = ((int64_t)(i / kBi) * nbj + j / kBj) * nbl + dl / kBl;
+                        const int64_t inner = ((i % kBi) * kBj + j % kBj) * kBl + dl % kBl;
+                        keys.push_back(Key{brick * (kBi * kBj * kBl) + inner,
+                                           (int32_t)(L.off[c] + (l - L.lo[c]))});
+                    }
+                }
+            std::sort(keys.begin(), keys.end(), [](const Key &a, const Key &b) { return a.k < b.k; });
+            if (keys.size() != o.size())
+                throw Error{HHFFBP_E_NUMERIC, "merge order does not cover the node's points"};
+            for (size_t k = 0; k < keys.size(); ++k) o[k] = keys[k].p;
+        }
+    });
+}
+
 // Fourier transform of the truncated ES kernel phi(t) = exp(beta (sqrt(1 - (2t/W)^2) - 1))
 // on |t| <= W/2, at angular frequency theta (rad per bin); composite Simpson.
 double es_hat(double theta, int W, double beta)
@@ -756,8 +812,9 @@ void pair_record(const Plan &P, const SubarrayMap &mc, const HostLattice &Lc, co
 }  // namespace
 
 // Records of the forward merge at depth d, in the order of its lanes: block k
-// of `blocks` (a node's points from `start`), thread t: wave t / 64 takes child
-// (t / 64) mod Q of point start + (t / 64) / Q * 64 + t mod 64.
+// of `blocks` (a node's lane slots from `start`), thread t: wave t / 64 takes
+// child (t / 64) mod Q of the point in slot start + (t / 64) / Q * 64 + t mod 64
+// of the node's merge order.
 void merge_records(const Plan &P, int d, const std::vector<BlockItem> &blocks,
                    std::vector<InterpIdx> &idx, std::vector<InterpGeo> &geo)
 {
@@ -778,10 +835,12 @@ void merge_records(const Plan &P, int d, const std::vector<BlockItem> &blocks,
             std::vector<int32_t> ch;  // compact indices of the non-empty children, in order
             for (int32_t c : hn.children)
                 if (!P.levels[d + 1][c].empty()) ch.push_back(P.levels[d + 1][c].compact);
+            const std::vector<int32_t> &ord = P.merge_order[d][bk.node];
             for (int t = 0; t < kBlockThreads; ++t) {
                 const int wave = t / 64, c = wave % P.Q;
-                const int64_t p = bk.start + (int64_t)(wave / P.Q) * 64 + t % 64;
-                if (p >= hn.lat.npts || c >= (int)ch.size()) continue;
+                const int64_t slot = bk.start + (int64_t)(wave / P.Q) * 64 + t % 64;
+                if (slot >= hn.lat.npts || c >= (int)ch.size()) continue;
+                const int64_t p = ord[slot];
                 const double *x = &hn.lat.xyz[3 * p];
                 if (!std::isfinite(x[2])) continue;  // absent parent point: value 0
                 double w[3], phip;
@@ -1036,6 +1095,8 @@ void build_plan_host(Plan &P)
     if (S > 0) build_final_tiles(P);  // with final_staging = 0 every box is left empty
     P.merge_bricks.assign(S + 1, {});
     for (int d = P.F; d < S; ++d) build_merge_bricks(P, d);
+    P.merge_order.assign(S + 1, {});
+    for (int d = P.F; d < S; ++d) build_merge_order(P, d);
 
     // workspace layout; profiles and subimages in the storage type
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -1186,6 +1247,8 @@ void upload_plan(Plan &P)
     P.dev.merge_blocks.assign(S + 1, nullptr);
     P.dev.merge_blocks_fwd.assign(S + 1, nullptr);
     P.dev.merge_bricks.assign(S + 1, nullptr);
+    P.dev.merge_order.assign(S + 1, nullptr);
+    P.dev.merge_rank.assign(S + 1, nullptr);
     P.dev.merge_idx.assign(S + 1, nullptr);
     P.dev.merge_geo.assign(S + 1, nullptr);
     P.n_blocks_merge.assign(S + 1, 0);
@@ -1345,6 +1408,19 @@ void upload_plan(Plan &P)
             P.n_blocks_merge[d] = (int64_t)blocks.size();
             upload_vec(P.device_bytes, &D.merge_blocks_fwd[d], blocks_fwd);
             upload_vec(P.device_bytes, &D.merge_bricks[d], P.merge_bricks[d]);
+            {
+                std::vector<int32_t> order, rank;
+                for (const std::vector<int32_t> &o : P.merge_order[d]) {
+                    const int32_t base = (int32_t)order.size();
+                    order.insert(order.end(), o.begin(), o.end());
+                    rank.resize(order.size());
+                    for (size_t k = 0; k < o.size(); ++k) rank[base + o[k]] = (int32_t)k;
+                }
+                if ((int64_t)order.size() != P.depth_points[d])
+                    throw Error{HHFFBP_E_NUMERIC, "merge order does not cover the depth's points"};
+                upload_vec(P.device_bytes, &D.merge_order[d], order);
+                upload_vec(P.device_bytes, &D.merge_rank[d], rank);
+            }
             P.n_blocks_merge_fwd[d] = (int64_t)blocks_fwd.size();
             std::vector<InterpIdx> ridx;
             std::vector<InterpGeo> rgeo;
@@ -1440,7 +1516,7 @@ void release_plan(Plan &P)
     fr(D.final_idx);
     fr(D.final_geo);
     for (auto *v : {&D.nodes, &D.cols, &D.colbase, &D.merge_blocks, &D.merge_blocks_fwd,
-                    &D.merge_bricks, &D.merge_idx, &D.merge_geo})
+                    &D.merge_bricks, &D.merge_idx, &D.merge_geo, &D.merge_order, &D.merge_rank})
         for (auto &p : *v) fr(p);
 }
 
