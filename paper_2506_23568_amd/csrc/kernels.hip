@@ -364,9 +364,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
     const float Rc = fast_sqrt(Rc2);
     const float frac_w = q.frac - 0.5f * W;  // tau = t - W/2 relative to the point's bin
     const int bin1 = q.bin + 1;
-    // the block's window holds every tap; clamping tau to [lo, hi] only keeps
-    // positions moved beyond the planned slack inside it
-    const float tau_lo = (float)(r0 - bin1), tau_hi = (float)(r0 + nrb - W - bin1);
+    // the block's window holds every tap of positions within the slack box
+    // (where the position pass clamps them), float32 rounding of tau included
     const float m2x = -2.0f * q.dx, m2y = -2.0f * q.dy, m2z = -2.0f * q.dz;
     float acc_re = 0.0f, acc_im = 0.0f;
     for (int c0 = nd.pos_begin; c0 < nd.pos_end; c0 += chunk) {
@@ -410,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
                 const float num = fmaf(m2x, d.x, fmaf(m2y, d.y, fmaf(m2z, d.z, d.w)));
                 const float R = fast_sqrt(num + Rc2);
                 const float dR = num * fast_rcp(R + Rc);
-                const float tau = __builtin_amdgcn_fmed3f(fmaf(dR, inv_dR, frac_w), tau_lo, tau_hi);
+                const float tau = fmaf(dR, inv_dR, frac_w);
                 const int r = bin1 - r0 + floor_int(tau);
                 const float x = __builtin_amdgcn_fractf(tau);
                 const float2 *pr = s_prof + i * nrb + r;
@@ -548,7 +547,7 @@ __global__ __launch_bounds__(kFusedPoints) void k_leaf_bp_fused(
                 const float num = fmaf(m2x, d.x, fmaf(m2y, d.y, fmaf(m2z, d.z, d.w)));
                 const float R = fast_sqrt(num + Rc2);
                 const float dR = num * fast_rcp(R + Rc);
-                const float tau = __builtin_amdgcn_fmed3f(fmaf(dR, inv_dR, frac_w), tau_lo, tau_hi);
+                const float tau = fmaf(dR, inv_dR, frac_w);
                 const int r = bin1 - r0 + floor_int(tau);
                 const float x = __builtin_amdgcn_fractf(tau);
                 const float2 v0 = prof[i * nrb + r], v1 = prof[i * nrb + r + 1];

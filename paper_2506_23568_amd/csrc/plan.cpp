@@ -1357,7 +1357,10 @@ void upload_plan(Plan &P)
                 // per block of 256 points: the bins its taps can reach.  With
                 // |Delta R| <= reach (the leaf's largest |p' - c| plus slack), tau =
                 // Delta R / dR + frac - W/2 lies in [-reach/dR - W/2, reach/dR + 1 - W/2)
-                // and a point with bin b reads b + 1 + floor(tau) .. + W - 1.
+                // and a point with bin b reads b + 1 + floor(tau) .. + W - 1.  One more
+                // bin on each side covers float32 rounding of tau, so the level-1 BP
+                // reads its taps without clamping tau (positions are clamped to the
+                // slack box before).
                 double reach = 0.0;
                 for (int32_t m : hn.members) {
                     const double *pm = &P.positions[3 * m];
@@ -1365,8 +1368,8 @@ void upload_plan(Plan &P)
                                                       (pm[1] - yc) * (pm[1] - yc) + pm[2] * pm[2]));
                 }
                 reach += std::sqrt(3.0) * P.cfg.position_slack;
-                const int32_t mlo = (int32_t)std::floor(-reach / P.dR - 0.5 * P.W);
-                const int32_t mhi = (int32_t)std::floor(reach / P.dR + 1.0 - 0.5 * P.W) + P.W - 1;
+                const int32_t mlo = (int32_t)std::floor(-reach / P.dR - 0.5 * P.W) - 1;
+                const int32_t mhi = (int32_t)std::floor(reach / P.dR + 1.0 - 0.5 * P.W) + P.W;
                 const int32_t Nr = (int32_t)P.Nr;
                 // the window of the block of points [st, st + len)
                 auto window = [&](int32_t st, int32_t len) {
