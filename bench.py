@@ -58,17 +58,16 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 MFMA_F32_PEAK = 157.3e12
 L1_PEAK_BPS = 256 * 64 * 2.4e9
 HBM_PEAK_BPS = 8.0e12
-# Algorithmic VALU lane-ops per (leaf grid point, position) backprojection, the
-# fixed yardstick of the range-compressed form (~25 VALU + 3 transcendentals):
-# distance |q - p'| 7 (3 differences, 3 for the squared norm, sqrt), distance
-# difference 6 (|d|^2 - 2 q.d as 3 FMA, then / (R + R_c) as add, reciprocal,
-# multiply), bin coordinate 4 (FMA, clamp, floor, fraction), carrier 3 (scale to
-# turns, sin, cos), complex accumulate 4; range read with the 7-tap ES kernel:
-# weights 6 per tap, tap sums 2 per tap; with the linear kernel v0 + x (v1 - v0)
-# per component (4).  (The kernel forms |q - p'| from |q - c|^2 plus the
-# distance-difference numerator and issues fewer than this count.)
-LEAF_OPS_PER_PAIR = 7 + 6 + 4 + 6 * 7 + 2 * 7 + 3 + 4
-LEAF_OPS_LINEAR = 7 + 6 + 4 + 4 + 3 + 4
+# Algorithmic VALU lane-ops per (leaf grid point, position) backprojection in
+# the cancellation-free range-compressed form, the fewest this evaluation
+# needs: the distance-difference numerator num = |d|^2 - 2 q.d 3 FMA,
+# |q - p'| = sqrt(|q - c|^2 + num) 2, Delta R = num / (|q - p'| + |q - c|) 3
+# (add, reciprocal, multiply), bin coordinate 3 (FMA, floor to int, fraction),
+# tap address 1, carrier 3 (scale to turns, sin, cos), complex accumulate 4;
+# the range read: linear kernel v0 + x (v1 - v0) per component 4, or the 7-tap
+# ES kernel with 6 per weight and 2 per tap sum.
+LEAF_OPS_LINEAR = 3 + 2 + 3 + 3 + 1 + 3 + 4 + 4
+LEAF_OPS_ES = 3 + 2 + 3 + 3 + 1 + 3 + 4 + (6 + 2) * 7
 # Algorithmic VALU lane-ops per (point, child) interpolation of a merge or the
 # final stage (T = 4, band-limited weights, geometry from the plan's records):
 # weights 54 (per axis y = x - 1/2, y^2, two 3-FMA Horner chains per tap pair
@@ -453,8 +452,10 @@ def imaging_report(args, index):
             rows["rc_gemm"] = {"bound": "mfma", "ms": rms, "flop": fl,
                                "achieved": fl / (rms * 1e-3) / 1e12, "peak": MFMA_F32_PEAK / 1e12,
                                "unit": "TFLOP/s", "frac": fl / (rms * 1e-3) / MFMA_F32_PEAK}
-        # interpolation kernels: VALU by the algorithmic count, and the gathers
-        # through the vector L1 (16 column bases of 4 B, 64 taps, the 24-B record)
+        # interpolation kernels: the merges gather through the vector L1 (16
+        # column bases of 4 B, 64 taps, the 24-B record per pair), which bounds
+        # them; the final stage reads its taps from LDS and is VALU-bound (the
+        # algorithmic count)
         gb = 16 * 4 + 64 * val_bytes + 24
         mpairs = {}
         for name, t in kms.items():
@@ -469,11 +470,17 @@ def imaging_report(args, index):
                 continue
             va = pairs * INTERP_OPS_PER_PAIR / (t * 1e-3)
             ga = pairs * gb / (t * 1e-3)
-            rows[name] = {"bound": "alu", "ms": t, "pairs": pairs,
-                          "ops_per_pair": INTERP_OPS_PER_PAIR, "achieved": va / 1e12,
-                          "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
-                          "frac": va / VALU_PEAK_OPS, "gather_bytes_per_pair": gb,
-                          "gather_frac_of_l1": ga / L1_PEAK_BPS}
+            if name == "final":
+                rows[name] = {"bound": "alu", "ms": t, "pairs": pairs,
+                              "ops_per_pair": INTERP_OPS_PER_PAIR, "achieved": va / 1e12,
+                              "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+                              "frac": va / VALU_PEAK_OPS}
+            else:
+                rows[name] = {"bound": "l1", "ms": t, "pairs": pairs,
+                              "gather_bytes_per_pair": gb, "achieved": ga / 1e12,
+                              "peak": L1_PEAK_BPS / 1e12, "unit": "TB/s",
+                              "frac": ga / L1_PEAK_BPS, "ops_per_pair": INTERP_OPS_PER_PAIR,
+                              "valu_frac": va / VALU_PEAK_OPS}
         return rows
 
     kern = roofline_rows(kernels_ms, info, LEAF_OPS_LINEAR, 8)
@@ -495,7 +502,9 @@ def imaging_report(args, index):
     pl_es = H.Plan(*args3, range_kernel="es", range_oversample=2.0, range_taps=7, **form)
     ms_es, k_es, img_es = timed(pl_es, ech, max(3, args.steps // 2), 1)
     extra["hhffbp_es"] = {"value": vp / (ms_es * 1e-3), "ms": ms_es, "kernels_ms": k_es,
-                          "mode": "ES U=2 W=7 (parity mode), same grids", **errors(img_es)}
+                          "mode": "ES U=2 W=7 (parity mode), same grids",
+                          "leaf_bp_roofline": roofline_rows(k_es, info, LEAF_OPS_ES, 8).get("leaf_bp"),
+                          **errors(img_es)}
     del pl_es, img_es
     for st in ("f16", "bf16"):
         pl_h = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, storage=st, **form)
