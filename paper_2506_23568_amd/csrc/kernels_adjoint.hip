@@ -94,6 +94,11 @@ __device__ __forceinline__ ChildCoord record_coord(const NodeDev &c, InterpIdx i
     return cc;
 }
 
+// Nearest integer of x, ties to even.  Rounding ties up (floor(x + 1/2), one
+// instruction) would bias the fixed-point sums: above 2^22 a float32 is often
+// a half-integer, and those ties would all round the same way.
+__device__ __forceinline__ int cvt_round_i32(float x) { return (int)rintf(x); }
+
 // --- block-aggregated scatter --------------------------------------------
 // The stencils of one block's points cover a small box of the child's (i, j, l)
 // index space.  The block accumulates its contributions there in LDS (int32
@@ -216,21 +221,29 @@ __device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c
             ov[t] = iv;
             on[t] = in;
         }
+        // the n weights times the scaled cotangent, once per point
+        float nre[T], nim[T];
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            nre[k] = wnr[k] * qre;
+            nim[k] = wnr[k] * qim;
+        }
 #pragma unroll
         for (int a = 0; a < T; ++a)
 #pragma unroll
             for (int b = 0; b < T; ++b) {
                 const float wab = wu[a] * wvr[b];
-                const int row = ((bi + a) * B1 + (bj + ov[b])) * B2 + bl;
+                unsigned long long *rowp = sh.box + ((bi + a) * B1 + (bj + ov[b])) * B2 + bl;
 #pragma unroll
                 for (int k = 0; k < T; ++k) {
                     // re 2^32 + im in one 64-bit add: both sums stay within int32
                     // (the scale q), so the low half is the imaginary sum exactly
-                    // and the carries it leaves make the high half the real sum
-                    const float w = wab * wnr[k];
-                    const long long v = (long long)(int)rintf(w * qre) * 4294967296ll +
-                                        (long long)(int)rintf(w * qim);
-                    atomicAdd(&sh.box[row + on[k]], (unsigned long long)v);
+                    // and the carries it leaves make the high half the real sum.
+                    // The word is formed in 32-bit halves: the high half takes
+                    // the sign of im (two's complement of the 64-bit sum).
+                    const int ar = cvt_round_i32(wab * nre[k]), ai = cvt_round_i32(wab * nim[k]);
+                    const uint32_t hi = (uint32_t)ar + (uint32_t)(ai >> 31);
+                    atomicAdd(rowp + on[k], ((unsigned long long)hi << 32) | (uint32_t)ai);
                 }
             }
     }
