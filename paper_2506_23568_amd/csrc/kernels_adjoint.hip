@@ -471,19 +471,20 @@ __global__ __launch_bounds__(kBlock) void k_leaf_adj(
         const float Rc = fast_sqrt(Rc2);
         const float frac_w = q.frac - 0.5f * W;
         const int bin1 = q.bin + 1;
-        // the taps stay inside the staged profiles: clamping tau to [lo, hi] keeps
-        // r in [0, Nr - W] for positions moved beyond the planned slack
-        const float tau_lo = (float)(-bin1), tau_hi = (float)(Nr - W - bin1);
+        // the taps stay inside the staged profiles, r in [0, Nr - W]: the range
+        // grid covers every distance from a leaf point to its positions' slack box
+        // with (W / 2 + 2) bins to spare, and positions are clamped to that box
+        const float m2x = -2.0f * q.dx, m2y = -2.0f * q.dy, m2z = -2.0f * q.dz;
 #pragma unroll
         for (int i = 0; i < kAdjPos; ++i) {
             if (i < n) {  // predicated, so every ap[i] index stays a constant
                 const float4 d = s_pos[i];
                 const float ex = q.dx - d.x, ey = q.dy - d.y, ez = q.dz - d.z;
                 // |q - p'|^2 = |q - c|^2 + num (as in the forward level-1 BP)
-                const float num = d.w - 2.0f * (q.dx * d.x + q.dy * d.y + q.dz * d.z);
+                const float num = fmaf(m2x, d.x, fmaf(m2y, d.y, fmaf(m2z, d.z, d.w)));
                 const float R = fast_sqrt(num + Rc2);
                 const float dR = num * fast_rcp(R + Rc);
-                const float tau = __builtin_amdgcn_fmed3f(fmaf(dR, inv_dR, frac_w), tau_lo, tau_hi);
+                const float tau = fmaf(dR, inv_dR, frac_w);
                 const int r = bin1 + floor_int(tau);
                 const float x = __builtin_amdgcn_fractf(tau);
                 float w[W];
