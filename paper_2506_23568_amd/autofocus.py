@@ -56,6 +56,9 @@ def autofocus(plan, echoes, positions, steps=20, lr=3e-5, clean=None, modes=16, 
     ws = plan._workspace(torch, backward=True)
     img = torch.empty(plan.dims, dtype=torch.complex64, device=dev)
     stream = torch.cuda.current_stream(dev)
+    # the slack check runs on a stream of its own (default priority), so that
+    # the host's wait for its count overlaps the image instead of stalling the GPU
+    side = torch.cuda.Stream(device=dev)
     hist = []
 
     def current():
@@ -66,14 +69,17 @@ def autofocus(plan, echoes, positions, steps=20, lr=3e-5, clean=None, modes=16, 
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         pos = current()
+        ready = torch.cuda.Event()
+        ready.record(stream)
+        plan.image(echoes, positions=pos, out=img, workspace=ws)
         # the plan's windows hold positions within its slack; beyond it the
         # kernels clamp, so stop rather than descend on clamped positions
-        n_out = plan.check_positions(pos)
+        side.wait_event(ready)
+        n_out = plan.check_positions(pos, stream=side.cuda_stream)
         if n_out:
             raise HHFFBPError(-1, f"autofocus step {k}: {n_out} positions moved beyond the plan's "
                                   f"slack of {plan.config.position_slack} m; plan again around "
                                   "the current positions")
-        plan.image(echoes, positions=pos, out=img, workspace=ws)
         st = image_stats(img, clean)
         loss, g = loss_grad(img, clean, st, w_entropy=w_entropy, w_l2=w_l2)
         if on_step is not None:
