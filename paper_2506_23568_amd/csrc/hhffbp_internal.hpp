@@ -231,6 +231,7 @@ struct Plan {
     int32_t leaf_win_max = 0;  // widest BinWindow of the level-1 BP blocks
     std::vector<TileBox> final_tiles;  // host copy, brick-major
     int64_t n_bricks = 0, n_tiled = 0;  // final-stage bricks; (brick, node) pairs with a box
+    bool final_box_only = false;        // every final-stage stencil lies in its brick's box
     int64_t leaf_pairs = 0, merge_pairs = 0, final_pairs = 0;
     std::vector<int64_t> merge_pairs_depth;  // per depth < S
     std::vector<double> level_estimate;      // per depth: gamma^3 * integral of |det J| over the voxels

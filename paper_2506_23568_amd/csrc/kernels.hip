@@ -641,7 +641,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
 // outside it (or a child without a box) gathers from the pencils.  Each
 // (voxel, child) pair's stencil, fractions and phase Phi_c come from its
 // plan-time record.
-template <int T, int ST, int K>
+template <int T, int ST, int K, bool BOX_ONLY>
 __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ children,
                                                   int nchild, const ColEntry *__restrict__ ccols,
                                                   const int32_t *__restrict__ ccolbase,
@@ -713,8 +713,9 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
             interp_weights3<T, K>(ip, g.fu, g.fv, g.fn, wu, wv, wn);
             const int ti = ci0 + ch.i0 - tb.i0, tj = cj0 + ch.j0 - tb.j0, tl = rx.l0 - tb.l0;
             float2 val;
-            if (tb.ni > 0 && (unsigned)ti <= (unsigned)(tb.ni - T) &&
-                (unsigned)tj <= (unsigned)(tb.nj - T) && (unsigned)tl <= (unsigned)(tb.nl - T))
+            // BOX_ONLY: the plan checked that every stencil lies in its box
+            if (BOX_ONLY || (tb.ni > 0 && (unsigned)ti <= (unsigned)(tb.ni - T) &&
+                             (unsigned)tj <= (unsigned)(tb.nj - T) && (unsigned)tl <= (unsigned)(tb.nl - T)))
                 val = interp_box<T>(s_tile + (ti * tb.nj + tj) * ((1 << tb.lsh) + 1) + tl, tb.nj,
                                     (1 << tb.lsh) + 1, wu, wv, wn);
             else
@@ -1048,7 +1049,8 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
     }
     const hhffbp_config &c = P.cfg;
     const int nx = (int)c.grid_dims[0], ny = (int)c.grid_dims[1], nz = (int)c.grid_dims[2];
-    hipLaunchKernelGGL((k_final<T, ST, K>), dim3(P.n_bricks), dim3(kBlock), 0, st,
+    auto final_kernel = P.final_box_only ? k_final<T, ST, K, true> : k_final<T, ST, K, false>;
+    hipLaunchKernelGGL(final_kernel, dim3(P.n_bricks), dim3(kBlock), 0, st,
                        (const NodeDev *)P.dev.nodes[P.F], (int)P.compact_to_tree[P.F].size(),
                        (const ColEntry *)P.dev.cols[P.F], (const int32_t *)P.dev.colbase[P.F],
                        (const C *)(ws + P.ws_vals[P.F]), (const TileBox *)P.dev.final_tiles, (const InterpIdx *)P.dev.final_idx,

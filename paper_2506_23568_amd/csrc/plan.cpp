@@ -1466,6 +1466,27 @@ void upload_plan(Plan &P)
         std::vector<InterpIdx> ridx;
         std::vector<InterpGeo> rgeo;
         final_records(P, ridx, rgeo);
+        // every pair's stencil inside its brick's LDS box: the final stage then
+        // runs without the pencil path (fewer registers, no per-lane test)
+        const int64_t nc = (int64_t)P.compact_to_tree[P.F].size();
+        bool box_only = true;
+        for (int64_t bc = 0; box_only && bc < P.n_bricks * nc; ++bc) {
+            const TileBox &tb = P.final_tiles[bc];
+            const int64_t c = bc % nc;
+            const HostLattice &Lc = P.levels[P.F][P.compact_to_tree[P.F][c]].lat;
+            for (int t = 0; t < kBlockThreads; ++t) {
+                const InterpIdx ix = ridx[(size_t)bc * kBlockThreads + t];
+                if (ix.cij == kNoPair) continue;
+                const int64_t ti = (int64_t)(ix.cij & 0xffffu) + Lc.i0 - tb.i0,
+                              tj = (int64_t)(ix.cij >> 16) + Lc.j0 - tb.j0, tl = (int64_t)ix.l0 - tb.l0;
+                if (tb.ni <= 0 || ti < 0 || ti > tb.ni - P.T || tj < 0 || tj > tb.nj - P.T || tl < 0 ||
+                    tl > tb.nl - P.T) {
+                    box_only = false;
+                    break;
+                }
+            }
+        }
+        P.final_box_only = box_only;
         upload_vec(P.device_bytes, &D.final_idx, ridx);
         upload_vec(P.device_bytes, &D.final_geo, rgeo);
     }
