@@ -582,6 +582,44 @@ def imaging_report(args, index):
     return rec
 
 
+def valu_probe_report(args):
+    """Issue rate of wave64 FP32 FMAs and transcendentals on the device
+    (libhhffbp_probe.so, built with the package): what the nominal VALU peak of
+    the rooflines comes to, and what a sine or square root costs."""
+    import ctypes
+
+    import torch
+
+    from paper_2506_23568_amd import build_lib
+
+    if not os.path.exists(build_lib.PROBE_LIB):
+        raise RuntimeError("libhhffbp_probe.so is missing: run __graft_entry__.build()")
+    L = ctypes.CDLL(build_lib.PROBE_LIB)
+    L.hhffbp_probe_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_double)]
+    L.hhffbp_probe_valu.restype = ctypes.c_int
+    blocks, iters, reps = 256 * 8, 2048, 5
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    nominal = 256 * 4 * 2.4e9 / 4  # wave64 instructions per second at 4 cycles each
+    names = ["4 fma", "4 sine", "3 fma + 1 sine (one chain)", "4 sqrt", "2 fma + 2 sine",
+             "3 fma + 1 sine (independent chains)", "4 fma (two chains)",
+             "level-1 BP mix: 20 fma + sqrt, rcp, sine, cosine"]
+    rows = {}
+    for mode, name in enumerate(names):
+        r = ctypes.c_double(0.0)
+        rc = L.hhffbp_probe_valu(mode, blocks, iters, reps, ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(st), ctypes.byref(r))
+        if rc != 0:
+            raise RuntimeError(f"probe mode {mode} failed: {rc}")
+        rows[name] = {"wave_instr_per_s": r.value, "frac_of_nominal": r.value / nominal}
+        log(f"{name}: {r.value:.3e} wave64 instructions/s = {r.value / nominal:.3f} of nominal")
+    print(json.dumps({"metric": "wave64 VALU instructions per second", "unit": "instr/s",
+                      "nominal": nominal, "blocks": blocks, "iters": iters, "reps": reps,
+                      "modes": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -603,12 +641,13 @@ def main():
                     help="autofocus workload: plans with a compressed root grid (the "
                          "last merge onto the full aperture's lattice, one resample to "
                          "the voxels)")
-    ap.add_argument("--workload", choices=["large", "mid", "autofocus", "paper_sim"],
+    ap.add_argument("--workload", choices=["large", "mid", "autofocus", "paper_sim", "valu_probe"],
                     default="large",
                     help="large: the imaging benchmark (default; the mid workload is "
                          "reported beside it); mid: the mid workload alone; autofocus: "
                          "the trajectory correction loop on the large scene; paper_sim: "
-                         "the paper's simulation geometry with point-response metrics")
+                         "the paper's simulation geometry with point-response metrics; "
+                         "valu_probe: the device's FMA and transcendental issue rates")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (the voxel "
@@ -620,6 +659,9 @@ def main():
         return
     if args.workload == "paper_sim":
         paper_sim_report(args)
+        return
+    if args.workload == "valu_probe":
+        valu_probe_report(args)
         return
 
     import torch

@@ -11,6 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhhffbp.so")
+PROBE_LIB = os.path.join(HERE, "libhhffbp_probe.so")  # VALU issue-rate probe (bench.py)
 SOURCES = ["api.cpp", "plan.cpp", "kernels.hip", "kernels_adjoint.hip", "kernels_metrics.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -41,6 +42,12 @@ def build(verbose=False, jobs=None):
         print(" ".join(link), flush=True)
     subprocess.check_call(link)
     os.replace(LIB + ".tmp", LIB)
+    probe = [HIPCC] + FLAGS + ["-x", "hip", "-shared", os.path.join(CSRC, "probe_valu.hip"),
+                               "-o", PROBE_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(probe), flush=True)
+    subprocess.check_call(probe)
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
     return LIB
 
 
