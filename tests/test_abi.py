@@ -33,6 +33,28 @@ def test_library_exports_every_declared_symbol():
         assert re.search(rf"\bT {n}\b", out), n
 
 
+def test_probe_library_exports_its_entry_point():
+    """The VALU issue-rate probe (bench.py --workload valu_probe) is built with the
+    package and exports its one C entry point; invalid arguments are refused
+    before any GPU call."""
+    import ctypes
+
+    from paper_2506_23568_amd import build_lib
+
+    assert os.path.exists(build_lib.PROBE_LIB), "run __graft_entry__.build()"
+    out = subprocess.run(["nm", "-D", "--defined-only", build_lib.PROBE_LIB], capture_output=True,
+                         text=True, check=True).stdout
+    assert re.search(r"\bT hhffbp_probe_valu\b", out)
+    L = ctypes.CDLL(build_lib.PROBE_LIB)
+    L.hhffbp_probe_valu.restype = ctypes.c_int
+    r = ctypes.c_double(0.0)
+    for mode, blocks, iters, reps in ((8, 1, 1, 1), (-1, 1, 1, 1), (0, 0, 1, 1), (0, 1, 0, 1),
+                                      (0, 1, 1, 0)):
+        assert L.hhffbp_probe_valu(mode, blocks, iters, reps, ctypes.c_void_p(1), None,
+                                   ctypes.byref(r)) == -1
+    assert L.hhffbp_probe_valu(0, 1, 1, 1, None, None, ctypes.byref(r)) == -1
+
+
 def test_config_default_layout():
     c = H.binding.default_config()
     assert (c.mode, c.stages, c.merge_factor, c.interp_taps) == (0, 3, 4, 4)
