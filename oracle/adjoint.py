@@ -50,11 +50,12 @@ def _split_to_children(plan, node, points, cot, phi_parent, child_cot):
         child = plan.levels[d + 1][ci]
         if child.empty:
             continue
-        t = plan.gamma * G.uvn(points, child.rect, plan.kmin, plan.kmax)
+        g = plan.gamma_at(d + 1)
+        t = g * G.uvn(points, child.rect, plan.kmin, plan.kmax)
         ph = G.phi(points, child.rect, plan.kmin, plan.kmax) - phi_parent
         acc = child_cot.setdefault((d + 1, ci), np.zeros(child.lattice.size, np.complex128))
         scatter_transpose(child.lattice, t, plan.taps, np.exp(-1j * ph) * cot, acc,
-                          kernel=plan.kernel, gamma=plan.gamma)
+                          kernel=plan.kernel, gamma=g)
 
 
 def leaf_cotangents(plan, grad_image):
@@ -68,11 +69,12 @@ def leaf_cotangents(plan, grad_image):
     if plan.root_grid:
         # transpose of the last resample: image = exp(+j Phi_root) I_root(voxels)
         root = levels[0][0]
-        t = plan.gamma * G.uvn(plan.voxels, root.rect, plan.kmin, plan.kmax)
+        g0 = plan.gamma_at(0)
+        t = g0 * G.uvn(plan.voxels, root.rect, plan.kmin, plan.kmax)
         ph = G.phi(plan.voxels, root.rect, plan.kmin, plan.kmax)
         cot[(0, 0)] = np.zeros(root.lattice.size, np.complex128)
         scatter_transpose(root.lattice, t, plan.taps, np.exp(-1j * ph) * g, cot[(0, 0)],
-                          kernel=plan.kernel, gamma=plan.gamma)
+                          kernel=plan.kernel, gamma=g0)
         first = 0
     else:
         _split_to_children(plan, levels[0][0], plan.voxels, g, 0.0, cot)

@@ -152,8 +152,9 @@ def leaf_bp_at(plan, node, echoes, positions, point_index, range_u=None):
 def resample(plan, node, vals, points):
     """exp(+j Phi_node) I_node((u, v, n)_node(points)): a node's compressed
     subimage, interpolated at ``points`` and with its SDC reverted."""
-    t = plan.gamma * G.uvn(points, node.rect, plan.kmin, plan.kmax)
-    val = interpolate(node.lattice, vals, t, plan.taps, kernel=plan.kernel, gamma=plan.gamma)
+    g = plan.gamma_at(node.depth)
+    t = g * G.uvn(points, node.rect, plan.kmin, plan.kmax)
+    val = interpolate(node.lattice, vals, t, plan.taps, kernel=plan.kernel, gamma=g)
     return val * np.exp(1j * G.phi(points, node.rect, plan.kmin, plan.kmax))
 
 
@@ -260,7 +261,7 @@ def image_at(plan, echoes, positions, voxel_index, range_u=None, weights=None, k
     top = 0 if plan.root_grid else 1
 
     def coords(node, pts):
-        return plan.gamma * G.uvn(pts, node.rect, plan.kmin, plan.kmax)
+        return plan.gamma_at(node.depth) * G.uvn(pts, node.rect, plan.kmin, plan.kmax)
 
     need = {}
     for d in range(top, S + 1):

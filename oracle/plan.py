@@ -250,11 +250,20 @@ class Plan:
     dims: tuple
     kernel: str = "lagrange"    # interpolation weights: "lagrange" or "bandlimited"
     root_grid: bool = False     # the root holds a compressed lattice (see module notes)
+    gamma_leaf: np.ndarray = None  # (3,) oversampling of the level-1 (leaf) grids; None: gamma
+
+    def gamma_at(self, depth):
+        """Oversampling of the grids at ``depth``: the leaf grids' own when set."""
+        if self.gamma_leaf is not None and depth == len(self.levels) - 1:
+            return self.gamma_leaf
+        return self.gamma
 
 
 def build_plan(positions, freqs_hz, origin, pitch, dims, stages, merge_factor,
-               gamma=3.0, taps=4, margin=0, kernel="lagrange", root_grid=False):
-    """Oracle plan: tree, top-down grids and their xyz preimages."""
+               gamma=3.0, taps=4, margin=0, kernel="lagrange", root_grid=False, gamma_leaf=None):
+    """Oracle plan: tree, top-down grids and their xyz preimages.  ``gamma_leaf``
+    (optional) is the oversampling of the level-1 (leaf) grids; the other grids
+    use ``gamma``."""
     from workloads import voxel_centres
 
     k = 2.0 * math.pi * np.asarray(freqs_hz, float) / C0
@@ -267,8 +276,10 @@ def build_plan(positions, freqs_hz, origin, pitch, dims, stages, merge_factor,
         raise ValueError(f"unknown interpolation kernel {kernel}")
     if root_grid and stages < 1:
         raise ValueError("a root grid needs at least one stage")
+    if gamma_leaf is not None:
+        gamma_leaf = np.broadcast_to(np.asarray(gamma_leaf, float), (3,)).copy()
     plan = Plan(levels, k, kmin, kmax, gamma, int(taps), int(margin), vox, tuple(dims), kernel,
-                bool(root_grid))
+                bool(root_grid), gamma_leaf)
     for d in range(0 if root_grid else 1, len(levels)):
         for node in levels[d]:
             if node.empty:
@@ -278,9 +289,10 @@ def build_plan(positions, freqs_hz, origin, pitch, dims, stages, merge_factor,
             else:
                 parent = levels[d - 1][node.parent]
                 ppts = parent.lattice.xyz[parent.lattice.valid]
-            t = gamma * G.uvn(ppts, node.rect, kmin, kmax)
+            g = plan.gamma_at(d)
+            t = g * G.uvn(ppts, node.rect, kmin, kmax)
             i0, j0, l_lo, l_hi = required_lattice(t, taps, margin)
             off, ijl = enumerate_points(i0, j0, l_lo, l_hi)
-            xyz, ok = invert_uvn(ijl / gamma, node.rect, kmin, kmax, z_valid)
+            xyz, ok = invert_uvn(ijl / g, node.rect, kmin, kmax, z_valid)
             node.lattice = Lattice(i0, j0, l_lo, l_hi, off, ijl, xyz, ok)
     return plan

@@ -205,3 +205,41 @@ def test_root_grid(small, direct_small):
     with pytest.raises(ValueError):
         OP.build_plan(small.positions, small.freqs_hz, small.grid_origin, small.grid_pitch,
                       small.grid_dims, 0, 4, 3.0, 4, root_grid=True)
+
+
+def test_leaf_oversampling(small, direct_small):
+    """Leaf grids at their own oversampling (gamma_leaf): the grids above the
+    leaves are those of the uniform plan, the leaf points map back to their
+    (u, v, n) at gamma_leaf, gamma_leaf = gamma reproduces the uniform plan's
+    image exactly, coarser leaf grids hold fewer points and lose accuracy
+    monotonically, and the image stays within -30 dB of eq. (4)."""
+    g = (2.2, 2.2, 2.6)
+    args = (small.positions, small.freqs_hz, small.grid_origin, small.grid_pitch, small.grid_dims,
+            2, 4, g, 4)
+    uni = OP.build_plan(*args, kernel="bandlimited")
+    same = OP.build_plan(*args, kernel="bandlimited", gamma_leaf=g)
+    img_u = OH.image(uni, small.echoes, small.positions)
+    assert np.array_equal(OH.image(same, small.echoes, small.positions), img_u)
+    err, npts = [], []
+    for gl in ((2.0, 2.0, 2.4), (1.8, 1.8, 2.2), (1.6, 1.6, 2.0)):
+        pl = OP.build_plan(*args, kernel="bandlimited", gamma_leaf=gl)
+        assert np.allclose(pl.gamma_at(1), g) and np.allclose(pl.gamma_at(2), gl)
+        for node_u, node in zip(uni.levels[1], pl.levels[1]):
+            if node.empty:
+                continue
+            assert np.array_equal(node.lattice.ijl, node_u.lattice.ijl)
+        n = 0
+        for node in pl.levels[2]:
+            if node.empty:
+                continue
+            L = node.lattice
+            back = G.uvn(L.xyz[L.valid], node.rect, pl.kmin, pl.kmax) * np.asarray(gl)
+            assert np.max(np.abs(back - L.ijl[L.valid])) < 1e-8
+            n += L.size
+        npts.append(n)
+        img = OH.image(pl, small.echoes, small.positions)
+        err.append(OH.nrmse(img, direct_small))
+        assert 20 * np.log10(err[-1]) <= -30.0, gl
+    e_u = OH.nrmse(img_u, direct_small)
+    assert npts[0] > npts[1] > npts[2]
+    assert e_u <= err[0] <= err[1] <= err[2]
