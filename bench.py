@@ -38,12 +38,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "voxel·position backprojections/s, HHFFBPA vs direct BP on 1 GPU at ≤−30 dB NRMSE"
 BL_GAMMA = (2.2, 2.2, 2.6)       # band-limited interpolation grids (the timed form)
+BL_LEAF = (1.8, 1.8, 2.2)        # ... its level-1 (leaf) grids
 BENCH_U = 4.0                    # range oversampling of its linear range kernel
 DIRECT_U = (2.0, 3.0, 4.0, 8.0)  # linear-kernel direct-BP candidates for the baseline
 AF_GAMMA = BL_GAMMA              # band-limited grids of the autofocus workload
+AF_LEAF = BL_LEAF                # ... its leaf grids
 TAPS = 4
 # the timed form per workload index: stages and root grid
-TIMED = {2: dict(stages=4, root_grid=True), 1: dict(stages=3, root_grid=False)}
+TIMED = {2: dict(stages=4, root_grid=True, oversample_leaf=BL_LEAF),
+         1: dict(stages=3, root_grid=False, oversample_leaf=BL_LEAF)}
 WORKLOAD_NAME = {
     2: "HHFFBPA large: 65536 handheld positions (44 serpentine strokes + 20 dense walks, "
        "0.5-3.7 samples/mm^2), 128 f 24-40 GHz, 256x256x128 voxels at 1 mm, 200 points + "
@@ -221,7 +224,8 @@ def autofocus_report(args):
     w = make_config(4, synth_device="cuda")
     p_img = w.imager_positions
     a3 = (p_img, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims)
-    kw = dict(stages=args.af_stages, merge_factor=4, oversample=AF_GAMMA, interp_taps=TAPS,
+    kw = dict(stages=args.af_stages, merge_factor=4, oversample=AF_GAMMA, oversample_leaf=AF_LEAF,
+              interp_taps=TAPS,
               interp_kernel="bandlimited")
     if args.af_range == "linear":
         kw.update(range_kernel="linear", range_oversample=args.af_u)
@@ -270,6 +274,7 @@ def autofocus_report(args):
                                f"slab, smooth trajectory error, S={args.af_stages} Q=4, 20 Adam steps (lr 0.03 mm) on 16 cosine modes per axis, relative-L2 loss to the clean-trajectory image",
                    "range_kernel": f"linear U={args.af_u:g}" if args.af_range == "linear" else "ES U=2 W=7",
                    "interp_kernel": "bandlimited", "oversample": list(AF_GAMMA),
+                   "oversample_leaf": list(AF_LEAF),
                    "root_grid": args.af_root_grid == "on", "parallelism": "single GPU"},
         "storage": out, "work": work,
         "reference": "float32 direct BP (ES U=2 W=7) at the true positions, full grid"}), flush=True)
@@ -525,12 +530,15 @@ def imaging_report(args, index):
         "nrmse_vs_two_kernel_form": (torch.linalg.norm(img_f - img) / torch.linalg.norm(img)).item(),
         **errors(img_f)}
     del pl_f, img_f
-    alt = dict(form, stages=3, root_grid=False) if index == 2 else dict(form, stages=4, root_grid=True)
+    # the same plan with uniform grids (leaf grids at the other grids' oversampling)
+    alt = dict(form, oversample_leaf=None)
     pl_a = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, **alt)
     ms_a, k_a, img_a = timed(pl_a, ech, max(3, args.steps // 2), 1)
-    extra["hhffbp_alt"] = {"value": vp / (ms_a * 1e-3), "ms": ms_a, "kernels_ms": k_a,
-                           "mode": f"S={alt['stages']}, root grid {alt['root_grid']}",
-                           **errors(img_a)}
+    extra["hhffbp_uniform_grids"] = {"value": vp / (ms_a * 1e-3), "ms": ms_a, "kernels_ms": k_a,
+                                     "mode": f"the same plan with every grid at {list(BL_GAMMA)} "
+                                             f"(S={alt['stages']}, root grid {alt['root_grid']})",
+                                     "work": {k: pl_a.info()[k] for k in ("leaf_pairs", "level_points")},
+                                     **errors(img_a)}
     del pl_a, img_a
     torch.cuda.empty_cache()
 

@@ -135,11 +135,18 @@ typedef struct {
                                    FACTORIZED with S >= 1, the linear range kernel
                                    and C64 storage, and an image only: hhffbp_backward
                                    returns HHFFBP_E_UNSUPPORTED for such a plan.     */
+    double oversample_leaf[3];  /* gamma of the level-1 (leaf) grids per LLT axis, each
+                                   in [1, 8]; 0 (the default): `oversample`.  The
+                                   level-1 BP's work scales with the leaf grids and
+                                   only the first merge interpolates from them, so a
+                                   coarser leaf grid trades that one interpolation's
+                                   error for level-1 work (Sec. III sampling, Sec.
+                                   IV-B operation count).  Factorised plans only.   */
 } hhffbp_config;
 
 /* Fill `cfg` with defaults: FACTORIZED, S = 3, Q = 4, gamma = (3, 3, 3.5), T = 4, ES with
  * U = 2 and W = 7, C64 storage, 5 mm slack, device 0, Lagrange interpolation, final-stage
- * staging on, no root grid.  Pointers and sizes are
+ * staging on, no root grid, leaf grids at `oversample`.  Pointers and sizes are
  * zeroed and must be set by the caller. */
 void hhffbp_config_default(hhffbp_config *cfg);
 

@@ -42,7 +42,7 @@ class Config(ctypes.Structure):
         ("position_slack", ctypes.c_double), ("device", ctypes.c_int32),
         ("interp_kernel", ctypes.c_int32), ("final_staging", ctypes.c_int32),
         ("weights", ctypes.POINTER(ctypes.c_double)), ("root_grid", ctypes.c_int32),
-        ("range_fused", ctypes.c_int32),
+        ("range_fused", ctypes.c_int32), ("oversample_leaf", ctypes.c_double * 3),
     ]
 
 
@@ -144,7 +144,7 @@ class Plan:
                  interp_taps=4,
                  range_kernel="es", range_oversample=2.0, range_taps=7, storage="c64",
                  position_slack=5e-3, device=0, interp_kernel="lagrange", final_staging=True,
-                 weights=None, root_grid=False, range_fused=False):
+                 weights=None, root_grid=False, range_fused=False, oversample_leaf=None):
         L = lib()
         self._pos = np.ascontiguousarray(positions, np.float64)
         self._freqs = np.ascontiguousarray(freqs_hz, np.float64)
@@ -176,6 +176,10 @@ class Plan:
         c.final_staging = 1 if final_staging else 0
         c.root_grid = 1 if root_grid else 0
         c.range_fused = 1 if range_fused else 0
+        if oversample_leaf is not None:
+            ol = np.broadcast_to(np.asarray(oversample_leaf, float), (3,))
+            for a in range(3):
+                c.oversample_leaf[a] = float(ol[a])
         if weights is not None:
             self._w = np.ascontiguousarray(weights, np.float64)
             if self._w.shape != (self._pos.shape[0],):

@@ -133,6 +133,7 @@ struct Rect {
 
 // Host view of one grid G of a subarray.
 struct HostLattice {
+    double gamma[3] = {3, 3, 3};  // the grid's oversampling per axis: point (i, j, l) at (i, j, l) / gamma
     int32_t i0 = 0, j0 = 0, ni = 0, nj = 0;
     std::vector<int32_t> lo, hi;  // per column
     std::vector<int64_t> off;     // per column, first point
@@ -198,6 +199,8 @@ struct Plan {
     // its own (then the final stage resamples that one node onto the voxels)
     int F = 1;
     double gamma[3] = {3, 3, 3};
+    double gamma_leaf[3] = {3, 3, 3};  // the level-1 (depth S) grids' oversampling
+    const double *gamma_of(int depth) const { return depth == S ? gamma_leaf : gamma; }
     // band
     std::vector<double> k;
     double kmin = 0, kmax = 0, kc = 0;
@@ -244,7 +247,10 @@ struct Plan {
     double leaf_reach = 0.0;  // max |p' - c| over leaf members and their leaf centres c (z = 0), plus slack
     double model_s = 0.0;     // the Sec. IV-B cost model's level-1 BP + interpolation time
     size_t adj_lds_max = 0;   // dynamic LDS per block the level-1 adjoint may use (plan time)
-    InterpPoly ipoly{};       // merge interpolation weights
+    InterpPoly ipoly{};       // interpolation weights from grids at gamma
+    InterpPoly ipoly_leaf{};  // ... from the level-1 grids (gamma_leaf)
+    // weights of an interpolation whose children sit at depth `child_depth`
+    const InterpPoly &ipoly_for(int child_depth) const { return child_depth == S ? ipoly_leaf : ipoly; }
     std::vector<size_t> ws_gvals;        // backward: float32 cotangents per depth
     std::vector<float> scale_mult;       // host copy of dev.scale_mult
     std::vector<size_t> ws_vals;         // per depth

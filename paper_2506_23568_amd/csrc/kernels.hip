@@ -1040,7 +1040,7 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
                                (const InterpIdx *)P.dev.merge_idx[d], (const InterpGeo *)P.dev.merge_geo[d],
                                (const NodeDev *)P.dev.nodes[d + 1],
                                (const int32_t *)P.dev.colbase[d + 1],
-                               (const C *)(ws + P.ws_vals[d + 1]), P.ipoly, scales,
+                               (const C *)(ws + P.ws_vals[d + 1]), P.ipoly_for(d + 1), scales,
                                P.scale_slot(d), P.scale_slot(d + 1), (C *)(ws + P.ws_vals[d]));
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
@@ -1054,7 +1054,7 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
                        (const NodeDev *)P.dev.nodes[P.F], (int)P.compact_to_tree[P.F].size(),
                        (const ColEntry *)P.dev.cols[P.F], (const int32_t *)P.dev.colbase[P.F],
                        (const C *)(ws + P.ws_vals[P.F]), (const TileBox *)P.dev.final_tiles, (const InterpIdx *)P.dev.final_idx,
-                       (const InterpGeo *)P.dev.final_geo, P.ipoly, scales, P.scale_slot(P.F), nx, ny,
+                       (const InterpGeo *)P.dev.final_geo, P.ipoly_for(P.F), scales, P.scale_slot(P.F), nx, ny,
                        nz, (float2 *)image);
     hipError_t e = hipGetLastError();
     if (ev && e == hipSuccess) (void)hipEventRecord(*ev, st);

@@ -646,7 +646,7 @@ hipError_t launch_scatters(const Plan &P, const void *grad_image, char *ws, hipS
                        (const NodeDev *)P.dev.nodes[P.F], (int)P.compact_to_tree[P.F].size(),
                        (const ColEntry *)P.dev.cols[P.F], (float2 *)(ws + P.ws_gvals[P.F]),
                        (const InterpIdx *)P.dev.final_idx, (const InterpGeo *)P.dev.final_geo,
-                       P.ipoly, nx, ny, nz, (const float2 *)grad_image);
+                       P.ipoly_for(P.F), nx, ny, nz, (const float2 *)grad_image);
     hipError_t e = hipGetLastError();
     for (int d = P.F; d < P.S && e == hipSuccess; ++d) {
         const int64_t nb = (int64_t)P.merge_bricks[d].size();
@@ -658,7 +658,7 @@ hipError_t launch_scatters(const Plan &P, const void *grad_image, char *ws, hipS
                            (const NodeDev *)P.dev.nodes[d + 1], (const ColEntry *)P.dev.cols[d + 1],
                            (float2 *)(ws + P.ws_gvals[d + 1]), (const InterpIdx *)P.dev.merge_idx[d],
                            (const InterpGeo *)P.dev.merge_geo[d],
-                           (const int32_t *)P.dev.merge_rank[d], P.Q, P.ipoly);
+                           (const int32_t *)P.dev.merge_rank[d], P.Q, P.ipoly_for(d + 1));
         e = hipGetLastError();
     }
     return e;

@@ -244,6 +244,7 @@ void partition(Plan &P)
 void build_lattice(Plan &P, HostNode &node, const std::vector<double> &parent_all)
 {
     const SubarrayMap map(node.rect, P.kmin, P.kmax);
+    const double *gam = P.gamma_of(node.depth);
     // absent parent points (no preimage) need no children
     std::vector<double> parent_xyz;
     parent_xyz.reserve(parent_all.size());
@@ -261,7 +262,7 @@ void build_lattice(Plan &P, HostNode &node, const std::vector<double> &parent_al
         for (int64_t q = b; q < e; ++q) {
             map.eval(&parent_xyz[3 * q], w, nullptr, nullptr);
             for (int a = 0; a < 3; ++a)
-                base[3 * q + a] = (int32_t)std::floor(P.gamma[a] * w[a] + kStencilEps);
+                base[3 * q + a] = (int32_t)std::floor(gam[a] * w[a] + kStencilEps);
         }
     });
     int32_t imin = INT32_MAX, imax = INT32_MIN, jmin = INT32_MAX, jmax = INT32_MIN;
@@ -272,6 +273,7 @@ void build_lattice(Plan &P, HostNode &node, const std::vector<double> &parent_al
         jmax = std::max(jmax, base[3 * q + 1]);
     }
     HostLattice &L = node.lat;
+    for (int a = 0; a < 3; ++a) L.gamma[a] = gam[a];
     L.i0 = imin + slo;
     L.j0 = jmin + slo;
     L.ni = imax - imin + (shi - slo) + 1;
@@ -311,7 +313,7 @@ void build_lattice(Plan &P, HostNode &node, const std::vector<double> &parent_al
             double p[3], prev[3];
             bool have_prev = false;
             for (int32_t l = L.lo[c]; l <= L.hi[c]; ++l) {
-                const double target[3] = {i / P.gamma[0], j / P.gamma[1], l / P.gamma[2]};
+                const double target[3] = {i / gam[0], j / gam[1], l / gam[2]};
                 if (have_prev) {
                     std::memcpy(p, prev, sizeof(p));
                 } else {
@@ -372,7 +374,7 @@ void build_final_tiles(Plan &P)
                             double w[3];
                             maps[ch].eval(p, w, nullptr, nullptr);
                             for (int a = 0; a < 3; ++a) {
-                                const int32_t t = (int32_t)std::floor(P.gamma[a] * w[a] + kStencilEps);
+                                const int32_t t = (int32_t)std::floor(L.gamma[a] * w[a] + kStencilEps);
                                 lo[a] = std::min(lo[a], t + slo);
                                 hi[a] = std::max(hi[a], t + shi);
                             }
@@ -600,9 +602,8 @@ double interp_poly_weight(const InterpPoly &ip, int a, int T, int t, double x)
 // first T/2 taps of every axis; the mirror tap is the same polynomial at -y.
 // Each fit, with its coefficients rounded to float, is checked against the
 // exact weights at 257 offsets.
-void fit_interp_poly(Plan &P)
+void fit_interp_poly(const Plan &P, const double *gamma, InterpPoly &ip)
 {
-    InterpPoly &ip = P.ipoly;
     std::memset(&ip, 0, sizeof(ip));
     ip.kind = P.cfg.interp_kernel;
     if (ip.kind != HHFFBP_INTERP_BANDLIMITED) return;
@@ -627,7 +628,7 @@ void fit_interp_poly(Plan &P)
         for (int k = 0; k < K; ++k) V[k][d] /= R[d][d];
     }
     for (int a = 0; a < 3; ++a) {
-        const double W = kPi / P.gamma[a];
+        const double W = kPi / gamma[a];
         double wk[K][kMaxTaps];
         for (int k = 0; k < K; ++k) bandlimited_weights(T, W, xk[k], wk[k]);
         for (int t = 0; t < T / 2; ++t) {
@@ -714,8 +715,10 @@ void level_estimates(Plan &P)
             part[(size_t)q] = acc;
         }
     });
-    const double g3 = P.gamma[0] * P.gamma[1] * P.gamma[2];
-    for (size_t q = 0; q < nodes.size(); ++q) P.level_estimate[nodes[q].first] += g3 * part[q];
+    for (size_t q = 0; q < nodes.size(); ++q) {
+        const double *g = P.gamma_of(nodes[q].first);
+        P.level_estimate[nodes[q].first] += g[0] * g[1] * g[2] * part[q];
+    }
 }
 
 void validate(const hhffbp_config &c)
@@ -730,7 +733,12 @@ void validate(const hhffbp_config &c)
         if (!(c.grid_pitch[a] > 0) || !std::isfinite(c.grid_pitch[a])) bad("grid_pitch must be > 0");
         if (!std::isfinite(c.grid_origin[a])) bad("grid_origin must be finite");
         if (!(c.oversample[a] >= 1.0 && c.oversample[a] <= 8.0)) bad("oversample must be in [1, 8]");
+        if (!(c.oversample_leaf[a] == 0.0 || (c.oversample_leaf[a] >= 1.0 && c.oversample_leaf[a] <= 8.0)))
+            bad("oversample_leaf must be 0 or in [1, 8]");
     }
+    if ((c.oversample_leaf[0] != 0.0 || c.oversample_leaf[1] != 0.0 || c.oversample_leaf[2] != 0.0) &&
+        (c.oversample_leaf[0] == 0.0 || c.oversample_leaf[1] == 0.0 || c.oversample_leaf[2] == 0.0))
+        bad("oversample_leaf: set all three axes or none");
     if (c.grid_dims[0] * c.grid_dims[1] * c.grid_dims[2] > ((int64_t)1 << 31))
         bad("grid too large");
     if (c.mode != HHFFBP_FACTORIZED && c.mode != HHFFBP_DIRECT_RC && c.mode != HHFFBP_DIRECT_EXACT)
@@ -787,7 +795,7 @@ void pair_record(const Plan &P, const SubarrayMap &mc, const HostLattice &Lc, co
     int32_t base[3];
     float frac[3];
     for (int a = 0; a < 3; ++a) {
-        const double t = P.gamma[a] * w[a];
+        const double t = Lc.gamma[a] * w[a];
         const double b = std::floor(t + kStencilEps);
         base[a] = (int32_t)b;
         frac[a] = (float)(t - b);
@@ -932,12 +940,16 @@ void build_plan_host(Plan &P)
     P.F = (c.root_grid && P.S > 0) ? 0 : 1;
     P.Q = c.merge_factor;
     P.T = c.interp_taps;
-    for (int a = 0; a < 3; ++a) P.gamma[a] = c.oversample[a];
+    for (int a = 0; a < 3; ++a) {
+        P.gamma[a] = c.oversample[a];
+        P.gamma_leaf[a] = c.oversample_leaf[a] > 0.0 ? c.oversample_leaf[a] : c.oversample[a];
+    }
     P.kernel = c.range_kernel;
     P.W = (c.range_kernel == HHFFBP_RANGE_ES) ? c.range_taps : 2;
     P.U = c.range_oversample;
     P.beta = kPi * P.W * (1.0 - 1.0 / (2.0 * P.U)) * 0.98;
-    fit_interp_poly(P);
+    fit_interp_poly(P, P.gamma, P.ipoly);
+    fit_interp_poly(P, P.gamma_leaf, P.ipoly_leaf);
     P.positions.assign(c.positions, c.positions + 3 * c.n_pos);
     P.weights.clear();
     if (c.weights) P.weights.assign(c.weights, c.weights + c.n_pos);
@@ -1139,21 +1151,25 @@ void build_plan_host(Plan &P)
     {
         double wmax = 0.0;
         for (size_t i = 0; i < P.Bmat.size(); ++i) wmax = std::max(wmax, (double)std::fabs(P.Bmat[i]));
-        double lt = 1.0;
-        for (int a = 0; a < 3; ++a) {
-            double la = (P.T == 4) ? 1.25 : 1.40;
-            if (P.ipoly.kind == HHFFBP_INTERP_BANDLIMITED) {
-                la = 0.0;
-                for (int i = 0; i <= 256; ++i) {
-                    const double x = i / 256.0;
-                    double sum = 0.0;
-                    for (int t = 0; t < P.T; ++t) sum += std::fabs(interp_poly_weight(P.ipoly, a, P.T, t, x));
-                    la = std::max(la, sum);
+        // L_u L_v L_n of the weights that interpolate from grids with these polynomials
+        auto weight_sums = [&](const InterpPoly &ip) {
+            double lt = 1.0;
+            for (int a = 0; a < 3; ++a) {
+                double la = (P.T == 4) ? 1.25 : 1.40;
+                if (ip.kind == HHFFBP_INTERP_BANDLIMITED) {
+                    la = 0.0;
+                    for (int i = 0; i <= 256; ++i) {
+                        const double x = i / 256.0;
+                        double sum = 0.0;
+                        for (int t = 0; t < P.T; ++t) sum += std::fabs(interp_poly_weight(ip, a, P.T, t, x));
+                        la = std::max(la, sum);
+                    }
+                    la *= 1.01;
                 }
-                la *= 1.01;
+                lt *= la;
             }
-            lt *= la;
-        }
+            return lt;
+        };
         P.scale_mult.assign(P.n_scales(), 0.0f);
         // the aperture weights scale each echo row before the range compression
         double wt = P.weights.empty() ? 1.0 : 0.0;
@@ -1168,7 +1184,7 @@ void build_plan_host(Plan &P)
             for (int d = S - 1; d >= P.F; --d) {
                 size_t nch = 0;
                 for (int32_t ti : P.compact_to_tree[d]) nch = std::max(nch, P.levels[d][ti].children.size());
-                m *= (double)nch * lt;
+                m *= (double)nch * weight_sums(P.ipoly_for(d + 1));
                 P.scale_mult[P.scale_slot(d)] = (float)m;
             }
         }

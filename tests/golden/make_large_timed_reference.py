@@ -4,8 +4,11 @@
 targets, 8 seeded):
 
 * tests/golden/large_bandlimited_oracle.npz: S = 3 onto the voxel grid (default);
-* tests/golden/large_s4_root_oracle.npz: S = 4 with a compressed root grid, the
-  benchmarked form (``--stages 4 --root-grid``);
+* tests/golden/large_s4_root_oracle.npz: S = 4 with a compressed root grid
+  (``--stages 4 --root-grid``);
+* tests/golden/large_s4_root_leaf_oracle.npz: the same with the leaf grids at
+  gamma = (1.8, 1.8, 2.2), the benchmarked form
+  (``--stages 4 --root-grid --gamma-leaf 1.8,1.8,2.2``);
 
 each in two forms of the level-1 sum:
 
@@ -21,6 +24,7 @@ oracle/ and workloads/; run from the repository root (CPU echo synthesis takes
 
     python tests/golden/make_large_timed_reference.py
     python tests/golden/make_large_timed_reference.py --stages 4 --root-grid
+    python tests/golden/make_large_timed_reference.py --stages 4 --root-grid --gamma-leaf 1.8,1.8,2.2
 """
 import argparse
 import os
@@ -67,19 +71,24 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--stages", type=int, default=3)
     ap.add_argument("--root-grid", action="store_true")
+    ap.add_argument("--gamma-leaf", default=None, help="leaf grids' oversampling, u,v,n")
     args = ap.parse_args()
     stages, root = args.stages, args.root_grid
-    name = "large_bandlimited_oracle.npz" if (stages, root) == (3, False) else \
-        f"large_s{stages}{'_root' if root else ''}_oracle.npz"
+    gleaf = None if args.gamma_leaf is None else tuple(float(x) for x in args.gamma_leaf.split(","))
+    name = "large_bandlimited_oracle.npz" if (stages, root, gleaf) == (3, False, None) else \
+        f"large_s{stages}{'_root' if root else ''}{'_leaf' if gleaf else ''}_oracle.npz"
     t0 = time.time()
     w = make_config(2)
     print(f"echoes {time.time() - t0:.0f} s", flush=True)
     pl = OP.build_plan(w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims,
-                       stages, 4, GAMMA, TAPS, kernel="bandlimited", root_grid=root)
+                       stages, 4, GAMMA, TAPS, kernel="bandlimited", root_grid=root,
+                       gamma_leaf=gleaf)
     print(f"plan {time.time() - t0:.0f} s", flush=True)
     index = bricks(w, np.random.default_rng(37))
     store = dict(index=index, gamma=np.array(GAMMA), taps=TAPS, stages=stages, range_u=RANGE_U,
                  root_grid=root)
+    if gleaf is not None:
+        store["gamma_leaf"] = np.array(gleaf)
     top = 0 if root else 1
     for form, ru in (("linear", RANGE_U), ("eq4", None)):
         img, kept = OH.image_at(pl, w.echoes, w.positions, index, range_u=ru, keep=True)

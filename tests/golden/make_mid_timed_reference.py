@@ -1,7 +1,9 @@
 """Write tests/golden/mid_bandlimited_oracle.npz: the float64 oracle HHFFBPA of
-the 16384-position, 64-frequency, 128x128x64-voxel handheld workload with the
-benchmarked plan choices (S = 3, Q = 4, band-limited weights, T = 4,
-gamma = (2.2, 2.2, 2.6)), in two forms of the level-1 sum:
+the 16384-position, 64-frequency, 128x128x64-voxel handheld workload with
+band-limited plan choices (S = 3, Q = 4, band-limited weights, T = 4,
+gamma = (2.2, 2.2, 2.6)); with ``--gamma-leaf 1.8,1.8,2.2``
+tests/golden/mid_bandlimited_leaf_oracle.npz, the benchmarked choices (the leaf
+grids at that oversampling).  Two forms of the level-1 sum:
 
 * "linear": range profiles at U = 4 read by linear interpolation (the timed form);
 * "eq4":    eq. (4) itself (what the ES parity mode approximates to ~1e-6).
@@ -12,7 +14,9 @@ compressed value).  Calls only oracle/ and workloads/; run from the repository
 root (a few minutes per form on 8 cores):
 
     python tests/golden/make_mid_timed_reference.py
+    python tests/golden/make_mid_timed_reference.py --gamma-leaf 1.8,1.8,2.2
 """
+import argparse
 import os
 import sys
 import time
@@ -62,14 +66,20 @@ def sample_stages(vals, plan, rng, per_depth=4096):
 
 
 def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gamma-leaf", default=None, help="leaf grids' oversampling, u,v,n")
+    args = ap.parse_args()
+    gleaf = None if args.gamma_leaf is None else tuple(float(x) for x in args.gamma_leaf.split(","))
     t0 = time.time()
     w = make_config(1)
     pl = OP.build_plan(w.positions, w.freqs_hz, w.grid_origin, w.grid_pitch, w.grid_dims,
-                       STAGES, 4, GAMMA, TAPS, kernel="bandlimited")
+                       STAGES, 4, GAMMA, TAPS, kernel="bandlimited", gamma_leaf=gleaf)
     print(f"plan {time.time() - t0:.0f} s", flush=True)
     rng = np.random.default_rng(29)
     index = sample_voxels(w, rng)
     store = dict(index=index, gamma=np.array(GAMMA), taps=TAPS, stages=STAGES, range_u=RANGE_U)
+    if gleaf is not None:
+        store["gamma_leaf"] = np.array(gleaf)
     for form, ru in (("linear", RANGE_U), ("eq4", None)):
         img, vals = OH.image(pl, w.echoes, w.positions, keep=True, range_u=ru)
         print(f"{form} image {time.time() - t0:.0f} s", flush=True)
@@ -78,7 +88,8 @@ def main():
             store[f"{form}_d{d}_node"] = node
             store[f"{form}_d{d}_point"] = point
             store[f"{form}_d{d}_value"] = v
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "mid_bandlimited_oracle.npz")
+    name = "mid_bandlimited_leaf_oracle.npz" if gleaf else "mid_bandlimited_oracle.npz"
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), name)
     np.savez_compressed(out, **store)
     print(f"wrote {out}: {index.size} voxels", flush=True)
 

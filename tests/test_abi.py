@@ -62,6 +62,7 @@ def test_config_default_layout():
     assert (c.range_kernel, c.range_taps, c.storage, c.device) == (0, 7, 0, 0)
     assert c.range_oversample == 2.0 and abs(c.position_slack - 5e-3) < 1e-15
     assert (c.interp_kernel, c.final_staging, c.root_grid, c.range_fused) == (0, 1, 0, 0)
+    assert list(c.oversample_leaf) == [0.0, 0.0, 0.0]
 
 
 def test_final_stage_bricks(small):
@@ -87,6 +88,8 @@ def _args(w):
     (dict(range_fused=True), -1),  # the ES range kernel
     (dict(range_fused=True, range_kernel="linear", storage="f16"), -1),
     (dict(range_fused=True, range_kernel="linear", mode="direct_rc"), -1),
+    (dict(oversample_leaf=0.5), -1), (dict(oversample_leaf=(2.0, 0.0, 2.0)), -1),
+    (dict(oversample_leaf=9.0), -1),
 ])
 def test_invalid_configurations_are_rejected(small, change, status):
     kw = dict(device=-1)
@@ -166,16 +169,17 @@ def test_host_only_plan_refuses_image(small):
         pl.node_layout(2, 0)
 
 
-@pytest.mark.parametrize("S,Q,gamma,T,root", [
-    (1, 4, 3.0, 4, False), (2, 4, 3.0, 4, False), (2, 2, (2.5, 2.5, 3.0), 6, False),
-    (1, 4, 3.0, 4, True), (2, 2, (2.5, 2.5, 3.0), 4, True),
+@pytest.mark.parametrize("S,Q,gamma,T,root,leaf", [
+    (1, 4, 3.0, 4, False, None), (2, 4, 3.0, 4, False, None), (2, 2, (2.5, 2.5, 3.0), 6, False, None),
+    (1, 4, 3.0, 4, True, None), (2, 2, (2.5, 2.5, 3.0), 4, True, None),
+    (2, 4, (2.2, 2.2, 2.6), 4, False, (1.8, 1.8, 2.2)), (2, 4, (2.2, 2.2, 2.6), 4, True, (1.8, 1.8, 2.2)),
 ])
-def test_host_plan_matches_oracle_plan(small, S, Q, gamma, T, root):
+def test_host_plan_matches_oracle_plan(small, S, Q, gamma, T, root, leaf):
     from oracle import plan as OP
 
     pl = H.Plan(*_args(small), stages=S, merge_factor=Q, oversample=gamma, interp_taps=T,
-                device=-1, root_grid=root)
-    op = OP.build_plan(*_args(small), S, Q, gamma, T, root_grid=root)
+                device=-1, root_grid=root, oversample_leaf=leaf)
+    op = OP.build_plan(*_args(small), S, Q, gamma, T, root_grid=root, gamma_leaf=leaf)
     info = pl.info()
     assert info["n_leaves"] == sum(1 for n in op.levels[S] if not n.empty)
     assert info["root_grid"] == int(root)

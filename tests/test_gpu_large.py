@@ -152,6 +152,7 @@ def test_large_direct_leaf_and_hhffbp(torch, large, gold):
 
 
 BL_GAMMA = (2.2, 2.2, 2.6)
+BL_LEAF = (1.8, 1.8, 2.2)
 PEAK_FORMS = {
     "bandlimited-linear-U4": dict(oversample=BL_GAMMA, interp_kernel="bandlimited",
                                   range_kernel="linear", range_oversample=4.0),
@@ -162,6 +163,10 @@ PEAK_FORMS = {
     "bandlimited-linear-U4-S4-root-grid": dict(oversample=BL_GAMMA, interp_kernel="bandlimited",
                                                range_kernel="linear", range_oversample=4.0,
                                                root_grid=True, stages=4),
+    "bandlimited-linear-U4-S4-root-grid-leaf": dict(oversample=BL_GAMMA, interp_kernel="bandlimited",
+                                                    range_kernel="linear", range_oversample=4.0,
+                                                    root_grid=True, stages=4,
+                                                    oversample_leaf=BL_LEAF),
     "lagrange-es": dict(oversample=GAMMA),
 }
 # Lagrange weights on (3, 3, 3.5) put two isolated targets' peaks one voxel off
@@ -190,12 +195,14 @@ def test_large_peaks(torch, large, gold, form):
     assert r["matched"] == r["compared"]
 
 
-@pytest.mark.parametrize("stored", ["large_bandlimited_oracle.npz", "large_s4_root_oracle.npz"])
+@pytest.mark.parametrize("stored", ["large_bandlimited_oracle.npz", "large_s4_root_oracle.npz",
+                                    "large_s4_root_leaf_oracle.npz"])
 @pytest.mark.parametrize("form", ["linear", "eq4"])
 def test_large_bandlimited_vs_stored_oracle(torch, large, form, stored):
     """Band-limited plans at full size against the stored oracle HHFFBPA of the
     same choices (tests/golden/make_large_timed_reference.py): S = 3 onto the
-    voxel grid, and the benchmarked form, S = 4 with a compressed root grid; on
+    voxel grid, S = 4 with a compressed root grid, and the benchmarked form, the
+    latter with the leaf grids at (1.8, 1.8, 2.2); on
     voxel bricks and on sampled grid points of every depth of their cones (the
     root's lattice included).  The linear range kernel at U = 4 (the timed form)
     against the oracle's linear form, the ES parity mode against the oracle with
@@ -208,11 +215,12 @@ def test_large_bandlimited_vs_stored_oracle(torch, large, form, stored):
     assert tuple(g["gamma"]) == BL_GAMMA and int(g["taps"]) == TAPS
     stages = int(g["stages"])
     root = bool(g["root_grid"]) if "root_grid" in g.files else False
+    leaf = tuple(g["gamma_leaf"]) if "gamma_leaf" in g.files else None
     w = large
     kw = dict(range_kernel="linear", range_oversample=float(g["range_u"])) if form == "linear" \
         else dict(range_kernel="es", range_oversample=2.0, range_taps=7)
     pl = H.Plan(*_args(w), stages=stages, merge_factor=4, oversample=BL_GAMMA, interp_taps=TAPS,
-                interp_kernel="bandlimited", root_grid=root, **kw)
+                interp_kernel="bandlimited", root_grid=root, oversample_leaf=leaf, **kw)
     ws = pl._workspace(torch)
     img = pl.image(_ech(torch, w), workspace=ws)
     torch.cuda.synchronize()

@@ -332,15 +332,19 @@ def test_mid_config_full_size(torch, mid, mid_fp64_boxes):
 
 # the benchmark's launch configuration: band-limited weights on coarser grids
 BENCH_GAMMA = (2.2, 2.2, 2.6)
+BENCH_LEAF = (1.8, 1.8, 2.2)   # the benchmarked form's leaf grids
 
 
-@pytest.mark.parametrize("kernel,gamma,U", [("lagrange", GAMMA, 8), ("bandlimited", BENCH_GAMMA, 8),
-                                            ("bandlimited", (2.0, 2.0, 2.4), 4)])
-def test_mid_fast_range_mode_full_size(torch, mid, mid_fp64_boxes, kernel, gamma, U):
+@pytest.mark.parametrize("kernel,gamma,U,leaf", [("lagrange", GAMMA, 8, None),
+                                                 ("bandlimited", BENCH_GAMMA, 8, None),
+                                                 ("bandlimited", (2.0, 2.0, 2.4), 4, None),
+                                                 ("bandlimited", BENCH_GAMMA, 4, BENCH_LEAF)])
+def test_mid_fast_range_mode_full_size(torch, mid, mid_fp64_boxes, kernel, gamma, U, leaf):
     """The fast range mode at full size: 16384 positions, 64 f, 128x128x64
     voxels, S = 3, Q = 4, linear range kernel; Lagrange weights at (3, 3, 3.5)
     with U = 8, band-limited weights at (2.2, 2.2, 2.6) with U = 8 and at the
-    coarser (2.0, 2.0, 2.4) with U = 4.  Level-1 subimages at seeded grid points against the
+    coarser (2.0, 2.0, 2.4) with U = 4, and the benchmarked form: (2.2, 2.2, 2.6)
+    with the leaf grids at (1.8, 1.8, 2.2), U = 4.  Level-1 subimages at seeded grid points against the
     oracle's level-1 sum of the same form (<= 1e-5); the image against GPU
     direct BP (pinned to eq. (4) by the test above) on the full grid (<= -30 dB)
     with the same isolated peaks; for the Lagrange form also against the stored
@@ -349,10 +353,11 @@ def test_mid_fast_range_mode_full_size(torch, mid, mid_fp64_boxes, kernel, gamma
     from oracle import hhffbp as OH
     from oracle import plan as OP
     w = mid
-    _say(f"mid fast range mode, {kernel} {gamma} U={U}: oracle plan")
-    op = OP.build_plan(*_args(w), 3, 4, gamma, TAPS, kernel=kernel)
+    _say(f"mid fast range mode, {kernel} {gamma} leaf {leaf} U={U}: oracle plan")
+    op = OP.build_plan(*_args(w), 3, 4, gamma, TAPS, kernel=kernel, gamma_leaf=leaf)
     pl = H.Plan(*_args(w), stages=3, merge_factor=4, oversample=gamma, interp_taps=TAPS,
-                range_kernel="linear", range_oversample=float(U), interp_kernel=kernel)
+                range_kernel="linear", range_oversample=float(U), interp_kernel=kernel,
+                oversample_leaf=leaf)
     ws = pl._workspace(torch)
     img = _run(torch, pl, w, workspace=ws)
     rng = np.random.default_rng(21)
@@ -379,25 +384,30 @@ def test_mid_fast_range_mode_full_size(torch, mid, mid_fp64_boxes, kernel, gamma
         assert e_o <= 2e-3
 
 
+@pytest.mark.parametrize("stored", ["mid_bandlimited_oracle.npz", "mid_bandlimited_leaf_oracle.npz"])
 @pytest.mark.parametrize("form", ["linear", "eq4"])
-def test_mid_bandlimited_vs_stored_oracle(torch, mid, mid_fp64_boxes, form):
-    """The benchmarked plan choices at full size (16384 positions, 64 f,
+def test_mid_bandlimited_vs_stored_oracle(torch, mid, mid_fp64_boxes, form, stored):
+    """Band-limited plan choices at full size (16384 positions, 64 f,
     128x128x64 voxels, S = 3, Q = 4, band-limited weights, gamma = (2.2, 2.2,
-    2.6)) against the stored float64 oracle HHFFBPA of the same choices
+    2.6); and the benchmarked form, its leaf grids at (1.8, 1.8, 2.2)) against
+    the stored float64 oracle HHFFBPA of the same choices
     (tests/golden/make_mid_timed_reference.py): the linear range kernel at U = 4
     (the timed form) against the oracle's linear form, the ES parity mode against
     the oracle with eq. (4) level-1 sums.  Image at 16384 seeded voxels and the
     point targets' boxes, and 4096 seeded grid points of every depth: NRMSE
     <= 1e-5 and no value off by more than 5e-5 of the reference's RMS; the
     image within -30 dB of GPU direct BP on the full grid, peaks by the S20 rule."""
-    gold = os.path.join(GOLDEN, "mid_bandlimited_oracle.npz")
+    gold = os.path.join(GOLDEN, stored)
+    if not os.path.exists(gold):
+        pytest.skip("stored oracle values missing (tests/golden/make_mid_timed_reference.py)")
     g = np.load(gold)
     assert tuple(g["gamma"]) == BENCH_GAMMA and int(g["taps"]) == TAPS
+    leaf = tuple(g["gamma_leaf"]) if "gamma_leaf" in g.files else None
     w = mid
     kw = dict(range_kernel="linear", range_oversample=float(g["range_u"])) if form == "linear" \
         else dict(range_kernel="es", range_oversample=2.0, range_taps=7)
     pl = H.Plan(*_args(w), stages=3, merge_factor=4, oversample=BENCH_GAMMA, interp_taps=TAPS,
-                interp_kernel="bandlimited", **kw)
+                interp_kernel="bandlimited", oversample_leaf=leaf, **kw)
     ws = pl._workspace(torch)
     img = _run(torch, pl, w, workspace=ws)
     got = img.ravel()[g["index"]]
@@ -507,6 +517,36 @@ def test_hhffbp_bandlimited_small(torch, small, oracle_small, S, Q, T):
          f"vs eq.4 {20 * np.log10(e_bp):.1f} dB")
     assert e <= 1e-5 and worst <= 1e-5
     assert 20 * np.log10(e_bp) <= -35.0
+
+
+@pytest.mark.parametrize("S,Q,root,storage", [(2, 4, False, "c64"), (2, 4, True, "c64"),
+                                               (3, 2, False, "c64"), (2, 4, True, "f16")])
+def test_leaf_oversampling_small(torch, small, S, Q, root, storage):
+    """Leaf grids at their own oversampling (oversample_leaf = (1.8, 1.8, 2.2)
+    under gamma = (2.2, 2.2, 2.6), band-limited weights fitted per grid spacing)
+    against the oracle plan with the same leaf grids: image and every stage
+    <= 1e-5 (f16 storage: 1e-3)."""
+    from oracle import hhffbp as OH
+    from oracle import plan as OP
+    g, gl = (2.2, 2.2, 2.6), (1.8, 1.8, 2.2)
+    op = OP.build_plan(*_args(small), S, Q, g, 4, kernel="bandlimited", root_grid=root,
+                       gamma_leaf=gl)
+    ref, vals = OH.image(op, small.echoes, small.positions, keep=True)
+    pl = H.Plan(*_args(small), stages=S, merge_factor=Q, oversample=g, interp_taps=4,
+                interp_kernel="bandlimited", root_grid=root, oversample_leaf=gl, storage=storage)
+    ws = pl._workspace(torch)
+    ech = torch.from_numpy(small.echoes.astype(np.complex64)).cuda()
+    if storage != "c64":
+        ech = H.Plan.pack_echoes(ech, storage)
+    img = pl.image(ech, workspace=ws)
+    torch.cuda.synchronize()
+    img = img.cpu().numpy().astype(np.complex128)
+    e = _nrmse(img, ref)
+    worst = max(_nrmse(pl.workspace_view(ws, d, i).cpu().numpy().astype(np.complex128), v)
+                for (d, i), v in vals.items())
+    _say(f"  leaf gamma S={S} Q={Q} root={root} {storage}: vs oracle {e:.3e}; worst stage {worst:.3e}")
+    bar = 1e-5 if storage == "c64" else 1e-3
+    assert e <= bar and worst <= bar
 
 
 @pytest.mark.parametrize("storage", ["c64", "f16"])
