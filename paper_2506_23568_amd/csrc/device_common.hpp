@@ -140,7 +140,7 @@ __device__ __forceinline__ int floor_int(float x)
 constexpr int kLeafChunkMax = 32;
 // thread-strided steps per round of the final stage's box staging (a box of
 // up to kTileCap values takes (kTileCap / kBlock) / kStageRound rounds)
-constexpr int kStageRound = 4;
+constexpr int kStageRound = 2;
 // thread-strided staging steps that cover a kLdsBudget tile of float2
 constexpr int kStageSteps = (int)((kLdsBudget / sizeof(float2) + kBlock - 1) / kBlock);
 __host__ __device__ inline int leaf_chunk(int nrb)
@@ -264,6 +264,7 @@ __device__ __forceinline__ float2 interp_rec(const NodeDev &c, const int32_t *__
     float are = 0.0f, aim = 0.0f;
 #pragma unroll
     for (int a = 0; a < T; ++a) {
+        float rre = 0.0f, rim = 0.0f;  // stencil row a: sum over b of wv[b] x column sum
 #pragma unroll
         for (int b = 0; b < T; ++b) {
             const typename Store<ST>::C *p = base + crow[a * c.nj + b];
@@ -274,10 +275,11 @@ __device__ __forceinline__ float2 interp_rec(const NodeDev &c, const int32_t *__
                 sre = fmaf(wn[k], v.x, sre);
                 sim = fmaf(wn[k], v.y, sim);
             }
-            const float wab = wu[a] * wv[b];
-            are = fmaf(wab, sre, are);
-            aim = fmaf(wab, sim, aim);
+            rre = fmaf(wv[b], sre, rre);
+            rim = fmaf(wv[b], sim, rim);
         }
+        are = fmaf(wu[a], rre, are);
+        aim = fmaf(wu[a], rim, aim);
         // one stencil row (T columns, T^2 values) in flight at a time: hoisting
         // every gather costs registers and occupancy, not latency
         __builtin_amdgcn_sched_barrier(0);
@@ -294,18 +296,21 @@ __device__ __forceinline__ void rotate_mac(float2 v, float turns, float &are, fl
 }
 
 // The T^3 taps from a dense LDS box: p points at the stencil's first tap, the
-// box holds nl values per (i, j) column and nj columns per i.  Same summation
-// order as interp_rec.
-template <int T>
-__device__ __forceinline__ float2 interp_box(const float2 *p, int nj, int nl, const float *wu,
-                                             const float *wv, const float *wn)
+// box's (i, j) columns lie cs values apart (CS when CS > 0, a compile-time
+// stride), nj columns per i.  Same summation order as interp_rec.
+template <int T, int CS>
+__device__ __forceinline__ float2 interp_box(const float2 *p, int nj, const float *wu, const float *wv,
+                                             const float *wn, int cs = CS)
 {
+    const int stride = CS > 0 ? CS : cs;
     float are = 0.0f, aim = 0.0f;
 #pragma unroll
     for (int a = 0; a < T; ++a) {
+        const float2 *row = p + a * nj * stride;
+        float rre = 0.0f, rim = 0.0f;
 #pragma unroll
         for (int b = 0; b < T; ++b) {
-            const float2 *q = p + (a * nj + b) * nl;
+            const float2 *q = row + b * stride;
             float sre = 0.0f, sim = 0.0f;
 #pragma unroll
             for (int k = 0; k < T; ++k) {
@@ -313,10 +318,11 @@ __device__ __forceinline__ float2 interp_box(const float2 *p, int nj, int nl, co
                 sre = fmaf(wn[k], v.x, sre);
                 sim = fmaf(wn[k], v.y, sim);
             }
-            const float wab = wu[a] * wv[b];
-            are = fmaf(wab, sre, are);
-            aim = fmaf(wab, sim, aim);
+            rre = fmaf(wv[b], sre, rre);
+            rim = fmaf(wv[b], sim, rim);
         }
+        are = fmaf(wu[a], rre, are);
+        aim = fmaf(wu[a], rim, aim);
     }
     return make_float2(are, aim);
 }

@@ -74,17 +74,25 @@ struct BlockItem {
 // Final stage: voxels are processed in bricks of kBrickX x kBrickY x kBrickZ
 // (z fastest in a brick, as in the image), and each (brick, depth-1 node) has
 // the box of that node's lattice indices [i0, i0 + ni) x [j0, j0 + nj) x
-// [l0, l0 + nl) its stencils use, with one index of margin on every side for
-// rounding.  In LDS a box column holds 2^lsh >= nl values; ni = 0 marks a box
-// of more than kTileCap such values (the kernel then gathers from the pencils).
+// [l0, l0 + nl) its stencils use: first from the maps with one index of margin
+// on every side for rounding, then, once the plan-time records exist, the
+// exact hull of the records' stencils.  In LDS the box's columns lie cs >= nl
+// values apart (ni * nj * cs <= kTileCap + kTileCap / 4); ni = 0 marks a box
+// of more than kTileCap values at 2^lsh >= nl per column (the kernel then
+// gathers from the pencils) or one no stencil uses.
 constexpr int kBrickX = 4, kBrickY = 4, kBrickZ = 16;
 constexpr int kTileCap = 2048;
+// The final stage's LDS column stride for boxes of nl <= 24 (TileBox::cs), which
+// the kernel also takes as a compile-time constant when every box has it.
+constexpr int kFinalCS = 24;
 // Positions per block of the level-1 adjoint (one block per leaf and kAdjPos
 // of its leaf-sorted positions).
 constexpr int kAdjPos = 8;
 struct TileBox {
     int32_t i0, j0, l0, ni, nj, nl, lsh;
     int32_t inv_nj;  // ceil(2^22 / nj): column c of the box is (c * inv_nj >> 22, c mod nj)
+    int32_t inv_nl;  // ceil(2^22 / nl): point e of the box, column-major, is in column e * inv_nl >> 22
+    int32_t cs;      // LDS column stride (values)
 };
 
 // Bricks of a parent grid for the merge adjoint: kBrickX x kBrickY columns
@@ -235,6 +243,9 @@ struct Plan {
     std::vector<TileBox> final_tiles;  // host copy, brick-major
     int64_t n_bricks = 0, n_tiled = 0;  // final-stage bricks; (brick, node) pairs with a box
     bool final_box_only = false;        // every final-stage stencil lies in its brick's box
+    int32_t final_cs = 0;               // the column stride every staged box shares, else 0
+    int64_t final_box_vals = 0;         // largest ni * nj * cs of a staged box
+    int64_t final_box_cols = 0;         // largest ni * nj of a staged box
     int64_t leaf_pairs = 0, merge_pairs = 0, final_pairs = 0;
     std::vector<int64_t> merge_pairs_depth;  // per depth < S
     std::vector<double> level_estimate;      // per depth: gamma^3 * integral of |det J| over the voxels
@@ -267,6 +278,13 @@ struct Plan {
     int scale_slot(int d) const { return d == 0 ? S + 1 : d; }
     int n_scales() const { return S + 1 + (F == 0 ? 1 : 0); }
 };
+
+// Dynamic LDS of the final stage: the largest staged box, one spare value per
+// thread and the largest box's column table (float2 and int2 entries).
+inline size_t final_lds_bytes(const Plan &P)
+{
+    return ((size_t)P.final_box_vals + kBlockThreads + (size_t)P.final_box_cols) * 8;
+}
 
 // Plan construction (host, float64).  Throws hh::Error on failure.
 struct Error {

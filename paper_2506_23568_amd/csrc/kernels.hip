@@ -635,13 +635,17 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
 // grid, then the only child); scales[sc] is their storage scale.  One lane per voxel,
 // a block per brick of kBrickX x kBrickY x kBrickZ voxels (lane t: z = t mod 16
 // fastest, then y, then x).  Per child, the block first stages the child's
-// values over the brick's stencil box (TileBox, from the plan) into LDS, dense
-// and zero outside the pencils, thread-strided over the box's items.  A lane whose stencil lies inside the box then
-// reads its T^3 taps from LDS in the same order as the pencil path; one
-// outside it (or a child without a box) gathers from the pencils.  Each
-// (voxel, child) pair's stencil, fractions and phase Phi_c come from its
-// plan-time record.
-template <int T, int ST, int K, bool BOX_ONLY>
+// values over the brick's stencil box (TileBox, from the plan) into LDS: a
+// table of the box's columns (where each column's pencil starts and which box
+// indices it covers), then every pencil value inside the box, thread-strided.
+// Box points outside the pencils are left unwritten: every stencil tap lies in
+// a pencil (the plan checks each record's stencil against them).  A lane whose
+// stencil lies inside the box then reads its T^3 taps from LDS in the same
+// order as the pencil path; one outside it (or a child without a box) gathers
+// from the pencils.  Each (voxel, child) pair's stencil, fractions and phase
+// Phi_c come from its plan-time record.  CS > 0: every box has column stride
+// CS, and the taps' offsets within a stencil row become immediates.
+template <int T, int ST, int K, bool BOX_ONLY, int CS>
 __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ children,
                                                   int nchild, const ColEntry *__restrict__ ccols,
                                                   const int32_t *__restrict__ ccolbase,
@@ -651,12 +655,17 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
                                                   const InterpGeo *__restrict__ rgeo,
                                                   const InterpPoly ip,
                                                   const float *__restrict__ scales, int sc,
-                                                  int nx, int ny, int nz,
+                                                  int nx, int ny, int nz, int box_vals,
                                                   float2 *__restrict__ image)
 {
-    // box columns 2^lsh + 1 values apart: a power-of-two stride would put the
-    // same n index of every column into one LDS bank
-    __shared__ float2 s_tile[kTileCap + kTileCap / 4];
+    // Dynamic LDS, sized by the plan's largest box: box_vals values (columns
+    // tb.cs apart), then one spare value per thread, the target of staging
+    // slots that hold nothing (unconditional loads and stores keep a round's
+    // loads in flight together), then per box column the value offset of box
+    // index l = 0 and lo | n << 16 for the box indices [lo, lo + n) its pencil
+    // covers.
+    extern __shared__ float2 s_tile[];
+    int2 *s_col = reinterpret_cast<int2 *>(s_tile + box_vals + kBlock);
     const int bz = (nz + kBrickZ - 1) / kBrickZ, by = (ny + kBrickY - 1) / kBrickY;
     const int brick = (int)blockIdx.x;
     const int kx = brick / (by * bz), ky = (brick / bz) % by, kz = brick % bz;
@@ -668,39 +677,45 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
     for (int c = 0; c < nchild; ++c) {
         const NodeDev ch = children[c];
         const TileBox tb = tiles[(size_t)brick * nchild + c];
-        __syncthreads();  // the previous child's box is consumed
+        const int ncol = tb.ni * tb.nj;
+        __syncthreads();  // the previous child's box and table are consumed
         if (tb.ni > 0) {
-            // item e = (column << lsh) + l over the padded box, thread-strided,
-            // in rounds of kStageRound items per thread (a uniform trip count: a
-            // small box takes one round); per round all entry loads, then all
-            // value loads, then the stores.  Indices are 32-bit offsets from the
-            // child's (uniform) arrays.
-            const int items = (tb.ni * tb.nj) << tb.lsh;
             const ColEntry *ccol = ccols + ch.col_base + (tb.i0 - ch.i0) * ch.nj + (tb.j0 - ch.j0);
+            for (int k = t; k < ncol; k += kBlock) {
+                const int ci = (k * tb.inv_nj) >> 22, cj = k - ci * tb.nj;
+                const ColEntry en = ld_u32(ccol, (uint32_t)(ci * ch.nj + cj));
+                const int lo = max(en.lo - tb.l0, 0), hi = min(en.hi - tb.l0, tb.nl - 1);
+                s_col[k] = make_int2(en.off - en.lo + tb.l0, lo | (max(hi - lo + 1, 0) << 16));
+            }
+        }
+        __syncthreads();
+        if (tb.ni > 0) {
+            // box point e = column * nl + l, thread-strided in rounds of
+            // kStageRound points per thread (a uniform trip count): per round
+            // all table reads, then all value loads, then the stores; a point
+            // outside the pencils (or past the box) loads the child's first
+            // value into this thread's spare slot
+            const int items = ncol * tb.nl, stride = CS > 0 ? CS : tb.cs;
             const typename Store<ST>::C *cv = cvals + ch.val_base;
 #pragma unroll 1
             for (int e0 = 0; e0 < items; e0 += kStageRound * kBlock) {
-                uint32_t roff[kStageRound];
-                bool take[kStageRound];
+                uint32_t src[kStageRound];
+                int dst[kStageRound];
 #pragma unroll
                 for (int k = 0; k < kStageRound; ++k) {
                     const int e = e0 + k * kBlock + t;
-                    const int col = min(e >> tb.lsh, tb.ni * tb.nj - 1);
-                    const int ci = (col * tb.inv_nj) >> 22, cj = col - ci * tb.nj;
-                    const ColEntry en = ld_u32(ccol, (uint32_t)(ci * ch.nj + cj));
-                    const int l = e & ((1 << tb.lsh) - 1);
-                    const int rr = tb.l0 + l - en.lo;  // position in the pencil
-                    take[k] = e < items && l < tb.nl && (unsigned)rr <= (unsigned)(en.hi - en.lo);
-                    roff[k] = take[k] ? (uint32_t)(en.off + rr) : 0u;
+                    const int col = min((int)(((uint32_t)e * (uint32_t)tb.inv_nl) >> 22), ncol - 1);
+                    const int l = e - col * tb.nl;
+                    const int2 q = s_col[col];
+                    const bool take = (e < items) & ((unsigned)(l - (q.y & 0xffff)) < (unsigned)(q.y >> 16));
+                    src[k] = take ? (uint32_t)(q.x + l) : 0u;
+                    dst[k] = take ? col * stride + l : box_vals + t;
                 }
                 float2 v[kStageRound];
 #pragma unroll
-                for (int k = 0; k < kStageRound; ++k) v[k] = Store<ST>::ld(ld_u32(cv, roff[k]));
+                for (int k = 0; k < kStageRound; ++k) v[k] = Store<ST>::ld(ld_u32(cv, src[k]));
 #pragma unroll
-                for (int k = 0; k < kStageRound; ++k) {
-                    const int e = e0 + k * kBlock + t;
-                    if (e < items) s_tile[e + (e >> tb.lsh)] = take[k] ? v[k] : make_float2(0.0f, 0.0f);
-                }
+                for (int k = 0; k < kStageRound; ++k) s_tile[dst[k]] = v[k];
             }
         }
         __syncthreads();
@@ -716,8 +731,9 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
             // BOX_ONLY: the plan checked that every stencil lies in its box
             if (BOX_ONLY || (tb.ni > 0 && (unsigned)ti <= (unsigned)(tb.ni - T) &&
                              (unsigned)tj <= (unsigned)(tb.nj - T) && (unsigned)tl <= (unsigned)(tb.nl - T)))
-                val = interp_box<T>(s_tile + (ti * tb.nj + tj) * ((1 << tb.lsh) + 1) + tl, tb.nj,
-                                    (1 << tb.lsh) + 1, wu, wv, wn);
+                val = CS > 0 ? interp_box<T, CS>(s_tile + (ti * tb.nj + tj) * CS + tl, tb.nj, wu, wv, wn)
+                             : interp_box<T, 0>(s_tile + (ti * tb.nj + tj) * tb.cs + tl, tb.nj, wu, wv, wn,
+                                                tb.cs);
             else
                 val = interp_rec<T, ST>(ch, ccolbase, cvals, ci0, cj0, rx.l0, wu, wv, wn);
             rotate_mac(val, g.turns, are, aim);
@@ -1049,13 +1065,15 @@ hipError_t launch_merges(const Plan &P, char *ws, void *image, const float *scal
     }
     const hhffbp_config &c = P.cfg;
     const int nx = (int)c.grid_dims[0], ny = (int)c.grid_dims[1], nz = (int)c.grid_dims[2];
-    auto final_kernel = P.final_box_only ? k_final<T, ST, K, true> : k_final<T, ST, K, false>;
-    hipLaunchKernelGGL(final_kernel, dim3(P.n_bricks), dim3(kBlock), 0, st,
+    auto final_kernel = !P.final_box_only       ? k_final<T, ST, K, false, 0>
+                        : P.final_cs == kFinalCS ? k_final<T, ST, K, true, kFinalCS>
+                                                 : k_final<T, ST, K, true, 0>;
+    hipLaunchKernelGGL(final_kernel, dim3(P.n_bricks), dim3(kBlock), final_lds_bytes(P), st,
                        (const NodeDev *)P.dev.nodes[P.F], (int)P.compact_to_tree[P.F].size(),
                        (const ColEntry *)P.dev.cols[P.F], (const int32_t *)P.dev.colbase[P.F],
                        (const C *)(ws + P.ws_vals[P.F]), (const TileBox *)P.dev.final_tiles, (const InterpIdx *)P.dev.final_idx,
                        (const InterpGeo *)P.dev.final_geo, P.ipoly_for(P.F), scales, P.scale_slot(P.F), nx, ny,
-                       nz, (float2 *)image);
+                       nz, (int)P.final_box_vals, (float2 *)image);
     hipError_t e = hipGetLastError();
     if (ev && e == hipSuccess) (void)hipEventRecord(*ev, st);
     return e;

@@ -343,6 +343,35 @@ void build_lattice(Plan &P, HostNode &node, const std::vector<double> &parent_al
 // stencils (base floor(gamma w + eps) - T/2 + 1 .. + T/2) of the brick's voxels,
 // widened by one index for rounding (the kernel evaluates w in float64 with a
 // ~2e-14 relative square root) and clipped to the node's columns.
+// The box [lo, hi] (inclusive lattice indices per axis) with its LDS column
+// length and the reciprocals that split a box index.  Exact integer quotients:
+// for x < 2^11 and d < 2^11, x * ceil(2^22 / d) >> 22 errs by < x / 2^22 < 1 / d.
+TileBox make_box(const int32_t *lo, const int32_t *hi)
+{
+    const int32_t ni = hi[0] - lo[0] + 1, nj = hi[1] - lo[1] + 1, nl = hi[2] - lo[2] + 1;
+    int32_t lsh = 0;
+    while ((1 << lsh) < nl) ++lsh;
+    // LDS column stride: the least cs >= nl with cs = 24 (mod 32) float2.  LDS
+    // has 64 four-byte banks, 32 float2; columns j, j + 1, j + 2, j + 3 then
+    // start 0, 24, 16, 8 float2 apart modulo 32, so a wave's lanes, whose
+    // stencils span a few columns and up to ~8 points along n, read disjoint
+    // banks (measured: 0.136 -> 0.132 ms on the large final stage against
+    // 2^lsh + 1).  A box too large at that stride takes 2^lsh + 1.
+    static_assert(kFinalCS == 24, "the stride rule below is cs = 24 (mod 32)");
+    TileBox b{lo[0], lo[1], lo[2], ni, nj, nl, lsh, ((1 << 22) + nj - 1) / nj, ((1 << 22) + nl - 1) / nl,
+              nl + ((kFinalCS - nl) % 32 + 32) % 32};
+    if (b.ni * b.nj * b.cs > kTileCap + kTileCap / 4) b.cs = (1 << lsh) + 1;
+    return b;
+}
+
+// A box the final stage can stage: at most kTileCap values at 2^lsh per column,
+// and its columns at stride cs within the kernel's kTileCap + kTileCap / 4 LDS
+// values.
+bool box_fits(const TileBox &b)
+{
+    return (b.ni * b.nj << b.lsh) <= kTileCap && b.ni * b.nj * b.cs <= kTileCap + kTileCap / 4;
+}
+
 void build_final_tiles(Plan &P)
 {
     const hhffbp_config &c = P.cfg;
@@ -352,7 +381,7 @@ void build_final_tiles(Plan &P)
     const std::vector<int32_t> &d1 = P.compact_to_tree[P.F];
     const int64_t nc = (int64_t)d1.size();
     P.n_bricks = bx * by * bz;
-    P.final_tiles.assign(P.n_bricks * nc, TileBox{0, 0, 0, 0, 0, 0, 0, 0});
+    P.final_tiles.assign(P.n_bricks * nc, TileBox{0, 0, 0, 0, 0, 0, 0, 0, 0, 0});
     P.n_tiled = 0;
     if (!c.final_staging) return;
     std::vector<SubarrayMap> maps;
@@ -383,15 +412,9 @@ void build_final_tiles(Plan &P)
                 hi[0] = std::min(hi[0], L.i0 + L.ni - 1);
                 lo[1] = std::max(lo[1], L.j0);
                 hi[1] = std::min(hi[1], L.j0 + L.nj - 1);
-                const int64_t ni = hi[0] - lo[0] + 1, nj = hi[1] - lo[1] + 1, nl = hi[2] - lo[2] + 1;
-                int32_t lsh = 0;
-                while ((1 << lsh) < nl) ++lsh;
-                if (ni < T || nj < T || nl < T || (ni * nj << lsh) > kTileCap) continue;
-                // exact integer quotient of a column index c < 2^11 by nj < 2^11:
-                // c * ceil(2^22 / nj) >> 22 errs by < c / 2^22 < 1 / nj
-                const int32_t inv_nj = (int32_t)(((1 << 22) + nj - 1) / nj);
-                P.final_tiles[b * nc + ch] =
-                    TileBox{lo[0], lo[1], lo[2], (int32_t)ni, (int32_t)nj, (int32_t)nl, lsh, inv_nj};
+                const TileBox box = make_box(lo, hi);
+                if (box.ni < T || box.nj < T || box.nl < T || !box_fits(box)) continue;
+                P.final_tiles[b * nc + ch] = box;
                 tiled.fetch_add(1);
             }
         }
@@ -862,6 +885,45 @@ void merge_records(const Plan &P, int d, const std::vector<BlockItem> &blocks,
 
 // Records of the final stage: brick b (as the final kernel numbers them), node c
 // of depth F, lane t: voxel (kx 4 + t / 64, ky 4 + (t / 16) mod 4, kz 16 + t mod 16).
+// Each staged box shrunk to the hull of the stencils its (brick, node) records
+// use; a box no record uses is dropped, and one that would exceed kTileCap
+// keeps no box (its lanes gather from the pencils).
+void tighten_final_tiles(Plan &P, const std::vector<InterpIdx> &ridx, int64_t nc)
+{
+    const int T = P.T;
+    std::atomic<int64_t> tiled{0};
+    parallel_for(P.n_bricks * nc, 64, [&](int64_t b0, int64_t b1) {
+        for (int64_t bc = b0; bc < b1; ++bc) {
+            TileBox &tb = P.final_tiles[bc];
+            if (tb.ni <= 0) continue;
+            const HostLattice &Lc = P.levels[P.F][P.compact_to_tree[P.F][bc % nc]].lat;
+            int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+            for (int t = 0; t < kBlockThreads; ++t) {
+                const InterpIdx ix = ridx[(size_t)bc * kBlockThreads + t];
+                if (ix.cij == kNoPair) continue;
+                const int32_t s0[3] = {(int32_t)(ix.cij & 0xffffu) + Lc.i0, (int32_t)(ix.cij >> 16) + Lc.j0,
+                                       ix.l0};
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = std::min(lo[a], s0[a]);
+                    hi[a] = std::max(hi[a], s0[a] + T - 1);
+                }
+            }
+            if (lo[0] > hi[0]) {
+                tb = TileBox{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+                continue;
+            }
+            const TileBox nb = make_box(lo, hi);
+            if (!box_fits(nb)) {
+                tb = TileBox{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+                continue;
+            }
+            tb = nb;
+            tiled.fetch_add(1);
+        }
+    });
+    P.n_tiled = tiled.load();
+}
+
 void final_records(const Plan &P, std::vector<InterpIdx> &idx, std::vector<InterpGeo> &geo)
 {
     const hhffbp_config &c = P.cfg;
@@ -1462,7 +1524,6 @@ void upload_plan(Plan &P)
                 (kp * 16 + 16 * 2 * (size_t)P.fused_win_max) * 4 + 16 * 16 > 65536)
                 throw Error{HHFFBP_E_UNSUPPORTED,
                             "range_fused: the echo rows and profile window exceed 64 KB of LDS"};
-            upload_vec(P.device_bytes, &D.final_tiles, P.final_tiles);
             P.n_blocks_leaf = (int64_t)blocks.size();
             const std::vector<int32_t> order = leaf_block_order(blocks, nodes);
             upload_vec(P.device_bytes, &D.leaf_order, order);
@@ -1482,9 +1543,10 @@ void upload_plan(Plan &P)
         std::vector<InterpIdx> ridx;
         std::vector<InterpGeo> rgeo;
         final_records(P, ridx, rgeo);
+        const int64_t nc = (int64_t)P.compact_to_tree[P.F].size();
+        tighten_final_tiles(P, ridx, nc);
         // every pair's stencil inside its brick's LDS box: the final stage then
         // runs without the pencil path (fewer registers, no per-lane test)
-        const int64_t nc = (int64_t)P.compact_to_tree[P.F].size();
         bool box_only = true;
         for (int64_t bc = 0; box_only && bc < P.n_bricks * nc; ++bc) {
             const TileBox &tb = P.final_tiles[bc];
@@ -1503,6 +1565,17 @@ void upload_plan(Plan &P)
             }
         }
         P.final_box_only = box_only;
+        P.final_cs = -1;
+        P.final_box_vals = P.final_box_cols = 0;
+        for (const TileBox &tb : P.final_tiles) {
+            if (tb.ni <= 0) continue;
+            if (P.final_cs < 0) P.final_cs = tb.cs;
+            if (tb.cs != P.final_cs) P.final_cs = 0;
+            P.final_box_vals = std::max(P.final_box_vals, (int64_t)tb.ni * tb.nj * tb.cs);
+            P.final_box_cols = std::max(P.final_box_cols, (int64_t)tb.ni * tb.nj);
+        }
+        if (P.final_cs < 0) P.final_cs = 0;
+        upload_vec(P.device_bytes, &D.final_tiles, P.final_tiles);
         upload_vec(P.device_bytes, &D.final_idx, ridx);
         upload_vec(P.device_bytes, &D.final_geo, rgeo);
     }
