@@ -74,9 +74,9 @@ LEAF_OPS_ES = 3 + 2 + 3 + 3 + 1 + 3 + 4 + (6 + 2) * 7
 # Algorithmic VALU lane-ops per (point, child) interpolation of a merge or the
 # final stage (T = 4, band-limited weights, geometry from the plan's records):
 # weights 54 (per axis y = x - 1/2, y^2, two 3-FMA Horner chains per tap pair
-# and the even/odd combination), taps 176 (64 x 2 FMA, and per column the
-# weight product and 2 FMA), rotation by the pair's phase 6 (sin, cos, 4 FMA).
-INTERP_OPS_PER_PAIR = 54 + 176 + 6
+# and the even/odd combination), taps 168 (64 x 2 FMA along n, 16 x 2 FMA
+# along v, 4 x 2 FMA along u), rotation by the pair's phase 6 (sin, cos, 4 FMA).
+INTERP_OPS_PER_PAIR = 54 + 168 + 6
 KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "hhffbp_internal.hpp")
 TRAFFIC_SUMMARY = "hhffbp_large_hbm_traffic.md"
 
