@@ -59,6 +59,7 @@ WORKLOAD_NAME = {
 # 157.3 TFLOP/s; vector L1 64 B/clk/CU; HBM 8 TB/s.
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 MFMA_F32_PEAK = 157.3e12
+MFMA_BF16_PEAK = 2.5e15  # dense
 L1_PEAK_BPS = 256 * 64 * 2.4e9
 HBM_PEAK_BPS = 8.0e12
 # Algorithmic VALU lane-ops per (leaf grid point, position) backprojection in
@@ -441,7 +442,7 @@ def imaging_report(args, index):
 
     rec.update(errors(img))
 
-    def roofline_rows(kms, inf, leaf_ops, val_bytes):
+    def roofline_rows(kms, inf, leaf_ops, val_bytes, gemm="split_bf16"):
         """Per-kernel achieved rate against its bound, from the per-stage times."""
         rows = {}
         lms = kms.get("leaf_bp")
@@ -453,10 +454,19 @@ def imaging_report(args, index):
                                "frac": a / VALU_PEAK_OPS}
         rms = kms.get("rc_gemm")
         if rms:
+            # the GEMM's float32 flops; the split-bfloat16 kernel (complex64
+            # storage) executes six bf16 partial products for each, on bf16 MFMA
             fl = 2.0 * w.n_pos * (2 * w.n_f) * (2 * inf["n_range_bins"])
-            rows["rc_gemm"] = {"bound": "mfma", "ms": rms, "flop": fl,
-                               "achieved": fl / (rms * 1e-3) / 1e12, "peak": MFMA_F32_PEAK / 1e12,
-                               "unit": "TFLOP/s", "frac": fl / (rms * 1e-3) / MFMA_F32_PEAK}
+            if gemm == "split_bf16":
+                rows["rc_gemm"] = {"bound": "mfma", "kernel": "split bf16 (6 partial products per f32 product)",
+                                   "ms": rms, "flop": 6 * fl, "achieved": 6 * fl / (rms * 1e-3) / 1e12,
+                                   "peak": MFMA_BF16_PEAK / 1e12, "unit": "TFLOP/s",
+                                   "frac": 6 * fl / (rms * 1e-3) / MFMA_BF16_PEAK,
+                                   "f32_flop_rate": fl / (rms * 1e-3) / 1e12}
+            else:
+                rows["rc_gemm"] = {"bound": "mfma", "kernel": "f32", "ms": rms, "flop": fl,
+                                   "achieved": fl / (rms * 1e-3) / 1e12, "peak": MFMA_F32_PEAK / 1e12,
+                                   "unit": "TFLOP/s", "frac": fl / (rms * 1e-3) / MFMA_F32_PEAK}
         # interpolation kernels: the merges gather through the vector L1 (16
         # column bases of 4 B, 64 taps, the 24-B record per pair), which bounds
         # them; the final stage reads its taps from LDS and is VALU-bound (the
@@ -540,6 +550,16 @@ def imaging_report(args, index):
                                      "work": {k: pl_a.info()[k] for k in ("leaf_pairs", "level_points")},
                                      **errors(img_a)}
     del pl_a, img_a
+    # the same plan with the float32 MFMA range compression
+    pl_g = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, range_gemm="f32", **form)
+    ms_g, k_g, img_g = timed(pl_g, ech, max(3, args.steps // 2), 1)
+    extra["hhffbp_f32_gemm"] = {
+        "value": vp / (ms_g * 1e-3), "ms": ms_g, "kernels_ms": k_g,
+        "mode": "the same plan with the float32 MFMA range-compression GEMM",
+        "rc_gemm_roofline": roofline_rows(k_g, info, LEAF_OPS_LINEAR, 8, gemm="f32").get("rc_gemm"),
+        "nrmse_vs_split_gemm": (torch.linalg.norm(img_g - img) / torch.linalg.norm(img)).item(),
+        **errors(img_g)}
+    del pl_g, img_g
     torch.cuda.empty_cache()
 
     log("direct-BP baselines")

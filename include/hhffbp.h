@@ -85,6 +85,14 @@ enum {
  * degree-7 polynomial in x (error < 1e-6, checked at plan time). */
 enum { HHFFBP_INTERP_LAGRANGE = 0, HHFFBP_INTERP_BANDLIMITED = 1 };
 
+/* Range-compression GEMM (eq. 2) of an image with C64 storage.  SPLIT_BF16:
+ * every float32 operand splits exactly into three bfloat16 parts (8 significant
+ * bits each, remainder <= 2^-27 relative) and the six partial products above
+ * 2^-26 relative, each exact in float32, accumulate in float32 on bf16 MFMA;
+ * the profiles then carry a float32 GEMM's error.  F32: float32 MFMA.  Half
+ * storage, the fused form and hhffbp_backward always take the float32 kernel. */
+enum { HHFFBP_GEMM_SPLIT_BF16 = 0, HHFFBP_GEMM_F32 = 1 };
+
 typedef struct {
     int64_t n_pos;              /* number of antenna positions, >= 1              */
     int64_t n_freq;             /* number of frequency samples, >= 2              */
@@ -142,11 +150,13 @@ typedef struct {
                                    coarser leaf grid trades that one interpolation's
                                    error for level-1 work (Sec. III sampling, Sec.
                                    IV-B operation count).  Factorised plans only.   */
+    int32_t range_gemm;         /* HHFFBP_GEMM_SPLIT_BF16 (the default) or
+                                   HHFFBP_GEMM_F32                                  */
 } hhffbp_config;
 
 /* Fill `cfg` with defaults: FACTORIZED, S = 3, Q = 4, gamma = (3, 3, 3.5), T = 4, ES with
  * U = 2 and W = 7, C64 storage, 5 mm slack, device 0, Lagrange interpolation, final-stage
- * staging on, no root grid, leaf grids at `oversample`.  Pointers and sizes are
+ * staging on, no root grid, leaf grids at `oversample`, the split-bfloat16 GEMM.  Pointers and sizes are
  * zeroed and must be set by the caller. */
 void hhffbp_config_default(hhffbp_config *cfg);
 

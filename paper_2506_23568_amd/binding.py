@@ -18,6 +18,7 @@ MODES = {"factorized": 0, "direct_rc": 1, "direct_exact": 2}
 RANGE_KERNELS = {"es": 0, "linear": 1}
 STORAGE = {"c64": 0, "f16": 1, "bf16": 2}
 INTERP_KERNELS = {"lagrange": 0, "bandlimited": 1}
+RANGE_GEMMS = {"split_bf16": 0, "f32": 1}
 # HHFFBP_NOALLOC_WORKSPACE_BYTES of include/hhffbp.h
 NOALLOC_WORKSPACE_BYTES = 256 << 20
 
@@ -43,6 +44,7 @@ class Config(ctypes.Structure):
         ("interp_kernel", ctypes.c_int32), ("final_staging", ctypes.c_int32),
         ("weights", ctypes.POINTER(ctypes.c_double)), ("root_grid", ctypes.c_int32),
         ("range_fused", ctypes.c_int32), ("oversample_leaf", ctypes.c_double * 3),
+        ("range_gemm", ctypes.c_int32),
     ]
 
 
@@ -144,7 +146,8 @@ class Plan:
                  interp_taps=4,
                  range_kernel="es", range_oversample=2.0, range_taps=7, storage="c64",
                  position_slack=5e-3, device=0, interp_kernel="lagrange", final_staging=True,
-                 weights=None, root_grid=False, range_fused=False, oversample_leaf=None):
+                 weights=None, root_grid=False, range_fused=False, oversample_leaf=None,
+                 range_gemm="split_bf16"):
         L = lib()
         self._pos = np.ascontiguousarray(positions, np.float64)
         self._freqs = np.ascontiguousarray(freqs_hz, np.float64)
@@ -176,6 +179,7 @@ class Plan:
         c.final_staging = 1 if final_staging else 0
         c.root_grid = 1 if root_grid else 0
         c.range_fused = 1 if range_fused else 0
+        c.range_gemm = RANGE_GEMMS[range_gemm] if isinstance(range_gemm, str) else int(range_gemm)
         if oversample_leaf is not None:
             ol = np.broadcast_to(np.asarray(oversample_leaf, float), (3,))
             for a in range(3):

@@ -52,6 +52,7 @@ void hhffbp_config_default(hhffbp_config *cfg)
     cfg->root_grid = 0;
     cfg->range_fused = 0;
     cfg->oversample_leaf[0] = cfg->oversample_leaf[1] = cfg->oversample_leaf[2] = 0.0;
+    cfg->range_gemm = HHFFBP_GEMM_SPLIT_BF16;
 }
 
 hhffbp_status hhffbp_plan(const hhffbp_config *cfg, hhffbp_plan_t *out)

@@ -163,6 +163,7 @@ struct HostNode {
 
 struct DeviceBuffers {
     void *B = nullptr;              // range-compression matrix, float [2 Nf][2 Nr]
+    void *Bx = nullptr;             // the same split for the bf16 GEMM (Plan::Bx), or none
     void *perm = nullptr;           // int32 [n_pos], sorted -> caller index
     void *leaf_of_sorted = nullptr; // int32 [n_pos]
     void *leaf_centre = nullptr;    // double2 [n_leaves]
@@ -219,6 +220,8 @@ struct Plan {
     double U = 2, dR = 0, R0 = 0, beta = 0;
     int64_t Nr = 0;
     std::vector<float> Bmat;  // [2 Nf][2 Nr]
+    std::vector<uint16_t> Bx; // Bmat split into bfloat16 parts in MFMA fragment order (split GEMM)
+    int32_t gemm_nt = 0;      // its 32-column tiles
     std::vector<float> Bdmat; // [2 Nf][2 Nr]
     std::vector<float> Badjmat; // [2 Nr][2 Nf]
     // tree

@@ -317,6 +317,161 @@ inline int gemm_vec(const void *A, int K, const float *B, int N)
 }
 
 // ---------------------------------------------------------------------------
+// Range compression of complex64 echoes on bf16 MFMA at float32 accuracy.
+// Every float32 operand x splits exactly into three bfloat16 parts x = x1 + x2
+// + x3, each rounded to nearest from the remainder (8 significant bits a part,
+// |x - x1 - x2 - x3| <= 2^-27 |x|).  A product a b is then the sum of the six
+// partial products a_i b_j with i + j <= 4 (relative size >= 2^-18; the three
+// left out are below 2^-26), each exact in float32, accumulated in float32 by
+// v_mfma_f32_32x32x16_bf16: the result carries a float32 GEMM's error.  A is
+// read straight from global memory (rows gathered through perm, times the row
+// weight) and split in registers; B comes split from the plan in fragment
+// order, [k16 step][32-column tile][part][lane][8], so a wave loads each of
+// its fragments with one 16-byte load per lane.  A wave covers 64 rows (two
+// 32-row tiles) and CT 32-column tiles; the four waves of a block take
+// consecutive row groups of the same columns, so their B fragments are one set
+// (read once from L2, then from the L1), and the column groups of one row block
+// are consecutive logical blocks on one XCD (its rows of A come from HBM once).
+// Steps alternate between two register sets, each set reloaded for two steps
+// ahead as soon as its step is issued; the MFMAs of a step go product by
+// product over the wave's 2 x CT tiles so consecutive MFMAs are independent.
+// VEC: K % 16 == 0 and 16-byte aligned rows of A, loaded 16 bytes at a time.
+// MFMA operand layout (32 x 32 x 16): lane l holds row (A) or column (B)
+// l mod 32 at k = 8 (l div 32) + e, e < 8; result register r of lane l is row
+// 8 (r div 4) + 4 (l div 32) + r mod 4, column l mod 32.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ void split_bf16x3(const float (&a)[8], bf16x8 &x1, bf16x8 &x2, bf16x8 &x3)
+{
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const __bf16 h = (__bf16)a[e];
+        const float r1 = a[e] - (float)h;
+        const __bf16 m = (__bf16)r1;
+        x1[e] = h;
+        x2[e] = m;
+        x3[e] = (__bf16)(r1 - (float)m);
+    }
+}
+
+template <int CT, bool VEC>
+__global__ __launch_bounds__(kBlock, 2) void k_rc_gemm_x6(const float *__restrict__ A,
+                                                        const int32_t *__restrict__ perm, int M, int K,
+                                                        const bf16x8 *__restrict__ Bx, int NT, int N,
+                                                        float *__restrict__ C,
+                                                        const float *__restrict__ scale,
+                                                        const float *__restrict__ a_w)
+{
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    const int ncg = (NT + CT - 1) / CT;
+    const int lb = xcd_block_run((int)blockIdx.x, (int)gridDim.x, ncg);
+    const int row0 = ((lb / ncg) * (kBlock / 64) + wave) * 64;
+    const int ct0 = (lb % ncg) * CT;  // this wave's first column tile
+    const int kl = 8 * (lane >> 5);                                   // its k offset in a step
+    const float *arow[2];
+    float aw[2];
+    bool aok[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int r = row0 + 32 * a + (lane & 31);
+        aok[a] = r < M;
+        const int src = aok[a] ? (perm ? perm[r] : r) : 0;
+        arow[a] = A + (size_t)src * K;
+        aw[a] = aok[a] ? (a_w ? a_w[src] : 1.0f) : 0.0f;
+    }
+    const int KS = (K + 15) / 16;
+    auto load_a = [&](int ks, float (&dst)[2][8]) {
+        const int k = 16 * ks + kl;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            if (VEC) {  // K % 16 == 0 and 16-byte aligned rows
+                const float4 u = *reinterpret_cast<const float4 *>(arow[a] + k);
+                const float4 v = *reinterpret_cast<const float4 *>(arow[a] + k + 4);
+                dst[a][0] = u.x; dst[a][1] = u.y; dst[a][2] = u.z; dst[a][3] = u.w;
+                dst[a][4] = v.x; dst[a][5] = v.y; dst[a][6] = v.z; dst[a][7] = v.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) dst[a][e] = (k + e < K) ? arow[a][k + e] : 0.0f;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dst[a][e] *= aw[a];
+        }
+    };
+    auto load_b = [&](int ks, bf16x8 (&dst)[CT][3]) {
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int ct = min(ct0 + c, NT - 1);  // a tile past N reads the last one; its columns are not stored
+#pragma unroll
+            for (int q = 0; q < 3; ++q) dst[c][q] = Bx[((size_t)(ks * NT + ct) * 3 + q) * 64 + lane];
+        }
+    };
+    f32x16 acc[2][CT];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][c][r] = 0.0f;
+    // one k step: split A, then the six products, smallest first, over the
+    // wave's 2 x CT tiles ((A part, B part) per product)
+    auto step = [&](const float (&av)[2][8], const bf16x8 (&bv)[CT][3]) {
+        bf16x8 x[2][3];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) split_bf16x3(av[a], x[a][0], x[a][1], x[a][2]);
+        constexpr int pa[6] = {2, 0, 1, 1, 0, 0}, pb[6] = {0, 2, 1, 0, 1, 0};
+#pragma unroll
+        for (int t = 0; t < 6; ++t)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+                    acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[a][pa[t]], bv[c][pb[t]], acc[a][c],
+                                                                        0, 0, 0);
+    };
+    // two register sets, steps alternating between them: a set's loads for
+    // step ks + 2 are issued right after its step ks, so they are in flight
+    // during the other set's step (the scheduling barriers keep the compiler
+    // from moving them next to their use)
+    float a0[2][8], a1[2][8];
+    bf16x8 b0[CT][3], b1[CT][3];
+    load_a(0, a0);
+    load_b(0, b0);
+    if (KS > 1) {
+        load_a(1, a1);
+        load_b(1, b1);
+    }
+    for (int ks = 0; ks < KS; ks += 2) {
+        __builtin_amdgcn_sched_barrier(0);
+        step(a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (ks + 2 < KS) {
+            load_a(ks + 2, a0);
+            load_b(ks + 2, b0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (ks + 1 < KS) step(a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+        if (ks + 3 < KS) {
+            load_a(ks + 3, a1);
+            load_b(ks + 3, b1);
+        }
+    }
+    const float sc = scale ? scale[0] : 1.0f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int col = 32 * (ct0 + c) + (lane & 31);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = row0 + 32 * a + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (row < M && col < N) C[(size_t)row * N + col] = acc[a][c][r] * sc;
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
 // Level-1 BP.  One lane per leaf grid point q; the leaf's positions are staged
 // through LDS in chunks together with their range profiles (leaf-sorted, so a
 // chunk's profiles are one contiguous block, widened to float32 on staging).
@@ -1176,12 +1331,24 @@ hhffbp_status image_for_storage(const Plan &P, const void *echoes, const double 
     }
     {
         const int M = n, K = (int)(2 * c.n_freq), N = (int)(2 * P.Nr);
-        dim3 grid(((M + 63) / 64) * ((N + 63) / 64));
-        hipLaunchKernelGGL((k_rc_gemm<ST, ST>), grid, dim3(kBlock), 0, st,
-                           (const typename Store<ST>::R *)echoes, (const int32_t *)P.dev.perm, M, K,
-                           (const float *)P.dev.B, N, (typename Store<ST>::R *)prof,
-                           (const int32_t *)nullptr, scales, gemm_vec(echoes, K, (const float *)P.dev.B, N),
-                           (const float *)P.dev.weights, (const float *)nullptr);
+        if (ST == HHFFBP_C64 && P.dev.Bx) {
+            constexpr int CT = 3;
+            const int NT = P.gemm_nt, rows_per_block = (kBlock / 64) * 64;
+            const bool vec = K % 16 == 0 && reinterpret_cast<uintptr_t>(echoes) % 16 == 0;
+            auto kern = vec ? k_rc_gemm_x6<CT, true> : k_rc_gemm_x6<CT, false>;
+            hipLaunchKernelGGL(kern, dim3(((M + rows_per_block - 1) / rows_per_block) * ((NT + CT - 1) / CT)),
+                               dim3(kBlock), 0, st,
+                               (const float *)echoes, (const int32_t *)P.dev.perm, M, K,
+                               (const bf16x8 *)P.dev.Bx, NT, N, (float *)prof, scales,
+                               (const float *)P.dev.weights);
+        } else {
+            dim3 grid(((M + 63) / 64) * ((N + 63) / 64));
+            hipLaunchKernelGGL((k_rc_gemm<ST, ST>), grid, dim3(kBlock), 0, st,
+                               (const typename Store<ST>::R *)echoes, (const int32_t *)P.dev.perm, M, K,
+                               (const float *)P.dev.B, N, (typename Store<ST>::R *)prof,
+                               (const int32_t *)nullptr, scales, gemm_vec(echoes, K, (const float *)P.dev.B, N),
+                               (const float *)P.dev.weights, (const float *)nullptr);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return HHFFBP_E_DEVICE;
         if (ev) (void)hipEventRecord(*ev++, st);
     }

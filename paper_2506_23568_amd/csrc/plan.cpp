@@ -529,6 +529,50 @@ double linear_hat(double theta)
 }
 
 // Range window and the pre-corrected DFT matrix of eq. (2) onto it.
+
+// bfloat16 of x, rounded to nearest even (finite x), and back.
+uint16_t bf16_rne(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+float bf16_value(uint16_t h)
+{
+    const uint32_t u = (uint32_t)h << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+
+// The range-compression matrix for the split-bfloat16 GEMM: each entry split
+// into three bfloat16 parts (x1 = rne(x), x2 = rne(x - x1), x3 = rne(x - x1 -
+// x2)), in MFMA fragment order [k16 step][32-column tile][part][lane][8]: lane
+// l holds column 32 tile + l mod 32 at k = 16 step + 8 (l div 32) + e, rows past
+// K zero.
+void split_gemm_matrix(Plan &P, int K, int N)
+{
+    const int KS = (K + 15) / 16, NT = N / 32;
+    P.gemm_nt = NT;
+    P.Bx.assign((size_t)KS * NT * 3 * 64 * 8, 0);
+    for (int ks = 0; ks < KS; ++ks)
+        for (int ct = 0; ct < NT; ++ct)
+            for (int l = 0; l < 64; ++l)
+                for (int e = 0; e < 8; ++e) {
+                    const int k = 16 * ks + 8 * (l >> 5) + e, n = 32 * ct + (l & 31);
+                    const float x = k < K ? P.Bmat[(size_t)k * N + n] : 0.0f;
+                    const uint16_t h1 = bf16_rne(x);
+                    const float r1 = x - bf16_value(h1);
+                    const uint16_t h2 = bf16_rne(r1);
+                    const uint16_t h3 = bf16_rne(r1 - bf16_value(h2));
+                    const uint16_t h[3] = {h1, h2, h3};
+                    for (int q = 0; q < 3; ++q)
+                        P.Bx[((((size_t)ks * NT + ct) * 3 + q) * 64 + l) * 8 + e] = h[q];
+                }
+}
+
 void range_setup(Plan &P, double rmin, double rmax)
 {
     const double dk = P.kmax - P.kmin;
@@ -569,6 +613,8 @@ void range_setup(Plan &P, double rmin, double rmax)
             put(P.Badjmat, 2 * nf, r, f, wr, -wi);
         }
     }
+    if (P.cfg.storage == HHFFBP_C64 && P.cfg.range_gemm == HHFFBP_GEMM_SPLIT_BF16 && !P.cfg.range_fused)
+        split_gemm_matrix(P, (int)(2 * nf), (int)(2 * nr));
 }
 
 // ---- band-limited interpolation weights -----------------------------------
@@ -762,6 +808,8 @@ void validate(const hhffbp_config &c)
     if ((c.oversample_leaf[0] != 0.0 || c.oversample_leaf[1] != 0.0 || c.oversample_leaf[2] != 0.0) &&
         (c.oversample_leaf[0] == 0.0 || c.oversample_leaf[1] == 0.0 || c.oversample_leaf[2] == 0.0))
         bad("oversample_leaf: set all three axes or none");
+    if (c.range_gemm != HHFFBP_GEMM_SPLIT_BF16 && c.range_gemm != HHFFBP_GEMM_F32)
+        bad("range_gemm must be HHFFBP_GEMM_SPLIT_BF16 or HHFFBP_GEMM_F32");
     if (c.grid_dims[0] * c.grid_dims[1] * c.grid_dims[2] > ((int64_t)1 << 31))
         bad("grid too large");
     if (c.mode != HHFFBP_FACTORIZED && c.mode != HHFFBP_DIRECT_RC && c.mode != HHFFBP_DIRECT_EXACT)
@@ -1337,6 +1385,7 @@ void upload_plan(Plan &P)
         throw Error{HHFFBP_E_DEVICE, "hipSetDevice failed"};
     DeviceBuffers &D = P.dev;
     upload_vec(P.device_bytes, &D.B, P.Bmat);
+    if (!P.Bx.empty()) upload_vec(P.device_bytes, &D.Bx, P.Bx);
     upload_vec(P.device_bytes, &D.Bd, P.Bdmat);
     upload_vec(P.device_bytes, &D.Badj, P.Badjmat);
     upload_vec(P.device_bytes, &D.scale_mult, P.scale_mult);
@@ -1605,6 +1654,7 @@ void release_plan(Plan &P)
         p = nullptr;
     };
     fr(D.B);
+    fr(D.Bx);
     fr(D.perm);
     fr(D.leaf_of_sorted);
     fr(D.leaf_centre);

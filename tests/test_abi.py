@@ -63,6 +63,7 @@ def test_config_default_layout():
     assert c.range_oversample == 2.0 and abs(c.position_slack - 5e-3) < 1e-15
     assert (c.interp_kernel, c.final_staging, c.root_grid, c.range_fused) == (0, 1, 0, 0)
     assert list(c.oversample_leaf) == [0.0, 0.0, 0.0]
+    assert c.range_gemm == H.binding.RANGE_GEMMS["split_bf16"] == 0
 
 
 def test_final_stage_bricks(small):
@@ -90,6 +91,7 @@ def _args(w):
     (dict(range_fused=True, range_kernel="linear", mode="direct_rc"), -1),
     (dict(oversample_leaf=0.5), -1), (dict(oversample_leaf=(2.0, 0.0, 2.0)), -1),
     (dict(oversample_leaf=9.0), -1),
+    (dict(range_gemm=2), -1), (dict(range_gemm=-1), -1),
 ])
 def test_invalid_configurations_are_rejected(small, change, status):
     kw = dict(device=-1)
