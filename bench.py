@@ -515,7 +515,7 @@ def imaging_report(args, index):
     log("parity mode (ES range kernel), half storage and the S = 3 voxel-root form")
     extra = {}
     pl_es = H.Plan(*args3, range_kernel="es", range_oversample=2.0, range_taps=7, **form)
-    ms_es, k_es, img_es = timed(pl_es, ech, max(3, args.steps // 2), 1)
+    ms_es, k_es, img_es = timed(pl_es, ech, max(3, args.steps // 2), args.warmup)
     extra["hhffbp_es"] = {"value": vp / (ms_es * 1e-3), "ms": ms_es, "kernels_ms": k_es,
                           "mode": "ES U=2 W=7 (parity mode), same grids",
                           "leaf_bp_roofline": roofline_rows(k_es, info, LEAF_OPS_ES, 8).get("leaf_bp"),
@@ -524,7 +524,7 @@ def imaging_report(args, index):
     for st in ("f16", "bf16"):
         pl_h = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, storage=st, **form)
         eh = H.Plan.pack_echoes(ech, st)
-        ms_h, k_h, img_h = timed(pl_h, eh, max(3, args.steps // 2), 1)
+        ms_h, k_h, img_h = timed(pl_h, eh, max(3, args.steps // 2), args.warmup)
         extra[f"hhffbp_{st}"] = {
             "value": vp / (ms_h * 1e-3), "ms": ms_h, "kernels_ms": k_h,
             "mode": f"{st} storage of echoes, profiles and subimages, f32 arithmetic",
@@ -533,7 +533,7 @@ def imaging_report(args, index):
         del pl_h, eh, img_h
     # the fused range compression + level-1 BP (one kernel, profiles in LDS)
     pl_f = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, range_fused=True, **form)
-    ms_f, k_f, img_f = timed(pl_f, ech, max(3, args.steps // 2), 1)
+    ms_f, k_f, img_f = timed(pl_f, ech, max(3, args.steps // 2), args.warmup)
     extra["hhffbp_fused"] = {
         "value": vp / (ms_f * 1e-3), "ms": ms_f, "kernels_ms": k_f,
         "mode": "range compression fused into the level-1 BP (range_fused), same plan",
@@ -543,7 +543,7 @@ def imaging_report(args, index):
     # the same plan with uniform grids (leaf grids at the other grids' oversampling)
     alt = dict(form, oversample_leaf=None)
     pl_a = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, **alt)
-    ms_a, k_a, img_a = timed(pl_a, ech, max(3, args.steps // 2), 1)
+    ms_a, k_a, img_a = timed(pl_a, ech, max(3, args.steps // 2), args.warmup)
     extra["hhffbp_uniform_grids"] = {"value": vp / (ms_a * 1e-3), "ms": ms_a, "kernels_ms": k_a,
                                      "mode": f"the same plan with every grid at {list(BL_GAMMA)} "
                                              f"(S={alt['stages']}, root grid {alt['root_grid']})",
@@ -552,7 +552,7 @@ def imaging_report(args, index):
     del pl_a, img_a
     # the same plan with the float32 MFMA range compression
     pl_g = H.Plan(*args3, range_kernel="linear", range_oversample=BENCH_U, range_gemm="f32", **form)
-    ms_g, k_g, img_g = timed(pl_g, ech, max(3, args.steps // 2), 1)
+    ms_g, k_g, img_g = timed(pl_g, ech, max(3, args.steps // 2), args.warmup)
     extra["hhffbp_f32_gemm"] = {
         "value": vp / (ms_g * 1e-3), "ms": ms_g, "kernels_ms": k_g,
         "mode": "the same plan with the float32 MFMA range-compression GEMM",
