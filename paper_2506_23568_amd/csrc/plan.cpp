@@ -1642,6 +1642,8 @@ void upload_plan(Plan &P)
             hipStreamSynchronize(nullptr) != hipSuccess)
             throw Error{HHFFBP_E_DEVICE, "position offsets failed during plan upload"};
     }
+    if (prepare_forward(P) != hipSuccess)
+        throw Error{HHFFBP_E_DEVICE, "split GEMM LDS opt-in failed"};
     if (prepare_backward(P) != hipSuccess)
         throw Error{HHFFBP_E_DEVICE, "setting the level-1 adjoint's LDS limit failed"};
 }
