@@ -171,13 +171,19 @@ def oracle_cpu_baseline(w, index, target_s=12.0):
 
 
 def kernel_source_hash():
-    """sha256 over the sources that make up the imaging kernels."""
+    """sha256 over the code of the sources that make up the imaging kernels:
+    comments and whitespace are left out, so that editing a comment does not
+    discard the measured traffic of unchanged code."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2506_23568_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2506_23568_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

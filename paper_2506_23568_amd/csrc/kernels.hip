@@ -2,7 +2,10 @@
 //
 //   k_prep_positions  antenna offsets from their leaf centre (float64 -> float32)
 //   k_absmax, k_scales  per-call power-of-two scales for half-precision storage
-//   k_rc_gemm         range compression, eq. (2): profiles = echoes x W on MFMA
+//   k_rc_gemm         range compression, eq. (2): profiles = echoes x W on float32 MFMA
+//   k_rc_gemm_x6_dma  the same for complex64 echoes as exact bfloat16 splits on bf16
+//                     MFMA (float32 accuracy), operands through LDS by direct loads;
+//                     k_rc_gemm_x6 its register form
 //   k_leaf_bp         level-1 BP onto each leaf grid + SDC (Sec. IV-A, eq. sdc_mul)
 //   k_merge           interpolate compressed children onto a parent grid, undo
 //                     their SDC, sum, compress with the parent's Phi (Sec. IV-A)
