@@ -6,11 +6,11 @@ partial product above 2^-26, so both GEMMs carry float32 accumulation error:
 images formed from either set of profiles differ by NRMSE <= 1e-6 and by no single
 value above 5e-5 of the RMS (the parity tests' per-value rule: a bright target's
 peak stands far above the RMS, and float32 rounding there is ~1e-7 of the peak),
-and direct BP on the split profiles stays within the
-same 1e-5 of eq. (4) as the float32 ones (ES range kernel, W = 7, U = 2).  The
-ragged case takes 13 frequencies (K = 26 reals, not a multiple of the 16-deep MFMA
-step: the unaligned load path) and 1000 positions (not a multiple of the 64-row
-tile)."""
+and direct BP on the split profiles stays within the same 1e-5 of eq. (4) as the
+float32 ones (ES range kernel, W = 7, U = 2).  The ragged case takes 13
+frequencies (K = 26 reals, not a multiple of the 16-deep MFMA step: the register
+form) and 1000 positions (not a multiple of the 64-row tile); the direct-load form
+(K a multiple of 16) runs with ragged rows and with one and two k steps."""
 import numpy as np
 import pytest
 
@@ -102,3 +102,21 @@ def test_split_gemm_hhffbpa_mid(torch):
     _compare(torch, w.positions, w.freqs_hz, w.echoes, w, stages=3, merge_factor=4, interp_taps=4,
              interp_kernel="bandlimited", oversample=(2.2, 2.2, 2.6), oversample_leaf=(1.8, 1.8, 2.2),
              range_kernel="linear", range_oversample=4.0)
+
+
+@pytest.mark.parametrize("n_pos,n_f", [(1000, 32), (300, 8), (777, 16)])
+def test_split_gemm_direct_load_edges(torch, small, n_pos, n_f):
+    """The direct-load form (K % 16 == 0): a row count that is not a multiple of
+    the block's 256 rows, and K of one and two 16-deep steps (the ring's
+    prologue and last-step waits)."""
+    from oracle import hhffbp as OH
+    from workloads import voxel_centres
+    pos, freqs = small.positions[:n_pos], small.freqs_hz[:n_f]
+    echoes = small.echoes[:n_pos, :n_f]
+    _say(f"direct_rc, {n_pos} positions x {n_f} frequencies (K = {2 * n_f}): split vs float32 GEMM, eq. (4)")
+    imgs = _compare(torch, pos, freqs, echoes, small, mode="direct_rc")
+    vox = voxel_centres(small.grid_origin, small.grid_pitch, small.grid_dims)
+    ref = OH.direct_bp(pos, freqs, echoes, vox).reshape(small.grid_dims)
+    e = _nrmse(imgs["split_bf16"], ref)
+    _say(f"  split GEMM direct BP vs eq. (4): {e:.2e}")
+    assert e <= 1e-5
