@@ -933,17 +933,18 @@ void merge_records(const Plan &P, int d, const std::vector<BlockItem> &blocks,
 
 // Records of the final stage: brick b (as the final kernel numbers them), node c
 // of depth F, lane t: voxel (kx 4 + t / 64, ky 4 + (t / 16) mod 4, kz 16 + t mod 16).
-// Each staged box shrunk to the hull of the stencils its (brick, node) records
-// use; a box no record uses is dropped, and one that would exceed kTileCap
-// keeps no box (its lanes gather from the pencils).
+// With final-stage staging on, every (brick, node) box becomes the hull of the
+// stencils its records use (also where the margin box was too large to stage);
+// a box no record uses is dropped, and one that would exceed kTileCap keeps no
+// box (its lanes gather from the pencils).
 void tighten_final_tiles(Plan &P, const std::vector<InterpIdx> &ridx, int64_t nc)
 {
+    if (!P.cfg.final_staging) return;
     const int T = P.T;
     std::atomic<int64_t> tiled{0};
     parallel_for(P.n_bricks * nc, 64, [&](int64_t b0, int64_t b1) {
         for (int64_t bc = b0; bc < b1; ++bc) {
             TileBox &tb = P.final_tiles[bc];
-            if (tb.ni <= 0) continue;
             const HostLattice &Lc = P.levels[P.F][P.compact_to_tree[P.F][bc % nc]].lat;
             int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
             for (int t = 0; t < kBlockThreads; ++t) {
