@@ -1010,13 +1010,14 @@ void final_records(const Plan &P, std::vector<InterpIdx> &idx, std::vector<Inter
 // interpolation error.  With stages = -K the plan takes the S in 1..K that
 // minimises that count on each candidate's exact pair counts (the range
 // compression term does not depend on S), with per-pair costs measured on
-// MI355X with this build (mid and large workloads, complex64): level-1 BP
-// 0.85 ps (linear range kernel) or 2.3 ps (ES); interpolation per (point,
-// child) pair, merges and final stage alike, 23 ps (T = 4) or 55 ps (T = 6).
+// MI355X with this build (large workload, S = 4 with a root grid, band-limited
+// weights, complex64): level-1 BP 0.71 ps (linear range kernel) or 2.24 ps (ES);
+// interpolation per (point, child) pair, merges and final stage alike, 20.2 ps
+// (T = 4) or 56.6 ps (T = 6).
 double model_seconds(const Plan &P)
 {
-    const double c2 = (P.kernel == HHFFBP_RANGE_ES) ? 2.3e-12 : 0.85e-12;
-    const double c3 = (P.T == 4) ? 23e-12 : 55e-12;
+    const double c2 = (P.kernel == HHFFBP_RANGE_ES) ? 2.24e-12 : 0.71e-12;
+    const double c3 = (P.T == 4) ? 20.2e-12 : 56.6e-12;
     return c2 * (double)P.leaf_pairs + c3 * (double)(P.merge_pairs + P.final_pairs);
 }
 
