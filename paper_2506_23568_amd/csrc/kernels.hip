@@ -478,17 +478,22 @@ __global__ __launch_bounds__(kBlock, 2) void k_rc_gemm_x6(const float *__restric
 // LDS stages by direct global-to-LDS loads (global_load_lds_dwordx4: each lane's
 // 16 bytes land at the wave-uniform LDS address + 16 x lane, with no registers
 // held while they are in flight), so two k steps are in flight while one is
-// computed.  A stage holds each wave's 64 rows of A for one k step (4 loads of
-// 1 KB: load (a, h), lane l -> row 32 a + l mod 32, k 8 h + 4 (l div 32) .. +3;
-// the MFMA operand of lane L is then the 32 bytes at loads (a, L div 32), lanes
-// L mod 32 and L mod 32 + 32) and the block's 9 B fragments (1 KB each; waves
-// 1-3 also load a tenth, discarded, so every wave issues 7 loads a step).  Per
-// step: wait for this wave's loads of the step, a barrier (everyone's loads
-// of the step have landed and the previous step's stage is free), the loads of
-// the step two ahead into that stage, then the fragments from LDS, the split
-// and the 36 MFMAs.  Needs K % 16 == 0 and 16-byte aligned rows of A.
+// computed.  A block of kX6Waves waves covers 32 kX6Waves rows, each wave 32
+// rows and the block's 3 column tiles (104 VGPRs: four waves per SIMD).  A stage
+// holds each wave's rows of A for one k step (2 loads of 1 KB: load h, lane l ->
+// row l mod 32, k 8 h + 4 (l div 32) .. +3; the MFMA operand of lane L is then
+// the 32 bytes at load L div 32, lanes L mod 32 and L mod 32 + 32) and the
+// block's 9 B fragments (1 KB each: wave 0 loads two, waves 1-7 one and a
+// discarded tenth, so every wave issues 4 loads a step).  Per step: wait for
+// this wave's loads of the step, a barrier (everyone's loads of the step have
+// landed and the previous step's stage is free), the loads of the step two
+// ahead into that stage, then the fragments from LDS, the split and the 18
+// MFMAs.  Needs K % 16 == 0 and 16-byte aligned rows of A.
 constexpr int kX6Stages = 3;
-constexpr int kX6StageBytes = (kBlock / 64) * 4096 + 10 * 1024;
+constexpr int kX6Waves = 8;  // 32 rows of A each
+// two B fragment loads per wave cover the 9 fragments (and a discarded tenth)
+static_assert(kX6Waves >= 5 && kX6Waves <= 9, "B fragments per wave");
+constexpr int kX6StageBytes = kX6Waves * 2048 + 10 * 1024;
 constexpr int kX6LdsBytes = kX6Stages * kX6StageBytes;
 
 // 16 bytes per lane from global memory to LDS address lds + 16 x lane (lds
@@ -503,118 +508,98 @@ __device__ __forceinline__ void dma16(const void *g, uint32_t lds)
                  : "memory", "m0");
 }
 
-__global__ __launch_bounds__(kBlock, 2) void k_rc_gemm_x6_dma(const float *__restrict__ A,
+__global__ __launch_bounds__(64 * kX6Waves, 2) void k_rc_gemm_x6_dma(const float *__restrict__ A,
                                                             const int32_t *__restrict__ perm, int M, int K,
                                                             const bf16x8 *__restrict__ Bx, int NT, int N,
                                                             float *__restrict__ C,
                                                             const float *__restrict__ scale,
                                                             const float *__restrict__ a_w)
 {
-    constexpr int CT = 3;  // 32-column tiles per wave: 9 B fragments a step
+    constexpr int CT = 3;
     extern __shared__ __align__(16) unsigned char lds[];
     const int lane = (int)(threadIdx.x & 63);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char *)lds;
     const int ncg = (NT + CT - 1) / CT;
     const int lb = xcd_block_run((int)blockIdx.x, (int)gridDim.x, ncg);
-    const int row0 = ((lb / ncg) * (kBlock / 64) + wave) * 64;
+    const int row0 = ((lb / ncg) * kX6Waves + wave) * 32;
     const int ct0 = (lb % ncg) * CT;
     const int KS = K / 16;
-    const float *asrc[2];
-    float aw[2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const int r = row0 + 32 * a + (lane & 31);
+    const float *asrc;
+    float aw;
+    {
+        const int r = row0 + (lane & 31);
         const bool ok = r < M;
-        const int src = ok ? (perm ? perm[r] : r) : 0;  // a row past M loads row 0, weighted 0
-        asrc[a] = A + (size_t)src * K + 4 * (lane >> 5);
-        aw[a] = ok ? (a_w ? a_w[src] : 1.0f) : 0.0f;
+        const int src = ok ? (perm ? perm[r] : r) : 0;
+        asrc = A + (size_t)src * K + 4 * (lane >> 5);
+        aw = ok ? (a_w ? a_w[src] : 1.0f) : 0.0f;
     }
-    const bf16x8 *bsrc[3];
-    int bslot[3];
+    const bf16x8 *bsrc[2];
+    int bslot[2];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const int f = wave + 4 * i, ff = f < 3 * CT ? f : 0;
+    for (int i = 0; i < 2; ++i) {
+        const int f = wave + kX6Waves * i, ff = f < 3 * CT ? f : 0;
         bslot[i] = f < 3 * CT ? f : 3 * CT;
         bsrc[i] = Bx + ((size_t)min(ct0 + ff / 3, NT - 1) * 3 + ff % 3) * 64 + lane;
     }
-    // the row permutation and weights have arrived before the first direct load,
-    // so that no wait for them lands inside the loop (where it would also drain
-    // the loads in flight)
-    __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
+    __builtin_amdgcn_s_waitcnt(0xF70);
     auto issue = [&](int ks) {
         const uint32_t st = lds0 + (uint32_t)((ks % kX6Stages) * kX6StageBytes);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int h = 0; h < 2; ++h) dma16(asrc + 16 * ks + 8 * h, st + wave * 2048 + h * 1024);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) dma16(asrc[a] + 16 * ks + 8 * h, st + wave * 4096 + (2 * a + h) * 1024);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-            dma16(bsrc[i] + (size_t)ks * NT * 3 * 64, st + (kBlock / 64) * 4096 + bslot[i] * 1024);
+        for (int i = 0; i < 2; ++i)
+            dma16(bsrc[i] + (size_t)ks * NT * 3 * 64, st + kX6Waves * 2048 + bslot[i] * 1024);
     };
-    f32x16 acc[2][CT];
+    f32x16 acc[CT];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < CT; ++c)
 #pragma unroll
-        for (int c = 0; c < CT; ++c)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[a][c][r] = 0.0f;
+        for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
 #pragma unroll
     for (int s = 0; s < kX6Stages - 1; ++s)
         if (s < KS) issue(s);
     for (int ks = 0; ks < KS; ++ks) {
-        // this wave's loads of step ks are done once only the next step's (7) remain
         if (ks + 1 < KS)
-            __builtin_amdgcn_s_waitcnt(0xF70 | 7);  // vmcnt(7), lgkmcnt and expcnt not waited for
+            __builtin_amdgcn_s_waitcnt(0xF70 | 4);  // vmcnt(4): the next step's loads may remain
         else
-            __builtin_amdgcn_s_waitcnt(0xF70);      // vmcnt(0)
+            __builtin_amdgcn_s_waitcnt(0xF70);
         __syncthreads();
         if (ks + kX6Stages - 1 < KS) issue(ks + kX6Stages - 1);
         const unsigned char *st = lds + (ks % kX6Stages) * kX6StageBytes;
-        float av[2][8];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const unsigned char *pa = st + wave * 4096 + (2 * a + (lane >> 5)) * 1024 + (lane & 31) * 16;
+        float av[8];
+        {
+            const unsigned char *pa = st + wave * 2048 + (lane >> 5) * 1024 + (lane & 31) * 16;
             const float4 u = *reinterpret_cast<const float4 *>(pa);
             const float4 v = *reinterpret_cast<const float4 *>(pa + 512);
-            av[a][0] = u.x * aw[a]; av[a][1] = u.y * aw[a]; av[a][2] = u.z * aw[a]; av[a][3] = u.w * aw[a];
-            av[a][4] = v.x * aw[a]; av[a][5] = v.y * aw[a]; av[a][6] = v.z * aw[a]; av[a][7] = v.w * aw[a];
+            av[0] = u.x * aw; av[1] = u.y * aw; av[2] = u.z * aw; av[3] = u.w * aw;
+            av[4] = v.x * aw; av[5] = v.y * aw; av[6] = v.z * aw; av[7] = v.w * aw;
         }
         bf16x8 bv[CT][3];
 #pragma unroll
         for (int c = 0; c < CT; ++c)
 #pragma unroll
             for (int q = 0; q < 3; ++q)
-                bv[c][q] = *reinterpret_cast<const bf16x8 *>(st + (kBlock / 64) * 4096 + (3 * c + q) * 1024 +
-                                                             lane * 16);
-        bf16x8 x[2][3];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) split_bf16x3(av[a], x[a][0], x[a][1], x[a][2]);
-        // products by the A part they need, high part first, so that the
-        // lower parts' split can overlap the first MFMAs (the order within a
-        // step does not matter for accuracy: each adds into the running sum)
+                bv[c][q] = *reinterpret_cast<const bf16x8 *>(st + kX6Waves * 2048 + (3 * c + q) * 1024 + lane * 16);
+        bf16x8 x[3];
+        split_bf16x3(av, x[0], x[1], x[2]);
         constexpr int pa_[6] = {0, 0, 1, 0, 1, 2}, pb_[6] = {0, 1, 0, 2, 1, 0};
 #pragma unroll
         for (int t = 0; t < 6; ++t)
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int c = 0; c < CT; ++c)
-                    acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[a][pa_[t]], bv[c][pb_[t]], acc[a][c],
-                                                                        0, 0, 0);
+            for (int c = 0; c < CT; ++c)
+                acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[pa_[t]], bv[c][pb_[t]], acc[c], 0, 0, 0);
     }
     const float sc = scale ? scale[0] : 1.0f;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < CT; ++c) {
+        const int col = 32 * (ct0 + c) + (lane & 31);
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
-            const int col = 32 * (ct0 + c) + (lane & 31);
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = row0 + 32 * a + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (row < M && col < N) C[(size_t)row * N + col] = acc[a][c][r] * sc;
-            }
+        for (int r = 0; r < 16; ++r) {
+            const int row = row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            if (row < M && col < N) C[(size_t)row * N + col] = acc[c][r] * sc;
         }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1483,7 +1468,9 @@ hhffbp_status image_for_storage(const Plan &P, const void *echoes, const double 
             const bool vec = K % 16 == 0 && reinterpret_cast<uintptr_t>(echoes) % 16 == 0;
             const dim3 grid(((M + rows_per_block - 1) / rows_per_block) * ((NT + CT - 1) / CT));
             if (vec && P.gemm_dma) {
-                hipLaunchKernelGGL(k_rc_gemm_x6_dma, grid, dim3(kBlock), kX6LdsBytes, st, (const float *)echoes,
+                const dim3 grid_dma(((M + 32 * kX6Waves - 1) / (32 * kX6Waves)) * ((NT + CT - 1) / CT));
+                hipLaunchKernelGGL(k_rc_gemm_x6_dma, grid_dma, dim3(64 * kX6Waves), kX6LdsBytes, st,
+                                   (const float *)echoes,
                                    (const int32_t *)P.dev.perm, M, K, (const bf16x8 *)P.dev.Bx, NT, N,
                                    (float *)prof, scales, (const float *)P.dev.weights);
             } else {
