@@ -640,6 +640,10 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
     const int chunk = leaf_chunk(nrb);
     const int i_first = (int)threadIdx.x / nrb, t_first = (int)threadIdx.x % nrb;
     const int di = kBlock / nrb, dt = kBlock % nrb;
+    // complex64: the same two bins at a time (nrb even, see below)
+    const int nrb2 = nrb >> 1;
+    const int i2_first = (int)threadIdx.x / nrb2, t2_first = (int)threadIdx.x % nrb2;
+    const int di2 = kBlock / nrb2, dt2 = kBlock % nrb2;
     float4 *s_pos = reinterpret_cast<float4 *>(smem);
     float2 *s_prof = reinterpret_cast<float2 *>(smem + chunk * sizeof(float4));
     const NodeDev nd = leaves[blk.node];
@@ -659,7 +663,39 @@ __global__ __launch_bounds__(kBlock) void k_leaf_bp(const NodeDev *__restrict__ 
         __syncthreads();
         for (int t = threadIdx.x; t < n; t += kBlock) s_pos[t] = posoff[c0 + t];
         const typename Store<ST>::C *src = prof + (size_t)c0 * Nr + r0;
-        {
+        if constexpr (ST == HHFFBP_C64) {
+            // the n x nrb tile two bins at a time: the plan makes r0 and nrb even
+            // (and Nr is even), so each pair is 16 aligned bytes at both ends;
+            // pair e = i nrb/2 + t, thread-strided, (i, t) advanced without a
+            // division as below
+            const int row2 = Nr >> 1, total = n * nrb2;
+            const float4 *src4 = reinterpret_cast<const float4 *>(src);
+            float4 *dst4 = reinterpret_cast<float4 *>(s_prof);
+            int i = i2_first, t = t2_first;
+            constexpr int kSteps2 = (kStageSteps + 1) / 2;
+            float4 v[kSteps2];
+#pragma unroll
+            for (int k = 0; k < kSteps2; ++k) {
+                const bool in = k * kBlock + (int)threadIdx.x < total;
+                v[k] = src4[in ? i * row2 + t : 0];
+                i += di2;
+                t += dt2;
+                if (t >= nrb2) {
+                    t -= nrb2;
+                    ++i;
+                }
+            }
+            // a step past the tile loaded pair 0 and stores it back there (the same
+            // value the pair's own thread stores): the stores stay unconditional,
+            // so the compiler keeps the loads together
+#pragma unroll
+            for (int k = 0; k < kSteps2; ++k) {
+                const int e = k * kBlock + (int)threadIdx.x;
+                dst4[e < total ? e : 0] = v[k];
+            }
+            for (int e = kSteps2 * kBlock + threadIdx.x; e < total; e += kBlock)
+                dst4[e] = src4[(size_t)(e / nrb2) * row2 + e % nrb2];
+        } else {
             // the n x nrb tile, element e = i nrb + t, thread-strided; (i, t) of e
             // advances by (di, dt) per step, so no division in the loop, and the
             // unrolled steps issue their loads together

@@ -1521,7 +1521,14 @@ void upload_plan(Plan &P)
                     }
                     return BinWindow{blo, bhi - blo + 1};
                 };
-                for (int32_t st = 0; st < nd.npts; st += 256) wins.push_back(window(st, 256));
+                // level-1 windows start at an even bin and span an even count (a
+                // superset; Nr is even, so it stays within the profile): the kernel
+                // stages complex64 bins two at a time in 16-byte loads
+                for (int32_t st = 0; st < nd.npts; st += 256) {
+                    BinWindow wv = window(st, 256);
+                    const int32_t lo2 = wv.lo & ~1, hi2 = (wv.lo + wv.n - 1) | 1;
+                    wins.push_back(BinWindow{lo2, hi2 - lo2 + 1});
+                }
                 if (P.cfg.range_fused)
                     for (int32_t st = 0; st < nd.npts; st += kFusedPoints) {
                         fused_blocks.push_back(BlockItem{hn.compact, st});
