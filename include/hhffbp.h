@@ -303,7 +303,26 @@ typedef struct {
                                        the depth's nodes: the sample count of Sec. IV-B
                                        (eq. 4_subimgsmppresimp) before the interpolation
                                        stencils' halos (midpoint rule on <= 32^3 cells) */
+    int32_t range_gemm_form;        /* the range-compression (eq. 2) kernel hhffbp_image
+                                       runs (modes other than HHFFBP_DIRECT_EXACT), for
+                                       echoes at a 16-byte aligned address:
+                                       HHFFBP_GEMM_FORM_* below (the form of
+                                       hhffbp_config.range_gemm the device and K allow) */
 } hhffbp_plan_info;
+
+/* Values of hhffbp_plan_info.range_gemm_form.  FUSED: none, range compression
+ * is fused into the level-1 BP (range_fused).  F32: float32 MFMA.  SPLIT_REG:
+ * split bfloat16 with operands loaded to registers.  SPLIT_DMA: split, operands
+ * streamed through LDS by direct global-to-LDS loads (K a multiple of 16).
+ * SPLIT_BRES: split, each block's B fragments resident in LDS for all of K and A
+ * loaded to registers (K a multiple of 64, K/16 x 9 KB of LDS a block). */
+enum {
+    HHFFBP_GEMM_FORM_FUSED = -1,
+    HHFFBP_GEMM_FORM_F32 = 0,
+    HHFFBP_GEMM_FORM_SPLIT_REG = 1,
+    HHFFBP_GEMM_FORM_SPLIT_DMA = 2,
+    HHFFBP_GEMM_FORM_SPLIT_BRES = 3
+};
 
 hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info);
 

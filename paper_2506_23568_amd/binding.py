@@ -61,7 +61,7 @@ class PlanInfo(ctypes.Structure):
         ("device_bytes", ctypes.c_int64), ("model_ms", ctypes.c_double),
         ("final_bricks", ctypes.c_int64), ("final_boxed", ctypes.c_int64),
         ("root_grid", ctypes.c_int32), ("merge_pairs_depth", ctypes.c_int64 * 16),
-        ("level_estimate", ctypes.c_double * 16),
+        ("level_estimate", ctypes.c_double * 16), ("range_gemm_form", ctypes.c_int32),
     ]
 
 

@@ -261,6 +261,18 @@ hhffbp_status hhffbp_get_plan_info(hhffbp_plan_t plan, hhffbp_plan_info *info)
         info->merge_pairs_depth[d] = P.merge_pairs_depth[d];
     for (int d = 0; d < (int)P.level_estimate.size() && d < 16; ++d)
         info->level_estimate[d] = P.level_estimate[d];
+    // the choice the range-compression launch makes for aligned echoes
+    const bool k16 = (2 * P.cfg.n_freq) % 16 == 0;
+    if (P.cfg.range_fused)
+        info->range_gemm_form = HHFFBP_GEMM_FORM_FUSED;
+    else if (P.cfg.storage != HHFFBP_C64 || (P.dev.Bx == nullptr && P.Bx.empty()))
+        info->range_gemm_form = HHFFBP_GEMM_FORM_F32;
+    else if (k16 && P.gemm_br_spx > 0)
+        info->range_gemm_form = HHFFBP_GEMM_FORM_SPLIT_BRES;
+    else if (k16 && P.gemm_dma)
+        info->range_gemm_form = HHFFBP_GEMM_FORM_SPLIT_DMA;
+    else
+        info->range_gemm_form = HHFFBP_GEMM_FORM_SPLIT_REG;
     return HHFFBP_OK;
 }
 

@@ -223,6 +223,7 @@ struct Plan {
     std::vector<uint16_t> Bx; // Bmat split into bfloat16 parts in MFMA fragment order (split GEMM)
     int32_t gemm_nt = 0;      // its 32-column tiles
     bool gemm_dma = false;    // the split GEMM's direct-load form may run (LDS opt-in granted)
+    int32_t gemm_br_spx = 0;  // row streams per XCD of its B-resident form (0: that form is off)
     std::vector<float> Bdmat; // [2 Nf][2 Nr]
     std::vector<float> Badjmat; // [2 Nr][2 Nf]
     // tree
@@ -315,7 +316,8 @@ hipError_t launch_rc_gemm(int storage_a, const void *A, const int32_t *a_perm, i
 // Plan time: the dynamic LDS the level-1 adjoint may use (adj_lds_max) and the
 // opt-in of its instances that need more than the default (kernels_adjoint.hip).
 hipError_t prepare_backward(Plan &P);
-// Plan time: the LDS opt-in of the split GEMM's direct-load form (gemm_dma).
+// Plan time: the LDS opt-ins of the split GEMM's direct-load (gemm_dma) and
+// B-resident (gemm_br_spx) forms.
 hipError_t prepare_forward(Plan &P);
 hhffbp_status launch_backward(const Plan &P, const void *echoes, const double *positions,
                               const void *grad_image, void *grad_echoes, double *grad_positions,

@@ -3,9 +3,11 @@
 //   k_prep_positions  antenna offsets from their leaf centre (float64 -> float32)
 //   k_absmax, k_scales  per-call power-of-two scales for half-precision storage
 //   k_rc_gemm         range compression, eq. (2): profiles = echoes x W on float32 MFMA
-//   k_rc_gemm_x6_dma  the same for complex64 echoes as exact bfloat16 splits on bf16
-//                     MFMA (float32 accuracy), operands through LDS by direct loads;
-//                     k_rc_gemm_x6 its register form
+//   k_rc_gemm_x6_br   the same for complex64 echoes as exact bfloat16 splits on bf16
+//                     MFMA (float32 accuracy), each block's B fragments resident in
+//                     LDS and A loaded to registers (two or more row tiles a wave);
+//                     k_rc_gemm_x6_dma with operands through LDS by direct loads,
+//                     k_rc_gemm_x6 with operands loaded to registers
 //   k_leaf_bp         level-1 BP onto each leaf grid + SDC (Sec. IV-A, eq. sdc_mul)
 //   k_merge           interpolate compressed children onto a parent grid, undo
 //                     their SDC, sum, compress with the parent's Phi (Sec. IV-A)
@@ -599,6 +601,152 @@ __global__ __launch_bounds__(64 * kX6Waves, 2) void k_rc_gemm_x6_dma(const float
             const int row = row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
             if (row < M && col < N) C[(size_t)row * N + col] = acc[c][r] * sc;
         }
+    }
+}
+
+// The same split GEMM with the block's B fragments resident in LDS for the whole
+// of K.  A block is one CU's 16 waves and one column group (3 tiles); it stages
+// the group's K/16 x 9 fragments (9 KB a k step) once, by direct global-to-LDS
+// loads and one barrier, and from then on every wave works alone: it takes 32-row
+// tiles of A in turn, loading each lane's 32 bytes of a k step straight into
+// registers kBrDepth steps ahead (past the end of a tile, the next tile's first
+// steps), so no wave waits on another and the MFMAs of one overlap the loads and
+// splits of the others.  The aperture weight of a row scales the finished row
+// (diag(w) A B), fetched from the lane that holds it.  Blocks map to XCDs so that
+// the column groups of one row stream share an XCD and read the same rows of A
+// at about the same time (one HBM read, the others from that XCD's L2).  Needs
+// K % (16 kBrDepth) == 0, 16-byte aligned rows of A and K/16 x 9 KB of LDS.
+constexpr int kBrWaves = 16;
+constexpr int kBrDepth = 4;
+constexpr int kBrStepBytes = 9 * 1024;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t cvt_pk_bf16(float a, float b)
+{
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 h2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){a, b}, h2));
+}
+
+// split_bf16x3 on pairs: one packed round-to-nearest-even conversion per pair
+// and part; a part's float32 value is its bfloat16 shifted up (low half) or
+// masked (high half), so the remainders are formed without unpacking.
+__device__ __forceinline__ void split_bf16x3_pk(const float4 &u, const float4 &v, bf16x8 &x1, bf16x8 &x2,
+                                                bf16x8 &x3)
+{
+    const float a[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+    u32x4 h, m, t;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const float a0 = a[2 * p], a1 = a[2 * p + 1];
+        h[p] = cvt_pk_bf16(a0, a1);
+        const float r0 = a0 - __uint_as_float(h[p] << 16), r1 = a1 - __uint_as_float(h[p] & 0xFFFF0000u);
+        m[p] = cvt_pk_bf16(r0, r1);
+        const float s0 = r0 - __uint_as_float(m[p] << 16), s1 = r1 - __uint_as_float(m[p] & 0xFFFF0000u);
+        t[p] = cvt_pk_bf16(s0, s1);
+    }
+    x1 = __builtin_bit_cast(bf16x8, h);
+    x2 = __builtin_bit_cast(bf16x8, m);
+    x3 = __builtin_bit_cast(bf16x8, t);
+}
+
+__global__ __launch_bounds__(64 * kBrWaves, 1) void k_rc_gemm_x6_br(const float *__restrict__ A,
+                                                          const int32_t *__restrict__ perm, int M, int K,
+                                                          const bf16x8 *__restrict__ Bx, int NT, int N,
+                                                          float *__restrict__ C,
+                                                          const float *__restrict__ scale,
+                                                          const float *__restrict__ a_w, int spx)
+{
+    constexpr int CT = 3, D = kBrDepth;
+    extern __shared__ __align__(16) unsigned char lds[];
+    const bf16x8 *sB = reinterpret_cast<const bf16x8 *>(lds);
+    const int lane = (int)(threadIdx.x & 63);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int ncg = (NT + CT - 1) / CT;
+    // workgroup b runs on XCD b mod kXcds: the ncg column groups of a stream are
+    // consecutive workgroups of one XCD
+    const int xcd = (int)blockIdx.x % kXcds, j = (int)blockIdx.x / kXcds;
+    const int cg = j % ncg, stream = xcd + kXcds * (j / ncg);
+    const int ct0 = cg * CT, KS = K / 16, ntiles = (M + 31) / 32;
+    const int tstep = kXcds * spx * kBrWaves;
+    int tile = stream * kBrWaves + wave;
+    // this lane's row of a tile: its A row (32 bytes a k step from k = 8 (lane div 32))
+    // and its aperture weight
+    auto row_src = [&](int t) {
+        const int r = t * 32 + (lane & 31);
+        return r < M ? (perm ? perm[r] : r) : -1;
+    };
+    auto row_ptr = [&](int src) { return A + (size_t)(src < 0 ? 0 : src) * K + 8 * (lane >> 5); };
+    int src_cur = row_src(tile);
+    const float *cur = row_ptr(src_cur), *nxt = row_ptr(row_src(tile + tstep));
+    float4 ab[D][2];
+    {
+        const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char *)lds;
+        for (int f = wave; f < KS * 9; f += kBrWaves) {
+            const int ks = f / 9, cq = f - 9 * ks, c = cq / 3, q = cq - 3 * c;
+            dma16(Bx + ((size_t)(ks * NT + min(ct0 + c, NT - 1)) * 3 + q) * 64 + lane, lds0 + (uint32_t)f * 1024);
+        }
+        __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
+        __syncthreads();
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        ab[d][0] = *reinterpret_cast<const float4 *>(cur + 16 * d);
+        ab[d][1] = *reinterpret_cast<const float4 *>(cur + 16 * d + 4);
+    }
+    const float sc = scale ? scale[0] : 1.0f;
+    for (; tile < ntiles; tile += tstep) {
+        f32x16 acc[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
+        for (int ks0 = 0; ks0 < KS; ks0 += D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int ks = ks0 + d;
+                bf16x8 x[3];
+                split_bf16x3_pk(ab[d][0], ab[d][1], x[0], x[1], x[2]);
+                // refill: step ks + D of this tile, else of the next one
+                const int kn = ks + D;
+                const float *src = kn < KS ? cur + 16 * kn : nxt + 16 * (kn - KS);
+                ab[d][0] = *reinterpret_cast<const float4 *>(src);
+                ab[d][1] = *reinterpret_cast<const float4 *>(src + 4);
+                const bf16x8 *b = sB + (size_t)ks * 9 * 64 + lane;
+                constexpr int pa_[6] = {0, 0, 1, 0, 1, 2}, pb_[6] = {0, 1, 0, 2, 1, 0};
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    const bf16x8 b0 = b[(3 * c) * 64], b1 = b[(3 * c + 1) * 64], b2 = b[(3 * c + 2) * 64];
+                    const bf16x8 bv[3] = {b0, b1, b2};
+#pragma unroll
+                    for (int t = 0; t < 6; ++t)
+                        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[pa_[t]], bv[pb_[t]], acc[c], 0, 0, 0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // C rows: result register r of lane l is row 8 (r div 4) + 4 (l div 32) + r mod 4
+        const int rt = tile * 32;
+        const float w_own = src_cur < 0 ? 0.0f : (a_w ? a_w[src_cur] : 1.0f);
+        float wr[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            wr[r] = sc * (a_w ? __shfl(w_own, 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) : 1.0f);
+        float *crow = C + (size_t)(rt + 4 * (lane >> 5)) * N + 32 * ct0 + (lane & 31);
+        const bool full = rt + 32 <= M;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            if (ct0 + c >= NT) break;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int ri = 8 * (r >> 2) + (r & 3);
+                if (full || rt + 4 * (lane >> 5) + ri < M) crow[(size_t)ri * N + 32 * c] = acc[c][r] * wr[r];
+            }
+        }
+        src_cur = row_src(tile + tstep);
+        cur = nxt;
+        nxt = row_ptr(row_src(tile + 2 * tstep));
     }
 }
 
@@ -1503,7 +1651,13 @@ hhffbp_status image_for_storage(const Plan &P, const void *echoes, const double 
             const int NT = P.gemm_nt, rows_per_block = (kBlock / 64) * 64;
             const bool vec = K % 16 == 0 && reinterpret_cast<uintptr_t>(echoes) % 16 == 0;
             const dim3 grid(((M + rows_per_block - 1) / rows_per_block) * ((NT + CT - 1) / CT));
-            if (vec && P.gemm_dma) {
+            if (vec && P.gemm_br_spx > 0) {
+                const int ncg = (NT + CT - 1) / CT;
+                hipLaunchKernelGGL(k_rc_gemm_x6_br, dim3(kXcds * ncg * P.gemm_br_spx), dim3(64 * kBrWaves),
+                                   (size_t)(K / 16) * kBrStepBytes, st, (const float *)echoes,
+                                   (const int32_t *)P.dev.perm, M, K, (const bf16x8 *)P.dev.Bx, NT, N,
+                                   (float *)prof, scales, (const float *)P.dev.weights, (int)P.gemm_br_spx);
+            } else if (vec && P.gemm_dma) {
                 const dim3 grid_dma(((M + 32 * kX6Waves - 1) / (32 * kX6Waves)) * ((NT + CT - 1) / CT));
                 hipLaunchKernelGGL(k_rc_gemm_x6_dma, grid_dma, dim3(64 * kX6Waves), kX6LdsBytes, st,
                                    (const float *)echoes,
@@ -1571,19 +1725,36 @@ hipError_t launch_check_positions(const Plan &P, const double *pos64, int32_t *c
 
 hipError_t prepare_forward(Plan &P)
 {
-    // the split GEMM's direct-load form needs kX6LdsBytes of LDS a block, more
-    // than the default: opt in where the device allows it, else the register form
+    // the split GEMM's direct-load form needs kX6LdsBytes of LDS a block and its
+    // B-resident form K/16 x kBrStepBytes, more than the default: opt in where the
+    // device allows it, else the register form
     P.gemm_dma = false;
+    P.gemm_br_spx = 0;
     if (P.dev.Bx == nullptr) return hipSuccess;
-    int dev = 0, optin = 0;
+    int dev = 0, optin = 0, ncu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     if (optin < kX6LdsBytes) return hipSuccess;
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rc_gemm_x6_dma),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kX6LdsBytes);
     if (e != hipSuccess) return e;
     P.gemm_dma = true;
+    const int K = (int)(2 * P.cfg.n_freq), ncg = (P.gemm_nt + 2) / 3;
+    const int br_lds = (K / 16) * kBrStepBytes;
+    if (K % (16 * kBrDepth) == 0 && br_lds <= optin && ncg > 0) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rc_gemm_x6_br),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, br_lds);
+        if (e != hipSuccess) return e;
+        // one block per CU: as many row streams per XCD as its CUs hold column
+        // groups.  Taken only where every wave gets two or more 32-row tiles, so
+        // that the staging of B and each wave's first loads are amortised (with
+        // fewer rows the direct-load form is faster)
+        const int spx = std::max(1, ncu / (kXcds * ncg));
+        const int64_t groups = (P.cfg.n_pos + 32 * kBrWaves - 1) / (32 * kBrWaves);
+        if (groups >= 2 * (int64_t)kXcds * spx) P.gemm_br_spx = spx;
+    }
     return hipSuccess;
 }
 

@@ -1404,6 +1404,9 @@ void upload_plan(Plan &P)
         upload_vec(P.device_bytes, &D.kf, P.k);
         upload_vec(P.device_bytes, &D.kf_turns, kt);
     }
+    // the range-compression GEMM's forms, for every mode that range-compresses
+    if (prepare_forward(P) != hipSuccess)
+        throw Error{HHFFBP_E_DEVICE, "split GEMM LDS opt-in failed"};
     if (S == 0) return;
     int32_t pos_cursor = 0;
     for (int d = P.F; d <= S; ++d) {
@@ -1651,8 +1654,6 @@ void upload_plan(Plan &P)
             hipStreamSynchronize(nullptr) != hipSuccess)
             throw Error{HHFFBP_E_DEVICE, "position offsets failed during plan upload"};
     }
-    if (prepare_forward(P) != hipSuccess)
-        throw Error{HHFFBP_E_DEVICE, "split GEMM LDS opt-in failed"};
     if (prepare_backward(P) != hipSuccess)
         throw Error{HHFFBP_E_DEVICE, "setting the level-1 adjoint's LDS limit failed"};
 }

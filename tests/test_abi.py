@@ -101,6 +101,18 @@ def test_invalid_configurations_are_rejected(small, change, status):
     assert e.value.status == status
 
 
+def test_range_gemm_form_is_reported(small):
+    """hhffbp_plan_info.range_gemm_form (the last field of the struct: a wrong
+    layout in the binding reads garbage there).  A host-only plan has no device
+    LDS opt-in, so the split GEMM reports its register form; the float32 GEMM
+    and the fused level-1 BP report their own values."""
+    kw = dict(device=-1, range_kernel="linear", range_oversample=4.0, stages=2)
+    assert H.Plan(*_args(small), **kw).info()["range_gemm_form"] == 1
+    assert H.Plan(*_args(small), range_gemm="f32", **kw).info()["range_gemm_form"] == 0
+    assert H.Plan(*_args(small), storage="f16", **kw).info()["range_gemm_form"] == 0
+    assert H.Plan(*_args(small), range_fused=True, **kw).info()["range_gemm_form"] == -1
+
+
 def test_exact_direct_mode_plans_on_the_host(small):
     """mode = direct_exact plans without stages; an unknown mode is rejected."""
     info = H.Plan(*_args(small), mode="direct_exact", device=-1).info()

@@ -221,6 +221,10 @@ def test_large_bandlimited_vs_stored_oracle(torch, large, form, stored):
         else dict(range_kernel="es", range_oversample=2.0, range_taps=7)
     pl = H.Plan(*_args(w), stages=stages, merge_factor=4, oversample=BL_GAMMA, interp_taps=TAPS,
                 interp_kernel="bandlimited", root_grid=root, oversample_leaf=leaf, **kw)
+    gf = pl.info()["range_gemm_form"]
+    _say(f"  range-compression kernel form {gf}")
+    if form == "linear":
+        assert gf == 3  # the timed form's split GEMM keeps its B fragments resident in LDS
     ws = pl._workspace(torch)
     img = pl.image(_ech(torch, w), workspace=ws)
     torch.cuda.synchronize()
