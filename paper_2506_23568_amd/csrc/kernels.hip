@@ -1148,6 +1148,12 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
         const NodeDev ch = children[c];
         const TileBox tb = tiles[(size_t)brick * nchild + c];
         const int ncol = tb.ni * tb.nj;
+        // this lane's record, loaded before the staging so that its latency
+        // overlaps the table and the box (a barrier keeps the compiler from
+        // moving global loads above it)
+        const size_t r = ((size_t)brick * nchild + c) * kBlock + t;
+        const InterpIdx rx = ridx[r];
+        const InterpGeo g = rgeo[r];
         __syncthreads();  // the previous child's box and table are consumed
         if (tb.ni > 0) {
             const ColEntry *ccol = ccols + ch.col_base + (tb.i0 - ch.i0) * ch.nj + (tb.j0 - ch.j0);
@@ -1189,10 +1195,7 @@ __global__ __launch_bounds__(kBlock) void k_final(const NodeDev *__restrict__ ch
             }
         }
         __syncthreads();
-        const size_t r = ((size_t)brick * nchild + c) * kBlock + t;
-        const InterpIdx rx = ridx[r];
         if (inside && rx.cij != kNoPair) {
-            const InterpGeo g = rgeo[r];
             const int ci0 = (int)(rx.cij & 0xffffu), cj0 = (int)(rx.cij >> 16);
             float wu[T], wv[T], wn[T];
             interp_weights3<T, K>(ip, g.fu, g.fv, g.fn, wu, wv, wn);
