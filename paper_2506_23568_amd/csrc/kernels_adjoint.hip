@@ -295,12 +295,14 @@ __global__ __launch_bounds__(kBlock) void k_final_adj(const NodeDev *__restrict_
     for (int c = 0; c < nchild; ++c) {
         const NodeDev ch = children[c];
         const size_t r = ((size_t)brick * nchild + c) * kBlock + t;
+        // both records at once (every slot has them), so that the geometry's
+        // load does not wait for the index's
         const InterpIdx rx = ridx[r];
+        const InterpGeo rg = rgeo[r];
         const bool on = active && rx.cij != kNoPair;
         ChildCoord cc{};
         float gre = 0.0f, gim = 0.0f;
         if (on) {
-            const InterpGeo rg = rgeo[r];
             cc = record_coord<T>(ch, rx, rg);
             rotate_back(g, rg.turns, gre, gim);
         }
@@ -354,15 +356,22 @@ __global__ __launch_bounds__(kBlock) void k_merge_adj(const NodeDev *__restrict_
     const int s = active ? rank[val_base + p] : 0;
     const int pb = kBlock / Q;
     const size_t rbase = (size_t)(fb0 + s / pb) * kBlock + (size_t)((s % pb) / 64 * Q) * 64 + s % 64;
+    // the records of child c + 1 are loaded before child c's scatter (whose
+    // barriers would otherwise hold them back); every slot has both records
+    InterpIdx rx_next = ridx[rbase];
+    InterpGeo rg_next = rgeo[rbase];
     for (int c = 0; c < nchild; ++c) {
         const NodeDev ch = children[ndp->child[c]];
-        InterpIdx rx{kNoPair, 0};
-        if (active) rx = ridx[rbase + (size_t)c * 64];
+        const InterpIdx rx = rx_next;
+        const InterpGeo rg = rg_next;
+        if (c + 1 < nchild) {
+            rx_next = ridx[rbase + (size_t)(c + 1) * 64];
+            rg_next = rgeo[rbase + (size_t)(c + 1) * 64];
+        }
         const bool on = active && rx.cij != kNoPair;  // absent parent points hold nothing
         ChildCoord cc{};
         float gre = 0.0f, gim = 0.0f;
         if (on) {
-            const InterpGeo rg = rgeo[rbase + (size_t)c * 64];
             cc = record_coord<T>(ch, rx, rg);
             rotate_back(g, rg.turns, gre, gim);
         }
