@@ -136,18 +136,22 @@ def large_scene():
     return make_config(2, synth_device="cuda")
 
 
-@pytest.mark.parametrize("n_pos,n_f,weighted", [(65521, 128, False), (65536, 128, True)])
+@pytest.mark.parametrize("n_pos,n_f,weighted", [(65521, 128, False), (65536, 128, True), (131072, 64, False)])
 def test_split_gemm_b_resident_large(torch, large_scene, n_pos, n_f, weighted):
     """The B-resident form, which takes over where every wave gets two or more
     32-row tiles: the large workload's positions (65521: a ragged last tile) on
     its voxel grid (direct BP's range extent at U = 4: N_r = 160, ten column
     tiles in four groups, the last group's two tiles past N clamped), the large
     workload's K = 256 (144 KB of resident fragments), with and without aperture
-    weights scaling the finished rows; split vs float32 GEMM through direct BP
-    (linear range kernel, U = 4, the timed form's)."""
+    weights scaling the finished rows; and the positions taken twice (131072
+    rows) with 64 frequencies: K = 128 (two k groups of the prefetch), N_r = 96
+    in two column groups, 16 row streams per XCD; split vs float32 GEMM through
+    direct BP (linear range kernel, U = 4, the timed form's)."""
     w = large_scene
-    pos, freqs = w.positions[:n_pos], w.freqs_hz[:n_f]
-    echoes = w.echoes[:n_pos, :n_f]
+    reps = -(-n_pos // w.positions.shape[0])
+    pos = np.concatenate([w.positions] * reps)[:n_pos]
+    echoes = np.concatenate([w.echoes[:, :n_f]] * reps)[:n_pos]
+    freqs = w.freqs_hz[:n_f]
     kw = {}
     if weighted:
         kw["weights"] = np.random.default_rng(11).uniform(0.2, 3.0, n_pos)
