@@ -449,16 +449,18 @@ void build_merge_bricks(Plan &P, int d)
 
 // Lane order of the forward merge at depth d (a wave takes 64 consecutive
 // entries).  Below the root: storage order, runs along the pencils.  Onto the
-// root's own lattice (d = 0): its points grouped in bricks of 2 x 4 x 8 lattice
+// root's own lattice (d = 0): its points grouped in bricks of 2 x 8 x 4 lattice
 // steps (i, j, l), bricks in (i, j, l) order, points within a brick in (i, j, l)
 // order.  There the children's frames are tilted most against the parent's
 // (their centres are a quarter aperture off), so a run along one parent pencil
 // crosses many child columns, and a compact group of points reaches fewer L1
-// lines per gather instruction (measured on the large workload: 0.129 ->
-// 0.102 ms; the deeper merges ran 3-5% slower in brick order).
+// lines per gather instruction (measured on the large workload: 0.129 ms in
+// storage order, 0.103 in 2 x 4 x 8 bricks, 0.100 in 2 x 8 x 4, the best of
+// eleven shapes of 64 and 128 points; the deeper merges ran 3-5% slower in brick
+// order).
 void build_merge_order(Plan &P, int d)
 {
-    constexpr int kBi = 2, kBj = 4, kBl = 8;
+    constexpr int kBi = 2, kBj = 8, kBl = 4;
     const std::vector<int32_t> &nodes = P.compact_to_tree[d];
     auto &out = P.merge_order[d];
     out.assign(nodes.size(), {});
