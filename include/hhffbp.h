@@ -289,7 +289,7 @@ typedef struct {
     int64_t device_bytes;           /* device memory the plan holds (its tables) */
     double model_ms;                /* Sec. IV-B cost model: level-1 BP + interpolation,
                                        with the per-pair costs of hhffbp_config.stages */
-    int64_t final_bricks;           /* final stage: voxel bricks of 4 x 4 x 16 */
+    int64_t final_bricks;           /* final stage: voxel bricks of 4 x 8 x 8 (x, y, z) */
     int64_t final_boxed;            /* (brick, depth-1 node) pairs (with a root grid:
                                        (brick, root)) whose stencils fit one staged
                                        box (the rest read the pencils directly)  */

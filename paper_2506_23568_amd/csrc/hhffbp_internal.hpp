@@ -80,7 +80,8 @@ struct BlockItem {
 // values apart (ni * nj * cs <= kTileCap + kTileCap / 4); ni = 0 marks a box
 // of more than kTileCap values at 2^lsh >= nl per column (the kernel then
 // gathers from the pencils) or one no stencil uses.
-constexpr int kBrickX = 4, kBrickY = 4, kBrickZ = 16;
+constexpr int kBrickX = 4, kBrickY = 8, kBrickZ = 8;
+static_assert(kBrickX * kBrickY * kBrickZ == kBlockThreads, "one voxel per thread of a block");
 constexpr int kTileCap = 2048;
 // The final stage's LDS column stride for boxes of nl <= 24 (TileBox::cs), which
 // the kernel also takes as a compile-time constant when every box has it.
@@ -95,11 +96,13 @@ struct TileBox {
     int32_t cs;      // LDS column stride (values)
 };
 
-// Bricks of a parent grid for the merge adjoint: kBrickX x kBrickY columns
-// (i, j) x kBrickZ lattice steps l of one node's grid, with origin (i, j, l); a
+// Bricks of a parent grid for the merge adjoint: kMBrickI x kMBrickJ columns
+// (i, j) x kMBrickL lattice steps l of one node's grid, with origin (i, j, l); a
 // lane's grid point is found through the node's column table (lanes outside
 // every pencil are idle).  Their stencils cover a smaller box of the child grid
 // than a run of points along the pencils does.
+constexpr int kMBrickI = 4, kMBrickJ = 4, kMBrickL = 16;
+static_assert(kMBrickI * kMBrickJ * kMBrickL == kBlockThreads, "one grid point per thread of a block");
 struct MergeBrick {
     int32_t node, i, j, l;
 };

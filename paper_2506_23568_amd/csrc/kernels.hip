@@ -1103,8 +1103,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(const NodeDev *__restrict__ pa
 
 // Final stage: user voxels, children are the depth-1 nodes (or the root's own
 // grid, then the only child); scales[sc] is their storage scale.  One lane per voxel,
-// a block per brick of kBrickX x kBrickY x kBrickZ voxels (lane t: z = t mod 16
-// fastest, then y, then x).  Per child, the block first stages the child's
+// a block per brick of kBrickX x kBrickY x kBrickZ voxels (lane t: z = t mod
+// kBrickZ fastest, then y, then x).  Per child, the block first stages the child's
 // values over the brick's stencil box (TileBox, from the plan) into LDS: a
 // table of the box's columns (where each column's pencil starts and which box
 // indices it covers), then every pencil value inside the box, thread-strided.

@@ -139,7 +139,7 @@ __device__ __forceinline__ float wave_sum_f(float v)
 }
 
 // Every lane of the block calls this (inactive lanes with active = false).
-template <int T, int K>
+template <int T, int K, int VSHIFT>
 __device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c,
                                     const ColEntry *__restrict__ cols, float2 *__restrict__ grad,
                                     const ChildCoord &g, const InterpPoly &ip, float gre,
@@ -200,11 +200,11 @@ __device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c
         const int bi = g.bi + lo - o0, bj = g.bj + lo - o1, bl = g.bl + lo - o2;
         // Neighbouring points often share a stencil base; taken in the same tap
         // order their atomics would hit one LDS address per instruction.  Each
-        // lane rotates its v and n tap order by lane bits (the z and y
-        // neighbours of the 4 x 4 x 16 bricks: z = lane mod 16, y = lane / 16),
-        // so such lanes add to different entries at once; integer sums do not
-        // depend on the order.
-        const int rn = lane % T, rv = (lane >> 4) % T;
+        // lane rotates its n tap order by its lowest bits and its v tap order by
+        // the bits above the brick's fastest axis (VSHIFT = log2 of its length:
+        // l and j of a merge brick, z and y of a voxel brick), so such lanes add
+        // to different entries at once; integer sums do not depend on the order.
+        const int rn = lane % T, rv = (lane >> VSHIFT) % T;
         float wvr[T], wnr[T];
         int ov[T], on[T];
 #pragma unroll
@@ -268,7 +268,7 @@ __device__ void block_scatter_child(BoxShared &sh, bool active, const NodeDev &c
     __syncthreads();
 }
 
-// F^H: a block per brick of the final stage (4 x 4 x 16 voxels, numbered and
+// F^H: a block per brick of the final stage (kBrickX x kBrickY x kBrickZ voxels, numbered and
 // laid out as k_final's); each voxel's cotangent is rotated by -Phi_child and
 // scattered into the child's grid through the block's box, with the stencil,
 // fractions and phase of the forward's plan-time record of that (voxel, child).
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_final_adj(const NodeDev *__restrict_
             cc = record_coord<T>(ch, rx, rg);
             rotate_back(g, rg.turns, gre, gim);
         }
-        block_scatter_child<T, K>(sh, on, ch, ccols, cgrad, cc, ip, gre, gim);
+        block_scatter_child<T, K, __builtin_ctz(kBrickZ)>(sh, on, ch, ccols, cgrad, cc, ip, gre, gim);
     }
 }
 
@@ -338,8 +338,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_adj(const NodeDev *__restrict_
     const int ni = ndp->ni, nj = ndp->nj, i0 = ndp->i0, j0 = ndp->j0, col_base = ndp->col_base;
     const int val_base = ndp->val_base, nchild = ndp->nchild, fb0 = ndp->fwd_block0;
     const int t = (int)threadIdx.x;
-    const int ci = mb.i + t / (kBrickY * kBrickZ) - i0, cj = mb.j + (t / kBrickZ) % kBrickY - j0;
-    const int l = mb.l + t % kBrickZ;
+    const int ci = mb.i + t / (kMBrickJ * kMBrickL) - i0, cj = mb.j + (t / kMBrickL) % kMBrickJ - j0;
+    const int l = mb.l + t % kMBrickL;
     bool active = false;
     int p = 0;
     if ((unsigned)ci < (unsigned)ni && (unsigned)cj < (unsigned)nj) {
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_adj(const NodeDev *__restrict_
             cc = record_coord<T>(ch, rx, rg);
             rotate_back(g, rg.turns, gre, gim);
         }
-        block_scatter_child<T, K>(sh, on, ch, ccols, cgrad, cc, ip, gre, gim);
+        block_scatter_child<T, K, __builtin_ctz(kMBrickL)>(sh, on, ch, ccols, cgrad, cc, ip, gre, gim);
     }
 }
 

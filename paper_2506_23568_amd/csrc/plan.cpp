@@ -422,8 +422,8 @@ void build_final_tiles(Plan &P)
     P.n_tiled = tiled.load();
 }
 
-// Merge bricks of depth d: per node, 4 x 4 column blocks of its grid, each cut
-// into runs of kBrickZ steps over the union of its columns' n ranges.
+// Merge bricks of depth d: per node, kMBrickI x kMBrickJ column blocks of its
+// grid, each cut into runs of kMBrickL steps over the union of its columns' n ranges.
 void build_merge_bricks(Plan &P, int d)
 {
     std::vector<MergeBrick> &bricks = P.merge_bricks[d];
@@ -431,17 +431,17 @@ void build_merge_bricks(Plan &P, int d)
     for (int32_t ti : P.compact_to_tree[d]) {
         const HostNode &nd = P.levels[d][ti];
         const HostLattice &L = nd.lat;
-        for (int32_t ib = 0; ib < L.ni; ib += kBrickX)
-            for (int32_t jb = 0; jb < L.nj; jb += kBrickY) {
+        for (int32_t ib = 0; ib < L.ni; ib += kMBrickI)
+            for (int32_t jb = 0; jb < L.nj; jb += kMBrickJ) {
                 int32_t lmin = INT32_MAX, lmax = INT32_MIN;
-                for (int32_t i = ib; i < std::min(L.ni, ib + kBrickX); ++i)
-                    for (int32_t j = jb; j < std::min(L.nj, jb + kBrickY); ++j) {
+                for (int32_t i = ib; i < std::min(L.ni, ib + kMBrickI); ++i)
+                    for (int32_t j = jb; j < std::min(L.nj, jb + kMBrickJ); ++j) {
                         const int64_t cidx = (int64_t)i * L.nj + j;
                         if (L.hi[cidx] < L.lo[cidx]) continue;
                         lmin = std::min(lmin, L.lo[cidx]);
                         lmax = std::max(lmax, L.hi[cidx]);
                     }
-                for (int32_t l = lmin; lmin <= lmax && l <= lmax; l += kBrickZ)
+                for (int32_t l = lmin; lmin <= lmax && l <= lmax; l += kMBrickL)
                     bricks.push_back(MergeBrick{nd.compact, L.i0 + ib, L.j0 + jb, l});
             }
     }
@@ -934,7 +934,7 @@ void merge_records(const Plan &P, int d, const std::vector<BlockItem> &blocks,
 }
 
 // Records of the final stage: brick b (as the final kernel numbers them), node c
-// of depth F, lane t: voxel (kx 4 + t / 64, ky 4 + (t / 16) mod 4, kz 16 + t mod 16).
+// of depth F, lane t: voxel (kx 4 + t / 64, ky 8 + (t / 8) mod 8, kz 8 + t mod 8).
 // With final-stage staging on, every (brick, node) box becomes the hull of the
 // stencils its records use (also where the margin box was too large to stage);
 // a box no record uses is dropped, and one that would exceed kTileCap keeps no

@@ -67,13 +67,13 @@ def test_config_default_layout():
 
 
 def test_final_stage_bricks(small):
-    """Voxel bricks of 4 x 4 x 16 for the final stage; with staging off no
+    """Voxel bricks of 4 x 8 x 8 for the final stage; with staging off no
     (brick, depth-1 node) pair has a box, with it on at most all of them."""
     import math
     on = H.Plan(*_args(small), stages=2, device=-1).info()
     off = H.Plan(*_args(small), stages=2, device=-1, final_staging=False).info()
     d = small.grid_dims
-    assert on["final_bricks"] == math.ceil(d[0] / 4) * math.ceil(d[1] / 4) * math.ceil(d[2] / 16)
+    assert on["final_bricks"] == math.ceil(d[0] / 4) * math.ceil(d[1] / 8) * math.ceil(d[2] / 8)
     assert off["final_bricks"] == on["final_bricks"] and off["final_boxed"] == 0
     assert 0 < on["final_boxed"] <= on["final_bricks"] * 4
 
