@@ -448,19 +448,19 @@ void build_merge_bricks(Plan &P, int d)
 }
 
 // Lane order of the forward merge at depth d (a wave takes 64 consecutive
-// entries).  Below the root: storage order, runs along the pencils.  Onto the
-// root's own lattice (d = 0): its points grouped in bricks of 2 x 8 x 4 lattice
-// steps (i, j, l), bricks in (i, j, l) order, points within a brick in (i, j, l)
-// order.  There the children's frames are tilted most against the parent's
+// entries).  At d >= 2: storage order, runs along the pencils.  Onto the root's
+// own lattice (d = 0) and onto depth 1: the points grouped in bricks of 2 x 8 x 4
+// (d = 0) or 1 x 4 x 16 (d = 1) lattice steps (i, j, l), bricks in (i, j, l)
+// order, points within a brick in (i, j, l) order.  There the children's frames are tilted most against the parent's
 // (their centres are a quarter aperture off), so a run along one parent pencil
 // crosses many child columns, and a compact group of points reaches fewer L1
 // lines per gather instruction (measured on the large workload: 0.129 ms in
 // storage order, 0.103 in 2 x 4 x 8 bricks, 0.100 in 2 x 8 x 4, the best of
-// eleven shapes of 64 and 128 points; the deeper merges ran 3-5% slower in brick
-// order).
+// eleven shapes of 64 and 128 points).  Onto depth 1, 1 x 4 x 16 bricks: 0.098 ->
+// 0.094 ms; at depths 2 and 3 the same shapes ran 1-2% slower than storage order.
 void build_merge_order(Plan &P, int d)
 {
-    constexpr int kBi = 2, kBj = 8, kBl = 4;
+    const int kBi = d == 0 ? 2 : 1, kBj = d == 0 ? 8 : 4, kBl = d == 0 ? 4 : 16;
     const std::vector<int32_t> &nodes = P.compact_to_tree[d];
     auto &out = P.merge_order[d];
     out.assign(nodes.size(), {});
@@ -469,7 +469,7 @@ void build_merge_order(Plan &P, int d)
             const HostLattice &L = P.levels[d][nodes[n]].lat;
             std::vector<int32_t> &o = out[n];
             o.resize((size_t)L.npts);
-            if (d > 0) {
+            if (d > 1) {
                 for (int64_t k = 0; k < L.npts; ++k) o[k] = (int32_t)k;
                 continue;
             }
